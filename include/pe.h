@@ -1,0 +1,169 @@
+/*
+ * pe.h - C ABI of libpe: parareal for the partially explicit temporal
+ * splitting scheme in CEM-GMsFEM multiscale spaces, on one MI355X (gfx950).
+ *
+ * Method (Wang, Yang, Leung, "Parallel in time partially explicit splitting
+ * scheme for high contrast linear multiscale diffusion problems"):
+ *   - the splitting scheme of eqs. (2.5)-(2.6): u in V_H1 implicit, w in
+ *     V_H2 explicit, step h, with mass-coupling differences of the previous
+ *     step;
+ *   - the coarse propagator G = one step of size dt_coarse, the fine
+ *     propagator F = P = dt_coarse/dt_fine steps of size dt_fine (the exact
+ *     solution of the all-at-once fine system of Section 4.2 on one coarse
+ *     interval), every propagator call starting with a fresh history;
+ *   - the parareal update of eq. (2.7) and the stopping test of eq. (2.8)
+ *     (Algorithm 1), iteration k applying F to iterate k-1.
+ *
+ * Conventions shared by every call:
+ *   - Matrices and state arrays are dense, row-major, FP64, contiguous.
+ *     "device" pointers are HIP device memory of the current device;
+ *     "host" pointers are ordinary host memory.
+ *   - State vectors are x = [u; w] with u in R^d1 (coefficients in the basis
+ *     of V_H1) and w in R^d2 (V_H2), D = d1 + d2.
+ *   - Input buffers are borrowed for the duration of the call only: the
+ *     library copies what it keeps. Output buffers are caller-allocated.
+ *   - All GPU work is ordered on the stream given at problem creation.
+ *     Calls that return results to the host synchronise that stream.
+ *   - Return value: 0 = success, > 0 = warning, < 0 = error. No exception
+ *     crosses the ABI. pe_last_error() gives a message for the calling
+ *     thread's last failing call. Handles are not thread-safe.
+ */
+#ifndef PE_H
+#define PE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int pe_status;
+typedef struct pe_problem_s* pe_problem;
+
+enum {
+    PE_OK = 0,
+    PE_WARN_NOT_CONVERGED = 1, /* k_max reached before the stopping test held */
+    PE_ERR_ARG = -1,           /* invalid argument (sizes, step ratio, symmetry) */
+    PE_ERR_NOT_SPD = -2,       /* a Cholesky factorisation met a non-positive pivot */
+    PE_ERR_NONFINITE = -3,     /* NaN or Inf in a parareal jump */
+    PE_ERR_STATE = -4,         /* call order violated (e.g. solve before source) */
+    PE_ERR_HIP = -5,           /* HIP runtime error */
+    PE_ERR_NOMEM = -6          /* device allocation failed */
+};
+
+/* precision of the fine propagator */
+enum {
+    PE_FP64 = 0,  /* every product in FP64 on FP64 MFMA */
+    PE_MIXED = 1  /* fine-step products in FP32 on MFMA with FP32 accumulation,
+                     applied to the deviation from an FP64 anchor state taken at
+                     each interval start; FP64 state accumulation, FP64
+                     factorisations, coarse propagator and jump norms */
+};
+
+/* time layout of the source amplitudes */
+enum {
+    PE_T_FINE = 0,     /* H[b][r][m], m = n*P + p: amplitude at t_n + (p+1) dt_fine */
+    PE_T_INTERVAL = 1  /* H[b][r][n]: amplitude constant on (t_n, t_{n+1}] */
+};
+
+/* stopping test of eq. (2.8), norm |e|_M = sqrt(e^T M e), M the full
+   projected mass matrix (the L2(Omega) norm of the coarse function) */
+enum {
+    PE_NORM_M_ABS = 0, /* stop when max_n |x_n^k - x_n^{k-1}|_M <= tol */
+    PE_NORM_M_REL = 1  /* ... <= tol * max_n |x_n^0|_M (x^0 = initial coarse sweep) */
+};
+
+/*
+ * pe_problem_create - set up the operators of one multiscale problem
+ * (Algorithm 1 "Require": the coarse matrices of eq. (3.8)).
+ *   d1, d2      dimensions of V_H1 and V_H2 (d1 >= 1, d2 >= 0).
+ *   M11 (d1 x d1), M12 (d1 x d2, NULL means zero), M22 (d2 x d2),
+ *   A11 (d1 x d1), A12 (d1 x d2), A21 (d2 x d1, NULL means A12^T),
+ *   A22 (d2 x d2): device pointers to the projected mass and stiffness
+ *               blocks. M11, M22, A11, A22 must be symmetric and A21 = A12^T
+ *               (relative tolerance 1e-12), else PE_ERR_ARG.
+ *   dt_coarse   coarse step Delta t = T/N (> 0).
+ *   dt_fine     fine step delta t; P = dt_coarse/dt_fine must be an integer
+ *               within 1e-9 relative, else PE_ERR_ARG.
+ *   N           number of coarse intervals (>= 1).
+ *   precision   PE_FP64 or PE_MIXED.
+ *   hip_stream  hipStream_t for all work of this handle (NULL = default).
+ * On the GPU: FP64 Cholesky factorisations of M11/dt_fine + A11,
+ * M11/dt_coarse + A11 and M22 (PE_ERR_NOT_SPD names the block and pivot),
+ * the inverses formed from the factors, and the step operators.
+ * On success *out owns all device memory it needs until pe_problem_destroy.
+ */
+pe_status pe_problem_create(pe_problem* out, int d1, int d2,
+                            const double* M11, const double* M12, const double* M22,
+                            const double* A11, const double* A12, const double* A21,
+                            const double* A22, double dt_coarse, double dt_fine, int N,
+                            int precision, void* hip_stream);
+
+/*
+ * pe_source_set - source term f(x, t) = sum_r g_r(x) h_r(t) in projected
+ * form (F_i^n of eq. (3.8)), taken at the new time level of every step.
+ *   B           number of samples (independent right-hand sides, >= 1).
+ *   R           number of spatial modes (>= 0; 0 means f = 0).
+ *   G           device, D x R: column r = [Psi1^T b_r; Psi2^T b_r].
+ *   H           device, B x R x T_len amplitudes, T_len = N*P for PE_T_FINE
+ *               (requires R <= 64) and N for PE_T_INTERVAL.
+ * The coarse step of interval n uses the amplitude at t_{n+1}
+ * (PE_T_FINE: index n*P + P - 1; PE_T_INTERVAL: index n).
+ */
+pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const double* H,
+                        int time_mode);
+
+/*
+ * pe_solve - parareal (Algorithm 1) for B samples that share the problem.
+ *   B           must equal the B of the last pe_source_set (or any B >= 1
+ *               when no source was set: f = 0).
+ *   x0          device, B x D initial states (x_0^k = x0 for every k).
+ *   tol, norm_mode   stopping test (see PE_NORM_*); tol >= 0.
+ *   k_max       maximum number of parareal iterations, 0 <= k_max <= N
+ *               (k_max = N reproduces the sequential fine solution).
+ *   X           device, B x (N+1) x D output: the last iterate of each
+ *               sample (samples stop updating once their own test holds).
+ *   iters       host, B ints (nullable): iterations taken per sample.
+ *   jump_hist   host, B x k_max doubles (nullable): max_n |x_n^k - x_n^{k-1}|_M
+ *               for k = 1..k_max (unused entries 0).
+ * Blocks until done; one scalar read-back per iteration.
+ * Returns PE_WARN_NOT_CONVERGED if some sample did not meet the test.
+ */
+pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_mode,
+                   int k_max, double* X, int* iters, double* jump_hist);
+
+/*
+ * pe_fine_propagate - the fine propagator F of Algorithm 1 (its parallel
+ * step) applied to B*N states at once: Y[b][n] = F(Xin[b][n]) over interval
+ * n with the source of sample b.
+ *   Xin, Y      device, B x N x D (may not alias).
+ */
+pe_status pe_fine_propagate(pe_problem p, int B, const double* Xin, double* Y);
+
+/*
+ * pe_coarse_propagate - the coarse propagator G (one step of dt_coarse)
+ * applied to B*N states at once: Y[b][n] = G(Xin[b][n]) over interval n.
+ *   Xin, Y      device, B x N x D (may not alias).
+ */
+pe_status pe_coarse_propagate(pe_problem p, int B, const double* Xin, double* Y);
+
+/*
+ * pe_mass_norms - |x|_M for `count` states (the norm of eq. (2.8)).
+ *   X           device, count x D;  out  host, count doubles.
+ */
+pe_status pe_mass_norms(pe_problem p, int count, const double* X, double* out);
+
+/* pe_problem_info - d1, d2, N, P (host ints, each nullable). */
+pe_status pe_problem_info(pe_problem p, int* d1, int* d2, int* N, int* P);
+
+/* pe_problem_destroy - release all device memory of the handle (NULL ok). */
+pe_status pe_problem_destroy(pe_problem p);
+
+/* message of the calling thread's last failing call ("" if none) */
+const char* pe_last_error(void);
+
+/* library version as an integer (major*10000 + minor*100 + patch) */
+int pe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PE_H */

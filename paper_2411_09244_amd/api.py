@@ -1,0 +1,118 @@
+"""Python binding of libpe: argument marshalling only. Every step of the
+parareal path runs in the library's HIP kernels; torch provides device
+memory and the stream."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev(x, device):
+    t = torch.as_tensor(x, dtype=torch.float64)
+    return t.to(device).contiguous()
+
+
+class Problem:
+    """One multiscale problem: blocks of eq. (3.8) + step sizes + N.
+
+    blocks: dict with M11, M22, A11, A12, A22 and optionally M12, A21 (numpy
+    arrays or tensors, FP64). precision: "fp64" or "mixed"."""
+
+    def __init__(self, blocks, dt, dt_fine, N, precision="fp64", device="cuda", stream=None):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.d1 = int(blocks["M11"].shape[0])
+        self.d2 = int(blocks["M22"].shape[0])
+        self.D = self.d1 + self.d2
+        self.N = int(N)
+        self.dt, self.dt_fine = float(dt), float(dt_fine)
+        self.precision = precision
+        prec = {"fp64": L.PE_FP64, "mixed": L.PE_MIXED}[precision]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        t = {k: _dev(v, self.device) for k, v in blocks.items() if v is not None}
+        h = ctypes.c_void_p()
+        st = L.check(self.lib.pe_problem_create(
+            ctypes.byref(h), self.d1, self.d2, _ptr(t["M11"]), _ptr(t.get("M12")), _ptr(t["M22"]),
+            _ptr(t["A11"]), _ptr(t["A12"]), _ptr(t.get("A21")), _ptr(t["A22"]), self.dt,
+            self.dt_fine, self.N, prec, ctypes.c_void_p(self.stream.cuda_stream)))
+        self.handle = h
+        P = ctypes.c_int()
+        self.lib.pe_problem_info(h, None, None, None, ctypes.byref(P))
+        self.P = P.value
+        self.B = None
+
+    def set_source(self, G, H, time_mode):
+        """G: D x R projected spatial factors, H: B x R x T_len amplitudes."""
+        G = None if G is None else _dev(G, self.device)
+        H = None if H is None else _dev(H, self.device)
+        R = 0 if G is None else int(G.shape[1])
+        B = 1 if H is None else int(H.shape[0])
+        mode = {"fine": L.PE_T_FINE, "interval": L.PE_T_INTERVAL, 0: L.PE_T_FINE,
+                1: L.PE_T_INTERVAL}[time_mode]
+        L.check(self.lib.pe_source_set(self.handle, B, R, _ptr(G), _ptr(H), mode))
+        self.B = B
+        self._src_keep = (G, H)
+
+    def solve(self, x0, tol, norm="abs", k_max=None, out=None):
+        """Parareal to the stopping test. Returns (X (B, N+1, D) tensor,
+        iters (B,) numpy, jump history (B, k_max) numpy, status)."""
+        x0 = _dev(x0, self.device).reshape(-1, self.D)
+        B = x0.shape[0]
+        k_max = self.N if k_max is None else int(k_max)
+        X = out if out is not None else torch.empty((B, self.N + 1, self.D), dtype=torch.float64,
+                                                   device=self.device)
+        iters = np.zeros(B, dtype=np.int32)
+        hist = np.zeros((B, max(k_max, 1)), dtype=np.float64)
+        mode = {"abs": L.PE_NORM_M_ABS, "rel": L.PE_NORM_M_REL}[norm]
+        st = L.check(self.lib.pe_solve(self.handle, B, _ptr(x0), float(tol), mode, k_max, _ptr(X),
+                                       iters.ctypes.data_as(ctypes.c_void_p),
+                                       hist.ctypes.data_as(ctypes.c_void_p)))
+        return X, iters, hist[:, :k_max], st
+
+    def fine(self, Xin):
+        """F applied to Xin (B, N, D) -> (B, N, D)."""
+        Xin = _dev(Xin, self.device)
+        B = Xin.shape[0]
+        Y = torch.empty_like(Xin)
+        L.check(self.lib.pe_fine_propagate(self.handle, B, _ptr(Xin), _ptr(Y)))
+        return Y
+
+    def coarse(self, Xin):
+        """G applied to Xin (B, N, D) -> (B, N, D)."""
+        Xin = _dev(Xin, self.device)
+        B = Xin.shape[0]
+        Y = torch.empty_like(Xin)
+        L.check(self.lib.pe_coarse_propagate(self.handle, B, _ptr(Xin), _ptr(Y)))
+        return Y
+
+    def mass_norms(self, X):
+        X = _dev(X, self.device).reshape(-1, self.D)
+        out = np.zeros(X.shape[0])
+        L.check(self.lib.pe_mass_norms(self.handle, X.shape[0], _ptr(X),
+                                       out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pe_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def problem_from(prob, precision="fp64", device="cuda"):
+    """Problem + source from a workload dict (blocks, G, H, time_mode)."""
+    blocks = {k: prob[k] for k in ("M11", "M12", "M22", "A11", "A12", "A22")}
+    pr = Problem(blocks, prob["dt"], prob["dt_fine"], prob["N"], precision=precision, device=device)
+    pr.set_source(prob["G"], prob["H"], int(prob["time_mode"]))
+    return pr

@@ -1,0 +1,1001 @@
+// C ABI of libpe: problem set-up (FP64 factorisations and step operators on
+// the GPU), the fine and coarse propagators, and the parareal iteration of
+// Algorithm 1 (update (2.7), stopping test (2.8)).
+//
+// Step of the splitting scheme, eqs. (2.5)-(2.6), written with residuals and
+// increments. Per state column keep [du_prev | u | w | dw_prev], where
+// du_prev = u_n - u_{n-1}, dw_prev = w_n - w_{n-1} (zero at an interval
+// start: every propagator call begins with a fresh history). With
+//     r_u = F1 - A11 u - A12 w - (M12/h) dw_prev
+//     r_w = F2 - A21 u - A22 w - (M21/h) du_prev
+// the step is
+//     (M11/h + A11) du = r_u,      M22 dw = h (r_w - A21 du),
+// i.e. [du; dw] = Z_h [r_u; r_w] with
+//     Z_h = [ K_h^-1            0        ]      K_h = M11/h + A11,
+//           [ -Q_h K_h^-1   h M22^-1     ]      Q_h = h M22^-1 A21.
+// So one step is two dense products over all columns at once:
+//     R = F - A x_a - W_h * dev          (W_h = [[0, A11, A12, M12/h],
+//     [du; dw] = Z_h * R                          [M21/h, A21, A22, 0]])
+// where x_a is an anchor state (the interval start) and dev the deviation
+// from it. K_h^-1 and M22^-1 are formed on the GPU from FP64 Cholesky
+// factors. In PE_MIXED the two products run in FP32 on MFMA; the anchor
+// residual A x_a, the state accumulation, the coarse propagator and the jump
+// norms stay FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pe.h"
+#include "pe_kernels.h"
+
+using namespace pe;
+
+namespace {
+
+thread_local std::string g_err;
+
+pe_status fail(pe_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+#define PE_HIP(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(PE_ERR_HIP, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define PE_TRY(expr)                    \
+    do {                                \
+        pe_status s_ = (expr);          \
+        if (s_ < 0) return s_;          \
+    } while (0)
+
+}  // namespace
+
+struct pe_problem_s {
+    int d1 = 0, d2 = 0, D = 0, d1p = 0, d2p = 0, Dp = 0, N = 0, P = 0;
+    double dt = 0, dtf = 0;
+    int prec = PE_FP64;
+    hipStream_t st = nullptr;
+    int n_cu = 256;
+
+    // operators (padded, row-major)
+    double* A64 = nullptr;   // Dp x Dp   full stiffness
+    double* M64 = nullptr;   // Dp x Dp   full mass
+    double* Wf64 = nullptr;  // Dp x 2Dp  fine residual operator
+    double* Zf64 = nullptr;  // Dp x Dp   fine increment operator
+    float* Wf32 = nullptr;
+    float* Zf32 = nullptr;
+    double* Zc64 = nullptr;  // Dp x Dp   coarse increment operator
+    // PE_MIXED: the fine sweep works in mass-whitened coordinates
+    // x~ = Tin x, Tin = blkdiag(L1^T, L2^T) with M11 = L1 L1^T, M22 = L2 L2^T
+    // (there M~11 = M~22 = I); x = Tout x~, Tout = Tin^-1; Linv = Tout^T
+    double* Aw64 = nullptr;    // Dp x Dp whitened stiffness
+    double* Tin64 = nullptr;   // Dp x Dp
+    double* Tout64 = nullptr;  // Dp x Dp
+    double* Linv64 = nullptr;  // Dp x Dp
+
+    // source
+    int src_set = 0, B_src = 0, R = 0, Rp = 0, time_mode = 0, src_kind = 0;
+    long Tlen = 0;
+    double* Gs = nullptr;    // Dp x Rp
+    double* Hs = nullptr;    // B x R x Tlen
+    double* Fint = nullptr;  // (B*N) x Dp
+    double* Gs_w = nullptr;    // whitened copies (PE_MIXED)
+    double* Fint_w = nullptr;
+
+    // iteration workspace (sized for B_cap samples)
+    int B_cap = 0;
+    double* Xk[2] = {nullptr, nullptr};  // B x (N+1) x Dp
+    double *Fbuf = nullptr, *Gold = nullptr, *Xa = nullptr, *Ya = nullptr, *R64 = nullptr;
+    double* dev64 = nullptr;
+    float *dev32 = nullptr, *R32 = nullptr;
+    double *E = nullptr, *Yn = nullptr, *Jd = nullptr, *x0p = nullptr, *io = nullptr;
+    int* active_d = nullptr;
+    GemmWork gw;
+
+    std::vector<void*> op_allocs, ws_allocs;
+};
+
+namespace {
+
+pe_status dalloc(pe_problem p, std::vector<void*>& list, void** out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return fail(PE_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                      hipGetErrorString(e));
+    }
+    list.push_back(*out);
+    return PE_OK;
+}
+
+template <typename T>
+pe_status dalloc_t(pe_problem p, std::vector<void*>& list, T** out, size_t count) {
+    void* v = nullptr;
+    PE_TRY(dalloc(p, list, &v, count * sizeof(T)));
+    *out = (T*)v;
+    return PE_OK;
+}
+
+void free_list(std::vector<void*>& list) {
+    for (void* v : list) (void)hipFree(v);
+    list.clear();
+}
+
+// grow the split-K workspace if a launch needs more (synchronises first)
+pe_status ensure_gemm_work(pe_problem p, size_t part_bytes, size_t n_tiles) {
+    GemmWork& w = p->gw;
+    if (part_bytes <= w.part_bytes && n_tiles <= w.n_counters) return PE_OK;
+    PE_HIP(hipStreamSynchronize(p->st));
+    if (part_bytes > w.part_bytes) {
+        if (w.part) (void)hipFree(w.part);
+        w.part = nullptr;
+        w.part_bytes = 0;
+        size_t nb = std::max(part_bytes, (size_t)1 << 20);
+        hipError_t e = hipMalloc(&w.part, nb);
+        if (e != hipSuccess) return fail(PE_ERR_NOMEM, "split-K workspace allocation failed");
+        w.part_bytes = nb;
+    }
+    if (n_tiles > w.n_counters) {
+        if (w.counters) (void)hipFree(w.counters);
+        w.counters = nullptr;
+        w.n_counters = 0;
+        size_t nc = std::max(n_tiles, (size_t)4096);
+        hipError_t e = hipMalloc((void**)&w.counters, nc * sizeof(unsigned));
+        if (e != hipSuccess) return fail(PE_ERR_NOMEM, "split-K counter allocation failed");
+        PE_HIP(hipMemsetAsync(w.counters, 0, nc * sizeof(unsigned), p->st));
+        w.n_counters = nc;
+    }
+    return PE_OK;
+}
+
+template <typename T>
+pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_splitk = 0) {
+    if (sh.Mr <= 0 || sh.Ns <= 0) return PE_OK;
+    TileCfg cfg = choose_tiles(sh, sizeof(T) == 4, p->n_cu);
+    if (force_splitk > 0) cfg.splitk = force_splitk;
+    PE_TRY(ensure_gemm_work(p, gemm_part_bytes(sh, cfg, sizeof(T)), gemm_n_tiles(sh, cfg)));
+    hipError_t e = gemm_launch<T>(sh, epi, cfg, p->gw, p->st);
+    if (e != hipSuccess)
+        return fail(PE_ERR_HIP, std::string("GEMM launch failed: ") + hipGetErrorString(e));
+    return PE_OK;
+}
+
+GemmShape shape(int Mr, int Ns, const void* A, long lda, const void* B, long ldb, int k0, int k1) {
+    GemmShape s;
+    s.Mr = Mr;
+    s.Ns = Ns;
+    s.A = A;
+    s.lda = lda;
+    s.B = B;
+    s.ldb = ldb;
+    s.s_split = Ns;
+    s.k0a = s.k0b = k0;
+    s.k1a = s.k1b = k1;
+    return s;
+}
+
+Epi store_epi(double* C, long ldc, double alpha = 1.0, const double* C0 = nullptr, long ldc0 = 0,
+              double beta = 0.0) {
+    Epi e;
+    e.mode = EPI_STORE;
+    e.C = C;
+    e.ldc = ldc;
+    e.alpha = alpha;
+    e.C0 = C0;
+    e.ldc0 = ldc0;
+    e.beta = beta;
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Cholesky (blocked, right-looking, 64-wide panels) and the inverse
+// K^-1 = L^-T L^-1, all on the GPU. Aemb (nf x nf, nf multiple of 64) is
+// overwritten by the factor. On a non-positive pivot returns PE_ERR_NOT_SPD.
+// ---------------------------------------------------------------------------
+pe_status factor_inverse(pe_problem p, double* Aemb, int nf, double* Kinv, const char* name, int d,
+                         double* Zt_out = nullptr) {
+    const int nb = 64, nblk = nf / nb;
+    std::vector<void*> tmp;
+    double *Dinv = nullptr, *Zt = nullptr, *T = nullptr;
+    int* info = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(p->st);
+        free_list(tmp);
+    };
+    pe_status s;
+    if ((s = dalloc_t(p, tmp, &Dinv, (size_t)nblk * nb * nb)) < 0 ||
+        (s = dalloc_t(p, tmp, &Zt, (size_t)nf * nf)) < 0 || (s = dalloc_t(p, tmp, &T, (size_t)nf * nb)) < 0 ||
+        (s = dalloc_t(p, tmp, &info, 2)) < 0) {
+        cleanup();
+        return s;
+    }
+    int h_info[2] = {0, -1};
+    PE_HIP(hipMemcpyAsync(info, h_info, sizeof(h_info), hipMemcpyHostToDevice, p->st));
+    for (int j = 0; j < nblk; ++j) {
+        PE_HIP(chol_diag(Aemb, nf, j, Dinv, info, p->st));
+        const int m = nf - (j + 1) * nb;
+        if (m <= 0) break;
+        double* panel = Aemb + (long)(j + 1) * nb * nf + (long)j * nb;
+        // panel <- panel * L_jj^-T (in place: one column tile, no split-K)
+        if ((s = gemm<double>(p, shape(m, nb, panel, nf, Dinv + (long)j * nb * nb, nb, 0, nb),
+                              store_epi(panel, nf), 1)) < 0) {
+            cleanup();
+            return s;
+        }
+        // trailing update  A22 -= L21 L21^T
+        double* trail = Aemb + (long)(j + 1) * nb * nf + (long)(j + 1) * nb;
+        if ((s = gemm<double>(p, shape(m, m, panel, nf, panel, nf, 0, nb),
+                              store_epi(trail, nf, -1.0, trail, nf, 1.0))) < 0) {
+            cleanup();
+            return s;
+        }
+    }
+    PE_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    if (h_info[0] != 0) {
+        cleanup();
+        const int piv = h_info[1];
+        return fail(PE_ERR_NOT_SPD, std::string("Cholesky of ") + name + " failed at pivot " +
+                                        std::to_string(piv) + (piv >= d ? " (padding)" : ""));
+    }
+    // forward substitution for Zt = L^-T (row c of Zt = column c of L^-1)
+    PE_HIP(hipMemsetAsync(Zt, 0, (size_t)nf * nf * sizeof(double), p->st));
+    for (int i = 0; i < nblk; ++i) {
+        Epi e = store_epi(T, nb, -1.0);
+        e.diag_add = 1.0;
+        e.diag_off = i * nb;
+        if ((s = gemm<double>(p, shape(nf, nb, Zt, nf, Aemb + (long)i * nb * nf, nf, 0, i * nb), e)) < 0 ||
+            (s = gemm<double>(p, shape(nf, nb, T, nb, Dinv + (long)i * nb * nb, nb, 0, nb),
+                              store_epi(Zt + (long)i * nb, nf))) < 0) {
+            cleanup();
+            return s;
+        }
+    }
+    s = PE_OK;
+    if (Kinv) s = gemm<double>(p, shape(nf, nf, Zt, nf, Zt, nf, 0, nf), store_epi(Kinv, nf));
+    if (s == PE_OK && Zt_out) {
+        hipError_t e = hipMemcpyAsync(Zt_out, Zt, sizeof(double) * nf * nf, hipMemcpyDeviceToDevice, p->st);
+        if (e != hipSuccess) s = fail(PE_ERR_HIP, "copy of the inverse factor failed");
+    }
+    cleanup();
+    return s;
+}
+
+// step operators for step size h: fills Z (Dp x Dp) and, if W != null, W (Dp x 2Dp)
+pe_status build_step_ops(pe_problem p, double h, const double* M11, const double* M12,
+                         const double* M22inv, const double* A11, const double* A12,
+                         const double* A21, const double* A22, double* Z, double* W) {
+    const int d1 = p->d1, d2 = p->d2, d1p = p->d1p, d2p = p->d2p, Dp = p->Dp;
+    const int nf1 = roundup(d1, 64);
+    std::vector<void*> tmp;
+    double *K = nullptr, *Kinv = nullptr, *Q = nullptr;
+    pe_status s;
+    if ((s = dalloc_t(p, tmp, &K, (size_t)nf1 * nf1)) < 0 || (s = dalloc_t(p, tmp, &Kinv, (size_t)nf1 * nf1)) < 0 ||
+        (s = dalloc_t(p, tmp, &Q, (size_t)std::max(d2p, 1) * std::max(d1p, 1))) < 0) {
+        free_list(tmp);
+        return s;
+    }
+    auto done = [&](pe_status r) {
+        (void)hipStreamSynchronize(p->st);
+        free_list(tmp);
+        return r;
+    };
+    // M11, A11 are d1p x d1p padded copies
+    PE_HIP(shifted_embed(K, nf1, A11, M11, d1p, d1, 1.0 / h, p->st));
+    char name[64];
+    snprintf(name, sizeof(name), "M11/%.3e + A11", h);
+    if ((s = factor_inverse(p, K, nf1, Kinv, name, d1)) < 0) return done(s);
+    PE_HIP(hipMemsetAsync(Z, 0, (size_t)Dp * Dp * sizeof(double), p->st));
+    PE_HIP(place(Z, Dp, 0, 0, Kinv, nf1, d1, d1, 1.0, 0, p->st));
+    if (d2 > 0) {
+        // Q = h M22^-1 A21  (d2 x d1): C[j][i] = h sum_k M22inv[j][k] A12[i][k]
+        PE_HIP(hipMemsetAsync(Q, 0, (size_t)d2p * d1p * sizeof(double), p->st));
+        const int nf2 = roundup(d2, 64);
+        if ((s = gemm<double>(p, shape(d2, d1, M22inv, nf2, A12, d2p, 0, d2p), store_epi(Q, d1p, h))) < 0)
+            return done(s);
+        // Z[w rows][u cols] = -Q K^-1
+        if ((s = gemm<double>(p, shape(d2, d1, Q, d1p, Kinv, nf1, 0, d1p),
+                              store_epi(Z + (long)d1p * Dp, Dp, -1.0))) < 0)
+            return done(s);
+        PE_HIP(place(Z, Dp, d1p, d1p, M22inv, nf2, d2, d2, h, 0, p->st));
+    }
+    if (W) {
+        const long ldw = 2L * Dp;
+        PE_HIP(hipMemsetAsync(W, 0, (size_t)Dp * ldw * sizeof(double), p->st));
+        // u rows: [0 | A11 | A12 | M12/h]
+        PE_HIP(place(W, ldw, 0, d1p, A11, d1p, d1, d1, 1.0, 0, p->st));
+        if (d2 > 0) {
+            PE_HIP(place(W, ldw, 0, 2 * d1p, A12, d2p, d1, d2, 1.0, 0, p->st));
+            PE_HIP(place(W, ldw, 0, 2 * d1p + d2p, M12, d2p, d1, d2, 1.0 / h, 0, p->st));
+            // w rows: [M21/h | A21 | A22 | 0]
+            PE_HIP(place(W, ldw, d1p, 0, M12, d2p, d2, d1, 1.0 / h, 1, p->st));
+            PE_HIP(place(W, ldw, d1p, d1p, A21, d1p, d2, d1, 1.0, 0, p->st));
+            PE_HIP(place(W, ldw, d1p, 2 * d1p, A22, d2p, d2, d2, 1.0, 0, p->st));
+        }
+    }
+    return done(PE_OK);
+}
+
+// Mass-whitened blocks for the mixed fine sweep: with L1 L1^T = M11 and
+// L2 L2^T = M22 the change of variables u = L1^-T u~, w = L2^-T w~ gives
+// M~11 = M~22 = I, M~12 = L1^-1 M12 L2^-T, A~ij = Li^-1 Aij Lj^-T. The
+// scheme is the same in these coordinates; its FP32 products are then well
+// scaled (the conditioning of M11, M22 no longer amplifies rounding).
+pe_status whiten(pe_problem p, std::vector<void*>& tmp, const double* pM11, const double* pM12,
+                 const double* pM22, const double* pA11, const double* pA12, const double* pA21,
+                 const double* pA22, double** wM12, double** wA11, double** wA12, double** wA21,
+                 double** wA22, double** I11, double** I22inv) {
+    const int d1 = p->d1, d2 = p->d2, d1p = p->d1p, d2p = p->d2p, Dp = p->Dp;
+    const int nf1 = roundup(d1, 64), nf2 = roundup(std::max(d2, 1), 64);
+    const int d2q = std::max(d2p, 8);
+    double *E1, *Z1, *E2 = nullptr, *Z2 = nullptr, *Li1, *Li2, *X, *M21;
+    auto& OL = p->op_allocs;
+    PE_TRY(dalloc_t(p, tmp, &E1, (size_t)nf1 * nf1));
+    PE_TRY(dalloc_t(p, tmp, &Z1, (size_t)nf1 * nf1));
+    PE_TRY(dalloc_t(p, tmp, &Li1, (size_t)d1p * d1p));
+    PE_TRY(dalloc_t(p, tmp, &Li2, (size_t)d2q * d2q));
+    PE_TRY(dalloc_t(p, tmp, &X, (size_t)std::max(d1p, d2q) * std::max(d1p, d2q)));
+    PE_TRY(dalloc_t(p, tmp, &M21, (size_t)d2q * d1p));
+    PE_TRY(dalloc_t(p, tmp, wM12, (size_t)d1p * d2q));
+    PE_TRY(dalloc_t(p, tmp, wA11, (size_t)d1p * d1p));
+    PE_TRY(dalloc_t(p, tmp, wA12, (size_t)d1p * d2q));
+    PE_TRY(dalloc_t(p, tmp, wA21, (size_t)d2q * d1p));
+    PE_TRY(dalloc_t(p, tmp, wA22, (size_t)d2q * d2q));
+    PE_TRY(dalloc_t(p, tmp, I11, (size_t)d1p * d1p));
+    PE_TRY(dalloc_t(p, tmp, I22inv, (size_t)nf2 * nf2));
+    for (double* z : {*wM12, *wA12}) PE_HIP(hipMemsetAsync(z, 0, sizeof(double) * d1p * d2q, p->st));
+    PE_HIP(hipMemsetAsync(*wA21, 0, sizeof(double) * d2q * d1p, p->st));
+    PE_HIP(hipMemsetAsync(*wA22, 0, sizeof(double) * d2q * d2q, p->st));
+    PE_HIP(hipMemsetAsync(*wA11, 0, sizeof(double) * d1p * d1p, p->st));
+    PE_HIP(hipMemsetAsync(Li1, 0, sizeof(double) * d1p * d1p, p->st));
+    PE_HIP(hipMemsetAsync(Li2, 0, sizeof(double) * d2q * d2q, p->st));
+    PE_HIP(eye(*I11, d1p, d1, p->st));
+    PE_HIP(eye(*I22inv, nf2, d2, p->st));
+    // factors L (lower part of E) and L^-T (Z)
+    PE_HIP(shifted_embed(E1, nf1, pM11, nullptr, d1p, d1, 0.0, p->st));
+    PE_TRY(factor_inverse(p, E1, nf1, nullptr, "M11", d1, Z1));
+    PE_HIP(tril(E1, nf1, p->st));
+    PE_HIP(place(Li1, d1p, 0, 0, Z1, nf1, d1, d1, 1.0, 1, p->st));
+    if (d2 > 0) {
+        PE_TRY(dalloc_t(p, tmp, &E2, (size_t)nf2 * nf2));
+        PE_TRY(dalloc_t(p, tmp, &Z2, (size_t)nf2 * nf2));
+        PE_HIP(shifted_embed(E2, nf2, pM22, nullptr, d2p, d2, 0.0, p->st));
+        PE_TRY(factor_inverse(p, E2, nf2, nullptr, "M22", d2, Z2));
+        PE_HIP(tril(E2, nf2, p->st));
+        PE_HIP(place(Li2, d2q, 0, 0, Z2, nf2, d2, d2, 1.0, 1, p->st));
+    }
+    // transforms (block diagonal, Dp x Dp)
+    PE_TRY(dalloc_t(p, OL, &p->Tin64, (size_t)Dp * Dp));
+    PE_TRY(dalloc_t(p, OL, &p->Tout64, (size_t)Dp * Dp));
+    PE_TRY(dalloc_t(p, OL, &p->Linv64, (size_t)Dp * Dp));
+    for (double* m : {p->Tin64, p->Tout64, p->Linv64})
+        PE_HIP(hipMemsetAsync(m, 0, sizeof(double) * Dp * Dp, p->st));
+    PE_HIP(place(p->Tin64, Dp, 0, 0, E1, nf1, d1, d1, 1.0, 1, p->st));
+    PE_HIP(place(p->Tout64, Dp, 0, 0, Z1, nf1, d1, d1, 1.0, 0, p->st));
+    PE_HIP(place(p->Linv64, Dp, 0, 0, Z1, nf1, d1, d1, 1.0, 1, p->st));
+    if (d2 > 0) {
+        PE_HIP(place(p->Tin64, Dp, d1p, d1p, E2, nf2, d2, d2, 1.0, 1, p->st));
+        PE_HIP(place(p->Tout64, Dp, d1p, d1p, Z2, nf2, d2, d2, 1.0, 0, p->st));
+        PE_HIP(place(p->Linv64, Dp, d1p, d1p, Z2, nf2, d2, d2, 1.0, 1, p->st));
+    }
+    // A~11 = L1^-1 A11 L1^-T  (two NT products)
+    PE_HIP(hipMemsetAsync(X, 0, sizeof(double) * std::max(d1p, d2q) * std::max(d1p, d2q), p->st));
+    PE_TRY(gemm<double>(p, shape(d1, d1, Li1, d1p, pA11, d1p, 0, d1p), store_epi(X, d1p)));
+    PE_TRY(gemm<double>(p, shape(d1, d1, X, d1p, Li1, d1p, 0, d1p), store_epi(*wA11, d1p)));
+    if (d2 > 0) {
+        // A~12 = L1^-1 A12 L2^-T (A12 as rows of A21), M~12 likewise
+        PE_HIP(hipMemsetAsync(X, 0, sizeof(double) * std::max(d1p, d2q) * std::max(d1p, d2q), p->st));
+        PE_TRY(gemm<double>(p, shape(d1, d2, Li1, d1p, pA21, d1p, 0, d1p), store_epi(X, d2p)));
+        PE_TRY(gemm<double>(p, shape(d1, d2, X, d2p, Li2, d2q, 0, d2p), store_epi(*wA12, d2p)));
+        PE_HIP(hipMemsetAsync(M21, 0, sizeof(double) * d2q * d1p, p->st));
+        PE_HIP(place(M21, d1p, 0, 0, pM12, d2p, d2, d1, 1.0, 1, p->st));
+        PE_HIP(hipMemsetAsync(X, 0, sizeof(double) * std::max(d1p, d2q) * std::max(d1p, d2q), p->st));
+        PE_TRY(gemm<double>(p, shape(d1, d2, Li1, d1p, M21, d1p, 0, d1p), store_epi(X, d2p)));
+        PE_TRY(gemm<double>(p, shape(d1, d2, X, d2p, Li2, d2q, 0, d2p), store_epi(*wM12, d2p)));
+        PE_HIP(place(*wA21, d1p, 0, 0, *wA12, d2p, d2, d1, 1.0, 1, p->st));
+        PE_HIP(hipMemsetAsync(X, 0, sizeof(double) * std::max(d1p, d2q) * std::max(d1p, d2q), p->st));
+        PE_TRY(gemm<double>(p, shape(d2, d2, Li2, d2q, pA22, d2p, 0, d2p), store_epi(X, d2p)));
+        PE_TRY(gemm<double>(p, shape(d2, d2, X, d2p, Li2, d2q, 0, d2p), store_epi(*wA22, d2p)));
+    }
+    // whitened full stiffness for the anchor residual
+    PE_TRY(dalloc_t(p, OL, &p->Aw64, (size_t)Dp * Dp));
+    PE_HIP(hipMemsetAsync(p->Aw64, 0, sizeof(double) * Dp * Dp, p->st));
+    PE_HIP(place(p->Aw64, Dp, 0, 0, *wA11, d1p, d1, d1, 1.0, 0, p->st));
+    if (d2 > 0) {
+        PE_HIP(place(p->Aw64, Dp, 0, d1p, *wA12, d2p, d1, d2, 1.0, 0, p->st));
+        PE_HIP(place(p->Aw64, Dp, d1p, 0, *wA21, d1p, d2, d1, 1.0, 0, p->st));
+        PE_HIP(place(p->Aw64, Dp, d1p, d1p, *wA22, d2p, d2, d2, 1.0, 0, p->st));
+    }
+    return PE_OK;
+}
+
+pe_status ensure_workspace(pe_problem p, int B) {
+    if (B <= p->B_cap) return PE_OK;
+    PE_HIP(hipStreamSynchronize(p->st));
+    free_list(p->ws_allocs);
+    const size_t N = p->N, Dp = p->Dp, Bs = B;
+    auto& L = p->ws_allocs;
+    PE_TRY(dalloc_t(p, L, &p->Xk[0], Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Xk[1], Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Fbuf, Bs * N * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Gold, Bs * N * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Xa, Bs * N * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Ya, Bs * N * Dp));
+    PE_TRY(dalloc_t(p, L, &p->R64, Bs * N * Dp));
+    PE_TRY(dalloc_t(p, L, &p->dev64, Bs * N * 2 * Dp));
+    if (p->prec == PE_MIXED) {
+        PE_TRY(dalloc_t(p, L, &p->dev32, Bs * N * 2 * Dp));
+        PE_TRY(dalloc_t(p, L, &p->R32, Bs * N * Dp));
+    }
+    PE_TRY(dalloc_t(p, L, &p->E, Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Yn, Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->io, Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Jd, Bs * (N + 1)));
+    PE_TRY(dalloc_t(p, L, &p->x0p, Bs * Dp));
+    PE_TRY(dalloc_t(p, L, &p->active_d, Bs));
+    p->B_cap = B;
+    return PE_OK;
+}
+
+void source_fields(pe_problem p, Epi& e, bool whitened = false) {
+    e.src_kind = p->src_set ? p->src_kind : 0;
+    e.Gs = whitened ? p->Gs_w : p->Gs;
+    e.Hs = p->Hs;
+    e.R = p->Rp;
+    e.Tlen = p->Tlen;
+    e.time_mode = p->time_mode;
+    e.P = p->P;
+    e.N = p->N;
+    e.Fint = whitened ? p->Fint_w : p->Fint;
+    e.ldf = p->Dp;
+}
+
+// ---------------------------------------------------------------------------
+// propagators
+// ---------------------------------------------------------------------------
+// F on B*N columns: anchors Xsrc[b][n - n_shift] (row stride ldXb per sample,
+// zero for n < n_shift) -> Y (B*N x Dp). Without the source this is the
+// homogeneous propagator; with accumulate the result is added to Y.
+pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double* Y, bool with_source = true,
+                     int n_shift = 0, bool accumulate = false) {
+    const int Dp = p->Dp, d1p = p->d1p, d2p = p->d2p;
+    const int rows = B * p->N;
+    const bool mixed = p->prec == PE_MIXED;
+    if (!mixed) {
+        PE_HIP(fine_init(Xsrc, ldXb, n_shift, p->Xa, p->dev64, nullptr, B, p->N, Dp, p->st));
+        PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->A64, Dp, 0, Dp), store_epi(p->Ya, Dp)));
+    } else {
+        // anchors into whitened coordinates: Xa = Tin x (block diagonal)
+        PE_HIP(fine_init(Xsrc, ldXb, n_shift, p->R64, p->dev64, p->dev32, B, p->N, Dp, p->st));
+        GemmShape gt = shape(rows, Dp, p->R64, Dp, p->Tin64, Dp, 0, d1p);
+        gt.s_split = d1p;
+        gt.k0b = d1p;
+        gt.k1b = Dp;
+        PE_TRY(gemm<double>(p, gt, store_epi(p->Xa, Dp)));
+        PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->Aw64, Dp, 0, Dp), store_epi(p->Ya, Dp)));
+    }
+    const long ldS = 2L * Dp;
+    for (int step = 0; step < p->P; ++step) {
+        GemmShape g1 = shape(rows, Dp, mixed ? (const void*)p->dev32 : (const void*)p->dev64, ldS,
+                             mixed ? (const void*)p->Wf32 : (const void*)p->Wf64, ldS, 0, 0);
+        g1.s_split = d1p;
+        if (step > 0) {  // the deviation is zero at the first step
+            g1.k0a = d1p;
+            g1.k1a = 2 * Dp;
+            g1.k0b = 0;
+            g1.k1b = 2 * d1p + d2p;
+        }
+        Epi e1;
+        e1.mode = EPI_RESID;
+        e1.R64 = p->R64;
+        e1.R32 = mixed ? p->R32 : nullptr;
+        e1.ldr = Dp;
+        e1.base = p->Ya;
+        e1.ldb = Dp;
+        source_fields(p, e1, mixed);
+        if (!with_source) e1.src_kind = 0;
+        e1.cols_per_b = p->N;
+        e1.n_fixed = -1;
+        e1.p_step = step;
+        if (mixed)
+            PE_TRY(gemm<float>(p, g1, e1));
+        else
+            PE_TRY(gemm<double>(p, g1, e1));
+
+        GemmShape g2 = shape(rows, Dp, mixed ? (const void*)p->R32 : (const void*)p->R64, Dp,
+                             mixed ? (const void*)p->Zf32 : (const void*)p->Zf64, Dp, 0, d1p);
+        g2.s_split = d1p;
+        g2.k0b = 0;
+        g2.k1b = Dp;
+        Epi e2;
+        e2.mode = EPI_STEP;
+        e2.dev64 = p->dev64;
+        e2.dev32 = mixed ? p->dev32 : nullptr;
+        e2.ldd = ldS;
+        e2.d1p = d1p;
+        e2.d2p = d2p;
+        if (mixed)
+            PE_TRY(gemm<float>(p, g2, e2));
+        else
+            PE_TRY(gemm<double>(p, g2, e2));
+    }
+    if (!mixed) {
+        PE_HIP(fine_final(p->Xa, p->dev64, Y, rows, Dp, d1p, accumulate ? 1 : 0, p->st));
+    } else {
+        // back to the caller's coordinates: Y (+)= Tout (Xa + dev)
+        PE_HIP(fine_final(p->Xa, p->dev64, p->R64, rows, Dp, d1p, 0, p->st));
+        GemmShape gt = shape(rows, Dp, p->R64, Dp, p->Tout64, Dp, 0, d1p);
+        gt.s_split = d1p;
+        gt.k0b = d1p;
+        gt.k1b = Dp;
+        PE_TRY(gemm<double>(p, gt, store_epi(Y, Dp, 1.0, accumulate ? Y : nullptr, Dp, accumulate ? 1.0 : 0.0)));
+    }
+    return PE_OK;
+}
+
+// one coarse step of interval n for the B samples of Xk, with the parareal
+// correction (or the plain coarse value when initial)
+pe_status coarse_step(pe_problem p, int B, double* Xk, int n, int initial, const int* active) {
+    const int Dp = p->Dp, N = p->N;
+    const long ldX = (long)(N + 1) * Dp;
+    Epi e1;
+    e1.mode = EPI_RESID;
+    e1.R64 = p->R64;
+    e1.ldr = Dp;
+    source_fields(p, e1);
+    e1.n_fixed = n;
+    e1.p_step = p->P - 1;
+    PE_TRY(gemm<double>(p, shape(B, Dp, Xk + (long)n * Dp, ldX, p->A64, Dp, 0, Dp), e1));
+    GemmShape g2 = shape(B, Dp, p->R64, Dp, p->Zc64, Dp, 0, p->d1p);
+    g2.s_split = p->d1p;
+    g2.k0b = 0;
+    g2.k1b = Dp;
+    Epi e2;
+    e2.mode = EPI_COARSE;
+    e2.xin = Xk + (long)n * Dp;
+    e2.ldx = ldX;
+    e2.xout = Xk + (long)(n + 1) * Dp;
+    e2.ldxo = ldX;
+    e2.fbuf = p->Fbuf + (long)n * Dp;
+    e2.ldfb = (long)N * Dp;
+    e2.gold = p->Gold + (long)n * Dp;
+    e2.ldg = (long)N * Dp;
+    e2.initial = initial;
+    e2.active = active;
+    PE_TRY(gemm<double>(p, g2, e2));
+    return PE_OK;
+}
+
+// J_b = max_{j < nr} |Xk[b][n0+j] - Xp[b][n0+j]|_M  (Xp null: plain norms)
+pe_status jumps(pe_problem p, int B, const double* Xk, const double* Xp, long ldXb, int n0, int nr,
+                double* Jhost, double* norms_dev) {
+    const int Dp = p->Dp;
+    PE_HIP(jump_diff(Xk, Xp, ldXb, n0, nr, B, Dp, p->E, p->st));
+    PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp)));
+    PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, norms_dev, p->st));
+    if (Jhost) {
+        PE_HIP(hipMemcpyAsync(Jhost, p->Jd, sizeof(double) * B, hipMemcpyDeviceToHost, p->st));
+        PE_HIP(hipStreamSynchronize(p->st));
+    }
+    return PE_OK;
+}
+
+pe_status check_handle(pe_problem p) {
+    if (!p) return fail(PE_ERR_ARG, "null problem handle");
+    return PE_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* pe_last_error(void) { return g_err.c_str(); }
+
+int pe_version(void) { return 100; }
+
+pe_status pe_problem_destroy(pe_problem p) {
+    if (!p) return PE_OK;
+    (void)hipStreamSynchronize(p->st);
+    free_list(p->ws_allocs);
+    free_list(p->op_allocs);
+    if (p->gw.part) (void)hipFree(p->gw.part);
+    if (p->gw.counters) (void)hipFree(p->gw.counters);
+    delete p;
+    return PE_OK;
+}
+
+pe_status pe_problem_info(pe_problem p, int* d1, int* d2, int* N, int* P) {
+    PE_TRY(check_handle(p));
+    if (d1) *d1 = p->d1;
+    if (d2) *d2 = p->d2;
+    if (N) *N = p->N;
+    if (P) *P = p->P;
+    return PE_OK;
+}
+
+pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, const double* M12,
+                            const double* M22, const double* A11, const double* A12, const double* A21,
+                            const double* A22, double dt_coarse, double dt_fine, int N, int precision,
+                            void* hip_stream) {
+    g_err.clear();
+    if (!out) return fail(PE_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (d1 < 1 || d2 < 0 || N < 1) return fail(PE_ERR_ARG, "need d1 >= 1, d2 >= 0, N >= 1");
+    if (!M11 || !A11 || (d2 > 0 && (!M22 || !A12 || !A22)))
+        return fail(PE_ERR_ARG, "required block pointer is null");
+    if (!(dt_coarse > 0) || !(dt_fine > 0) || !std::isfinite(dt_coarse) || !std::isfinite(dt_fine))
+        return fail(PE_ERR_ARG, "step sizes must be positive and finite");
+    const double ratio = dt_coarse / dt_fine;
+    const double Pr = std::round(ratio);
+    if (Pr < 1 || std::fabs(ratio - Pr) > 1e-9 * Pr || Pr > 1e7)
+        return fail(PE_ERR_ARG, "dt_coarse / dt_fine must be a positive integer");
+    if (precision != PE_FP64 && precision != PE_MIXED) return fail(PE_ERR_ARG, "unknown precision");
+
+    pe_problem p = new pe_problem_s();
+    p->d1 = d1;
+    p->d2 = d2;
+    p->D = d1 + d2;
+    p->d1p = roundup(d1, 8);
+    p->d2p = roundup(d2, 8);
+    p->Dp = p->d1p + p->d2p;
+    p->N = N;
+    p->P = (int)Pr;
+    p->dt = dt_coarse;
+    p->dtf = dt_fine;
+    p->prec = precision;
+    p->st = (hipStream_t)hip_stream;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        p->n_cu = ncu;
+
+    auto bail = [&](pe_status s) {
+        std::string msg = g_err;
+        pe_problem_destroy(p);
+        g_err = msg;
+        return s;
+    };
+    const int d1p = p->d1p, d2p = p->d2p, Dp = p->Dp;
+    auto& OL = p->op_allocs;
+    std::vector<void*> tmp;
+    auto bail_tmp = [&](pe_status s) {
+        (void)hipStreamSynchronize(p->st);
+        free_list(tmp);
+        return bail(s);
+    };
+#define CK(expr)                              \
+    do {                                      \
+        pe_status s__ = (expr);               \
+        if (s__ < 0) return bail_tmp(s__);    \
+    } while (0)
+#define CKH(expr)                                                                              \
+    do {                                                                                       \
+        hipError_t e__ = (expr);                                                               \
+        if (e__ != hipSuccess)                                                                 \
+            return bail_tmp(fail(PE_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e__))); \
+    } while (0)
+
+    // symmetry checks (relative 1e-12 of the largest entry)
+    {
+        unsigned long long* red = nullptr;
+        CK(dalloc_t(p, tmp, &red, 2 * 5));
+        CKH(hipMemsetAsync(red, 0, sizeof(unsigned long long) * 10, p->st));
+        CKH(asym(M11, M11, d1, d1, d1, d1, red + 0, p->st));
+        CKH(asym(A11, A11, d1, d1, d1, d1, red + 2, p->st));
+        if (d2 > 0) {
+            CKH(asym(M22, M22, d2, d2, d2, d2, red + 4, p->st));
+            CKH(asym(A22, A22, d2, d2, d2, d2, red + 6, p->st));
+            if (A21) CKH(asym(A21, A12, d1, d2, d2, d1, red + 8, p->st));
+        }
+        unsigned long long h[10];
+        CKH(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, p->st));
+        CKH(hipStreamSynchronize(p->st));
+        const char* names[5] = {"M11", "A11", "M22", "A22", "A21 vs A12^T"};
+        for (int i = 0; i < 5; ++i) {
+            double dmax, amax;
+            memcpy(&dmax, &h[2 * i], 8);
+            memcpy(&amax, &h[2 * i + 1], 8);
+            if (!(dmax <= 1e-12 * amax) && dmax != 0.0)
+                return bail_tmp(fail(PE_ERR_ARG, std::string(names[i]) + " is not symmetric (max diff " +
+                                                     std::to_string(dmax) + ")"));
+        }
+    }
+
+    // padded FP64 copies of the blocks
+    double *pM11, *pM12, *pM22, *pA11, *pA12, *pA21, *pA22, *M22inv;
+    const int nf2 = roundup(std::max(d2, 1), 64);
+    CK(dalloc_t(p, tmp, &pM11, (size_t)d1p * d1p));
+    CK(dalloc_t(p, tmp, &pA11, (size_t)d1p * d1p));
+    CK(dalloc_t(p, tmp, &pM12, (size_t)d1p * std::max(d2p, 8)));
+    CK(dalloc_t(p, tmp, &pA12, (size_t)d1p * std::max(d2p, 8)));
+    CK(dalloc_t(p, tmp, &pA21, (size_t)std::max(d2p, 8) * d1p));
+    CK(dalloc_t(p, tmp, &pM22, (size_t)std::max(d2p, 8) * std::max(d2p, 8)));
+    CK(dalloc_t(p, tmp, &pA22, (size_t)std::max(d2p, 8) * std::max(d2p, 8)));
+    CK(dalloc_t(p, tmp, &M22inv, (size_t)nf2 * nf2));
+    CKH(hipMemsetAsync(pM11, 0, sizeof(double) * d1p * d1p, p->st));
+    CKH(hipMemsetAsync(pA11, 0, sizeof(double) * d1p * d1p, p->st));
+    CKH(place(pM11, d1p, 0, 0, M11, d1, d1, d1, 1.0, 0, p->st));
+    CKH(place(pA11, d1p, 0, 0, A11, d1, d1, d1, 1.0, 0, p->st));
+    if (d2 > 0) {
+        CKH(hipMemsetAsync(pM12, 0, sizeof(double) * d1p * d2p, p->st));
+        CKH(hipMemsetAsync(pA12, 0, sizeof(double) * d1p * d2p, p->st));
+        CKH(hipMemsetAsync(pA21, 0, sizeof(double) * d2p * d1p, p->st));
+        CKH(hipMemsetAsync(pM22, 0, sizeof(double) * d2p * d2p, p->st));
+        CKH(hipMemsetAsync(pA22, 0, sizeof(double) * d2p * d2p, p->st));
+        if (M12) CKH(place(pM12, d2p, 0, 0, M12, d2, d1, d2, 1.0, 0, p->st));
+        CKH(place(pA12, d2p, 0, 0, A12, d2, d1, d2, 1.0, 0, p->st));
+        if (A21)
+            CKH(place(pA21, d1p, 0, 0, A21, d1, d2, d1, 1.0, 0, p->st));
+        else
+            CKH(place(pA21, d1p, 0, 0, A12, d2, d2, d1, 1.0, 1, p->st));
+        CKH(place(pM22, d2p, 0, 0, M22, d2, d2, d2, 1.0, 0, p->st));
+        CKH(place(pA22, d2p, 0, 0, A22, d2, d2, d2, 1.0, 0, p->st));
+        // M22^-1
+        double* Mem = nullptr;
+        CK(dalloc_t(p, tmp, &Mem, (size_t)nf2 * nf2));
+        CKH(shifted_embed(Mem, nf2, pM22, nullptr, d2p, d2, 0.0, p->st));
+        CK(factor_inverse(p, Mem, nf2, M22inv, "M22", d2));
+    }
+
+    // full stiffness and mass (FP64)
+    CK(dalloc_t(p, OL, &p->A64, (size_t)Dp * Dp));
+    CK(dalloc_t(p, OL, &p->M64, (size_t)Dp * Dp));
+    CKH(hipMemsetAsync(p->A64, 0, sizeof(double) * Dp * Dp, p->st));
+    CKH(hipMemsetAsync(p->M64, 0, sizeof(double) * Dp * Dp, p->st));
+    CKH(place(p->A64, Dp, 0, 0, pA11, d1p, d1, d1, 1.0, 0, p->st));
+    CKH(place(p->M64, Dp, 0, 0, pM11, d1p, d1, d1, 1.0, 0, p->st));
+    if (d2 > 0) {
+        CKH(place(p->A64, Dp, 0, d1p, pA12, d2p, d1, d2, 1.0, 0, p->st));
+        CKH(place(p->A64, Dp, d1p, 0, pA21, d1p, d2, d1, 1.0, 0, p->st));
+        CKH(place(p->A64, Dp, d1p, d1p, pA22, d2p, d2, d2, 1.0, 0, p->st));
+        CKH(place(p->M64, Dp, 0, d1p, pM12, d2p, d1, d2, 1.0, 0, p->st));
+        CKH(place(p->M64, Dp, d1p, 0, pM12, d2p, d2, d1, 1.0, 1, p->st));
+        CKH(place(p->M64, Dp, d1p, d1p, pM22, d2p, d2, d2, 1.0, 0, p->st));
+    }
+
+    // coarse operator (FP64) and fine operators
+    CK(dalloc_t(p, OL, &p->Zc64, (size_t)Dp * Dp));
+    CK(build_step_ops(p, dt_coarse, pM11, pM12, M22inv, pA11, pA12, pA21, pA22, p->Zc64, nullptr));
+    if (precision == PE_FP64) {
+        CK(dalloc_t(p, OL, &p->Zf64, (size_t)Dp * Dp));
+        CK(dalloc_t(p, OL, &p->Wf64, (size_t)Dp * 2 * Dp));
+        CK(build_step_ops(p, dt_fine, pM11, pM12, M22inv, pA11, pA12, pA21, pA22, p->Zf64, p->Wf64));
+    } else {
+        double *wM12, *wA11, *wA12, *wA21, *wA22, *I11, *I22inv, *Z64, *W64;
+        CK(whiten(p, tmp, pM11, pM12, pM22, pA11, pA12, pA21, pA22, &wM12, &wA11, &wA12, &wA21, &wA22,
+                  &I11, &I22inv));
+        CK(dalloc_t(p, tmp, &Z64, (size_t)Dp * Dp));
+        CK(dalloc_t(p, tmp, &W64, (size_t)Dp * 2 * Dp));
+        CK(build_step_ops(p, dt_fine, I11, wM12, I22inv, wA11, wA12, wA21, wA22, Z64, W64));
+        CK(dalloc_t(p, OL, &p->Zf32, (size_t)Dp * Dp));
+        CK(dalloc_t(p, OL, &p->Wf32, (size_t)Dp * 2 * Dp));
+        CKH(to_f32(Z64, p->Zf32, (long)Dp * Dp, p->st));
+        CKH(to_f32(W64, p->Wf32, (long)Dp * 2 * Dp, p->st));
+    }
+    CKH(hipStreamSynchronize(p->st));
+    free_list(tmp);
+#undef CK
+#undef CKH
+    *out = p;
+    return PE_OK;
+}
+
+pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const double* H, int time_mode) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1 || R < 0) return fail(PE_ERR_ARG, "need B >= 1 and R >= 0");
+    if (time_mode != PE_T_FINE && time_mode != PE_T_INTERVAL) return fail(PE_ERR_ARG, "unknown time_mode");
+    if (R > 0 && (!G || !H)) return fail(PE_ERR_ARG, "G and H must be given when R > 0");
+    if (time_mode == PE_T_FINE && R > 64) return fail(PE_ERR_ARG, "PE_T_FINE supports R <= 64");
+    PE_HIP(hipStreamSynchronize(p->st));
+    for (void* v : {(void*)p->Gs, (void*)p->Hs, (void*)p->Fint, (void*)p->Gs_w, (void*)p->Fint_w}) {
+        if (!v) continue;
+        auto it = std::find(p->op_allocs.begin(), p->op_allocs.end(), v);
+        if (it != p->op_allocs.end()) p->op_allocs.erase(it);
+        (void)hipFree(v);
+    }
+    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = nullptr;
+    p->src_set = 1;
+    p->B_src = B;
+    p->R = R;
+    p->time_mode = time_mode;
+    p->Tlen = (time_mode == PE_T_FINE) ? (long)p->N * p->P : (long)p->N;
+    if (R == 0) {
+        p->src_kind = 0;
+        return PE_OK;
+    }
+    const int D = p->D, d1 = p->d1, d1p = p->d1p, Dp = p->Dp;
+    const bool dense = (time_mode == PE_T_INTERVAL && R > 16);
+    p->Rp = dense ? roundup(R, 2) : R;
+    PE_TRY(dalloc_t(p, p->op_allocs, &p->Gs, (size_t)Dp * p->Rp));
+    PE_HIP(hipMemsetAsync(p->Gs, 0, sizeof(double) * Dp * p->Rp, p->st));
+    PE_HIP(place(p->Gs, p->Rp, 0, 0, G, R, d1, R, 1.0, 0, p->st));
+    PE_HIP(place(p->Gs, p->Rp, d1p, 0, G + (long)d1 * R, R, D - d1, R, 1.0, 0, p->st));
+    PE_TRY(dalloc_t(p, p->op_allocs, &p->Hs, (size_t)B * R * p->Tlen));
+    PE_HIP(hipMemcpyAsync(p->Hs, H, sizeof(double) * B * R * p->Tlen, hipMemcpyDeviceToDevice, p->st));
+    if (dense) {
+        // Fint[(b, n)][s] = sum_r G[s][r] H[b][r][n]
+        double* Ht = nullptr;
+        std::vector<void*> tmp;
+        PE_TRY(dalloc_t(p, tmp, &Ht, (size_t)B * p->N * p->Rp));
+        PE_HIP(hipMemsetAsync(Ht, 0, sizeof(double) * B * p->N * p->Rp, p->st));
+        for (int b = 0; b < B; ++b)
+            PE_HIP(place(Ht + (long)b * p->N * p->Rp, p->Rp, 0, 0, p->Hs + (long)b * R * p->N, p->N, p->N, R,
+                         1.0, 1, p->st));
+        PE_TRY(dalloc_t(p, p->op_allocs, &p->Fint, (size_t)B * p->N * Dp));
+        pe_status s = gemm<double>(p, shape(B * p->N, Dp, Ht, p->Rp, p->Gs, p->Rp, 0, p->Rp),
+                                   store_epi(p->Fint, Dp));
+        (void)hipStreamSynchronize(p->st);
+        free_list(tmp);
+        if (s < 0) return s;
+        p->src_kind = 2;
+    } else {
+        p->src_kind = 1;
+    }
+    if (p->prec == PE_MIXED) {
+        // whitened source for the mixed fine sweep: F~ = Tout^T F = Linv F
+        if (p->src_kind == 2) {
+            PE_TRY(dalloc_t(p, p->op_allocs, &p->Fint_w, (size_t)B * p->N * Dp));
+            PE_TRY(gemm<double>(p, shape(B * p->N, Dp, p->Fint, Dp, p->Linv64, Dp, 0, Dp),
+                                store_epi(p->Fint_w, Dp)));
+        } else {
+            double *GT = nullptr, *GwT = nullptr;
+            std::vector<void*> tmp;
+            PE_TRY(dalloc_t(p, tmp, &GT, (size_t)p->Rp * Dp));
+            PE_TRY(dalloc_t(p, tmp, &GwT, (size_t)p->Rp * Dp));
+            PE_HIP(place(GT, Dp, 0, 0, p->Gs, p->Rp, p->Rp, Dp, 1.0, 1, p->st));
+            pe_status s = gemm<double>(p, shape(p->Rp, Dp, GT, Dp, p->Linv64, Dp, 0, Dp), store_epi(GwT, Dp));
+            if (s == PE_OK) s = dalloc_t(p, p->op_allocs, &p->Gs_w, (size_t)Dp * p->Rp);
+            if (s == PE_OK && place(p->Gs_w, p->Rp, 0, 0, GwT, Dp, Dp, p->Rp, 1.0, 1, p->st) != hipSuccess)
+                s = fail(PE_ERR_HIP, "source transpose failed");
+            (void)hipStreamSynchronize(p->st);
+            free_list(tmp);
+            if (s < 0) return s;
+        }
+    }
+    PE_HIP(hipStreamSynchronize(p->st));
+    return PE_OK;
+}
+
+pe_status pe_fine_propagate(pe_problem p, int B, const double* Xin, double* Y) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1 || !Xin || !Y) return fail(PE_ERR_ARG, "bad arguments");
+    if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    PE_TRY(ensure_workspace(p, B));
+    const long rows = (long)B * p->N;
+    PE_HIP(pack_states(Xin, p->io, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_TRY(fine_sweep(p, B, p->io, (long)p->N * p->Dp, p->Fbuf));
+    PE_HIP(unpack_states(p->Fbuf, Y, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    return PE_OK;
+}
+
+pe_status pe_coarse_propagate(pe_problem p, int B, const double* Xin, double* Y) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1 || !Xin || !Y) return fail(PE_ERR_ARG, "bad arguments");
+    if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    PE_TRY(ensure_workspace(p, B));
+    const int Dp = p->Dp;
+    const long rows = (long)B * p->N;
+    PE_HIP(pack_states(Xin, p->Xa, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    Epi e1;
+    e1.mode = EPI_RESID;
+    e1.R64 = p->R64;
+    e1.ldr = Dp;
+    source_fields(p, e1);
+    e1.cols_per_b = p->N;
+    e1.p_step = p->P - 1;
+    PE_TRY(gemm<double>(p, shape((int)rows, Dp, p->Xa, Dp, p->A64, Dp, 0, Dp), e1));
+    GemmShape g2 = shape((int)rows, Dp, p->R64, Dp, p->Zc64, Dp, 0, p->d1p);
+    g2.s_split = p->d1p;
+    g2.k0b = 0;
+    g2.k1b = Dp;
+    PE_TRY(gemm<double>(p, g2, store_epi(p->Ya, Dp, 1.0, p->Xa, Dp, 1.0)));
+    PE_HIP(unpack_states(p->Ya, Y, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    return PE_OK;
+}
+
+pe_status pe_mass_norms(pe_problem p, int count, const double* X, double* out) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (count < 1 || !X || !out) return fail(PE_ERR_ARG, "bad arguments");
+    const int Dp = p->Dp;
+    // workspace rows are B_cap*(N+1); grow if needed
+    const int need_B = (count + p->N) / (p->N + 1);
+    PE_TRY(ensure_workspace(p, std::max(need_B, 1)));
+    PE_HIP(pack_states(X, p->io, count, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_HIP(jump_diff(p->io, nullptr, (long)Dp, 0, 1, count, Dp, p->E, p->st));
+    PE_TRY(gemm<double>(p, shape(count, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp)));
+    PE_HIP(jump_reduce(p->E, p->Yn, count, 1, Dp, p->Jd, nullptr, p->st));
+    PE_HIP(hipMemcpyAsync(out, p->Jd, sizeof(double) * count, hipMemcpyDeviceToHost, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    return PE_OK;
+}
+
+pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_mode, int k_max, double* X,
+                   int* iters, double* jump_hist) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1 || !x0 || !X) return fail(PE_ERR_ARG, "bad arguments");
+    if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    if (!(tol >= 0) || k_max < 0 || k_max > p->N) return fail(PE_ERR_ARG, "need tol >= 0 and 0 <= k_max <= N");
+    if (norm_mode != PE_NORM_M_ABS && norm_mode != PE_NORM_M_REL) return fail(PE_ERR_ARG, "unknown norm_mode");
+    PE_TRY(ensure_workspace(p, B));
+    const int N = p->N, Dp = p->Dp;
+    const long ldX = (long)(N + 1) * Dp;
+
+    std::vector<int> active(B, 1);
+    std::vector<double> thr(B, tol), J(B, 0.0);
+    if (iters)
+        for (int b = 0; b < B; ++b) iters[b] = 0;
+    if (jump_hist)
+        for (long i = 0; i < (long)B * k_max; ++i) jump_hist[i] = 0.0;
+    PE_HIP(hipMemcpyAsync(p->active_d, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, p->st));
+
+    int cur = 0;
+    PE_HIP(pack_states(x0, p->x0p, B, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_HIP(set_x0(p->x0p, p->Xk[cur], ldX, B, Dp, p->st));
+    for (int n = 0; n < N; ++n) PE_TRY(coarse_step(p, B, p->Xk[cur], n, 1, nullptr));
+    if (norm_mode == PE_NORM_M_REL) {
+        PE_TRY(jumps(p, B, p->Xk[cur], nullptr, ldX, 0, N + 1, thr.data(), nullptr));
+        for (int b = 0; b < B; ++b) thr[b] *= tol;
+    }
+    int n_active = B;
+    for (int k = 1; k <= k_max && n_active > 0; ++k) {
+        const int nxt = 1 - cur;
+        if (p->prec == PE_MIXED && k >= 2) {
+            // F is affine: F(x^{k-1}) = F(x^{k-2}) + F_hom(x^{k-1} - x^{k-2}). The
+            // change (left in E by the previous jump test, rows n = 1..N) is
+            // propagated without source and added to the stored F values, so
+            // FP32 rounding scales with the change, not with the state.
+            PE_TRY(fine_sweep(p, B, p->E, (long)N * Dp, p->Fbuf, false, 1, true));
+        } else {
+            PE_TRY(fine_sweep(p, B, p->Xk[cur], ldX, p->Fbuf));
+        }
+        if (n_active < B) PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, ldX, B, p->st));
+        PE_HIP(set_x0(p->x0p, p->Xk[nxt], ldX, B, Dp, p->st));
+        for (int n = 0; n < N; ++n) PE_TRY(coarse_step(p, B, p->Xk[nxt], n, 0, p->active_d));
+        PE_TRY(jumps(p, B, p->Xk[nxt], p->Xk[cur], ldX, 1, N, J.data(), nullptr));
+        cur = nxt;
+        for (int b = 0; b < B; ++b) {
+            if (!active[b]) continue;
+            if (!std::isfinite(J[b])) {
+                PE_HIP(unpack_states(p->Xk[cur], X, (long)B * (N + 1), p->d1, p->d2, p->d1p, p->d2p, p->st));
+                PE_HIP(hipStreamSynchronize(p->st));
+                return fail(PE_ERR_NONFINITE, "non-finite parareal jump for sample " + std::to_string(b) +
+                                                  " at iteration " + std::to_string(k));
+            }
+            if (jump_hist) jump_hist[(long)b * k_max + (k - 1)] = J[b];
+            if (iters) iters[b] = k;
+            if (J[b] <= thr[b]) {
+                active[b] = 0;
+                --n_active;
+            }
+        }
+        if (n_active > 0 && n_active < B)
+            PE_HIP(hipMemcpyAsync(p->active_d, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, p->st));
+    }
+    PE_HIP(unpack_states(p->Xk[cur], X, (long)B * (N + 1), p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    return n_active > 0 ? PE_WARN_NOT_CONVERGED : PE_OK;
+}
+
+}  // extern "C"

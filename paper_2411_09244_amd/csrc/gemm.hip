@@ -1,0 +1,378 @@
+// MFMA GEMM for gfx950 with the fused epilogues of the splitting-scheme step.
+//
+// C[r][s] = epi( sum_k A[r][k] * B[s][k] ), A and B both K-contiguous.
+// Work-group: 256 threads = 4 wave64, arranged 2 x 2 over a BR x BS tile;
+// each wave owns a (BR/2) x (BS/2) sub-tile made of 16x16 MFMA blocks
+// (v_mfma_f32_16x16x4f32 for FP32, v_mfma_f64_16x16x4f64 for FP64).
+// Operand tiles are staged through LDS (BK deep, padded rows, register
+// prefetch of the next K tile). With split-K, every work-group writes its
+// partial tile to a workspace and the last one to arrive (atomic tile
+// counter) sums the partials in split order - a fixed order, so results are
+// bitwise reproducible - and runs the epilogue; it then resets the counter.
+#include "pe_internal.h"
+
+namespace pe {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaOp;
+
+template <>
+struct MfmaOp<float> {
+    typedef f32x4 acc_t;
+    typedef float4 vec_t;  // 16-byte global/LDS vector
+    static constexpr int BK = 32;
+    __device__ static inline acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // row of accumulator element q held by `lane` (column is lane % 16)
+    __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+
+template <>
+struct MfmaOp<double> {
+    typedef f64x4 acc_t;
+    typedef double2 vec_t;
+    static constexpr int BK = 16;
+    __device__ static inline acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // the FP64 block interleaves rows: element q of `lane` is row lane/16 + 4q
+    __device__ static inline int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+};
+
+// ---------------------------------------------------------------------------
+// epilogue
+// ---------------------------------------------------------------------------
+__device__ inline double source_value(const Epi& e, int r, int s) {
+    if (e.src_kind == 0) return 0.0;
+    int b, n;
+    if (e.n_fixed >= 0) {
+        b = r;
+        n = e.n_fixed;
+    } else {
+        b = r / e.cols_per_b;
+        n = r - b * e.cols_per_b;
+    }
+    if (e.src_kind == 2) return e.Fint[((long)b * e.N + n) * e.ldf + s];
+    const long tau = (e.time_mode == 0) ? (long)n * e.P + e.p_step : (long)n;
+    const double* g = e.Gs + (long)s * e.R;
+    const double* h = e.Hs + (long)b * e.R * e.Tlen + tau;
+    double v = 0.0;
+    for (int q = 0; q < e.R; ++q) v += g[q] * h[(long)q * e.Tlen];
+    return v;
+}
+
+__device__ inline void epilogue(const Epi& e, int r, int s, double acc) {
+    switch (e.mode) {
+        case EPI_STORE: {
+            double v = e.alpha * acc;
+            if (e.beta != 0.0) v += e.beta * e.C0[(long)r * e.ldc0 + s];
+            if (e.diag_add != 0.0 && r == s + e.diag_off) v += e.diag_add;
+            e.C[(long)r * e.ldc + s] = v;
+            break;
+        }
+        case EPI_RESID: {
+            double v = source_value(e, r, s) - acc;
+            if (e.base) v -= e.base[(long)r * e.ldb + s];
+            e.R64[(long)r * e.ldr + s] = v;
+            if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
+            break;
+        }
+        case EPI_STEP: {
+            // state layout per column: [du_prev | u - u_a | w - w_a | dw_prev]
+            double* d = e.dev64 + (long)r * e.ldd;
+            float* d32 = e.dev32 ? e.dev32 + (long)r * e.ldd : nullptr;
+            if (s < e.d1p) {
+                const double u = d[e.d1p + s] + acc;
+                d[s] = acc;
+                d[e.d1p + s] = u;
+                if (d32) {
+                    d32[s] = (float)acc;
+                    d32[e.d1p + s] = (float)u;
+                }
+            } else {
+                const int j = s - e.d1p;
+                const long ow = 2L * e.d1p + j, oh = 2L * e.d1p + e.d2p + j;
+                const double w = d[ow] + acc;
+                d[ow] = w;
+                d[oh] = acc;
+                if (d32) {
+                    d32[ow] = (float)w;
+                    d32[oh] = (float)acc;
+                }
+            }
+            break;
+        }
+        case EPI_COARSE: {
+            const int b = r;
+            if (e.active && !e.active[b]) break;
+            const double g = e.xin[(long)b * e.ldx + s] + acc;
+            double x = g;
+            if (!e.initial) x = g + (e.fbuf[(long)b * e.ldfb + s] - e.gold[(long)b * e.ldg + s]);
+            e.xout[(long)b * e.ldxo + s] = x;
+            e.gold[(long)b * e.ldg + s] = g;
+            break;
+        }
+        default:
+            break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernel
+// ---------------------------------------------------------------------------
+template <typename T, int BR, int BS>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const Epi epi,
+                                                      const int tiles_r, const int splitk,
+                                                      T* __restrict__ part,
+                                                      unsigned* __restrict__ counters) {
+    using Op = MfmaOp<T>;
+    using acc_t = typename Op::acc_t;
+    using vec_t = typename Op::vec_t;
+    constexpr int BK = Op::BK;
+    constexpr int VW = 16 / sizeof(T);      // elements per 16-byte vector
+    constexpr int LDT = BK + VW;            // padded LDS row (elements)
+    constexpr int KV = BK / VW;             // vectors per tile row
+    constexpr int AV = BR * KV / 256;       // A vectors per thread
+    constexpr int BV = BS * KV / 256;       // B vectors per thread
+    constexpr int MI = BR / 32, MJ = BS / 32;
+    static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+    static_assert(BR % 32 == 0 && BS % 32 == 0, "tile must be a multiple of 32");
+
+    __shared__ __align__(16) T As[BR * LDT];
+    __shared__ __align__(16) T Bs[BS * LDT];
+    __shared__ int s_last;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave & 1, wsi = wave >> 1;
+    const int tile = blockIdx.x;
+    const int split = blockIdx.y;
+    const int tr = tile % tiles_r, ts = tile / tiles_r;
+    const int r0 = tr * BR, s0 = ts * BS;
+    const int s1 = min(s0 + BS, sh.Ns);
+
+    int k0, k1;
+    if (s1 <= sh.s_split) {
+        k0 = sh.k0a;
+        k1 = sh.k1a;
+    } else if (s0 >= sh.s_split) {
+        k0 = sh.k0b;
+        k1 = sh.k1b;
+    } else {
+        k0 = min(sh.k0a, sh.k0b);
+        k1 = max(sh.k1a, sh.k1b);
+    }
+    const int nkt = (k1 > k0) ? (k1 - k0 + BK - 1) / BK : 0;
+    const int per = (nkt + splitk - 1) / splitk;
+    const int kt0 = min(nkt, split * per);
+    const int kt1 = min(nkt, kt0 + per);
+
+    const T* __restrict__ A = (const T*)sh.A;
+    const T* __restrict__ B = (const T*)sh.B;
+
+    acc_t acc[MI][MJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < MJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    vec_t ra[AV], rb[BV];
+    auto gload = [&](int kbase) {
+#pragma unroll
+        for (int v = 0; v < AV; ++v) {
+            const int idx = tid + v * 256;
+            const int row = idx / KV, kk = (idx % KV) * VW;
+            const int r = r0 + row, k = kbase + kk;
+            if (r < sh.Mr && k < k1)
+                ra[v] = *(const vec_t*)(A + (long)r * sh.lda + k);
+            else
+                ra[v] = vec_t{};
+        }
+#pragma unroll
+        for (int v = 0; v < BV; ++v) {
+            const int idx = tid + v * 256;
+            const int row = idx / KV, kk = (idx % KV) * VW;
+            const int s = s0 + row, k = kbase + kk;
+            if (s < sh.Ns && k < k1)
+                rb[v] = *(const vec_t*)(B + (long)s * sh.ldb + k);
+            else
+                rb[v] = vec_t{};
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int v = 0; v < AV; ++v) {
+            const int idx = tid + v * 256;
+            const int row = idx / KV, kk = (idx % KV) * VW;
+            *(vec_t*)(As + row * LDT + kk) = ra[v];
+        }
+#pragma unroll
+        for (int v = 0; v < BV; ++v) {
+            const int idx = tid + v * 256;
+            const int row = idx / KV, kk = (idx % KV) * VW;
+            *(vec_t*)(Bs + row * LDT + kk) = rb[v];
+        }
+    };
+
+    if (kt0 < kt1) gload(k0 + kt0 * BK);
+    for (int kt = kt0; kt < kt1; ++kt) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (kt + 1 < kt1) gload(k0 + (kt + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            T a[MI][4], b[MJ][4];
+            const int koff = kk + 4 * (lane >> 4);
+#pragma unroll
+            for (int i = 0; i < MI; ++i) {
+                const T* pa = As + (wr * (BR / 2) + i * 16 + (lane & 15)) * LDT + koff;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[i][q] = pa[q];
+            }
+#pragma unroll
+            for (int j = 0; j < MJ; ++j) {
+                const T* pb = Bs + (wsi * (BS / 2) + j * 16 + (lane & 15)) * LDT + koff;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) b[j][q] = pb[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < MI; ++i)
+#pragma unroll
+                    for (int j = 0; j < MJ; ++j) acc[i][j] = Op::mma(a[i][q], b[j][q], acc[i][j]);
+        }
+    }
+
+    // output coordinates of this lane: 16x16 block (i, j), element q ->
+    // row Op::row(lane, q), column lane % 16 of the block
+    if (splitk == 1) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < MJ; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = r0 + wr * (BR / 2) + i * 16 + Op::row(lane, q);
+                    const int s = s0 + wsi * (BS / 2) + j * 16 + (lane & 15);
+                    if (r < sh.Mr && s < sh.Ns) epilogue(epi, r, s, (double)acc[i][j][q]);
+                }
+        return;
+    }
+
+    // split-K: publish the partial tile
+    T* mine = part + ((long)tile * splitk + split) * (BR * BS);
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < MJ; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rl = wr * (BR / 2) + i * 16 + Op::row(lane, q);
+                const int sl = wsi * (BS / 2) + j * 16 + (lane & 15);
+                mine[rl * BS + sl] = acc[i][j][q];
+            }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned prev = atomicAdd(&counters[tile], 1u);
+        s_last = (prev == (unsigned)(splitk - 1));
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const T* base = part + (long)tile * splitk * (BR * BS);
+    for (int e = tid; e < BR * BS; e += 256) {
+        const int rl = e / BS, sl = e % BS;
+        const int r = r0 + rl, s = s0 + sl;
+        if (r >= sh.Mr || s >= sh.Ns) continue;
+        double v = 0.0;
+        for (int sp = 0; sp < splitk; ++sp) v += (double)base[(long)sp * (BR * BS) + e];
+        epilogue(epi, r, s, v);
+    }
+    if (tid == 0) counters[tile] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+static int k_extent(const GemmShape& sh) {
+    const int la = sh.k1a - sh.k0a, lb = sh.k1b - sh.k0b;
+    return la > lb ? la : lb;
+}
+
+size_t gemm_n_tiles(const GemmShape& sh, const TileCfg& cfg) {
+    return (size_t)cdiv(sh.Mr, cfg.br) * cdiv(sh.Ns, cfg.bs);
+}
+
+size_t gemm_part_bytes(const GemmShape& sh, const TileCfg& cfg, size_t elem) {
+    if (cfg.splitk <= 1) return 0;
+    return gemm_n_tiles(sh, cfg) * (size_t)cfg.splitk * cfg.br * cfg.bs * elem;
+}
+
+TileCfg choose_tiles(const GemmShape& sh, bool fp32, int n_cu) {
+    TileCfg c;
+    c.br = sh.Mr <= 32 ? 32 : 64;
+    c.bs = 64;
+    const long tiles = (long)cdiv(sh.Mr, c.br) * cdiv(sh.Ns, c.bs);
+    const int bk = fp32 ? 32 : 16;
+    const int nkt = cdiv(k_extent(sh), bk);
+    const long target = 2L * n_cu;
+    int sk = 1;
+    if (tiles < target && nkt > 1) {
+        sk = (int)((target + tiles - 1) / tiles);
+        const int max_sk = nkt / 2 > 1 ? nkt / 2 : 1;   // keep >= 2 K tiles per split
+        if (sk > max_sk) sk = max_sk;
+        if (sk > 32) sk = 32;
+        if (sk < 1) sk = 1;
+    }
+    c.splitk = sk;
+    return c;
+}
+
+template <typename T, int BR, int BS>
+static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, GemmWork& ws,
+                             hipStream_t stream) {
+    const int tr = cdiv(sh.Mr, BR), tsn = cdiv(sh.Ns, BS);
+    dim3 grid(tr * tsn, splitk);
+    if (splitk > 1) {
+        const size_t need = (size_t)tr * tsn * splitk * BR * BS * sizeof(T);
+        if (need > ws.part_bytes || (size_t)tr * tsn > ws.n_counters) return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BR, BS>), grid, dim3(256), 0, stream, sh, epi, tr, splitk,
+                       (T*)ws.part, ws.counters);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, GemmWork& ws,
+                       hipStream_t stream) {
+    if (sh.Mr <= 0 || sh.Ns <= 0) return hipSuccess;
+    // operand offsets and strides must keep 16-byte vector loads aligned
+    const long vw = 16 / sizeof(T);
+    if ((sh.lda % vw) || (sh.ldb % vw) || (sh.k0a % vw) || (sh.k0b % vw) || (sh.k1a % vw) ||
+        (sh.k1b % vw) || (((uintptr_t)sh.A) % 16) || (((uintptr_t)sh.B) % 16))
+        return hipErrorInvalidValue;
+    const int sk = cfg.splitk < 1 ? 1 : cfg.splitk;
+    if (cfg.br == 32 && cfg.bs == 64) return launch_cfg<T, 32, 64>(sh, epi, sk, ws, stream);
+    if (cfg.br == 64 && cfg.bs == 64) return launch_cfg<T, 64, 64>(sh, epi, sk, ws, stream);
+    if (cfg.br == 64 && cfg.bs == 128) return launch_cfg<T, 64, 128>(sh, epi, sk, ws, stream);
+    if (cfg.br == 128 && cfg.bs == 64) return launch_cfg<T, 128, 64>(sh, epi, sk, ws, stream);
+    if (cfg.br == 128 && cfg.bs == 128) return launch_cfg<T, 128, 128>(sh, epi, sk, ws, stream);
+    return hipErrorInvalidValue;
+}
+
+template hipError_t gemm_launch<float>(const GemmShape&, const Epi&, const TileCfg&, GemmWork&,
+                                       hipStream_t);
+template hipError_t gemm_launch<double>(const GemmShape&, const Epi&, const TileCfg&, GemmWork&,
+                                        hipStream_t);
+
+}  // namespace pe

@@ -1,0 +1,370 @@
+// Element-wise and reduction kernels of libpe: state layout conversion, fine
+// sweep set-up/finish, parareal jump norms (eq. (2.8)), step-operator
+// assembly and the per-block part of the FP64 Cholesky factorisation.
+#include "pe_kernels.h"
+
+namespace pe {
+
+static inline dim3 grid1(long n, int bs = 256) {
+    long g = (n + bs - 1) / bs;
+    if (g > 65535L * 64) g = 65535L * 64;
+    return dim3((unsigned)(g < 1 ? 1 : g));
+}
+
+// ---------------------------------------------------------------------------
+// state layout: user [u (d1) | w (d2)]  <->  internal [u (d1p) | w (d2p)]
+// ---------------------------------------------------------------------------
+__global__ void k_pack(const double* __restrict__ src, double* __restrict__ dst, long rows, int d1,
+                       int d2, int d1p, int d2p) {
+    const long Dp = d1p + d2p, D = d1 + d2;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        double v = 0.0;
+        if (s < d1)
+            v = src[r * D + s];
+        else if (s >= d1p && s < d1p + d2)
+            v = src[r * D + d1 + (s - d1p)];
+        dst[i] = v;
+    }
+}
+
+__global__ void k_unpack(const double* __restrict__ src, double* __restrict__ dst, long rows, int d1,
+                         int d2, int d1p, int d2p) {
+    const long Dp = d1p + d2p, D = d1 + d2;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * D;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / D;
+        const int s = (int)(i - r * D);
+        dst[i] = (s < d1) ? src[r * Dp + s] : src[r * Dp + d1p + (s - d1)];
+    }
+}
+
+hipError_t pack_states(const double* src, double* dst, long rows, int d1, int d2, int d1p, int d2p,
+                       hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack, grid1(rows * (d1p + d2p)), dim3(256), 0, st, src, dst, rows, d1, d2,
+                       d1p, d2p);
+    return hipGetLastError();
+}
+
+hipError_t unpack_states(const double* src, double* dst, long rows, int d1, int d2, int d1p, int d2p,
+                         hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpack, grid1(rows * (long)(d1 + d2)), dim3(256), 0, st, src, dst, rows, d1,
+                       d2, d1p, d2p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fine sweep: gather anchors X[b][n - n_shift] (zero for n < n_shift) into
+// Xa[b*N + n], zero the deviation state; afterwards Y (+)= Xa + deviation.
+// ---------------------------------------------------------------------------
+__global__ void k_fine_init(const double* __restrict__ X, long ldXb, int n_shift, double* __restrict__ Xa,
+                            double* __restrict__ dev64, float* __restrict__ dev32, int B, int N,
+                            int Dp) {
+    const long rows = (long)B * N;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const long b = r / N, n = r - b * N;
+        Xa[i] = (n >= n_shift) ? X[b * ldXb + (n - n_shift) * Dp + s] : 0.0;
+        dev64[r * 2 * Dp + s] = 0.0;
+        dev64[r * 2 * Dp + Dp + s] = 0.0;
+        if (dev32) {
+            dev32[r * 2 * Dp + s] = 0.0f;
+            dev32[r * 2 * Dp + Dp + s] = 0.0f;
+        }
+    }
+}
+
+hipError_t fine_init(const double* X, long ldXb, int n_shift, double* Xa, double* dev64, float* dev32,
+                     int B, int N, int Dp, hipStream_t st) {
+    hipLaunchKernelGGL(k_fine_init, grid1((long)B * N * Dp), dim3(256), 0, st, X, ldXb, n_shift, Xa,
+                       dev64, dev32, B, N, Dp);
+    return hipGetLastError();
+}
+
+// Y[r][s] (+)= Xa[r][s] + dev[r][d1p + s]  (u and w deviations sit at d1p + s)
+__global__ void k_fine_final(const double* __restrict__ Xa, const double* __restrict__ dev64,
+                             double* __restrict__ Y, long rows, int Dp, int d1p, int accumulate) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const double v = Xa[i] + dev64[r * 2 * Dp + d1p + s];
+        Y[i] = accumulate ? Y[i] + v : v;
+    }
+}
+
+hipError_t fine_final(const double* Xa, const double* dev64, double* Y, long rows, int Dp, int d1p,
+                      int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_fine_final, grid1(rows * Dp), dim3(256), 0, st, Xa, dev64, Y, rows, Dp, d1p,
+                       accumulate);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// jump norms of eq. (2.8): E[b*nr + j] = Xk[b][n0 + j] - Xp[b][n0 + j]
+// (Xp may be null: plain norms), then J_b = max_j sqrt(E_j . (M E_j)).
+// ---------------------------------------------------------------------------
+__global__ void k_jump_diff(const double* __restrict__ Xk, const double* __restrict__ Xp, long ldXb,
+                            int n0, int nr, int B, int Dp, double* __restrict__ E) {
+    const long rows = (long)B * nr;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const long b = r / nr, j = r - b * nr;
+        const long o = b * ldXb + (n0 + j) * Dp + s;
+        E[i] = Xp ? (Xk[o] - Xp[o]) : Xk[o];
+    }
+}
+
+hipError_t jump_diff(const double* Xk, const double* Xp, long ldXb, int n0, int nr, int B, int Dp,
+                     double* E, hipStream_t st) {
+    hipLaunchKernelGGL(k_jump_diff, grid1((long)B * nr * Dp), dim3(256), 0, st, Xk, Xp, ldXb, n0, nr, B,
+                       Dp, E);
+    return hipGetLastError();
+}
+
+// one work-group per sample; fixed reduction order (deterministic)
+__global__ void k_jump_reduce(const double* __restrict__ E, const double* __restrict__ Y, int nr,
+                              int Dp, double* __restrict__ J, double* __restrict__ norms) {
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    double jmax = 0.0;
+    bool bad = false;
+    for (int j = 0; j < nr; ++j) {
+        const long r = (long)b * nr + j;
+        double acc = 0.0;
+        for (int s = threadIdx.x; s < Dp; s += blockDim.x) acc += E[r * Dp + s] * Y[r * Dp + s];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        const double q = red[0];
+        __syncthreads();
+        if (!(q == q) || q > 1.7e308 || q < -1.7e308) bad = true;
+        const double nrm = sqrt(q > 0.0 ? q : 0.0);
+        if (norms && threadIdx.x == 0) norms[r] = nrm;
+        if (nrm > jmax) jmax = nrm;
+    }
+    if (threadIdx.x == 0) J[b] = bad ? __builtin_nan("") : jmax;
+}
+
+hipError_t jump_reduce(const double* E, const double* Y, int B, int nr, int Dp, double* J, double* norms,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_jump_reduce, dim3(B), dim3(256), 0, st, E, Y, nr, Dp, J, norms);
+    return hipGetLastError();
+}
+
+// copy Xsrc[b] -> Xdst[b] for samples that stopped iterating
+__global__ void k_freeze(const double* __restrict__ Xsrc, double* __restrict__ Xdst,
+                         const int* __restrict__ active, long ldXb, int B) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)B * ldXb;
+         i += (long)gridDim.x * blockDim.x) {
+        const long b = i / ldXb;
+        if (!active[b]) Xdst[i] = Xsrc[i];
+    }
+}
+
+hipError_t freeze_inactive(const double* Xsrc, double* Xdst, const int* active, long ldXb, int B,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_freeze, grid1((long)B * ldXb), dim3(256), 0, st, Xsrc, Xdst, active, ldXb, B);
+    return hipGetLastError();
+}
+
+// x0 into row 0 of every sample of X (x_0^k = x_0)
+__global__ void k_set_x0(const double* __restrict__ x0p, double* __restrict__ X, long ldXb, int B,
+                         int Dp) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)B * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long b = i / Dp;
+        const int s = (int)(i - b * Dp);
+        X[b * ldXb + s] = x0p[i];
+    }
+}
+
+hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_x0, grid1((long)B * Dp), dim3(256), 0, st, x0p, X, ldXb, B, Dp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// operator assembly
+// ---------------------------------------------------------------------------
+// generic placement: dst[(ro + i) * ldd + co + j] = scale * (trans ? src[j*lds + i] : src[i*lds + j])
+__global__ void k_place(double* __restrict__ dst, long ldd, int ro, int co, const double* __restrict__ src,
+                        long lds, int rows, int cols, double scale, int trans) {
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)rows * cols;
+         t += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(t / cols), j = (int)(t - (long)i * cols);
+        const double v = trans ? src[(long)j * lds + i] : src[(long)i * lds + j];
+        dst[(long)(ro + i) * ldd + co + j] = scale * v;
+    }
+}
+
+hipError_t place(double* dst, long ldd, int ro, int co, const double* src, long lds, int rows, int cols,
+                 double scale, int trans, hipStream_t st) {
+    if (rows <= 0 || cols <= 0 || !src) return hipSuccess;
+    hipLaunchKernelGGL(k_place, grid1((long)rows * cols), dim3(256), 0, st, dst, ldd, ro, co, src, lds,
+                       rows, cols, scale, trans);
+    return hipGetLastError();
+}
+
+// dst = A + c*B on a rows x cols block (row-major, lds), written into a
+// square padded buffer of size n with identity on the padding diagonal
+__global__ void k_shifted_embed(double* __restrict__ dst, int n, const double* __restrict__ A,
+                                const double* __restrict__ Bm, long lds, int d, double cb) {
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)n * n;
+         t += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(t / n), j = (int)(t - (long)i * n);
+        double v;
+        if (i < d && j < d)
+            v = A[(long)i * lds + j] + (Bm ? cb * Bm[(long)i * lds + j] : 0.0);
+        else
+            v = (i == j) ? 1.0 : 0.0;
+        dst[t] = v;
+    }
+}
+
+hipError_t shifted_embed(double* dst, int n, const double* A, const double* Bm, long lds, int d,
+                         double cb, hipStream_t st) {
+    hipLaunchKernelGGL(k_shifted_embed, grid1((long)n * n), dim3(256), 0, st, dst, n, A, Bm, lds, d, cb);
+    return hipGetLastError();
+}
+
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+// zero the strict upper triangle of an n x n row-major matrix
+__global__ void k_tril(double* __restrict__ A, int n) {
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)n * n;
+         t += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(t / n), j = (int)(t - (long)i * n);
+        if (j > i) A[t] = 0.0;
+    }
+}
+
+hipError_t tril(double* A, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_tril, grid1((long)n * n), dim3(256), 0, st, A, n);
+    return hipGetLastError();
+}
+
+// identity on the leading d x d block of an n x n matrix, zero elsewhere
+__global__ void k_eye(double* __restrict__ A, int n, int d) {
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)n * n;
+         t += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(t / n), j = (int)(t - (long)i * n);
+        A[t] = (i == j && i < d) ? 1.0 : 0.0;
+    }
+}
+
+hipError_t eye(double* A, int n, int d, hipStream_t st) {
+    hipLaunchKernelGGL(k_eye, grid1((long)n * n), dim3(256), 0, st, A, n, d);
+    return hipGetLastError();
+}
+
+hipError_t to_f32(const double* src, float* dst, long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, grid1(n), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+// max |X[i][j] - Y[j][i]| and max |X[i][j]| (Y = X for a symmetry test);
+// non-negative doubles order like their bit patterns
+__global__ void k_asym(const double* __restrict__ X, const double* __restrict__ Y, long ldx, long ldy,
+                       int rows, int cols, unsigned long long* __restrict__ out) {
+    double dmax = 0.0, amax = 0.0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)rows * cols;
+         t += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(t / cols), j = (int)(t - (long)i * cols);
+        const double x = X[(long)i * ldx + j];
+        const double y = Y[(long)j * ldy + i];
+        const double d = fabs(x - y);
+        if (!(d <= dmax)) dmax = (d == d) ? d : 1.0e308;
+        const double a = fabs(x);
+        if (!(a <= amax)) amax = (a == a) ? a : 1.0e308;
+    }
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(dmax));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(amax));
+}
+
+hipError_t asym(const double* X, const double* Y, long ldx, long ldy, int rows, int cols,
+                unsigned long long* out2, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_asym, dim3(256), dim3(256), 0, st, X, Y, ldx, ldy, rows, cols, out2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of the 64 x 64 diagonal block (j, j) of a padded SPD matrix, in
+// LDS, plus the inverse of the factor block. A non-positive pivot records
+// (block, pivot) in info (first failure wins) and poisons the block.
+// ---------------------------------------------------------------------------
+constexpr int NB = 64;
+
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ Am, long ld, int j,
+                                                   double* __restrict__ Linv, int* __restrict__ info) {
+    __shared__ double L[NB][NB + 1];
+    __shared__ double X[NB][NB + 1];
+    const int tid = threadIdx.x;
+    const long o = (long)j * NB;
+    for (int t = tid; t < NB * NB; t += 256) {
+        const int r = t / NB, c = t % NB;
+        L[r][c] = Am[(o + r) * ld + o + c];
+    }
+    __syncthreads();
+    for (int k = 0; k < NB; ++k) {
+        if (tid == 0) {
+            const double d = L[k][k];
+            if (!(d > 0.0)) {
+                if (info[0] == 0) {
+                    info[0] = 1;
+                    info[1] = j * NB + k;
+                }
+                L[k][k] = __builtin_nan("");
+            } else {
+                L[k][k] = sqrt(d);
+            }
+        }
+        __syncthreads();
+        for (int i = k + 1 + tid; i < NB; i += 256) L[i][k] /= L[k][k];
+        __syncthreads();
+        for (int t = tid; t < NB * NB; t += 256) {
+            const int i = t / NB, c = t % NB;
+            if (i > k && c > k && c <= i) L[i][c] -= L[i][k] * L[c][k];
+        }
+        __syncthreads();
+    }
+    // inverse of the lower-triangular factor, one column per thread
+    if (tid < NB) {
+        const int c = tid;
+        for (int i = 0; i < NB; ++i) X[i][c] = 0.0;
+        for (int i = c; i < NB; ++i) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int m = c; m < i; ++m) v -= L[i][m] * X[m][c];
+            X[i][c] = v / L[i][i];
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < NB * NB; t += 256) {
+        const int r = t / NB, c = t % NB;
+        Am[(o + r) * ld + o + c] = (c <= r) ? L[r][c] : 0.0;
+        Linv[(long)j * NB * NB + r * NB + c] = (c <= r) ? X[r][c] : 0.0;
+    }
+}
+
+hipError_t chol_diag(double* Am, long ld, int j, double* Linv, int* info, hipStream_t st) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, Am, ld, j, Linv, info);
+    return hipGetLastError();
+}
+
+}  // namespace pe

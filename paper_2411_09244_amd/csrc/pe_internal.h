@@ -1,0 +1,107 @@
+// Internal declarations of libpe (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace pe {
+
+// ---------------------------------------------------------------------------
+// GEMM descriptor. Every dense product of the path has the form
+//     C[r][s] = epilogue( sum_k A[r][k] * B[s][k] )
+// with both operands K-contiguous ("NT"): A rows are state columns (one per
+// interval x sample), B rows are operator rows. The K range depends on the
+// operator row block: rows s < s_split use [k0a, k1a), rows s >= s_split use
+// [k0b, k1b) (the zero blocks of the step operators are skipped).
+// ---------------------------------------------------------------------------
+struct GemmShape {
+    int Mr = 0, Ns = 0;
+    const void* A = nullptr;
+    long lda = 0;
+    const void* B = nullptr;
+    long ldb = 0;
+    int s_split = 0;
+    int k0a = 0, k1a = 0, k0b = 0, k1b = 0;
+};
+
+enum EpiMode : int {
+    EPI_STORE = 0,   // C = alpha*acc + beta*C0 (+ diag_add on r == s + diag_off)
+    EPI_RESID = 1,   // R = f(t) - base - acc               (residual of a step)
+    EPI_STEP = 2,    // increment -> state/history update    (fine step)
+    EPI_COARSE = 3,  // coarse step + parareal correction    (eq. (2.7))
+};
+
+struct Epi {
+    int mode = EPI_STORE;
+    // EPI_STORE
+    double alpha = 1.0, beta = 0.0;
+    double diag_add = 0.0;
+    int diag_off = 0;
+    double* C = nullptr;
+    const double* C0 = nullptr;
+    long ldc = 0, ldc0 = 0;
+    // EPI_RESID
+    double* R64 = nullptr;
+    float* R32 = nullptr;
+    long ldr = 0;
+    const double* base = nullptr;
+    long ldb = 0;
+    int src_kind = 0;            // 0: f = 0, 1: low-rank G*H, 2: dense per-interval table
+    const double* Gs = nullptr;  // Dp x R
+    const double* Hs = nullptr;  // B x R x Tlen
+    int R = 0;
+    long Tlen = 0;
+    int time_mode = 0;           // 0: amplitude per fine step, 1: per interval
+    int P = 1;
+    int p_step = 0;              // fine step index inside the interval
+    int cols_per_b = 1;          // column r -> sample r / cols_per_b, interval r % cols_per_b
+    int n_fixed = -1;            // >= 0: every column belongs to this interval (r = sample)
+    int N = 1;
+    const double* Fint = nullptr;  // (B*N) x Dp table of per-interval sources
+    long ldf = 0;
+    // EPI_STEP / EPI_COARSE
+    double* dev64 = nullptr;
+    float* dev32 = nullptr;
+    long ldd = 0;
+    int d1p = 0, d2p = 0;
+    // EPI_COARSE
+    const double* xin = nullptr;
+    long ldx = 0;
+    double* xout = nullptr;
+    long ldxo = 0;
+    const double* fbuf = nullptr;
+    long ldfb = 0;
+    double* gold = nullptr;
+    long ldg = 0;
+    int initial = 0;
+    const int* active = nullptr;
+};
+
+// Tile configuration of one GEMM launch.
+struct TileCfg {
+    int br = 64, bs = 64, splitk = 1;
+};
+
+// Workspace for split-K partial tiles and tile counters.
+struct GemmWork {
+    void* part = nullptr;
+    size_t part_bytes = 0;
+    unsigned* counters = nullptr;
+    size_t n_counters = 0;
+};
+
+// Launch C = epi(A * B^T) in precision T (float: FP32 MFMA, double: FP64
+// MFMA). Returns hipSuccess or an error; throws nothing.
+template <typename T>
+hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, GemmWork& ws,
+                       hipStream_t stream);
+
+// Choose a tile configuration for a product of this shape.
+TileCfg choose_tiles(const GemmShape& sh, bool fp32, int n_cu);
+
+// Upper bound of workspace bytes/counters a launch with cfg needs.
+size_t gemm_part_bytes(const GemmShape& sh, const TileCfg& cfg, size_t elem);
+size_t gemm_n_tiles(const GemmShape& sh, const TileCfg& cfg);
+
+}  // namespace pe

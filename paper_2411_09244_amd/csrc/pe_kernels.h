@@ -1,0 +1,31 @@
+// Launchers of the element-wise / reduction kernels of libpe.
+#pragma once
+#include "pe_internal.h"
+
+namespace pe {
+hipError_t pack_states(const double* src, double* dst, long rows, int d1, int d2, int d1p, int d2p,
+                       hipStream_t st);
+hipError_t unpack_states(const double* src, double* dst, long rows, int d1, int d2, int d1p, int d2p,
+                         hipStream_t st);
+hipError_t fine_init(const double* X, long ldXb, int n_shift, double* Xa, double* dev64, float* dev32,
+                     int B, int N, int Dp, hipStream_t st);
+hipError_t fine_final(const double* Xa, const double* dev64, double* Y, long rows, int Dp, int d1p,
+                      int accumulate, hipStream_t st);
+hipError_t jump_diff(const double* Xk, const double* Xp, long ldXb, int n0, int nr, int B, int Dp,
+                     double* E, hipStream_t st);
+hipError_t jump_reduce(const double* E, const double* Y, int B, int nr, int Dp, double* J, double* norms,
+                       hipStream_t st);
+hipError_t freeze_inactive(const double* Xsrc, double* Xdst, const int* active, long ldXb, int B,
+                           hipStream_t st);
+hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st);
+hipError_t place(double* dst, long ldd, int ro, int co, const double* src, long lds, int rows, int cols,
+                 double scale, int trans, hipStream_t st);
+hipError_t shifted_embed(double* dst, int n, const double* A, const double* Bm, long lds, int d,
+                         double cb, hipStream_t st);
+hipError_t tril(double* A, int n, hipStream_t st);
+hipError_t eye(double* A, int n, int d, hipStream_t st);
+hipError_t to_f32(const double* src, float* dst, long n, hipStream_t st);
+hipError_t asym(const double* X, const double* Y, long ldx, long ldy, int rows, int cols,
+                unsigned long long* out2, hipStream_t st);
+hipError_t chol_diag(double* Am, long ld, int j, double* Linv, int* info, hipStream_t st);
+}  // namespace pe

@@ -151,6 +151,32 @@ pe_status pe_coarse_propagate(pe_problem p, int B, const double* Xin, double* Y)
  */
 pe_status pe_mass_norms(pe_problem p, int count, const double* X, double* out);
 
+/* launch classes timed by pe_profile */
+enum {
+    PE_PROF_FINE_RESIDUAL = 0,  /* fine step, R = F - A x_a - W dev (steps 2..P)  */
+    PE_PROF_FINE_INCREMENT = 1, /* fine step, [du; dw] = Z R and state update     */
+    PE_PROF_FINE_FIRST = 2,     /* fine step 1 residual (zero deviation: source only) */
+    PE_PROF_ANCHOR = 3,         /* fine sweep anchors: A x_a and coordinate changes */
+    PE_PROF_COARSE = 4,         /* coarse step + parareal correction              */
+    PE_PROF_NORM = 5,           /* mass products of the stopping test             */
+    PE_PROF_KINDS = 6
+};
+
+/*
+ * pe_profile - enable (1) or disable (0) launch timing and reset the totals.
+ * When enabled, every launch of the classes above is bracketed by a pair of
+ * HIP events recorded on the handle's stream (GPU time from the start to
+ * the end of that launch).
+ */
+pe_status pe_profile(pe_problem p, int enable);
+
+/*
+ * pe_profile_read - accumulated GPU milliseconds and number of launches of
+ * class `kind` since the last pe_profile call (host out-pointers, nullable).
+ * Synchronises the handle's stream.
+ */
+pe_status pe_profile_read(pe_problem p, int kind, double* total_ms, long long* launches);
+
 /* pe_problem_info - d1, d2, N, P (host ints, each nullable). */
 pe_status pe_problem_info(pe_problem p, int* d1, int* d2, int* N, int* P);
 

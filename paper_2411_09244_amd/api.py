@@ -98,6 +98,20 @@ class Problem:
                                        out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
+    def profile(self, enable=True):
+        """Enable/disable per-launch HIP-event timing (resets totals)."""
+        L.check(self.lib.pe_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kind: (total GPU ms, launches)} since the last profile() call."""
+        out = {}
+        for name, k in L.PROFILE_KINDS.items():
+            ms = ctypes.c_double()
+            n = ctypes.c_longlong()
+            L.check(self.lib.pe_profile_read(self.handle, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.pe_problem_destroy(self.handle)

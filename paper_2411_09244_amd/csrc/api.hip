@@ -97,9 +97,18 @@ struct pe_problem_s {
     double *Fbuf = nullptr, *Gold = nullptr, *Xa = nullptr, *Ya = nullptr, *R64 = nullptr;
     double* dev64 = nullptr;
     float *dev32 = nullptr, *R32 = nullptr;
-    double *E = nullptr, *Yn = nullptr, *Jd = nullptr, *x0p = nullptr, *io = nullptr;
+    double *E = nullptr, *Yn = nullptr, *Jd = nullptr, *x0p = nullptr, *io = nullptr, *nrm = nullptr;
     int* active_d = nullptr;
     GemmWork gw;
+
+    // launch timing (pe_profile): HIP event pairs around each launch of a
+    // kernel class, on the handle's stream
+    int prof_on = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_pending;  // (kind, index of first event)
+    double prof_ms[PE_PROF_KINDS] = {0};
+    long long prof_n[PE_PROF_KINDS] = {0};
 
     std::vector<void*> op_allocs, ws_allocs;
 };
@@ -133,41 +142,66 @@ void free_list(std::vector<void*>& list) {
 }
 
 // grow the split-K workspace if a launch needs more (synchronises first)
-pe_status ensure_gemm_work(pe_problem p, size_t part_bytes, size_t n_tiles) {
+pe_status ensure_gemm_work(pe_problem p, size_t part_bytes) {
     GemmWork& w = p->gw;
-    if (part_bytes <= w.part_bytes && n_tiles <= w.n_counters) return PE_OK;
+    if (part_bytes <= w.part_bytes) return PE_OK;
     PE_HIP(hipStreamSynchronize(p->st));
-    if (part_bytes > w.part_bytes) {
-        if (w.part) (void)hipFree(w.part);
-        w.part = nullptr;
-        w.part_bytes = 0;
-        size_t nb = std::max(part_bytes, (size_t)1 << 20);
-        hipError_t e = hipMalloc(&w.part, nb);
-        if (e != hipSuccess) return fail(PE_ERR_NOMEM, "split-K workspace allocation failed");
-        w.part_bytes = nb;
+    if (w.part) (void)hipFree(w.part);
+    w.part = nullptr;
+    w.part_bytes = 0;
+    const size_t nb = std::max(part_bytes, (size_t)1 << 20);
+    hipError_t e = hipMalloc(&w.part, nb);
+    if (e != hipSuccess) return fail(PE_ERR_NOMEM, "split-K workspace allocation failed");
+    w.part_bytes = nb;
+    return PE_OK;
+}
+
+pe_status prof_begin(pe_problem p, int kind, size_t* slot) {
+    *slot = (size_t)-1;
+    if (!p->prof_on || kind < 0) return PE_OK;
+    while (p->ev_pool.size() < p->ev_used + 2) {
+        hipEvent_t ev;
+        PE_HIP(hipEventCreate(&ev));
+        p->ev_pool.push_back(ev);
     }
-    if (n_tiles > w.n_counters) {
-        if (w.counters) (void)hipFree(w.counters);
-        w.counters = nullptr;
-        w.n_counters = 0;
-        size_t nc = std::max(n_tiles, (size_t)4096);
-        hipError_t e = hipMalloc((void**)&w.counters, nc * sizeof(unsigned));
-        if (e != hipSuccess) return fail(PE_ERR_NOMEM, "split-K counter allocation failed");
-        PE_HIP(hipMemsetAsync(w.counters, 0, nc * sizeof(unsigned), p->st));
-        w.n_counters = nc;
+    *slot = p->ev_used;
+    p->ev_used += 2;
+    PE_HIP(hipEventRecord(p->ev_pool[*slot], p->st));
+    p->ev_pending.emplace_back(kind, *slot);
+    return PE_OK;
+}
+
+pe_status prof_end(pe_problem p, size_t slot) {
+    if (slot == (size_t)-1) return PE_OK;
+    PE_HIP(hipEventRecord(p->ev_pool[slot + 1], p->st));
+    return PE_OK;
+}
+
+// fold completed event pairs into the per-kind totals (stream must be idle)
+pe_status prof_collect(pe_problem p) {
+    for (auto& kv : p->ev_pending) {
+        float ms = 0.f;
+        PE_HIP(hipEventElapsedTime(&ms, p->ev_pool[kv.second], p->ev_pool[kv.second + 1]));
+        p->prof_ms[kv.first] += ms;
+        p->prof_n[kv.first] += 1;
     }
+    p->ev_pending.clear();
+    p->ev_used = 0;
     return PE_OK;
 }
 
 template <typename T>
-pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_splitk = 0) {
+pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_splitk = 0, int kind = -1) {
     if (sh.Mr <= 0 || sh.Ns <= 0) return PE_OK;
     TileCfg cfg = choose_tiles(sh, sizeof(T) == 4, p->n_cu);
     if (force_splitk > 0) cfg.splitk = force_splitk;
-    PE_TRY(ensure_gemm_work(p, gemm_part_bytes(sh, cfg, sizeof(T)), gemm_n_tiles(sh, cfg)));
+    PE_TRY(ensure_gemm_work(p, gemm_part_bytes(sh, cfg, sizeof(T))));
+    size_t slot;
+    PE_TRY(prof_begin(p, kind, &slot));
     hipError_t e = gemm_launch<T>(sh, epi, cfg, p->gw, p->st);
     if (e != hipSuccess)
         return fail(PE_ERR_HIP, std::string("GEMM launch failed: ") + hipGetErrorString(e));
+    PE_TRY(prof_end(p, slot));
     return PE_OK;
 }
 
@@ -442,6 +476,7 @@ pe_status ensure_workspace(pe_problem p, int B) {
     PE_TRY(dalloc_t(p, L, &p->Yn, Bs * (N + 1) * Dp));
     PE_TRY(dalloc_t(p, L, &p->io, Bs * (N + 1) * Dp));
     PE_TRY(dalloc_t(p, L, &p->Jd, Bs * (N + 1)));
+    PE_TRY(dalloc_t(p, L, &p->nrm, Bs * (N + 1)));
     PE_TRY(dalloc_t(p, L, &p->x0p, Bs * Dp));
     PE_TRY(dalloc_t(p, L, &p->active_d, Bs));
     p->B_cap = B;
@@ -474,7 +509,8 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     const bool mixed = p->prec == PE_MIXED;
     if (!mixed) {
         PE_HIP(fine_init(Xsrc, ldXb, n_shift, p->Xa, p->dev64, nullptr, B, p->N, Dp, p->st));
-        PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->A64, Dp, 0, Dp), store_epi(p->Ya, Dp)));
+        PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->A64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
+                            PE_PROF_ANCHOR));
     } else {
         // anchors into whitened coordinates: Xa = Tin x (block diagonal)
         PE_HIP(fine_init(Xsrc, ldXb, n_shift, p->R64, p->dev64, p->dev32, B, p->N, Dp, p->st));
@@ -482,8 +518,9 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         gt.s_split = d1p;
         gt.k0b = d1p;
         gt.k1b = Dp;
-        PE_TRY(gemm<double>(p, gt, store_epi(p->Xa, Dp)));
-        PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->Aw64, Dp, 0, Dp), store_epi(p->Ya, Dp)));
+        PE_TRY(gemm<double>(p, gt, store_epi(p->Xa, Dp), 0, PE_PROF_ANCHOR));
+        PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->Aw64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
+                            PE_PROF_ANCHOR));
     }
     const long ldS = 2L * Dp;
     for (int step = 0; step < p->P; ++step) {
@@ -508,10 +545,11 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         e1.cols_per_b = p->N;
         e1.n_fixed = -1;
         e1.p_step = step;
+        const int k1 = step > 0 ? PE_PROF_FINE_RESIDUAL : PE_PROF_FINE_FIRST;
         if (mixed)
-            PE_TRY(gemm<float>(p, g1, e1));
+            PE_TRY(gemm<float>(p, g1, e1, 0, k1));
         else
-            PE_TRY(gemm<double>(p, g1, e1));
+            PE_TRY(gemm<double>(p, g1, e1, 0, k1));
 
         GemmShape g2 = shape(rows, Dp, mixed ? (const void*)p->R32 : (const void*)p->R64, Dp,
                              mixed ? (const void*)p->Zf32 : (const void*)p->Zf64, Dp, 0, d1p);
@@ -526,9 +564,9 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         e2.d1p = d1p;
         e2.d2p = d2p;
         if (mixed)
-            PE_TRY(gemm<float>(p, g2, e2));
+            PE_TRY(gemm<float>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT));
         else
-            PE_TRY(gemm<double>(p, g2, e2));
+            PE_TRY(gemm<double>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT));
     }
     if (!mixed) {
         PE_HIP(fine_final(p->Xa, p->dev64, Y, rows, Dp, d1p, accumulate ? 1 : 0, p->st));
@@ -539,7 +577,8 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         gt.s_split = d1p;
         gt.k0b = d1p;
         gt.k1b = Dp;
-        PE_TRY(gemm<double>(p, gt, store_epi(Y, Dp, 1.0, accumulate ? Y : nullptr, Dp, accumulate ? 1.0 : 0.0)));
+        PE_TRY(gemm<double>(p, gt, store_epi(Y, Dp, 1.0, accumulate ? Y : nullptr, Dp, accumulate ? 1.0 : 0.0),
+                            0, PE_PROF_ANCHOR));
     }
     return PE_OK;
 }
@@ -556,7 +595,7 @@ pe_status coarse_step(pe_problem p, int B, double* Xk, int n, int initial, const
     source_fields(p, e1);
     e1.n_fixed = n;
     e1.p_step = p->P - 1;
-    PE_TRY(gemm<double>(p, shape(B, Dp, Xk + (long)n * Dp, ldX, p->A64, Dp, 0, Dp), e1));
+    PE_TRY(gemm<double>(p, shape(B, Dp, Xk + (long)n * Dp, ldX, p->A64, Dp, 0, Dp), e1, 0, PE_PROF_COARSE));
     GemmShape g2 = shape(B, Dp, p->R64, Dp, p->Zc64, Dp, 0, p->d1p);
     g2.s_split = p->d1p;
     g2.k0b = 0;
@@ -573,7 +612,7 @@ pe_status coarse_step(pe_problem p, int B, double* Xk, int n, int initial, const
     e2.ldg = (long)N * Dp;
     e2.initial = initial;
     e2.active = active;
-    PE_TRY(gemm<double>(p, g2, e2));
+    PE_TRY(gemm<double>(p, g2, e2, 0, PE_PROF_COARSE));
     return PE_OK;
 }
 
@@ -582,11 +621,13 @@ pe_status jumps(pe_problem p, int B, const double* Xk, const double* Xp, long ld
                 double* Jhost, double* norms_dev) {
     const int Dp = p->Dp;
     PE_HIP(jump_diff(Xk, Xp, ldXb, n0, nr, B, Dp, p->E, p->st));
-    PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp)));
-    PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, norms_dev, p->st));
+    PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp), 0,
+                        PE_PROF_NORM));
+    PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, norms_dev ? norms_dev : p->nrm, p->st));
     if (Jhost) {
         PE_HIP(hipMemcpyAsync(Jhost, p->Jd, sizeof(double) * B, hipMemcpyDeviceToHost, p->st));
         PE_HIP(hipStreamSynchronize(p->st));
+        PE_TRY(prof_collect(p));
     }
     return PE_OK;
 }
@@ -612,9 +653,34 @@ pe_status pe_problem_destroy(pe_problem p) {
     (void)hipStreamSynchronize(p->st);
     free_list(p->ws_allocs);
     free_list(p->op_allocs);
+    for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
     if (p->gw.part) (void)hipFree(p->gw.part);
-    if (p->gw.counters) (void)hipFree(p->gw.counters);
     delete p;
+    return PE_OK;
+}
+
+pe_status pe_profile(pe_problem p, int enable) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    PE_HIP(hipStreamSynchronize(p->st));
+    p->ev_pending.clear();
+    p->ev_used = 0;
+    for (int k = 0; k < PE_PROF_KINDS; ++k) {
+        p->prof_ms[k] = 0.0;
+        p->prof_n[k] = 0;
+    }
+    p->prof_on = enable ? 1 : 0;
+    return PE_OK;
+}
+
+pe_status pe_profile_read(pe_problem p, int kind, double* total_ms, long long* launches) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (kind < 0 || kind >= PE_PROF_KINDS) return fail(PE_ERR_ARG, "unknown profile kind");
+    PE_HIP(hipStreamSynchronize(p->st));
+    PE_TRY(prof_collect(p));
+    if (total_ms) *total_ms = p->prof_ms[kind];
+    if (launches) *launches = p->prof_n[kind];
     return PE_OK;
 }
 
@@ -883,6 +949,7 @@ pe_status pe_fine_propagate(pe_problem p, int B, const double* Xin, double* Y) {
     PE_TRY(fine_sweep(p, B, p->io, (long)p->N * p->Dp, p->Fbuf));
     PE_HIP(unpack_states(p->Fbuf, Y, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
     PE_HIP(hipStreamSynchronize(p->st));
+    PE_TRY(prof_collect(p));
     return PE_OK;
 }
 
@@ -924,7 +991,7 @@ pe_status pe_mass_norms(pe_problem p, int count, const double* X, double* out) {
     PE_HIP(pack_states(X, p->io, count, p->d1, p->d2, p->d1p, p->d2p, p->st));
     PE_HIP(jump_diff(p->io, nullptr, (long)Dp, 0, 1, count, Dp, p->E, p->st));
     PE_TRY(gemm<double>(p, shape(count, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp)));
-    PE_HIP(jump_reduce(p->E, p->Yn, count, 1, Dp, p->Jd, nullptr, p->st));
+    PE_HIP(jump_reduce(p->E, p->Yn, count, 1, Dp, p->Jd, p->nrm, p->st));
     PE_HIP(hipMemcpyAsync(out, p->Jd, sizeof(double) * count, hipMemcpyDeviceToHost, p->st));
     PE_HIP(hipStreamSynchronize(p->st));
     return PE_OK;
@@ -995,6 +1062,7 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
     }
     PE_HIP(unpack_states(p->Xk[cur], X, (long)B * (N + 1), p->d1, p->d2, p->d1p, p->d2p, p->st));
     PE_HIP(hipStreamSynchronize(p->st));
+    PE_TRY(prof_collect(p));
     return n_active > 0 ? PE_WARN_NOT_CONVERGED : PE_OK;
 }
 

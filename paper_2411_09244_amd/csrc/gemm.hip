@@ -6,9 +6,10 @@
 // (v_mfma_f32_16x16x4f32 for FP32, v_mfma_f64_16x16x4f64 for FP64).
 // Operand tiles are staged through LDS (BK deep, padded rows, register
 // prefetch of the next K tile). With split-K, every work-group writes its
-// partial tile to a workspace and the last one to arrive (atomic tile
-// counter) sums the partials in split order - a fixed order, so results are
-// bitwise reproducible - and runs the epilogue; it then resets the counter.
+// partial tile into the plane of its split; a second, element-parallel kernel
+// sums the planes in split order (a fixed order, so results are bitwise
+// reproducible) and runs the epilogue. Products with at most 4 state columns
+// (the coarse sweep) use a row-parallel GEMV kernel instead.
 #include "pe_internal.h"
 
 namespace pe {
@@ -127,8 +128,7 @@ __device__ inline void epilogue(const Epi& e, int r, int s, double acc) {
 template <typename T, int BR, int BS>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const Epi epi,
                                                       const int tiles_r, const int splitk,
-                                                      T* __restrict__ part,
-                                                      unsigned* __restrict__ counters) {
+                                                      T* __restrict__ part) {
     using Op = MfmaOp<T>;
     using acc_t = typename Op::acc_t;
     using vec_t = typename Op::vec_t;
@@ -144,7 +144,6 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
 
     __shared__ __align__(16) T As[BR * LDT];
     __shared__ __align__(16) T Bs[BS * LDT];
-    __shared__ int s_last;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -266,37 +265,69 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
         return;
     }
 
-    // split-K: publish the partial tile
-    T* mine = part + ((long)tile * splitk + split) * (BR * BS);
+    // split-K: write the partial tile into this split's plane (Mr x Ns)
+    T* plane = part + (long)split * sh.Mr * sh.Ns;
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < MJ; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int rl = wr * (BR / 2) + i * 16 + Op::row(lane, q);
-                const int sl = wsi * (BS / 2) + j * 16 + (lane & 15);
-                mine[rl * BS + sl] = acc[i][j][q];
+                const int r = r0 + wr * (BR / 2) + i * 16 + Op::row(lane, q);
+                const int s = s0 + wsi * (BS / 2) + j * 16 + (lane & 15);
+                if (r < sh.Mr && s < sh.Ns) plane[(long)r * sh.Ns + s] = acc[i][j][q];
             }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned prev = atomicAdd(&counters[tile], 1u);
-        s_last = (prev == (unsigned)(splitk - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const T* base = part + (long)tile * splitk * (BR * BS);
-    for (int e = tid; e < BR * BS; e += 256) {
-        const int rl = e / BS, sl = e % BS;
-        const int r = r0 + rl, s = s0 + sl;
-        if (r >= sh.Mr || s >= sh.Ns) continue;
+}
+
+// sum of the split-K planes in split order, then the epilogue; one thread per element
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_epilogue_kernel(const int Mr, const int Ns, const int splitk,
+                                                              const T* __restrict__ part, const Epi epi) {
+    const long total = (long)Mr * Ns;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
         double v = 0.0;
-        for (int sp = 0; sp < splitk; ++sp) v += (double)base[(long)sp * (BR * BS) + e];
+        for (int sp = 0; sp < splitk; ++sp) v += (double)part[(long)sp * total + i];
+        const int r = (int)(i / Ns), s = (int)(i - (long)r * Ns);
         epilogue(epi, r, s, v);
     }
-    if (tid == 0) counters[tile] = 0u;
+}
+
+// y[r][s] = sum_k A[r][k] B[s][k] for MR <= 4 state columns: one wave per
+// operator row, 16-byte loads along K, wave reduction, epilogue by lane 0
+template <typename T, int MR>
+__global__ __launch_bounds__(256) void gemv_kernel(const GemmShape sh, const Epi epi) {
+    using vec_t = typename MfmaOp<T>::vec_t;
+    constexpr int VW = 16 / sizeof(T);
+    const int lane = threadIdx.x & 63;
+    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= sh.Ns) return;
+    const int k0 = s < sh.s_split ? sh.k0a : sh.k0b;
+    const int k1 = s < sh.s_split ? sh.k1a : sh.k1b;
+    const T* __restrict__ B = (const T*)sh.B + (long)s * sh.ldb;
+    const T* __restrict__ A = (const T*)sh.A;
+    double acc[MR];
+#pragma unroll
+    for (int r = 0; r < MR; ++r) acc[r] = 0.0;
+    for (int k = k0 + VW * lane; k < k1; k += 64 * VW) {
+        const vec_t w = *(const vec_t*)(B + k);
+        const T* wp = (const T*)&w;
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            if (r < sh.Mr) {
+                const vec_t x = *(const vec_t*)(A + (long)r * sh.lda + k);
+                const T* xp = (const T*)&x;
+#pragma unroll
+                for (int q = 0; q < VW; ++q) acc[r] += (double)wp[q] * (double)xp[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+        for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int r = 0; r < MR; ++r)
+            if (r < sh.Mr) epilogue(epi, r, s, acc[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,13 +340,9 @@ static int k_extent(const GemmShape& sh) {
     return la > lb ? la : lb;
 }
 
-size_t gemm_n_tiles(const GemmShape& sh, const TileCfg& cfg) {
-    return (size_t)cdiv(sh.Mr, cfg.br) * cdiv(sh.Ns, cfg.bs);
-}
-
 size_t gemm_part_bytes(const GemmShape& sh, const TileCfg& cfg, size_t elem) {
-    if (cfg.splitk <= 1) return 0;
-    return gemm_n_tiles(sh, cfg) * (size_t)cfg.splitk * cfg.br * cfg.bs * elem;
+    if (cfg.splitk <= 1 || sh.Mr <= 4) return 0;
+    return (size_t)cfg.splitk * sh.Mr * sh.Ns * elem;
 }
 
 TileCfg choose_tiles(const GemmShape& sh, bool fp32, int n_cu) {
@@ -344,11 +371,29 @@ static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, Ge
     const int tr = cdiv(sh.Mr, BR), tsn = cdiv(sh.Ns, BS);
     dim3 grid(tr * tsn, splitk);
     if (splitk > 1) {
-        const size_t need = (size_t)tr * tsn * splitk * BR * BS * sizeof(T);
-        if (need > ws.part_bytes || (size_t)tr * tsn > ws.n_counters) return hipErrorInvalidValue;
+        const size_t need = (size_t)splitk * sh.Mr * sh.Ns * sizeof(T);
+        if (need > ws.part_bytes) return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL((gemm_nt_kernel<T, BR, BS>), grid, dim3(256), 0, stream, sh, epi, tr, splitk,
-                       (T*)ws.part, ws.counters);
+                       (T*)ws.part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || splitk == 1) return e;
+    const long total = (long)sh.Mr * sh.Ns;
+    long blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL((splitk_epilogue_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, stream, sh.Mr,
+                       sh.Ns, splitk, (const T*)ws.part, epi);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_gemv(const GemmShape& sh, const Epi& epi, hipStream_t stream) {
+    dim3 grid((unsigned)cdiv(sh.Ns, 4));
+    switch (sh.Mr) {
+        case 1: hipLaunchKernelGGL((gemv_kernel<T, 1>), grid, dim3(256), 0, stream, sh, epi); break;
+        case 2: hipLaunchKernelGGL((gemv_kernel<T, 2>), grid, dim3(256), 0, stream, sh, epi); break;
+        default: hipLaunchKernelGGL((gemv_kernel<T, 4>), grid, dim3(256), 0, stream, sh, epi); break;
+    }
     return hipGetLastError();
 }
 
@@ -361,6 +406,7 @@ hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, 
     if ((sh.lda % vw) || (sh.ldb % vw) || (sh.k0a % vw) || (sh.k0b % vw) || (sh.k1a % vw) ||
         (sh.k1b % vw) || (((uintptr_t)sh.A) % 16) || (((uintptr_t)sh.B) % 16))
         return hipErrorInvalidValue;
+    if (sh.Mr <= 4) return launch_gemv<T>(sh, epi, stream);
     const int sk = cfg.splitk < 1 ? 1 : cfg.splitk;
     if (cfg.br == 32 && cfg.bs == 64) return launch_cfg<T, 32, 64>(sh, epi, sk, ws, stream);
     if (cfg.br == 64 && cfg.bs == 64) return launch_cfg<T, 64, 64>(sh, epi, sk, ws, stream);

@@ -130,36 +130,42 @@ hipError_t jump_diff(const double* Xk, const double* Xp, long ldXb, int n0, int 
     return hipGetLastError();
 }
 
-// one work-group per sample; fixed reduction order (deterministic)
-__global__ void k_jump_reduce(const double* __restrict__ E, const double* __restrict__ Y, int nr,
-                              int Dp, double* __restrict__ J, double* __restrict__ norms) {
-    __shared__ double red[256];
-    const int b = blockIdx.x;
-    double jmax = 0.0;
+// one work-group per state row: norms[r] = sqrt(E_r . Y_r) (fixed order)
+__global__ __launch_bounds__(256) void k_row_norms(const double* __restrict__ E, const double* __restrict__ Y,
+                                                   int Dp, double* __restrict__ norms) {
+    __shared__ double red[4];
+    const long r = blockIdx.x;
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < Dp; s += 256) acc += E[r * Dp + s] * Y[r * Dp + s];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double q = (red[0] + red[1]) + (red[2] + red[3]);
+        norms[r] = (q == q && q < 1.7e308 && q > -1.7e308) ? sqrt(q > 0.0 ? q : 0.0) : __builtin_nan("");
+    }
+}
+
+// J[b] = max_j norms[b*nr + j] (NaN if any is NaN)
+__global__ void k_sample_max(const double* __restrict__ norms, int B, int nr, double* __restrict__ J) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double m = 0.0;
     bool bad = false;
     for (int j = 0; j < nr; ++j) {
-        const long r = (long)b * nr + j;
-        double acc = 0.0;
-        for (int s = threadIdx.x; s < Dp; s += blockDim.x) acc += E[r * Dp + s] * Y[r * Dp + s];
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        const double q = red[0];
-        __syncthreads();
-        if (!(q == q) || q > 1.7e308 || q < -1.7e308) bad = true;
-        const double nrm = sqrt(q > 0.0 ? q : 0.0);
-        if (norms && threadIdx.x == 0) norms[r] = nrm;
-        if (nrm > jmax) jmax = nrm;
+        const double v = norms[(long)b * nr + j];
+        if (!(v == v)) bad = true;
+        if (v > m) m = v;
     }
-    if (threadIdx.x == 0) J[b] = bad ? __builtin_nan("") : jmax;
+    J[b] = bad ? __builtin_nan("") : m;
 }
 
 hipError_t jump_reduce(const double* E, const double* Y, int B, int nr, int Dp, double* J, double* norms,
                        hipStream_t st) {
-    hipLaunchKernelGGL(k_jump_reduce, dim3(B), dim3(256), 0, st, E, Y, nr, Dp, J, norms);
+    hipLaunchKernelGGL(k_row_norms, dim3((unsigned)((long)B * nr)), dim3(256), 0, st, E, Y, Dp, norms);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sample_max, dim3((B + 63) / 64), dim3(64), 0, st, norms, B, nr, J);
     return hipGetLastError();
 }
 

@@ -83,12 +83,10 @@ struct TileCfg {
     int br = 64, bs = 64, splitk = 1;
 };
 
-// Workspace for split-K partial tiles and tile counters.
+// Workspace for split-K partial planes.
 struct GemmWork {
     void* part = nullptr;
     size_t part_bytes = 0;
-    unsigned* counters = nullptr;
-    size_t n_counters = 0;
 };
 
 // Launch C = epi(A * B^T) in precision T (float: FP32 MFMA, double: FP64
@@ -100,8 +98,7 @@ hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, 
 // Choose a tile configuration for a product of this shape.
 TileCfg choose_tiles(const GemmShape& sh, bool fp32, int n_cu);
 
-// Upper bound of workspace bytes/counters a launch with cfg needs.
+// Workspace bytes a launch with cfg needs.
 size_t gemm_part_bytes(const GemmShape& sh, const TileCfg& cfg, size_t elem);
-size_t gemm_n_tiles(const GemmShape& sh, const TileCfg& cfg);
 
 }  // namespace pe

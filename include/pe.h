@@ -85,7 +85,9 @@ enum {
  *               within 1e-9 relative, else PE_ERR_ARG.
  *   N           number of coarse intervals (>= 1).
  *   precision   PE_FP64 or PE_MIXED.
- *   hip_stream  hipStream_t for all work of this handle (NULL = default).
+ *   hip_stream  hipStream_t for all work of this handle. NULL: the handle
+ *               creates and owns a non-blocking stream (the caller then
+ *               orders its own producers/consumers by the blocking calls).
  * On the GPU: FP64 Cholesky factorisations of M11/dt_fine + A11,
  * M11/dt_coarse + A11 and M22 (PE_ERR_NOT_SPD names the block and pivot),
  * the inverses formed from the factors, and the step operators.
@@ -124,7 +126,10 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
  *   iters       host, B ints (nullable): iterations taken per sample.
  *   jump_hist   host, B x k_max doubles (nullable): max_n |x_n^k - x_n^{k-1}|_M
  *               for k = 1..k_max (unused entries 0).
- * Blocks until done; one scalar read-back per iteration.
+ * Blocks until done; one scalar read-back per iteration. After the first
+ * call for a given B, each sweep (fine sweep, coarse sweep + stopping-test
+ * products) is replayed from a captured HIP graph (PE_GRAPHS=0 in the
+ * environment at problem creation keeps every launch eager).
  * Returns PE_WARN_NOT_CONVERGED if some sample did not meet the test.
  */
 pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_mode,
@@ -176,6 +181,17 @@ pe_status pe_profile(pe_problem p, int enable);
  * Synchronises the handle's stream.
  */
 pe_status pe_profile_read(pe_problem p, int kind, double* total_ms, long long* launches);
+
+/*
+ * pe_autotune - choose the tile configuration (tile shape, K depth per LDS
+ * stage, split-K) of each product of the fine sweep and of the stopping test
+ * for B samples, by timing candidates on this problem's operands; the
+ * choices are kept in the handle (and appended to the file named by the
+ * environment variable PE_TUNE_CACHE, which later handles read back). The
+ * same happens lazily at the first use of a shape unless PE_AUTOTUNE=0.
+ * Results are bitwise reproducible for fixed configurations.
+ */
+pe_status pe_autotune(pe_problem p, int B);
 
 /* pe_problem_info - d1, d2, N, P (host ints, each nullable). */
 pe_status pe_problem_info(pe_problem p, int* d1, int* d2, int* N, int* P);

@@ -34,8 +34,12 @@ class Problem:
         self.dt, self.dt_fine = float(dt), float(dt_fine)
         self.precision = precision
         prec = {"fp64": L.PE_FP64, "mixed": L.PE_MIXED}[precision]
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of the problem's own (default priority), ordered after the
+        # caller's current stream at every call; every library call blocks
+        # until its work is done, so results are ready when it returns
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         t = {k: _dev(v, self.device) for k, v in blocks.items() if v is not None}
+        self._order()
         h = ctypes.c_void_p()
         st = L.check(self.lib.pe_problem_create(
             ctypes.byref(h), self.d1, self.d2, _ptr(t["M11"]), _ptr(t.get("M12")), _ptr(t["M22"]),
@@ -47,10 +51,14 @@ class Problem:
         self.P = P.value
         self.B = None
 
+    def _order(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
     def set_source(self, G, H, time_mode):
         """G: D x R projected spatial factors, H: B x R x T_len amplitudes."""
         G = None if G is None else _dev(G, self.device)
         H = None if H is None else _dev(H, self.device)
+        self._order()
         R = 0 if G is None else int(G.shape[1])
         B = 1 if H is None else int(H.shape[0])
         mode = {"fine": L.PE_T_FINE, "interval": L.PE_T_INTERVAL, 0: L.PE_T_FINE,
@@ -70,6 +78,7 @@ class Problem:
         iters = np.zeros(B, dtype=np.int32)
         hist = np.zeros((B, max(k_max, 1)), dtype=np.float64)
         mode = {"abs": L.PE_NORM_M_ABS, "rel": L.PE_NORM_M_REL}[norm]
+        self._order()
         st = L.check(self.lib.pe_solve(self.handle, B, _ptr(x0), float(tol), mode, k_max, _ptr(X),
                                        iters.ctypes.data_as(ctypes.c_void_p),
                                        hist.ctypes.data_as(ctypes.c_void_p)))
@@ -80,6 +89,7 @@ class Problem:
         Xin = _dev(Xin, self.device)
         B = Xin.shape[0]
         Y = torch.empty_like(Xin)
+        self._order()
         L.check(self.lib.pe_fine_propagate(self.handle, B, _ptr(Xin), _ptr(Y)))
         return Y
 
@@ -88,15 +98,22 @@ class Problem:
         Xin = _dev(Xin, self.device)
         B = Xin.shape[0]
         Y = torch.empty_like(Xin)
+        self._order()
         L.check(self.lib.pe_coarse_propagate(self.handle, B, _ptr(Xin), _ptr(Y)))
         return Y
 
     def mass_norms(self, X):
         X = _dev(X, self.device).reshape(-1, self.D)
         out = np.zeros(X.shape[0])
+        self._order()
         L.check(self.lib.pe_mass_norms(self.handle, X.shape[0], _ptr(X),
                                        out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def autotune(self, B=None):
+        """Time candidate tile configurations for the fine sweep (B samples)."""
+        self._order()
+        L.check(self.lib.pe_autotune(self.handle, int(B or self.B or 1)))
 
     def profile(self, enable=True):
         """Enable/disable per-launch HIP-event timing (resets totals)."""

@@ -24,8 +24,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pe.h"
@@ -64,6 +68,7 @@ struct pe_problem_s {
     double dt = 0, dtf = 0;
     int prec = PE_FP64;
     hipStream_t st = nullptr;
+    int own_stream = 0;  // st created by the handle (the caller passed NULL)
     int n_cu = 256;
 
     // operators (padded, row-major)
@@ -74,6 +79,8 @@ struct pe_problem_s {
     float* Wf32 = nullptr;
     float* Zf32 = nullptr;
     double* Zc64 = nullptr;  // Dp x Dp   coarse increment operator
+    double* PhiG64 = nullptr;  // Dp x Dp   coarse step matrix I - Z_dt A
+    float* PhiG32 = nullptr;
     // PE_MIXED: the fine sweep works in mass-whitened coordinates
     // x~ = Tin x, Tin = blkdiag(L1^T, L2^T) with M11 = L1 L1^T, M22 = L2 L2^T
     // (there M~11 = M~22 = I); x = Tout x~, Tout = Tin^-1; Linv = Tout^T
@@ -90,11 +97,14 @@ struct pe_problem_s {
     double* Fint = nullptr;  // (B*N) x Dp
     double* Gs_w = nullptr;    // whitened copies (PE_MIXED)
     double* Fint_w = nullptr;
+    double* CS = nullptr;      // (B*N) x Dp: Z_dt F(t_{n+1}), the coarse step's source term
 
     // iteration workspace (sized for B_cap samples)
     int B_cap = 0;
     double* Xk[2] = {nullptr, nullptr};  // B x (N+1) x Dp
-    double *Fbuf = nullptr, *Gold = nullptr, *Xa = nullptr, *Ya = nullptr, *R64 = nullptr;
+    double *Fbuf = nullptr, *Xa = nullptr, *Ya = nullptr, *R64 = nullptr;
+    double* Dl64[2] = {nullptr, nullptr};  // B x Dp: x_n^k - x_n^{k-1} along the coarse sweep
+    float* Dl32[2] = {nullptr, nullptr};
     double* dev64 = nullptr;
     float *dev32 = nullptr, *R32 = nullptr;
     double *E = nullptr, *Yn = nullptr, *Jd = nullptr, *x0p = nullptr, *io = nullptr, *nrm = nullptr;
@@ -109,6 +119,15 @@ struct pe_problem_s {
     std::vector<std::pair<int, size_t>> ev_pending;  // (kind, index of first event)
     double prof_ms[PE_PROF_KINDS] = {0};
     long long prof_n[PE_PROF_KINDS] = {0};
+
+    // autotuned tile configurations per product site and shape
+    int autotune = 1;
+    std::map<std::vector<int>, pe::TileCfg> tuned;
+
+    // captured HIP graphs of the sweeps, keyed by (kind, B, buffer parity)
+    int use_graphs = 1;
+    std::map<std::vector<long>, hipGraphExec_t> graphs;
+    std::set<std::vector<long>> graph_seen, graph_bad;
 
     std::vector<void*> op_allocs, ws_allocs;
 };
@@ -141,11 +160,14 @@ void free_list(std::vector<void*>& list) {
     list.clear();
 }
 
+void graphs_clear(pe_problem p);
+
 // grow the split-K workspace if a launch needs more (synchronises first)
 pe_status ensure_gemm_work(pe_problem p, size_t part_bytes) {
     GemmWork& w = p->gw;
     if (part_bytes <= w.part_bytes) return PE_OK;
     PE_HIP(hipStreamSynchronize(p->st));
+    graphs_clear(p);
     if (w.part) (void)hipFree(w.part);
     w.part = nullptr;
     w.part_bytes = 0;
@@ -190,11 +212,191 @@ pe_status prof_collect(pe_problem p) {
     return PE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// HIP graphs: a sweep's launches are recorded once (stream capture) and
+// replayed. The first visit of a key runs eagerly (autotuning, workspace
+// growth and any other synchronising work happen there); the second visit
+// captures. Graphs hold only kernel nodes (no memset nodes). Pointer changes
+// (workspace growth, a new source) drop every graph.
+// ---------------------------------------------------------------------------
+void graphs_clear(pe_problem p) {
+    for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    p->graphs.clear();
+    p->graph_seen.clear();
+    p->graph_bad.clear();
+}
+
+template <typename Fn>
+pe_status graph_run(pe_problem p, const std::vector<long>& key, Fn&& fn) {
+    if (!p->use_graphs || p->prof_on || p->graph_bad.count(key) || !p->st) return fn();
+    auto it = p->graphs.find(key);
+    if (it != p->graphs.end()) {
+        PE_HIP(hipGraphLaunch(it->second, p->st));
+        return PE_OK;
+    }
+    if (!p->graph_seen.count(key)) {
+        p->graph_seen.insert(key);
+        return fn();
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(p->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        p->use_graphs = 0;  // this stream cannot be captured: stay eager
+        return fn();
+    }
+    const pe_status s = fn();
+    const hipError_t e = hipStreamEndCapture(p->st, &g);
+    hipGraphExec_t ex = nullptr;
+    hipError_t ei = hipErrorUnknown;
+    if (s == PE_OK && e == hipSuccess && g) ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (s != PE_OK || e != hipSuccess || ei != hipSuccess) {
+        // not capturable: keep this sweep eager
+        (void)hipGetLastError();
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(p->st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+            hipGraph_t g2 = nullptr;
+            (void)hipStreamEndCapture(p->st, &g2);
+            if (g2) (void)hipGraphDestroy(g2);
+        }
+        p->graph_bad.insert(key);
+        g_err.clear();
+        return fn();
+    }
+    p->graphs[key] = ex;
+    PE_HIP(hipGraphLaunch(ex, p->st));
+    return PE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: time candidate tile configurations of a product on its real
+// operands (output to a scratch buffer, so no side effects) and keep the
+// fastest. Choices can be persisted in the text file named by PE_TUNE_CACHE
+// (one line per site: key fields then br bs bk2 splitk), which makes runs
+// that share the file use identical configurations (identical rounding).
+// ---------------------------------------------------------------------------
+std::vector<int> tune_key(int site, bool fp32, const GemmShape& sh) {
+    return {site, fp32 ? 1 : 0, sh.Mr, sh.Ns, sh.s_split, sh.k0a, sh.k1a, sh.k0b, sh.k1b};
+}
+
+void tune_cache_load(pe_problem p) {
+    const char* path = getenv("PE_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+        std::vector<int> v;
+        char* tok = strtok(line, " \t\n");
+        while (tok) {
+            v.push_back(atoi(tok));
+            tok = strtok(nullptr, " \t\n");
+        }
+        if (v.size() != 13) continue;
+        TileCfg c;
+        c.br = v[9];
+        c.bs = v[10];
+        c.bk2 = v[11];
+        c.splitk = v[12];
+        v.resize(9);
+        p->tuned[v] = c;
+    }
+    fclose(f);
+}
+
+void tune_cache_store(const std::vector<int>& key, const TileCfg& c) {
+    const char* path = getenv("PE_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    for (int x : key) fprintf(f, "%d ", x);
+    fprintf(f, "%d %d %d %d\n", c.br, c.bs, c.bk2, c.splitk);
+    fclose(f);
+}
+
+pe_status ensure_gemm_work(pe_problem p, size_t part_bytes);
+
 template <typename T>
-pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_splitk = 0, int kind = -1) {
+pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
+    const bool fp32 = sizeof(T) == 4;
+    *best_out = choose_tiles(sh, fp32, p->n_cu);
+    double* scratch = nullptr;
+    if (hipMalloc((void**)&scratch, sizeof(double) * sh.Mr * sh.Ns) != hipSuccess) return PE_OK;
+    hipEvent_t e0, e1;
+    PE_HIP(hipEventCreate(&e0));
+    PE_HIP(hipEventCreate(&e1));
+    Epi epi;
+    epi.mode = EPI_STORE;
+    epi.C = scratch;
+    epi.ldc = sh.Ns;
+    const int la = sh.k1a - sh.k0a, lb = sh.k1b - sh.k0b;
+    const int kext = std::max(la, lb);
+    const int bk0 = fp32 ? 32 : 16;
+    const int shapes[6][2] = {{32, 64}, {64, 32}, {64, 64}, {64, 128}, {128, 64}, {128, 128}};
+    double best = 1e30;
+    for (auto& rs : shapes) {
+        for (int bk2 = 0; bk2 < 2; ++bk2) {
+            const int bk = bk0 << bk2;
+            const int nkt = (kext + bk - 1) / bk;
+            const long tiles = (long)((sh.Mr + rs[0] - 1) / rs[0]) * ((sh.Ns + rs[1] - 1) / rs[1]);
+            for (int sk = 1; sk <= 32; sk *= 2) {
+                if (sk > 1 && (nkt / sk < 2 || tiles * sk > 4L * 2048)) break;
+                if (tiles > 2048 && sk > 1) break;
+                TileCfg c;
+                c.br = rs[0];
+                c.bs = rs[1];
+                c.bk2 = bk2;
+                c.splitk = sk;
+                const size_t need = gemm_part_bytes(sh, c, sizeof(T));
+                if (need > ((size_t)512 << 20)) continue;
+                PE_TRY(ensure_gemm_work(p, need));
+                if (gemm_launch<T>(sh, epi, c, p->gw, p->st) != hipSuccess) continue;
+                const int reps = 3;
+                PE_HIP(hipEventRecord(e0, p->st));
+                for (int i = 0; i < reps; ++i) PE_HIP(gemm_launch<T>(sh, epi, c, p->gw, p->st));
+                PE_HIP(hipEventRecord(e1, p->st));
+                PE_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                PE_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms / reps < best) {
+                    best = ms / reps;
+                    *best_out = c;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    if (getenv("PE_VERBOSE"))
+        fprintf(stderr, "[libpe] tuned %s Mr=%d Ns=%d K=%d: tile %dx%d bk2=%d splitk=%d (%.2f us)\n",
+                fp32 ? "f32" : "f64", sh.Mr, sh.Ns, kext, best_out->br, best_out->bs, best_out->bk2,
+                best_out->splitk, best * 1e3);
+    return PE_OK;
+}
+
+enum { SITE_NONE = -1, SITE_FINE_RES = 0, SITE_FINE_INC = 1, SITE_ANCHOR = 2, SITE_NORM = 3 };
+
+template <typename T>
+pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_splitk = 0, int kind = -1,
+               int site = SITE_NONE) {
     if (sh.Mr <= 0 || sh.Ns <= 0) return PE_OK;
     TileCfg cfg = choose_tiles(sh, sizeof(T) == 4, p->n_cu);
-    if (force_splitk > 0) cfg.splitk = force_splitk;
+    if (force_splitk > 0) {
+        cfg.splitk = force_splitk;
+    } else if (site != SITE_NONE && p->autotune && sh.Mr > 4) {
+        const std::vector<int> key = tune_key(site, sizeof(T) == 4, sh);
+        auto it = p->tuned.find(key);
+        if (it == p->tuned.end()) {
+            TileCfg c;
+            PE_TRY(tune<T>(p, sh, &c));
+            p->tuned[key] = c;
+            tune_cache_store(key, c);
+            cfg = c;
+        } else {
+            cfg = it->second;
+        }
+    }
     PE_TRY(ensure_gemm_work(p, gemm_part_bytes(sh, cfg, sizeof(T))));
     size_t slot;
     PE_TRY(prof_begin(p, kind, &slot));
@@ -457,13 +659,17 @@ pe_status whiten(pe_problem p, std::vector<void*>& tmp, const double* pM11, cons
 pe_status ensure_workspace(pe_problem p, int B) {
     if (B <= p->B_cap) return PE_OK;
     PE_HIP(hipStreamSynchronize(p->st));
+    graphs_clear(p);
     free_list(p->ws_allocs);
     const size_t N = p->N, Dp = p->Dp, Bs = B;
     auto& L = p->ws_allocs;
     PE_TRY(dalloc_t(p, L, &p->Xk[0], Bs * (N + 1) * Dp));
     PE_TRY(dalloc_t(p, L, &p->Xk[1], Bs * (N + 1) * Dp));
     PE_TRY(dalloc_t(p, L, &p->Fbuf, Bs * N * Dp));
-    PE_TRY(dalloc_t(p, L, &p->Gold, Bs * N * Dp));
+    for (int i = 0; i < 2; ++i) {
+        PE_TRY(dalloc_t(p, L, &p->Dl64[i], Bs * Dp));
+        PE_TRY(dalloc_t(p, L, &p->Dl32[i], Bs * Dp));
+    }
     PE_TRY(dalloc_t(p, L, &p->Xa, Bs * N * Dp));
     PE_TRY(dalloc_t(p, L, &p->Ya, Bs * N * Dp));
     PE_TRY(dalloc_t(p, L, &p->R64, Bs * N * Dp));
@@ -510,7 +716,7 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     if (!mixed) {
         PE_HIP(fine_init(Xsrc, ldXb, n_shift, p->Xa, p->dev64, nullptr, B, p->N, Dp, p->st));
         PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->A64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
-                            PE_PROF_ANCHOR));
+                            PE_PROF_ANCHOR, SITE_ANCHOR));
     } else {
         // anchors into whitened coordinates: Xa = Tin x (block diagonal)
         PE_HIP(fine_init(Xsrc, ldXb, n_shift, p->R64, p->dev64, p->dev32, B, p->N, Dp, p->st));
@@ -518,9 +724,9 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         gt.s_split = d1p;
         gt.k0b = d1p;
         gt.k1b = Dp;
-        PE_TRY(gemm<double>(p, gt, store_epi(p->Xa, Dp), 0, PE_PROF_ANCHOR));
+        PE_TRY(gemm<double>(p, gt, store_epi(p->Xa, Dp), 0, PE_PROF_ANCHOR, SITE_ANCHOR));
         PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->Aw64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
-                            PE_PROF_ANCHOR));
+                            PE_PROF_ANCHOR, SITE_ANCHOR));
     }
     const long ldS = 2L * Dp;
     for (int step = 0; step < p->P; ++step) {
@@ -547,9 +753,9 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         e1.p_step = step;
         const int k1 = step > 0 ? PE_PROF_FINE_RESIDUAL : PE_PROF_FINE_FIRST;
         if (mixed)
-            PE_TRY(gemm<float>(p, g1, e1, 0, k1));
+            PE_TRY(gemm<float>(p, g1, e1, 0, k1, SITE_FINE_RES));
         else
-            PE_TRY(gemm<double>(p, g1, e1, 0, k1));
+            PE_TRY(gemm<double>(p, g1, e1, 0, k1, SITE_FINE_RES));
 
         GemmShape g2 = shape(rows, Dp, mixed ? (const void*)p->R32 : (const void*)p->R64, Dp,
                              mixed ? (const void*)p->Zf32 : (const void*)p->Zf64, Dp, 0, d1p);
@@ -564,9 +770,9 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         e2.d1p = d1p;
         e2.d2p = d2p;
         if (mixed)
-            PE_TRY(gemm<float>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT));
+            PE_TRY(gemm<float>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT, SITE_FINE_INC));
         else
-            PE_TRY(gemm<double>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT));
+            PE_TRY(gemm<double>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT, SITE_FINE_INC));
     }
     if (!mixed) {
         PE_HIP(fine_final(p->Xa, p->dev64, Y, rows, Dp, d1p, accumulate ? 1 : 0, p->st));
@@ -578,51 +784,82 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         gt.k0b = d1p;
         gt.k1b = Dp;
         PE_TRY(gemm<double>(p, gt, store_epi(Y, Dp, 1.0, accumulate ? Y : nullptr, Dp, accumulate ? 1.0 : 0.0),
-                            0, PE_PROF_ANCHOR));
+                            0, PE_PROF_ANCHOR, SITE_ANCHOR));
     }
     return PE_OK;
 }
 
-// one coarse step of interval n for the B samples of Xk, with the parareal
-// correction (or the plain coarse value when initial)
-pe_status coarse_step(pe_problem p, int B, double* Xk, int n, int initial, const int* active) {
+// Coarse sweep. G is affine, G(x) = Phi_G x + c_n with Phi_G = I - Z_dt A and
+// c_n = Z_dt F(t_{n+1}), so the update of eq. (2.7),
+//     x_{n+1}^k = G(x_n^k) + F(x_n^{k-1}) - G(x_n^{k-1}),
+// is x_{n+1}^k = F(x_n^{k-1}) + Phi_G (x_n^k - x_n^{k-1}): one product per
+// coarse step, on the iterate change (FP32 in PE_MIXED: its rounding then
+// scales with the change). The initial sweep is x_{n+1}^0 = Phi_G x_n^0 + c_n.
+pe_status coarse_sweep_initial(pe_problem p, int B, double* Xk) {
     const int Dp = p->Dp, N = p->N;
     const long ldX = (long)(N + 1) * Dp;
-    Epi e1;
-    e1.mode = EPI_RESID;
-    e1.R64 = p->R64;
-    e1.ldr = Dp;
-    source_fields(p, e1);
-    e1.n_fixed = n;
-    e1.p_step = p->P - 1;
-    PE_TRY(gemm<double>(p, shape(B, Dp, Xk + (long)n * Dp, ldX, p->A64, Dp, 0, Dp), e1, 0, PE_PROF_COARSE));
-    GemmShape g2 = shape(B, Dp, p->R64, Dp, p->Zc64, Dp, 0, p->d1p);
-    g2.s_split = p->d1p;
-    g2.k0b = 0;
-    g2.k1b = Dp;
-    Epi e2;
-    e2.mode = EPI_COARSE;
-    e2.xin = Xk + (long)n * Dp;
-    e2.ldx = ldX;
-    e2.xout = Xk + (long)(n + 1) * Dp;
-    e2.ldxo = ldX;
-    e2.fbuf = p->Fbuf + (long)n * Dp;
-    e2.ldfb = (long)N * Dp;
-    e2.gold = p->Gold + (long)n * Dp;
-    e2.ldg = (long)N * Dp;
-    e2.initial = initial;
-    e2.active = active;
-    PE_TRY(gemm<double>(p, g2, e2, 0, PE_PROF_COARSE));
+    for (int n = 0; n < N; ++n) {
+        Epi e;
+        e.mode = EPI_COARSE_INIT;
+        e.xout = Xk + (long)(n + 1) * Dp;
+        e.ldxo = ldX;
+        e.cs = p->CS ? p->CS + (long)n * Dp : nullptr;
+        e.ldcs = (long)N * Dp;
+        PE_TRY(gemm<double>(p, shape(B, Dp, Xk + (long)n * Dp, ldX, p->PhiG64, Dp, 0, Dp), e, 0, PE_PROF_COARSE));
+    }
+    return PE_OK;
+}
+
+pe_status coarse_sweep_correct(pe_problem p, int B, double* Xk, const double* Xprev, const int* active) {
+    const int Dp = p->Dp, N = p->N;
+    const long ldX = (long)(N + 1) * Dp;
+    const bool mixed = p->prec == PE_MIXED;
+    int c = 0;
+    PE_HIP(zero_fill(mixed ? nullptr : p->Dl64[0], mixed ? p->Dl32[0] : nullptr, (long)B * Dp, p->st));
+    for (int n = 0; n < N; ++n) {
+        Epi e;
+        e.mode = EPI_COARSE_DELTA;
+        e.xout = Xk + (long)(n + 1) * Dp;
+        e.ldxo = ldX;
+        e.xprev = Xprev + (long)(n + 1) * Dp;
+        e.fbuf = p->Fbuf + (long)n * Dp;
+        e.ldfb = (long)N * Dp;
+        e.dl64 = mixed ? nullptr : p->Dl64[1 - c];
+        e.dl32 = mixed ? p->Dl32[1 - c] : nullptr;
+        e.ldl = Dp;
+        e.active = active;
+        if (mixed)
+            PE_TRY(gemm<float>(p, shape(B, Dp, p->Dl32[c], Dp, p->PhiG32, Dp, 0, Dp), e, 0, PE_PROF_COARSE));
+        else
+            PE_TRY(gemm<double>(p, shape(B, Dp, p->Dl64[c], Dp, p->PhiG64, Dp, 0, Dp), e, 0, PE_PROF_COARSE));
+        c = 1 - c;
+    }
     return PE_OK;
 }
 
 // J_b = max_{j < nr} |Xk[b][n0+j] - Xp[b][n0+j]|_M  (Xp null: plain norms)
+pe_status jumps_launch(pe_problem p, int B, const double* Xk, const double* Xp, long ldXb, int n0, int nr) {
+    const int Dp = p->Dp;
+    PE_HIP(jump_diff(Xk, Xp, ldXb, n0, nr, B, Dp, p->E, p->st));
+    PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp), 0,
+                        PE_PROF_NORM, SITE_NORM));
+    PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, p->nrm, p->st));
+    return PE_OK;
+}
+
+pe_status jumps_read(pe_problem p, int B, double* Jhost) {
+    PE_HIP(hipMemcpyAsync(Jhost, p->Jd, sizeof(double) * B, hipMemcpyDeviceToHost, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    PE_TRY(prof_collect(p));
+    return PE_OK;
+}
+
 pe_status jumps(pe_problem p, int B, const double* Xk, const double* Xp, long ldXb, int n0, int nr,
                 double* Jhost, double* norms_dev) {
     const int Dp = p->Dp;
     PE_HIP(jump_diff(Xk, Xp, ldXb, n0, nr, B, Dp, p->E, p->st));
     PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp), 0,
-                        PE_PROF_NORM));
+                        PE_PROF_NORM, SITE_NORM));
     PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, norms_dev ? norms_dev : p->nrm, p->st));
     if (Jhost) {
         PE_HIP(hipMemcpyAsync(Jhost, p->Jd, sizeof(double) * B, hipMemcpyDeviceToHost, p->st));
@@ -651,10 +888,12 @@ int pe_version(void) { return 100; }
 pe_status pe_problem_destroy(pe_problem p) {
     if (!p) return PE_OK;
     (void)hipStreamSynchronize(p->st);
+    graphs_clear(p);
     free_list(p->ws_allocs);
     free_list(p->op_allocs);
     for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
     if (p->gw.part) (void)hipFree(p->gw.part);
+    if (p->own_stream) (void)hipStreamDestroy(p->st);
     delete p;
     return PE_OK;
 }
@@ -682,6 +921,25 @@ pe_status pe_profile_read(pe_problem p, int kind, double* total_ms, long long* l
     if (total_ms) *total_ms = p->prof_ms[kind];
     if (launches) *launches = p->prof_n[kind];
     return PE_OK;
+}
+
+pe_status pe_autotune(pe_problem p, int B) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1) return fail(PE_ERR_ARG, "need B >= 1");
+    if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    PE_TRY(ensure_workspace(p, B));
+    const int save = p->autotune;
+    p->autotune = 1;
+    // one fine sweep and one stopping-test product on zero states visit every tuned site
+    PE_HIP(zero_fill(p->Xk[0], nullptr, (long)B * (p->N + 1) * p->Dp, p->st));
+    pe_status s = fine_sweep(p, B, p->Xk[0], (long)(p->N + 1) * p->Dp, p->Fbuf);
+    if (s == PE_OK) s = jumps(p, B, p->Xk[0], nullptr, (long)(p->N + 1) * p->Dp, 1, p->N, nullptr, nullptr);
+    p->autotune = save;
+    PE_HIP(hipStreamSynchronize(p->st));
+    p->ev_pending.clear();
+    p->ev_used = 0;
+    return s;
 }
 
 pe_status pe_problem_info(pe_problem p, int* d1, int* d2, int* N, int* P) {
@@ -724,6 +982,21 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
     p->dtf = dt_fine;
     p->prec = precision;
     p->st = (hipStream_t)hip_stream;
+    if (!p->st) {
+        // no stream given: the handle owns one (default priority, non-blocking)
+        if (hipStreamCreateWithFlags(&p->st, hipStreamNonBlocking) != hipSuccess) {
+            delete p;
+            return fail(PE_ERR_HIP, "stream creation failed");
+        }
+        p->own_stream = 1;
+    }
+    {
+        const char* at = getenv("PE_AUTOTUNE");
+        p->autotune = (at && at[0] == '0') ? 0 : 1;
+        const char* gr = getenv("PE_GRAPHS");
+        p->use_graphs = (gr && gr[0] == '0') ? 0 : 1;
+        tune_cache_load(p);
+    }
     int dev = 0;
     (void)hipGetDevice(&dev);
     int ncu = 0;
@@ -837,6 +1110,17 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
     // coarse operator (FP64) and fine operators
     CK(dalloc_t(p, OL, &p->Zc64, (size_t)Dp * Dp));
     CK(build_step_ops(p, dt_coarse, pM11, pM12, M22inv, pA11, pA12, pA21, pA22, p->Zc64, nullptr));
+    // coarse step matrix Phi_G = I - Z_dt A  (A symmetric: rows of A serve as columns)
+    CK(dalloc_t(p, OL, &p->PhiG64, (size_t)Dp * Dp));
+    {
+        Epi e = store_epi(p->PhiG64, Dp, -1.0);
+        e.diag_add = 1.0;
+        CK(gemm<double>(p, shape(Dp, Dp, p->Zc64, Dp, p->A64, Dp, 0, Dp), e));
+    }
+    if (precision == PE_MIXED) {
+        CK(dalloc_t(p, OL, &p->PhiG32, (size_t)Dp * Dp));
+        CKH(to_f32(p->PhiG64, p->PhiG32, (long)Dp * Dp, p->st));
+    }
     if (precision == PE_FP64) {
         CK(dalloc_t(p, OL, &p->Zf64, (size_t)Dp * Dp));
         CK(dalloc_t(p, OL, &p->Wf64, (size_t)Dp * 2 * Dp));
@@ -869,13 +1153,14 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
     if (R > 0 && (!G || !H)) return fail(PE_ERR_ARG, "G and H must be given when R > 0");
     if (time_mode == PE_T_FINE && R > 64) return fail(PE_ERR_ARG, "PE_T_FINE supports R <= 64");
     PE_HIP(hipStreamSynchronize(p->st));
-    for (void* v : {(void*)p->Gs, (void*)p->Hs, (void*)p->Fint, (void*)p->Gs_w, (void*)p->Fint_w}) {
+    graphs_clear(p);
+    for (void* v : {(void*)p->Gs, (void*)p->Hs, (void*)p->Fint, (void*)p->Gs_w, (void*)p->Fint_w, (void*)p->CS}) {
         if (!v) continue;
         auto it = std::find(p->op_allocs.begin(), p->op_allocs.end(), v);
         if (it != p->op_allocs.end()) p->op_allocs.erase(it);
         (void)hipFree(v);
     }
-    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = nullptr;
+    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = p->CS = nullptr;
     p->src_set = 1;
     p->B_src = B;
     p->R = R;
@@ -912,6 +1197,31 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
         p->src_kind = 2;
     } else {
         p->src_kind = 1;
+    }
+    {
+        // coarse source term c_n = Z_dt F(t_{n+1}) for every (sample, interval)
+        double* Fc = nullptr;
+        std::vector<void*> tmp;
+        PE_TRY(dalloc_t(p, tmp, &Fc, (size_t)B * p->N * Dp));
+        Epi e;
+        e.mode = EPI_RESID;
+        e.R64 = Fc;
+        e.ldr = Dp;
+        source_fields(p, e);
+        e.cols_per_b = p->N;
+        e.p_step = p->P - 1;
+        pe_status s = gemm<double>(p, shape(B * p->N, Dp, Fc, Dp, p->Zc64, Dp, 0, 0), e);
+        if (s == PE_OK) s = dalloc_t(p, p->op_allocs, &p->CS, (size_t)B * p->N * Dp);
+        if (s == PE_OK) {
+            GemmShape g = shape(B * p->N, Dp, Fc, Dp, p->Zc64, Dp, 0, p->d1p);
+            g.s_split = p->d1p;
+            g.k0b = 0;
+            g.k1b = Dp;
+            s = gemm<double>(p, g, store_epi(p->CS, Dp));
+        }
+        (void)hipStreamSynchronize(p->st);
+        free_list(tmp);
+        if (s < 0) return s;
     }
     if (p->prec == PE_MIXED) {
         // whitened source for the mixed fine sweep: F~ = Tout^T F = Linv F
@@ -1019,10 +1329,15 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
 
     int cur = 0;
     PE_HIP(pack_states(x0, p->x0p, B, p->d1, p->d2, p->d1p, p->d2p, p->st));
-    PE_HIP(set_x0(p->x0p, p->Xk[cur], ldX, B, Dp, p->st));
-    for (int n = 0; n < N; ++n) PE_TRY(coarse_step(p, B, p->Xk[cur], n, 1, nullptr));
-    if (norm_mode == PE_NORM_M_REL) {
-        PE_TRY(jumps(p, B, p->Xk[cur], nullptr, ldX, 0, N + 1, thr.data(), nullptr));
+    const long rel = norm_mode == PE_NORM_M_REL ? 1 : 0;
+    PE_TRY(graph_run(p, {0, B, rel}, [&]() -> pe_status {
+        PE_HIP(set_x0(p->x0p, p->Xk[0], ldX, B, Dp, p->st));
+        PE_TRY(coarse_sweep_initial(p, B, p->Xk[0]));
+        if (rel) PE_TRY(jumps_launch(p, B, p->Xk[0], nullptr, ldX, 0, N + 1));
+        return PE_OK;
+    }));
+    if (rel) {
+        PE_TRY(jumps_read(p, B, thr.data()));
         for (int b = 0; b < B; ++b) thr[b] *= tol;
     }
     int n_active = B;
@@ -1033,14 +1348,19 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
             // change (left in E by the previous jump test, rows n = 1..N) is
             // propagated without source and added to the stored F values, so
             // FP32 rounding scales with the change, not with the state.
-            PE_TRY(fine_sweep(p, B, p->E, (long)N * Dp, p->Fbuf, false, 1, true));
+            PE_TRY(graph_run(p, {1, B, 2},
+                             [&]() { return fine_sweep(p, B, p->E, (long)N * Dp, p->Fbuf, false, 1, true); }));
         } else {
-            PE_TRY(fine_sweep(p, B, p->Xk[cur], ldX, p->Fbuf));
+            PE_TRY(graph_run(p, {1, B, cur}, [&]() { return fine_sweep(p, B, p->Xk[cur], ldX, p->Fbuf); }));
         }
         if (n_active < B) PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, ldX, B, p->st));
-        PE_HIP(set_x0(p->x0p, p->Xk[nxt], ldX, B, Dp, p->st));
-        for (int n = 0; n < N; ++n) PE_TRY(coarse_step(p, B, p->Xk[nxt], n, 0, p->active_d));
-        PE_TRY(jumps(p, B, p->Xk[nxt], p->Xk[cur], ldX, 1, N, J.data(), nullptr));
+        PE_TRY(graph_run(p, {2, B, cur}, [&]() -> pe_status {
+            PE_HIP(set_x0(p->x0p, p->Xk[nxt], ldX, B, Dp, p->st));
+            PE_TRY(coarse_sweep_correct(p, B, p->Xk[nxt], p->Xk[cur], p->active_d));
+            PE_TRY(jumps_launch(p, B, p->Xk[nxt], p->Xk[cur], ldX, 1, N));
+            return PE_OK;
+        }));
+        PE_TRY(jumps_read(p, B, J.data()));
         cur = nxt;
         for (int b = 0; b < B; ++b) {
             if (!active[b]) continue;

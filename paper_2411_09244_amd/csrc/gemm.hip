@@ -107,14 +107,21 @@ __device__ inline void epilogue(const Epi& e, int r, int s, double acc) {
             }
             break;
         }
-        case EPI_COARSE: {
+        case EPI_COARSE_INIT: {
+            const int b = r;
+            double x = acc;
+            if (e.cs) x += e.cs[(long)b * e.ldcs + s];
+            e.xout[(long)b * e.ldxo + s] = x;
+            break;
+        }
+        case EPI_COARSE_DELTA: {
             const int b = r;
             if (e.active && !e.active[b]) break;
-            const double g = e.xin[(long)b * e.ldx + s] + acc;
-            double x = g;
-            if (!e.initial) x = g + (e.fbuf[(long)b * e.ldfb + s] - e.gold[(long)b * e.ldg + s]);
+            const double x = e.fbuf[(long)b * e.ldfb + s] + acc;
             e.xout[(long)b * e.ldxo + s] = x;
-            e.gold[(long)b * e.ldg + s] = g;
+            const double d = x - e.xprev[(long)b * e.ldxo + s];
+            if (e.dl64) e.dl64[(long)b * e.ldl + s] = d;
+            if (e.dl32) e.dl32[(long)b * e.ldl + s] = (float)d;
             break;
         }
         default:
@@ -125,14 +132,13 @@ __device__ inline void epilogue(const Epi& e, int r, int s, double acc) {
 // ---------------------------------------------------------------------------
 // kernel
 // ---------------------------------------------------------------------------
-template <typename T, int BR, int BS>
+template <typename T, int BR, int BS, int BK>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const Epi epi,
                                                       const int tiles_r, const int splitk,
                                                       T* __restrict__ part) {
     using Op = MfmaOp<T>;
     using acc_t = typename Op::acc_t;
     using vec_t = typename Op::vec_t;
-    constexpr int BK = Op::BK;
     constexpr int VW = 16 / sizeof(T);      // elements per 16-byte vector
     constexpr int LDT = BK + VW;            // padded LDS row (elements)
     constexpr int KV = BK / VW;             // vectors per tile row
@@ -140,10 +146,11 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
     constexpr int BV = BS * KV / 256;       // B vectors per thread
     constexpr int MI = BR / 32, MJ = BS / 32;
     static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
-    static_assert(BR % 32 == 0 && BS % 32 == 0, "tile must be a multiple of 32");
+    static_assert(BR % 32 == 0 && BS % 32 == 0 && BK % 16 == 0, "bad tile");
 
-    __shared__ __align__(16) T As[BR * LDT];
-    __shared__ __align__(16) T Bs[BS * LDT];
+    // two LDS stages: the next K tile is stored while the current one is used
+    __shared__ __align__(16) T As[2][BR * LDT];
+    __shared__ __align__(16) T Bs[2][BS * LDT];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -203,40 +210,45 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
                 rb[v] = vec_t{};
         }
     };
-    auto sstore = [&]() {
+    auto sstore = [&](int stage) {
 #pragma unroll
         for (int v = 0; v < AV; ++v) {
             const int idx = tid + v * 256;
             const int row = idx / KV, kk = (idx % KV) * VW;
-            *(vec_t*)(As + row * LDT + kk) = ra[v];
+            *(vec_t*)(&As[stage][row * LDT + kk]) = ra[v];
         }
 #pragma unroll
         for (int v = 0; v < BV; ++v) {
             const int idx = tid + v * 256;
             const int row = idx / KV, kk = (idx % KV) * VW;
-            *(vec_t*)(Bs + row * LDT + kk) = rb[v];
+            *(vec_t*)(&Bs[stage][row * LDT + kk]) = rb[v];
         }
     };
 
-    if (kt0 < kt1) gload(k0 + kt0 * BK);
+    int stage = 0;
+    if (kt0 < kt1) {
+        gload(k0 + kt0 * BK);
+        sstore(0);
+        __syncthreads();
+    }
     for (int kt = kt0; kt < kt1; ++kt) {
-        __syncthreads();
-        sstore();
-        __syncthreads();
-        if (kt + 1 < kt1) gload(k0 + (kt + 1) * BK);
+        const bool more = kt + 1 < kt1;
+        if (more) gload(k0 + (kt + 1) * BK);
+        const T* Asc = As[stage];
+        const T* Bsc = Bs[stage];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             T a[MI][4], b[MJ][4];
             const int koff = kk + 4 * (lane >> 4);
 #pragma unroll
             for (int i = 0; i < MI; ++i) {
-                const T* pa = As + (wr * (BR / 2) + i * 16 + (lane & 15)) * LDT + koff;
+                const T* pa = Asc + (wr * (BR / 2) + i * 16 + (lane & 15)) * LDT + koff;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) a[i][q] = pa[q];
             }
 #pragma unroll
             for (int j = 0; j < MJ; ++j) {
-                const T* pb = Bs + (wsi * (BS / 2) + j * 16 + (lane & 15)) * LDT + koff;
+                const T* pb = Bsc + (wsi * (BS / 2) + j * 16 + (lane & 15)) * LDT + koff;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) b[j][q] = pb[q];
             }
@@ -247,6 +259,9 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
 #pragma unroll
                     for (int j = 0; j < MJ; ++j) acc[i][j] = Op::mma(a[i][q], b[j][q], acc[i][j]);
         }
+        if (more) sstore(stage ^ 1);
+        __syncthreads();
+        stage ^= 1;
     }
 
     // output coordinates of this lane: 16x16 block (i, j), element q ->
@@ -365,7 +380,7 @@ TileCfg choose_tiles(const GemmShape& sh, bool fp32, int n_cu) {
     return c;
 }
 
-template <typename T, int BR, int BS>
+template <typename T, int BR, int BS, int BK>
 static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, GemmWork& ws,
                              hipStream_t stream) {
     const int tr = cdiv(sh.Mr, BR), tsn = cdiv(sh.Ns, BS);
@@ -374,7 +389,7 @@ static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, Ge
         const size_t need = (size_t)splitk * sh.Mr * sh.Ns * sizeof(T);
         if (need > ws.part_bytes) return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BR, BS>), grid, dim3(256), 0, stream, sh, epi, tr, splitk,
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BR, BS, BK>), grid, dim3(256), 0, stream, sh, epi, tr, splitk,
                        (T*)ws.part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || splitk == 1) return e;
@@ -408,11 +423,19 @@ hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, 
         return hipErrorInvalidValue;
     if (sh.Mr <= 4) return launch_gemv<T>(sh, epi, stream);
     const int sk = cfg.splitk < 1 ? 1 : cfg.splitk;
-    if (cfg.br == 32 && cfg.bs == 64) return launch_cfg<T, 32, 64>(sh, epi, sk, ws, stream);
-    if (cfg.br == 64 && cfg.bs == 64) return launch_cfg<T, 64, 64>(sh, epi, sk, ws, stream);
-    if (cfg.br == 64 && cfg.bs == 128) return launch_cfg<T, 64, 128>(sh, epi, sk, ws, stream);
-    if (cfg.br == 128 && cfg.bs == 64) return launch_cfg<T, 128, 64>(sh, epi, sk, ws, stream);
-    if (cfg.br == 128 && cfg.bs == 128) return launch_cfg<T, 128, 128>(sh, epi, sk, ws, stream);
+    constexpr int B0 = MfmaOp<T>::BK;  // base K depth: 32 (FP32), 16 (FP64)
+    const bool deep = cfg.bk2 != 0;
+#define PE_CFG(R, S)                                                                 \
+    if (cfg.br == R && cfg.bs == S)                                                  \
+        return deep ? launch_cfg<T, R, S, 2 * B0>(sh, epi, sk, ws, stream)           \
+                    : launch_cfg<T, R, S, B0>(sh, epi, sk, ws, stream);
+    PE_CFG(32, 64)
+    PE_CFG(64, 32)
+    PE_CFG(64, 64)
+    PE_CFG(64, 128)
+    PE_CFG(128, 64)
+    PE_CFG(128, 128)
+#undef PE_CFG
     return hipErrorInvalidValue;
 }
 

@@ -169,6 +169,19 @@ hipError_t jump_reduce(const double* E, const double* Y, int B, int nr, int Dp, 
     return hipGetLastError();
 }
 
+__global__ void k_zero(double* __restrict__ a, float* __restrict__ b, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        if (a) a[i] = 0.0;
+        if (b) b[i] = 0.0f;
+    }
+}
+
+hipError_t zero_fill(double* a, float* b, long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, grid1(n), dim3(256), 0, st, a, b, n);
+    return hipGetLastError();
+}
+
 // copy Xsrc[b] -> Xdst[b] for samples that stopped iterating
 __global__ void k_freeze(const double* __restrict__ Xsrc, double* __restrict__ Xdst,
                          const int* __restrict__ active, long ldXb, int B) {

@@ -29,7 +29,8 @@ enum EpiMode : int {
     EPI_STORE = 0,   // C = alpha*acc + beta*C0 (+ diag_add on r == s + diag_off)
     EPI_RESID = 1,   // R = f(t) - base - acc               (residual of a step)
     EPI_STEP = 2,    // increment -> state/history update    (fine step)
-    EPI_COARSE = 3,  // coarse step + parareal correction    (eq. (2.7))
+    EPI_COARSE_INIT = 3,   // initial coarse sweep: x_{n+1} = Phi_G x_n + c_n
+    EPI_COARSE_DELTA = 4,  // correction of eq. (2.7): x_{n+1}^k = F_n + Phi_G (x_n^k - x_n^{k-1})
 };
 
 struct Epi {
@@ -65,22 +66,24 @@ struct Epi {
     float* dev32 = nullptr;
     long ldd = 0;
     int d1p = 0, d2p = 0;
-    // EPI_COARSE
-    const double* xin = nullptr;
-    long ldx = 0;
-    double* xout = nullptr;
+    // EPI_COARSE_*  (column r is sample r)
+    double* xout = nullptr;         // X^k[b][n+1] = xout + b*ldxo
     long ldxo = 0;
-    const double* fbuf = nullptr;
+    const double* cs = nullptr;     // INIT: c_n = Z_dt F(t_{n+1}) at cs + b*ldcs (nullable)
+    long ldcs = 0;
+    const double* fbuf = nullptr;   // DELTA: F(x_n^{k-1}) at fbuf + b*ldfb
     long ldfb = 0;
-    double* gold = nullptr;
-    long ldg = 0;
-    int initial = 0;
+    const double* xprev = nullptr;  // DELTA: X^{k-1}[b][n+1] at xprev + b*ldxo
+    double* dl64 = nullptr;         // DELTA: next change x_{n+1}^k - x_{n+1}^{k-1} (b*ldl)
+    float* dl32 = nullptr;
+    long ldl = 0;
     const int* active = nullptr;
 };
 
 // Tile configuration of one GEMM launch.
 struct TileCfg {
     int br = 64, bs = 64, splitk = 1;
+    int bk2 = 0;  // 1: twice the base K depth per LDS stage
 };
 
 // Workspace for split-K partial planes.

@@ -17,6 +17,7 @@ hipError_t jump_reduce(const double* E, const double* Y, int B, int nr, int Dp, 
                        hipStream_t st);
 hipError_t freeze_inactive(const double* Xsrc, double* Xdst, const int* active, long ldXb, int B,
                            hipStream_t st);
+hipError_t zero_fill(double* a, float* b, long n, hipStream_t st);
 hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st);
 hipError_t place(double* dst, long ldd, int ro, int co, const double* src, long lds, int rows, int cols,
                  double scale, int trans, hipStream_t st);

@@ -31,6 +31,13 @@ METRIC = "parareal solves/sec to 1e-6 rel L2: batched FP32-MFMA+refine vs plain 
 PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6
 
+# HBM bytes per launch of the fine residual product, from two rocprofv3 --pmc
+# passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0: the factors a 256 MiB device
+# copy reads for the same counters), keyed by workload and the kernel's tile
+# configuration (state-tile rows, operator-tile rows, K depth, split-K).
+# Reported only when the timed run used that configuration.
+MEASURED_TRAFFIC = {("c1", (64, 32, 64, 8)): 2.0 * 15685.2 * 1024 + 1.0 * 4000.0 * 1024}
+
 
 def time_solves(pr, x0, tol, steps, warmup, torch):
     """Warm-up (includes the autotuner's first visit of each product shape),
@@ -83,6 +90,9 @@ def main():
     ap.add_argument("--config", default="c1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a kernel of known "
+                         "HBM traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
@@ -116,27 +126,50 @@ def main():
         setup = time.perf_counter() - ts
         dt, X, iters, hist, st, prof, dt_prof = time_solves(pr, x0, tol, args.steps, args.warmup, torch)
         res[prec] = dict(seconds=dt, X=X[0].cpu().numpy(), iters=int(iters[0]), status=st,
-                         setup=setup, prof=prof, seconds_profiled=dt_prof)
+                         setup=setup, prof=prof, seconds_profiled=dt_prof,
+                         tiles=pr.last_tiles("fine_residual"))
         log(f"{prec}: {args.steps} solves in {dt:.3f}s ({1e3 * dt / args.steps:.2f} ms/solve), "
             f"iterations {iters[0]}, set-up {setup:.2f}s; event-timed pass {1e3 * dt_prof / args.steps:.2f} ms/solve")
         log(f"{prec} launch timing: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in prof.items()))
         pr.close()
+
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written")
+        del a, b
 
     mixed = res["mixed"]
     ms_per_step = 1e3 * mixed["seconds"] / args.steps
     value = args.steps / mixed["seconds"]
 
     # roofline of the dominant kernel: the fine-step residual product
-    # R = F - A x_a - W dev, algorithmic 2*(d1^2 + 4 d1 d2 + d2^2) flops per column
+    # R = F - A x_a - W dev, algorithmic 2*(d1^2 + 4 d1 d2 + d2^2) flops per
+    # column (the scheme's products (i) and (iii)), N columns per launch. The
+    # product kernel is timed alone; its split-K reduction kernel (shared by
+    # both fine-step products) is reported beside it.
     ms_tot, n_launch = mixed["prof"]["fine_residual"]
+    ms_red, n_red = mixed["prof"]["splitk_reduce"]
     flops_per_launch = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + d2 * d2) * N
     avg_s = (ms_tot / n_launch) * 1e-3 if n_launch else float("nan")
+    avg_red = (ms_red / n_red) * 1e-3 if n_red else 0.0
     achieved = flops_per_launch / avg_s / 1e12
-    roofline = dict(kernel="gemm_nt_kernel<float> fine-step residual (W * dev, fused source/anchor epilogue)",
-                    bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP32_MFMA, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_MFMA, 5), traffic=None,
+    tiles = tuple(mixed["tiles"])
+    traffic = MEASURED_TRAFFIC.get((args.config, tiles))
+    roofline = dict(kernel="gemm_nt_kernel<float,%d,%d,%d> fine-step residual product (W * dev), split-K %d"
+                    % tiles, bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP32_MFMA, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP32_MFMA, 5),
+                    traffic=None if traffic is None else round(traffic),
                     avg_launch_us=round(avg_s * 1e6, 3), launches=n_launch,
-                    flops_per_launch=flops_per_launch)
+                    flops_per_launch=flops_per_launch,
+                    traffic_unit="bytes per launch (HBM, FETCH_SIZE+WRITE_SIZE, calibrated)",
+                    algorithmic_bytes=round((d1 * d1 + 4.0 * d1 * d2 + d2 * d2) * 4 + N * 2 * (d1 + d2) * 4),
+                    splitk_reduce_avg_us=round(avg_red * 1e6, 3),
+                    achieved_with_reduce=round(flops_per_launch / (avg_s + avg_red) / 1e12, 3))
 
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1,

@@ -164,14 +164,17 @@ enum {
     PE_PROF_ANCHOR = 3,         /* fine sweep anchors: A x_a and coordinate changes */
     PE_PROF_COARSE = 4,         /* coarse step + parareal correction              */
     PE_PROF_NORM = 5,           /* mass products of the stopping test             */
-    PE_PROF_KINDS = 6
+    PE_PROF_SPLITK_REDUCE = 6,  /* split-K reduction + epilogue kernels of the above */
+    PE_PROF_KINDS = 7
 };
 
 /*
  * pe_profile - enable (1) or disable (0) launch timing and reset the totals.
  * When enabled, every launch of the classes above is bracketed by a pair of
  * HIP events recorded on the handle's stream (GPU time from the start to
- * the end of that launch).
+ * the end of that launch); a product that splits K launches a second,
+ * reduction kernel, which is bracketed separately (PE_PROF_SPLITK_REDUCE).
+ * Sweeps then run with eager launches (no graph replay).
  */
 pe_status pe_profile(pe_problem p, int enable);
 
@@ -189,9 +192,19 @@ pe_status pe_profile_read(pe_problem p, int kind, double* total_ms, long long* l
  * choices are kept in the handle (and appended to the file named by the
  * environment variable PE_TUNE_CACHE, which later handles read back). The
  * same happens lazily at the first use of a shape unless PE_AUTOTUNE=0.
+ * Shapes listed in the read-only file named by PE_TUNE_DB (a database of
+ * configurations measured on MI355X) are not re-tuned.
  * Results are bitwise reproducible for fixed configurations.
  */
 pe_status pe_autotune(pe_problem p, int B);
+
+/*
+ * pe_last_tiles - tile configuration of the last product launched in class
+ * `kind` (PE_PROF_*): tiles4 = {rows of the state tile, rows of the operator
+ * tile, K depth per LDS stage, split-K count}; all 0 for the GEMV kernel or
+ * if the class has not run. tiles4: host, 4 ints.
+ */
+pe_status pe_last_tiles(pe_problem p, int kind, int* tiles4);
 
 /* pe_problem_info - d1, d2, N, P (host ints, each nullable). */
 pe_status pe_problem_info(pe_problem p, int* d1, int* d2, int* N, int* P);

@@ -5,6 +5,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpe.so")
+# tile configurations measured on MI355X for the shapes used here (read-only)
+TUNE_DB = os.path.join(HERE, "tune", "gfx950.txt")
 
 PE_OK = 0
 PE_WARN_NOT_CONVERGED = 1
@@ -23,11 +25,11 @@ PE_NORM_M_REL = 1
 
 # every entry point declared in include/pe.h
 EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate",
-           "pe_coarse_propagate", "pe_mass_norms", "pe_profile", "pe_profile_read", "pe_autotune",
+           "pe_coarse_propagate", "pe_mass_norms", "pe_profile", "pe_profile_read", "pe_autotune", "pe_last_tiles",
            "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
 PROFILE_KINDS = {"fine_residual": 0, "fine_increment": 1, "fine_first": 2, "anchor": 3,
-                 "coarse": 4, "norm": 5}
+                 "coarse": 4, "norm": 5, "splitk_reduce": 6}
 
 
 class PeError(RuntimeError):
@@ -46,6 +48,8 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2411_09244_amd.build` (hipcc, gfx950)")
+    if os.path.exists(TUNE_DB):
+        os.environ.setdefault("PE_TUNE_DB", TUNE_DB)
     lib = ctypes.CDLL(LIB_PATH)
     vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lib.pe_problem_create.argtypes = [ctypes.POINTER(vp), ci, ci, vp, vp, vp, vp, vp, vp, vp,
@@ -58,6 +62,7 @@ def load():
     lib.pe_problem_info.argtypes = [vp, vp, vp, vp, vp]
     lib.pe_profile.argtypes = [vp, ci]
     lib.pe_autotune.argtypes = [vp, ci]
+    lib.pe_last_tiles.argtypes = [vp, ci, vp]
     lib.pe_profile_read.argtypes = [vp, ci, vp, vp]
     lib.pe_problem_destroy.argtypes = [vp]
     lib.pe_last_error.restype = ctypes.c_char_p

@@ -129,6 +129,13 @@ class Problem:
             out[name] = (ms.value, n.value)
         return out
 
+    def last_tiles(self, kind="fine_residual"):
+        """(state-tile rows, operator-tile rows, K depth, split-K) of the last
+        launch of a product class."""
+        out = (ctypes.c_int * 4)()
+        L.check(self.lib.pe_last_tiles(self.handle, L.PROFILE_KINDS[kind], out))
+        return tuple(out)
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.pe_problem_destroy(self.handle)

@@ -120,6 +120,9 @@ struct pe_problem_s {
     double prof_ms[PE_PROF_KINDS] = {0};
     long long prof_n[PE_PROF_KINDS] = {0};
 
+    // tile configuration of the last launch of each profiled class
+    int last_cfg[PE_PROF_KINDS][4] = {{0}};
+
     // autotuned tile configurations per product site and shape
     int autotune = 1;
     std::map<std::vector<int>, pe::TileCfg> tuned;
@@ -271,16 +274,17 @@ pe_status graph_run(pe_problem p, const std::vector<long>& key, Fn&& fn) {
 // ---------------------------------------------------------------------------
 // autotuner: time candidate tile configurations of a product on its real
 // operands (output to a scratch buffer, so no side effects) and keep the
-// fastest. Choices can be persisted in the text file named by PE_TUNE_CACHE
-// (one line per site: key fields then br bs bk2 splitk), which makes runs
-// that share the file use identical configurations (identical rounding).
+// fastest. Choices are looked up first in the read-only database named by
+// PE_TUNE_DB and the cache named by PE_TUNE_CACHE (one line per site: key
+// fields then br bs bk2 splitk); new choices are appended to the cache.
+// Runs that share these files use identical configurations (identical
+// rounding).
 // ---------------------------------------------------------------------------
 std::vector<int> tune_key(int site, bool fp32, const GemmShape& sh) {
     return {site, fp32 ? 1 : 0, sh.Mr, sh.Ns, sh.s_split, sh.k0a, sh.k1a, sh.k0b, sh.k1b};
 }
 
-void tune_cache_load(pe_problem p) {
-    const char* path = getenv("PE_TUNE_CACHE");
+void tune_file_load(pe_problem p, const char* path) {
     if (!path || !*path) return;
     FILE* f = fopen(path, "r");
     if (!f) return;
@@ -302,6 +306,13 @@ void tune_cache_load(pe_problem p) {
         p->tuned[v] = c;
     }
     fclose(f);
+}
+
+// read-only database shipped with the library (PE_TUNE_DB), then the
+// read/append cache (PE_TUNE_CACHE); later entries override earlier ones
+void tune_cache_load(pe_problem p) {
+    tune_file_load(p, getenv("PE_TUNE_DB"));
+    tune_file_load(p, getenv("PE_TUNE_CACHE"));
 }
 
 void tune_cache_store(const std::vector<int>& key, const TileCfg& c) {
@@ -398,12 +409,38 @@ pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_spli
         }
     }
     PE_TRY(ensure_gemm_work(p, gemm_part_bytes(sh, cfg, sizeof(T))));
+    if (kind >= 0 && kind < PE_PROF_KINDS) {
+        const bool gemv = sh.Mr <= 4;
+        p->last_cfg[kind][0] = gemv ? 0 : cfg.br;
+        p->last_cfg[kind][1] = gemv ? 0 : cfg.bs;
+        p->last_cfg[kind][2] = gemv ? 0 : (sizeof(T) == 4 ? 32 : 16) << cfg.bk2;
+        p->last_cfg[kind][3] = gemv ? 0 : cfg.splitk;
+    }
     size_t slot;
     PE_TRY(prof_begin(p, kind, &slot));
+    // with split-K the reduction kernel is timed as its own class
+    struct Hook {
+        pe_problem p;
+        size_t slot;
+        pe_status st;
+    } hook{p, slot, PE_OK};
+    if (slot != (size_t)-1) {
+        p->gw.between = [](void* a) {
+            Hook* h = (Hook*)a;
+            size_t s2 = (size_t)-1;
+            h->st = prof_end(h->p, h->slot);
+            if (h->st == PE_OK) h->st = prof_begin(h->p, PE_PROF_SPLITK_REDUCE, &s2);
+            h->slot = s2;
+        };
+        p->gw.between_arg = &hook;
+    }
     hipError_t e = gemm_launch<T>(sh, epi, cfg, p->gw, p->st);
+    p->gw.between = nullptr;
+    p->gw.between_arg = nullptr;
     if (e != hipSuccess)
         return fail(PE_ERR_HIP, std::string("GEMM launch failed: ") + hipGetErrorString(e));
-    PE_TRY(prof_end(p, slot));
+    PE_TRY(hook.st);
+    PE_TRY(prof_end(p, hook.slot));
     return PE_OK;
 }
 
@@ -940,6 +977,14 @@ pe_status pe_autotune(pe_problem p, int B) {
     p->ev_pending.clear();
     p->ev_used = 0;
     return s;
+}
+
+pe_status pe_last_tiles(pe_problem p, int kind, int* tiles4) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (kind < 0 || kind >= PE_PROF_KINDS || !tiles4) return fail(PE_ERR_ARG, "bad arguments");
+    for (int i = 0; i < 4; ++i) tiles4[i] = p->last_cfg[kind][i];
+    return PE_OK;
 }
 
 pe_status pe_problem_info(pe_problem p, int* d1, int* d2, int* N, int* P) {

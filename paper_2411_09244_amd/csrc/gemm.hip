@@ -393,6 +393,7 @@ static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, Ge
                        (T*)ws.part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || splitk == 1) return e;
+    if (ws.between) ws.between(ws.between_arg);
     const long total = (long)sh.Mr * sh.Ns;
     long blocks = (total + 255) / 256;
     if (blocks > 8192) blocks = 8192;

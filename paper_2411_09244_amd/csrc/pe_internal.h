@@ -90,6 +90,10 @@ struct TileCfg {
 struct GemmWork {
     void* part = nullptr;
     size_t part_bytes = 0;
+    // optional hook run on the host between the product kernel and the
+    // split-K reduction kernel (used to place timing events)
+    void (*between)(void*) = nullptr;
+    void* between_arg = nullptr;
 };
 
 // Launch C = epi(A * B^T) in precision T (float: FP32 MFMA, double: FP64

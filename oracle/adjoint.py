@@ -3,12 +3,15 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 The forward map (x0, H) -> X = (X*_0, ..., X*_N), X*_{n+1} = F(X*_n) (the
-limit of parareal, eq. (2.7)), is linear in (x0, H) jointly. Given the
-cotangents Xbar_n = dL/dX*_n, the adjoint returns dL/dx0 and dL/dH by running
-the transpose of every fine step of eqs. (2.5)-(2.6) backward in time: the
-transposed implicit solve with M11/h + A11, the transposed explicit solve
-with M22, the history copies, and the fresh history at every interval start
-(whose transpose adds the history adjoint to the state adjoint there).
+limit of parareal, eq. (2.7)), is linear in (x0, H) jointly, and so is the
+map to every fine time level of that solution. Given the cotangents
+Xbar_n = dL/dX*_n at the coarse boundaries and, optionally, cotangents at
+the fine levels (a tracking term), the adjoint returns dL/dx0 and dL/dH by
+running the transpose of every fine step of eqs. (2.5)-(2.6) backward in
+time: the transposed implicit solve with M11/h + A11, the transposed
+explicit solve with M22, the history copies, and the fresh history at every
+interval start (whose transpose adds the history adjoint to the state
+adjoint there).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -45,39 +48,77 @@ def _step_adjoint(bl, h, ub, wb, upb, wpb):
     return u_b, w_b, up_b, wp_b, np.concatenate([F1_b, F2_b])
 
 
-def fine_propagator_adjoint(bl, lam):
+def fine_propagator_adjoint(bl, lam, inj=None):
     """Transpose of the linear part of F over one interval, plus the
     adjoints of the P step sources. lam: adjoint of F's output (D,) or
-    (D, ncol). Returns (adjoint of the interval-start state, list of the
-    source adjoints of steps p = 0..P-1)."""
+    (D, ncol). inj (optional, (P, D)): extra cotangents of the states after
+    steps p = 0..P-1 of the interval (inj[P-1] is at F's output). Returns
+    (adjoint of the interval-start state, list of the source adjoints of
+    steps p = 0..P-1)."""
     d1 = bl.d1
     ub, wb = lam[:d1].copy(), lam[d1:].copy()
     upb, wpb = np.zeros_like(ub), np.zeros_like(wb)
     srcb = [None] * bl.P
     for p in reversed(range(bl.P)):
+        if inj is not None:
+            ub += inj[p][:d1]
+            wb += inj[p][d1:]
         ub, wb, upb, wpb, fb = _step_adjoint(bl, bl.dt_fine, ub, wb, upb, wpb)
         srcb[p] = fb
     # fresh history at the interval start: u_p = u, w_p = w
     return np.concatenate([ub + upb, wb + wpb]), srcb
 
 
-def adjoint(bl, src, Xbar, b=0):
-    """Gradients of L with dL/dX*_n = Xbar[n] (n = 0..N) for sample b.
-    Returns (x0bar (D,), Hbar shaped like src.H[b] (R, T_len), lam (N+1, D))
-    where lam[n] is the adjoint of X*_n."""
-    N = bl.N
+def adjoint(bl, src, Xbar, b=0, Xbar_fine=None):
+    """Gradients of L with dL/dX*_n = Xbar[n] (n = 0..N) for sample b and,
+    if given, dL/dx_m = Xbar_fine[m] at the fine levels m = 0..N*P (x_m the
+    state at time m*dt_fine of the sequential fine solution; level n*P is
+    X*_n, level 0 is x0). Returns (x0bar (D,), Hbar shaped like src.H[b]
+    (R, T_len), lam (N+1, D)) where lam[n] = Xbar[n] + (transpose of F over
+    interval n, including that interval's fine-level cotangents) lam[n+1]."""
+    N, P = bl.N, bl.P
     lam = np.zeros((N + 1, bl.D))
     lam[N] = Xbar[N]
     R = 0 if src.G is None else src.G.shape[1]
     Hbar = np.zeros((R, src.H.shape[2])) if R else None
     for n in reversed(range(N)):
-        back, srcb = fine_propagator_adjoint(bl, lam[n + 1])
+        inj = None if Xbar_fine is None else Xbar_fine[n * P + 1:(n + 1) * P + 1]
+        back, srcb = fine_propagator_adjoint(bl, lam[n + 1], inj)
         lam[n] = Xbar[n] + back
         if R:
             for p, fb in enumerate(srcb):
                 tau = n * bl.P + p if src.mode == TIME_FINE else n
                 Hbar[:, tau] += src.G.T @ fb
-    return lam[0], Hbar, lam
+    x0bar = lam[0] if Xbar_fine is None else lam[0] + Xbar_fine[0]
+    return x0bar, Hbar, lam
+
+
+def fine_trajectory(bl, src, x0, b=0):
+    """Every fine time level of the sequential fine solution: row m is the
+    state at t = m dt_fine, m = 0..N*P (row n*P is X*_n). Each interval
+    starts with a fresh history, as F does."""
+    from .scheme import step
+    N, P, d1 = bl.N, bl.P, bl.d1
+    X = np.zeros((N * P + 1, bl.D))
+    X[0] = x0
+    for n in range(N):
+        u, w = X[n * P, :d1].copy(), X[n * P, d1:].copy()
+        u_prev, w_prev = u.copy(), w.copy()
+        for p in range(P):
+            u_new, w_new = step(bl, bl.dt_fine, u, w, u_prev, w_prev, src.at_fine(b, n, p))
+            u_prev, w_prev, u, w = u, w, u_new, w_new
+            X[n * P + p + 1] = np.concatenate([u, w])
+    return X
+
+
+def tracking_cotangents(bl, Y, beta):
+    """Cotangents of the fine-step tracking term
+        1/2 beta sum_{m=1}^{N*P} dt_fine |y_m|_M^2
+    of a fine trajectory y (rows m = 0..N*P): beta dt_fine M y_m, zero at
+    m = 0 (the initial level is not tracked)."""
+    Xf = beta * bl.dt_fine * (Y @ bl.M)
+    Xf[0] = 0.0
+    return Xf
 
 
 def forward_linear(bl, src_G, src_mode, x0, H):
@@ -87,13 +128,22 @@ def forward_linear(bl, src_G, src_mode, x0, H):
     return fine_composition(bl, s, x0, 0)
 
 
-def fd_check(bl, src_G, src_mode, x0, H, loss, grad_x0, grad_H, directions, h=1e-6):
+def forward_fine_linear(bl, src_G, src_mode, x0, H):
+    """Fine trajectory (N*P+1, D) with source amplitudes H for one sample."""
+    from .scheme import Source
+    s = Source(src_G, H[None], src_mode, bl.N, bl.P)
+    return fine_trajectory(bl, s, x0, 0)
+
+
+def fd_check(bl, src_G, src_mode, x0, H, loss, grad_x0, grad_H, directions, h=1e-6, fine=False):
     """Central differences of the scalar loss(X) along the given unit
-    directions (dx0, dH); returns (fd values, adjoint values)."""
+    directions (dx0, dH); X is the coarse-boundary solution, or the fine
+    trajectory if fine. Returns (fd values, adjoint values)."""
+    fwd = forward_fine_linear if fine else forward_linear
     fd, ad = [], []
     for dx0, dH in directions:
-        lp = loss(forward_linear(bl, src_G, src_mode, x0 + h * dx0, H + h * dH))
-        lm = loss(forward_linear(bl, src_G, src_mode, x0 - h * dx0, H - h * dH))
+        lp = loss(fwd(bl, src_G, src_mode, x0 + h * dx0, H + h * dH))
+        lm = loss(fwd(bl, src_G, src_mode, x0 - h * dx0, H - h * dH))
         fd.append((lp - lm) / (2 * h))
         ad.append(float(np.sum(dx0 * grad_x0) + (np.sum(dH * grad_H) if grad_H is not None else 0.0)))
     return np.array(fd), np.array(ad)

@@ -64,6 +64,91 @@ def time_solves(pr, x0, tol, steps, warmup, torch):
     return dt, X, iters, hist, st, prof, dt_prof
 
 
+ADJ_WORKLOAD = ("same medium and spaces as the forward workload; source sum_i theta_{i,n} 1_{K_i}(x) "
+                "1_{(t_n,t_{n+1}]}(t) over the 400 coarse elements (theta 400 x 64), loss "
+                "1/2 |x(T)-r(T)|_M^2 + 1/2 sum_m dt_fine |x_m-r_m|_M^2 against the trajectory r of "
+                "(theta_ref ~ N(0,1), x0_ref = 0), evaluated at theta_ref + 0.1 N(0,1), x0 = 0.1 N(0,1)/sqrt(D); "
+                "forward and transposed parareal to rel tol 1e-7")
+
+
+def adjoint_leg(args, torch, pe, build_problem, precs):
+    """Forward + adjoint workload: one step is a forward parareal solve of
+    the tracking error y = x - r (source theta - theta_ref, start x0: the
+    scheme is linear) and the transposed parareal with the terminal and
+    fine-step tracking cotangents (fine levels recomputed inside the
+    intervals), giving dL/dtheta and dL/dx0."""
+    import numpy as np
+    t0 = time.perf_counter()
+    p = build_problem("c3", verbose=False)
+    log(f"adjoint workload c3 built in {time.perf_counter() - t0:.1f}s")
+    d1, d2, N, P = p["d1"], p["d2"], p["N"], p["P"]
+    D = d1 + d2
+    rng = np.random.default_rng(3)
+    theta_ref = p["H"][0]
+    theta = theta_ref + 0.1 * rng.standard_normal(theta_ref.shape)
+    x0 = torch.tensor(0.1 * rng.standard_normal((1, D)) / np.sqrt(D), device="cuda")
+    dH = torch.tensor((theta - theta_ref)[None], device="cuda")
+    M = np.block([[p["M11"], p["M12"]], [p["M12"].T, p["M22"]]])
+    Mt = torch.tensor(M, device="cuda")
+    tol = 1e-7
+    out = {}
+    for prec in precs:
+        pr = pe.problem_from(dict(p, H=dH.cpu().numpy()), prec)
+
+        def step():
+            Y, itf, _, _ = pr.solve(x0, tol=tol, norm="rel")
+            Xbar = torch.zeros_like(Y)
+            Xbar[:, -1] = Y[:, -1] @ Mt
+            r = pr.adjoint(Xbar=Xbar, beta=1.0, Ybnd=Y, dH=dH, tol=tol)
+            return itf, r
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            itf, r = step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ts
+        pr.profile(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        prof = pr.profile_read()
+        pr.profile(False)
+        out[prec] = dict(seconds=dt, it_fwd=int(itf[0]), it_adj=int(r["iters"][0]), prof=prof,
+                         grad=np.concatenate([r["x0bar"].cpu().numpy().ravel(), r["Hbar"].cpu().numpy().ravel()]),
+                         tiles=pr.last_tiles("adj_state"))
+        log(f"adjoint {prec}: {args.steps} forward+adjoint solves in {dt:.3f}s, iterations fwd {itf[0]} "
+            f"adj {r['iters'][0]}; launch timing: " +
+            ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in prof.items() if v[1]))
+        pr.close()
+    mixed = out[precs[0]]
+    ms, n = mixed["prof"]["adj_state"]
+    flops = 4.0 * D * D * N
+    avg = (ms / n) * 1e-3 if n else float("nan")
+    res = {"workload": ADJ_WORKLOAD, "name": "c3", "metric": "forward+adjoint solves/s (gradient wrt theta, x0)",
+           "value": round(args.steps / mixed["seconds"], 4), "unit": "solves/s",
+           "ms_per_step": round(1e3 * mixed["seconds"] / args.steps, 4), "precision": precs[0],
+           "iterations": {"forward": mixed["it_fwd"], "adjoint": mixed["it_adj"]},
+           "roofline": dict(kernel="gemm_nt_kernel<%s,%d,%d,%d> adjoint state update ([A; A+Mh] rho), split-K %d"
+                            % (("float" if precs[0] == "mixed" else "double",) + tuple(mixed["tiles"])),
+                            bound="mfma", achieved=round(flops / avg / 1e12, 3),
+                            peak=PEAK_FP32_MFMA if precs[0] == "mixed" else PEAK_FP64_MFMA, unit="TFLOP/s",
+                            frac=round(flops / avg / 1e12 / (PEAK_FP32_MFMA if precs[0] == "mixed"
+                                                            else PEAK_FP64_MFMA), 5),
+                            traffic=None, avg_launch_us=round(avg * 1e6, 3), launches=n,
+                            flops_per_launch=flops)}
+    if len(precs) > 1:
+        f64 = out[precs[1]]
+        res["fp64"] = {"value": round(args.steps / f64["seconds"], 4), "unit": "solves/s",
+                       "iterations": {"forward": f64["it_fwd"], "adjoint": f64["it_adj"]}}
+        res["speedup_mixed_vs_fp64"] = round(f64["seconds"] / mixed["seconds"], 4)
+        res["grad_rel_diff_mixed_vs_fp64"] = float("%.3e" % (np.linalg.norm(mixed["grad"] - f64["grad"]) /
+                                                            np.linalg.norm(f64["grad"])))
+    return res
+
+
 def cpu_baseline(p, tol):
     """The FP64 oracle's plain parareal on the same workload, one solve."""
     import numpy as np
@@ -90,6 +175,7 @@ def main():
     ap.add_argument("--config", default="c1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
                          "HBM traffic, to scale hardware byte counters)")
@@ -193,6 +279,8 @@ def main():
             a64 = flops_per_launch / ((ms64 / n64) * 1e-3) / 1e12
             out["fp64"]["roofline"] = dict(bound="mfma", achieved=round(a64, 3), peak=PEAK_FP64_MFMA,
                                            unit="TFLOP/s", frac=round(a64 / PEAK_FP64_MFMA, 5))
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args, torch, pe, build_problem, ["mixed"] if args.no_fp64 else ["mixed", "fp64"])
     if not args.no_cpu_baseline:
         import oracle.scheme as S
         log("cpu baseline: FP64 oracle parareal on the host ...")

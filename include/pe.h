@@ -156,6 +156,56 @@ pe_status pe_coarse_propagate(pe_problem p, int B, const double* Xin, double* Y)
  */
 pe_status pe_mass_norms(pe_problem p, int count, const double* X, double* out);
 
+/*
+ * pe_adjoint - gradients of a loss L of the sequential fine solution (the
+ * limit of parareal, eq. (2.7)) with respect to the initial states and the
+ * source amplitudes. The transposed splitting scheme of eqs. (2.5)-(2.6) is
+ * run backward in time, itself parallel across the intervals by parareal:
+ *     lambda_N = Xbar_N,
+ *     lambda_n^k = Xbar_n + F_n^T lambda_{n+1}^{k-1}
+ *                  + Phi_G^T (lambda_{n+1}^k - lambda_{n+1}^{k-1}),
+ * with F_n^T the transposed fine propagator (every fine step transposed,
+ * forward states never needed: the scheme is linear) and Phi_G the linear
+ * part of the coarse step G. lambda_n is the adjoint of the state X_n.
+ *   B           samples (the B of the last pe_source_set when a source is set).
+ *   Xbar        device, B x (N+1) x D: dL/dX_n at the coarse boundaries
+ *               (nullable: zero).
+ *   beta        >= 0: weight of a fine-step tracking term
+ *                   1/2 beta sum_{m=1}^{N*P} dt_fine |y_m|_M^2
+ *               in L, where y is a trajectory of the scheme given by its
+ *               coarse-boundary states Ybnd and source amplitudes dH; its
+ *               fine levels are recomputed inside each interval from Ybnd
+ *               (for the tracking error x - x_ref of two solves of the same
+ *               problem, Ybnd = X - X_ref and dH = H - H_ref). 0: no term.
+ *   Ybnd        device, B x (N+1) x D (required when beta > 0, else unused).
+ *   dH          device, B x R x T_len in the layout of pe_source_set
+ *               (nullable: y has no source).
+ *   tol, k_max  stop when max_{n<N} |lambda_n^k - lambda_n^{k-1}|_2 <=
+ *               tol * max_n |lambda_n^0|_2 (Euclidean: lambda is a dual
+ *               vector), or after k_max <= N iterations (k_max = N gives the
+ *               exact transposed sequential solution).
+ *   x0bar       device, B x D out: dL/dx0 = lambda_0.
+ *   Hbar        device, B x R x T_len out (nullable): dL/dH for the
+ *               handle's G and time layout.
+ *   Lam         device, B x (N+1) x D out (nullable): lambda_n.
+ *   iters, jump_hist   host, as in pe_solve (nullable).
+ * Works independently of pe_solve (the loss's dependence on the forward
+ * solution enters only through Xbar and Ybnd). Returns
+ * PE_WARN_NOT_CONVERGED if some sample did not meet the test.
+ */
+pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const double* Ybnd,
+                     const double* dH, double tol, int k_max, double* x0bar, double* Hbar,
+                     double* Lam, int* iters, double* jump_hist);
+
+/*
+ * pe_tracking - the fine-step tracking term of pe_adjoint,
+ *     J_b = 1/2 beta sum_{m=1}^{N*P} dt_fine |y_m|_M^2,
+ * for the trajectory y with coarse-boundary states Ybnd (device,
+ * B x (N+1) x D) and source amplitudes dH (device, nullable), every fine
+ * level recomputed by the fine propagator. J: host, B doubles.
+ */
+pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH, double beta, double* J);
+
 /* launch classes timed by pe_profile */
 enum {
     PE_PROF_FINE_RESIDUAL = 0,  /* fine step, R = F - A x_a - W dev (steps 2..P)  */
@@ -165,7 +215,9 @@ enum {
     PE_PROF_COARSE = 4,         /* coarse step + parareal correction              */
     PE_PROF_NORM = 5,           /* mass products of the stopping test             */
     PE_PROF_SPLITK_REDUCE = 6,  /* split-K reduction + epilogue kernels of the above */
-    PE_PROF_KINDS = 7
+    PE_PROF_ADJ_RHO = 7,        /* transposed fine step, rho = Z^T nu                */
+    PE_PROF_ADJ_STATE = 8,      /* transposed fine step, adjoint state update        */
+    PE_PROF_KINDS = 9
 };
 
 /*

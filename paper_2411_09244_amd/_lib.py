@@ -25,11 +25,11 @@ PE_NORM_M_REL = 1
 
 # every entry point declared in include/pe.h
 EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate",
-           "pe_coarse_propagate", "pe_mass_norms", "pe_profile", "pe_profile_read", "pe_autotune", "pe_last_tiles",
-           "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
+           "pe_coarse_propagate", "pe_mass_norms", "pe_adjoint", "pe_tracking", "pe_profile", "pe_profile_read",
+           "pe_autotune", "pe_last_tiles", "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
 PROFILE_KINDS = {"fine_residual": 0, "fine_increment": 1, "fine_first": 2, "anchor": 3,
-                 "coarse": 4, "norm": 5, "splitk_reduce": 6}
+                 "coarse": 4, "norm": 5, "splitk_reduce": 6, "adj_rho": 7, "adj_state": 8}
 
 
 class PeError(RuntimeError):
@@ -59,6 +59,8 @@ def load():
     lib.pe_fine_propagate.argtypes = [vp, ci, vp, vp]
     lib.pe_coarse_propagate.argtypes = [vp, ci, vp, vp]
     lib.pe_mass_norms.argtypes = [vp, ci, vp, vp]
+    lib.pe_adjoint.argtypes = [vp, ci, vp, cd, vp, vp, cd, ci, vp, vp, vp, vp, vp]
+    lib.pe_tracking.argtypes = [vp, ci, vp, vp, cd, vp]
     lib.pe_problem_info.argtypes = [vp, vp, vp, vp, vp]
     lib.pe_profile.argtypes = [vp, ci]
     lib.pe_autotune.argtypes = [vp, ci]

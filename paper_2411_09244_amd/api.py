@@ -65,6 +65,9 @@ class Problem:
                 1: L.PE_T_INTERVAL}[time_mode]
         L.check(self.lib.pe_source_set(self.handle, B, R, _ptr(G), _ptr(H), mode))
         self.B = B
+        self.R = R
+        self.time_mode = mode
+        self.T_len = self.N * self.P if mode == L.PE_T_FINE else self.N
         self._src_keep = (G, H)
 
     def solve(self, x0, tol, norm="abs", k_max=None, out=None):
@@ -83,6 +86,40 @@ class Problem:
                                        iters.ctypes.data_as(ctypes.c_void_p),
                                        hist.ctypes.data_as(ctypes.c_void_p)))
         return X, iters, hist[:, :k_max], st
+
+    def adjoint(self, Xbar=None, beta=0.0, Ybnd=None, dH=None, tol=0.0, k_max=None, lam=False):
+        """Transposed parareal (pe_adjoint). Xbar: (B, N+1, D) cotangents at
+        the coarse boundaries; beta, Ybnd (B, N+1, D), dH (B, R, T_len): the
+        fine-step tracking term. Returns dict with x0bar (B, D), Hbar
+        (B, R, T_len) or None, lam (B, N+1, D) or None, iters, hist, status."""
+        Xbar = None if Xbar is None else _dev(Xbar, self.device).reshape(-1, self.N + 1, self.D)
+        Ybnd = None if Ybnd is None else _dev(Ybnd, self.device).reshape(-1, self.N + 1, self.D)
+        dH = None if dH is None else _dev(dH, self.device)
+        B = Xbar.shape[0] if Xbar is not None else (Ybnd.shape[0] if Ybnd is not None else (self.B or 1))
+        k_max = self.N if k_max is None else int(k_max)
+        x0bar = torch.empty((B, self.D), dtype=torch.float64, device=self.device)
+        R = getattr(self, "R", 0)
+        Hbar = torch.empty((B, R, self.T_len), dtype=torch.float64, device=self.device) if R else None
+        Lam = torch.empty((B, self.N + 1, self.D), dtype=torch.float64, device=self.device) if lam else None
+        iters = np.zeros(B, dtype=np.int32)
+        hist = np.zeros((B, max(k_max, 1)), dtype=np.float64)
+        self._order()
+        st = L.check(self.lib.pe_adjoint(self.handle, B, _ptr(Xbar), float(beta), _ptr(Ybnd), _ptr(dH),
+                                         float(tol), k_max, _ptr(x0bar), _ptr(Hbar), _ptr(Lam),
+                                         iters.ctypes.data_as(ctypes.c_void_p),
+                                         hist.ctypes.data_as(ctypes.c_void_p)))
+        return dict(x0bar=x0bar, Hbar=Hbar, lam=Lam, iters=iters, hist=hist[:, :k_max], status=st)
+
+    def tracking(self, Ybnd, dH=None, beta=1.0):
+        """J_b = 1/2 beta sum_m dt_fine |y_m|_M^2 over the fine levels of the
+        trajectory with boundary states Ybnd and source amplitudes dH."""
+        Ybnd = _dev(Ybnd, self.device).reshape(-1, self.N + 1, self.D)
+        dH = None if dH is None else _dev(dH, self.device)
+        J = np.zeros(Ybnd.shape[0])
+        self._order()
+        L.check(self.lib.pe_tracking(self.handle, Ybnd.shape[0], _ptr(Ybnd), _ptr(dH), float(beta),
+                                     J.ctypes.data_as(ctypes.c_void_p)))
+        return J
 
     def fine(self, Xin):
         """F applied to Xin (B, N, D) -> (B, N, D)."""
@@ -154,3 +191,55 @@ def problem_from(prob, precision="fp64", device="cuda"):
     pr = Problem(blocks, prob["dt"], prob["dt_fine"], prob["N"], precision=precision, device=device)
     pr.set_source(prob["G"], prob["H"], int(prob["time_mode"]))
     return pr
+
+
+class ParaSolve(torch.autograd.Function):
+    """X = parareal solution (B, N+1, D) for source amplitudes H (B, R, T_len)
+    on the spatial factors G and initial states x0 (B, D). The backward pass
+    runs the transposed parareal (pe_adjoint) with dL/dX as the boundary
+    cotangents and returns dL/dH and dL/dx0.
+
+    Usage: X = ParaSolve.apply(H, x0, problem, G, time_mode, tol, adj_tol)."""
+
+    @staticmethod
+    def forward(ctx, H, x0, problem, G, time_mode, tol, adj_tol):
+        problem.set_source(G, H.detach(), time_mode)
+        X, _, _, _ = problem.solve(x0.detach(), tol=tol, norm="rel")
+        ctx.problem, ctx.adj_tol = problem, adj_tol
+        return X
+
+    @staticmethod
+    def backward(ctx, dX):
+        r = ctx.problem.adjoint(Xbar=dX.contiguous(), tol=ctx.adj_tol)
+        return r["Hbar"], r["x0bar"], None, None, None, None, None
+
+
+class TrackedSolve(torch.autograd.Function):
+    """(X, J): the parareal solution for (H, x0) as in ParaSolve, and the
+    fine-step tracking term J_b = 1/2 beta sum_{m>=1} dt_fine |x_m - r_m|_M^2
+    against the reference trajectory r of (H_ref, x0_ref), given by its
+    boundary states X_ref (B, N+1, D). Both terms are differentiated by one
+    transposed parareal run.
+
+    Usage: X, J = TrackedSolve.apply(H, x0, problem, G, time_mode, H_ref,
+    X_ref, beta, tol, adj_tol)."""
+
+    @staticmethod
+    def forward(ctx, H, x0, problem, G, time_mode, H_ref, X_ref, beta, tol, adj_tol):
+        problem.set_source(G, H.detach(), time_mode)
+        X, _, _, _ = problem.solve(x0.detach(), tol=tol, norm="rel")
+        Y = (X - X_ref).contiguous()
+        dH = (H.detach() - H_ref).contiguous()
+        J = torch.as_tensor(problem.tracking(Y, dH, beta), device=X.device)
+        ctx.problem, ctx.adj_tol, ctx.beta = problem, adj_tol, beta
+        ctx.save_for_backward(Y, dH)
+        return X, J
+
+    @staticmethod
+    def backward(ctx, dX, dJ):
+        Y, dH = ctx.saved_tensors
+        # the tracking term is quadratic in y: its cotangent dJ_b scales y_b
+        w = dJ.to(torch.float64).reshape(-1, 1, 1)
+        r = ctx.problem.adjoint(Xbar=dX.contiguous(), beta=ctx.beta, Ybnd=(w * Y).contiguous(),
+                                dH=(w * dH).contiguous(), tol=ctx.adj_tol)
+        return r["Hbar"], r["x0bar"], None, None, None, None, None, None, None, None

@@ -88,6 +88,18 @@ struct pe_problem_s {
     double* Tin64 = nullptr;   // Dp x Dp
     double* Tout64 = nullptr;  // Dp x Dp
     double* Linv64 = nullptr;  // Dp x Dp
+    // adjoint (transposed) operators, in the fine sweep's precision and
+    // coordinates: Z^T of the fine step, Yop = [A; A + Mh] (2Dp x Dp, Mh the
+    // off-diagonal mass coupling over dt_fine), Phi_G^T; PE_MIXED also keeps
+    // Tin^T and the whitened mass
+    double* ZT64 = nullptr;
+    double* Yop64 = nullptr;
+    float* ZT32 = nullptr;
+    float* Yop32 = nullptr;
+    double* PhiGT64 = nullptr;
+    float* PhiGT32 = nullptr;
+    double* TinT64 = nullptr;
+    double* Mw64 = nullptr;
 
     // source
     int src_set = 0, B_src = 0, R = 0, Rp = 0, time_mode = 0, src_kind = 0;
@@ -98,6 +110,8 @@ struct pe_problem_s {
     double* Gs_w = nullptr;    // whitened copies (PE_MIXED)
     double* Fint_w = nullptr;
     double* CS = nullptr;      // (B*N) x Dp: Z_dt F(t_{n+1}), the coarse step's source term
+    double* GT = nullptr;      // Rp x Dp: G^T (source adjoint)
+    double* GwT = nullptr;     // Rp x Dp: whitened G^T (PE_MIXED)
 
     // iteration workspace (sized for B_cap samples)
     int B_cap = 0;
@@ -110,6 +124,12 @@ struct pe_problem_s {
     double *E = nullptr, *Yn = nullptr, *Jd = nullptr, *x0p = nullptr, *io = nullptr, *nrm = nullptr;
     int* active_d = nullptr;
     GemmWork gw;
+
+    // adjoint workspace (pe_adjoint / pe_tracking), sized for adj_B samples
+    int adj_B = 0, adj_Rp = 0, adj_traj = 0, adj_rho = 0, adj_fdh = 0;
+    double *S2 = nullptr, *Xb = nullptr, *Qb = nullptr, *Yb = nullptr, *Sacc = nullptr, *Hb = nullptr;
+    double *Rho = nullptr, *Ytraj = nullptr, *Inj = nullptr, *Fdh = nullptr, *Fdh_w = nullptr, *rowtmp = nullptr;
+    std::vector<void*> adj_allocs;
 
     // launch timing (pe_profile): HIP event pairs around each launch of a
     // kernel class, on the handle's stream
@@ -386,7 +406,16 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
     return PE_OK;
 }
 
-enum { SITE_NONE = -1, SITE_FINE_RES = 0, SITE_FINE_INC = 1, SITE_ANCHOR = 2, SITE_NORM = 3 };
+enum {
+    SITE_NONE = -1,
+    SITE_FINE_RES = 0,
+    SITE_FINE_INC = 1,
+    SITE_ANCHOR = 2,
+    SITE_NORM = 3,
+    SITE_ADJ_RHO = 4,
+    SITE_ADJ_STATE = 5,
+    SITE_TRAJ = 6
+};
 
 template <typename T>
 pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_splitk = 0, int kind = -1,
@@ -600,6 +629,21 @@ pe_status build_step_ops(pe_problem p, double h, const double* M11, const double
     return done(PE_OK);
 }
 
+// Second operator of the transposed fine step, Yop = [A; A + Mh] (2Dp x Dp):
+// A the full stiffness (Dp x Dp, symmetric) and Mh = [[0, M12/h], [M21/h, 0]]
+// the mass coupling of the history terms of eqs. (2.5)-(2.6). M12 is d1 x d2
+// with leading dimension ld12.
+pe_status build_adj_state_op(pe_problem p, const double* A, const double* M12, long ld12, double h, double* Y) {
+    const int d1 = p->d1, d2 = p->d2, d1p = p->d1p, Dp = p->Dp;
+    PE_HIP(place(Y, Dp, 0, 0, A, Dp, Dp, Dp, 1.0, 0, p->st));
+    PE_HIP(place(Y, Dp, Dp, 0, A, Dp, Dp, Dp, 1.0, 0, p->st));
+    if (d2 > 0) {
+        PE_HIP(place(Y, Dp, Dp, d1p, M12, ld12, d1, d2, 1.0 / h, 0, p->st, 1));
+        PE_HIP(place(Y, Dp, Dp + d1p, 0, M12, ld12, d2, d1, 1.0 / h, 1, p->st, 1));
+    }
+    return PE_OK;
+}
+
 // Mass-whitened blocks for the mixed fine sweep: with L1 L1^T = M11 and
 // L2 L2^T = M22 the change of variables u = L1^-T u~, w = L2^-T w~ gives
 // M~11 = M~22 = I, M~12 = L1^-1 M12 L2^-T, A~ij = Li^-1 Aij Lj^-T. The
@@ -726,6 +770,37 @@ pe_status ensure_workspace(pe_problem p, int B) {
     return PE_OK;
 }
 
+// Dense per-interval source table out[(b, n)][s] = sum_r G[s][r] H[b][r][n]
+// (H: B x R x N amplitudes on the handle's G); out_w (nullable) gets the
+// whitened copy Linv out.
+pe_status interval_table(pe_problem p, int B, const double* H, double* out, double* out_w) {
+    const int Dp = p->Dp, N = p->N, R = p->R, Rp = p->Rp;
+    double* Ht = nullptr;
+    std::vector<void*> tmp;
+    PE_TRY(dalloc_t(p, tmp, &Ht, (size_t)B * N * Rp));
+    pe_status s = PE_OK;
+    if (hipMemsetAsync(Ht, 0, sizeof(double) * B * N * Rp, p->st) != hipSuccess)
+        s = fail(PE_ERR_HIP, "memset failed");
+    for (int b = 0; b < B && s == PE_OK; ++b)
+        if (place(Ht + (long)b * N * Rp, Rp, 0, 0, H + (long)b * R * N, N, N, R, 1.0, 1, p->st) != hipSuccess)
+            s = fail(PE_ERR_HIP, "source transpose failed");
+    if (s == PE_OK) s = gemm<double>(p, shape(B * N, Dp, Ht, Rp, p->Gs, Rp, 0, Rp), store_epi(out, Dp));
+    if (s == PE_OK && out_w)
+        s = gemm<double>(p, shape(B * N, Dp, out, Dp, p->Linv64, Dp, 0, Dp), store_epi(out_w, Dp));
+    (void)hipStreamSynchronize(p->st);
+    free_list(tmp);
+    return s;
+}
+
+// source fields of a fine-sweep residual epilogue; sv (nullable) replaces
+// the handle's amplitudes (same G, same time layout)
+struct SrcView {
+    int kind = 0;
+    const double* Hs = nullptr;
+    const double* Fint = nullptr;
+    const double* Fint_w = nullptr;
+};
+
 void source_fields(pe_problem p, Epi& e, bool whitened = false) {
     e.src_kind = p->src_set ? p->src_kind : 0;
     e.Gs = whitened ? p->Gs_w : p->Gs;
@@ -745,18 +820,22 @@ void source_fields(pe_problem p, Epi& e, bool whitened = false) {
 // F on B*N columns: anchors Xsrc[b][n - n_shift] (row stride ldXb per sample,
 // zero for n < n_shift) -> Y (B*N x Dp). Without the source this is the
 // homogeneous propagator; with accumulate the result is added to Y.
+// sv (nullable) replaces the source amplitudes; traj (nullable) receives the
+// state after every fine step, row (b*N + n)*P + p (in the sweep's
+// coordinates: whitened in PE_MIXED).
 pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double* Y, bool with_source = true,
-                     int n_shift = 0, bool accumulate = false) {
+                     int n_shift = 0, bool accumulate = false, const SrcView* sv = nullptr,
+                     double* traj = nullptr) {
     const int Dp = p->Dp, d1p = p->d1p, d2p = p->d2p;
     const int rows = B * p->N;
     const bool mixed = p->prec == PE_MIXED;
     if (!mixed) {
-        PE_HIP(fine_init(Xsrc, ldXb, n_shift, p->Xa, p->dev64, nullptr, B, p->N, Dp, p->st));
+        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->Xa, p->dev64, nullptr, B, p->N, Dp, p->st));
         PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->A64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
                             PE_PROF_ANCHOR, SITE_ANCHOR));
     } else {
         // anchors into whitened coordinates: Xa = Tin x (block diagonal)
-        PE_HIP(fine_init(Xsrc, ldXb, n_shift, p->R64, p->dev64, p->dev32, B, p->N, Dp, p->st));
+        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->R64, p->dev64, p->dev32, B, p->N, Dp, p->st));
         GemmShape gt = shape(rows, Dp, p->R64, Dp, p->Tin64, Dp, 0, d1p);
         gt.s_split = d1p;
         gt.k0b = d1p;
@@ -784,6 +863,11 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         e1.base = p->Ya;
         e1.ldb = Dp;
         source_fields(p, e1, mixed);
+        if (sv) {
+            e1.src_kind = sv->kind;
+            e1.Hs = sv->Hs;
+            e1.Fint = mixed ? sv->Fint_w : sv->Fint;
+        }
         if (!with_source) e1.src_kind = 0;
         e1.cols_per_b = p->N;
         e1.n_fixed = -1;
@@ -806,6 +890,11 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         e2.ldd = ldS;
         e2.d1p = d1p;
         e2.d2p = d2p;
+        if (traj) {
+            e2.traj = traj + (long)step * Dp;
+            e2.ldtraj = (long)p->P * Dp;
+            e2.xa = p->Xa;
+        }
         if (mixed)
             PE_TRY(gemm<float>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT, SITE_FINE_INC));
         else
@@ -906,6 +995,219 @@ pe_status jumps(pe_problem p, int B, const double* Xk, const double* Xp, long ld
     return PE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+// The transposed fine step. With the step state s = [du_prev | u | w | dw_prev]
+// and the step written as R = F - W s, d = Z R, s' = [du, u + du, w + dw, dw],
+// the adjoint of s' maps back through
+//     rho = Z^T nu,   a <- a - A rho,   nu <- a - (A + Mh) rho,
+// where a is the adjoint of (u, w), nu = a + (adjoint of the history), rho the
+// adjoint of the step's source F, and Mh = [[0, M12/h], [M21/h, 0]]. At the
+// interval end a = nu = lambda (the history is not an output); at the start
+// the fresh history does not depend on the state, so F^T lambda = a there.
+// A cotangent of an intermediate state adds to both a and nu.
+
+pe_status ensure_adj_workspace(pe_problem p, int B, bool traj, bool rho, bool fdh) {
+    const bool grow = B > p->adj_B || std::max(p->Rp, 1) > p->adj_Rp || (traj && !p->adj_traj) ||
+                      (rho && !p->adj_rho) || (fdh && !p->adj_fdh);
+    if (!grow) return PE_OK;
+    B = std::max(B, p->adj_B);
+    traj = traj || p->adj_traj;
+    rho = rho || p->adj_rho;
+    fdh = fdh || p->adj_fdh;
+    PE_HIP(hipStreamSynchronize(p->st));
+    graphs_clear(p);
+    free_list(p->adj_allocs);
+    p->S2 = p->Xb = p->Qb = p->Yb = p->Sacc = p->Hb = p->Rho = p->Ytraj = p->Inj = p->Fdh = p->Fdh_w = p->rowtmp =
+        nullptr;
+    p->adj_B = p->adj_Rp = p->adj_traj = p->adj_rho = p->adj_fdh = 0;
+    const size_t N = p->N, P = p->P, Dp = p->Dp, Bs = B, Rp = std::max(p->Rp, 1);
+    auto& L = p->adj_allocs;
+    PE_TRY(dalloc_t(p, L, &p->S2, Bs * N * 2 * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Xb, Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Qb, Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Yb, Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Sacc, Bs * N * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Hb, Bs * N * (rho ? P : 1) * Rp));
+    if (rho) PE_TRY(dalloc_t(p, L, &p->Rho, Bs * N * P * Dp));
+    if (traj) {
+        PE_TRY(dalloc_t(p, L, &p->Ytraj, Bs * N * P * Dp));
+        PE_TRY(dalloc_t(p, L, &p->Inj, Bs * N * P * Dp));
+        PE_TRY(dalloc_t(p, L, &p->rowtmp, Bs * N * P));
+    }
+    if (fdh) {
+        PE_TRY(dalloc_t(p, L, &p->Fdh, Bs * N * Dp));
+        if (p->prec == PE_MIXED) PE_TRY(dalloc_t(p, L, &p->Fdh_w, Bs * N * Dp));
+    }
+    p->adj_B = B;
+    p->adj_Rp = (int)Rp;
+    p->adj_traj = traj;
+    p->adj_rho = rho;
+    p->adj_fdh = fdh;
+    return PE_OK;
+}
+
+// Y[b][n] (+)= F_n^T lam[b][n+1] on all B*N intervals, lam rows read from L
+// (sample stride ldLb; row n+1 taken when n+1 < nvalid, else zero), plus the
+// transposed steps applied to the fine-level cotangents inj (nullable; row
+// (b*N + n)*P + p is the cotangent of the state after step p). srcadj: 0 no
+// source adjoint, 1 sum rho over the steps into Sacc, 2 every rho into Rho.
+pe_status fine_adjoint_sweep(pe_problem p, int B, const double* L, long ldLb, int nvalid, const double* inj,
+                             double* Y, bool accumulate, int srcadj) {
+    const int Dp = p->Dp, d1p = p->d1p, P = p->P, N = p->N;
+    const int rows = B * N;
+    const long ldS = 2L * Dp;
+    const bool mixed = p->prec == PE_MIXED;
+    float* nu32 = mixed ? p->dev32 : nullptr;
+    PE_HIP(fine_init(L, ldLb, 1, nvalid, p->Xa, p->dev64, nullptr, B, N, Dp, p->st));
+    const double* lam0 = p->Xa;
+    if (mixed) {
+        // lambda~ = Tout^T lambda = Linv lambda (block diagonal)
+        GemmShape gt = shape(rows, Dp, p->Xa, Dp, p->Linv64, Dp, 0, d1p);
+        gt.s_split = d1p;
+        gt.k0b = d1p;
+        gt.k1b = Dp;
+        PE_TRY(gemm<double>(p, gt, store_epi(p->R64, Dp), 0, PE_PROF_ANCHOR, SITE_ANCHOR));
+        lam0 = p->R64;
+    }
+    const long ldinj = (long)P * Dp;
+    PE_HIP(adj_init(lam0, inj ? inj + (long)(P - 1) * Dp : nullptr, ldinj, p->dev64, nu32, rows, Dp, p->st));
+    if (srcadj == 1) PE_HIP(zero_fill(p->Sacc, nullptr, (long)rows * Dp, p->st));
+    double* Sb[2] = {p->dev64, p->S2};
+    int c = 0;
+    for (int step = P - 1; step >= 0; --step) {
+        // rho = Z^T nu: u-rows of Z^T use K over [0, Dp), w-rows [d1p, Dp)
+        GemmShape g1 = shape(rows, Dp, mixed ? (const void*)nu32 : (const void*)(Sb[c] + Dp), mixed ? Dp : ldS,
+                             mixed ? (const void*)p->ZT32 : (const void*)p->ZT64, Dp, 0, Dp);
+        g1.s_split = d1p;
+        g1.k0b = d1p;
+        g1.k1b = Dp;
+        Epi e1;
+        e1.mode = EPI_ADJ_RHO;
+        e1.R64 = mixed ? nullptr : p->R64;
+        e1.R32 = mixed ? p->R32 : nullptr;
+        e1.ldr = Dp;
+        e1.sacc = srcadj == 1 ? p->Sacc : nullptr;
+        e1.rho_all = srcadj == 2 ? p->Rho : nullptr;
+        e1.P = P;
+        e1.m_step = step;
+        if (mixed)
+            PE_TRY(gemm<float>(p, g1, e1, 0, PE_PROF_ADJ_RHO, SITE_ADJ_RHO));
+        else
+            PE_TRY(gemm<double>(p, g1, e1, 0, PE_PROF_ADJ_RHO, SITE_ADJ_RHO));
+        // [a; nu] <- a - [A; A + Mh] rho (+ cotangent of the state before this step)
+        GemmShape g2 = shape(rows, 2 * Dp, mixed ? (const void*)p->R32 : (const void*)p->R64, Dp,
+                             mixed ? (const void*)p->Yop32 : (const void*)p->Yop64, Dp, 0, Dp);
+        Epi e2;
+        e2.mode = EPI_ADJ_STATE;
+        e2.ldr = Dp;
+        e2.s_cur = Sb[c];
+        e2.s_nxt = Sb[1 - c];
+        e2.nu32 = nu32;
+        if (inj && step > 0) {
+            e2.inj = inj + (long)(step - 1) * Dp;
+            e2.ldinj = ldinj;
+        }
+        if (mixed)
+            PE_TRY(gemm<float>(p, g2, e2, 0, PE_PROF_ADJ_STATE, SITE_ADJ_STATE));
+        else
+            PE_TRY(gemm<double>(p, g2, e2, 0, PE_PROF_ADJ_STATE, SITE_ADJ_STATE));
+        c = 1 - c;
+    }
+    if (!mixed) {
+        PE_HIP(take_a(Sb[c], Y, rows, Dp, accumulate ? 1 : 0, p->st));
+    } else {
+        // back to the caller's coordinates: Y (+)= Tin^T a~
+        GemmShape gt = shape(rows, Dp, Sb[c], ldS, p->TinT64, Dp, 0, d1p);
+        gt.s_split = d1p;
+        gt.k0b = d1p;
+        gt.k1b = Dp;
+        PE_TRY(gemm<double>(p, gt, store_epi(Y, Dp, 1.0, accumulate ? Y : nullptr, Dp, accumulate ? 1.0 : 0.0),
+                            0, PE_PROF_ANCHOR, SITE_ANCHOR));
+    }
+    return PE_OK;
+}
+
+// Backward coarse sweeps on lambda (B x (N+1) x Dp, row N fixed):
+// initial  lam_n = cs_n + Phi_G^T lam_{n+1}, lam_N = cs_N;
+// correction  lam_n^k = Fbuf_n + Phi_G^T (lam_{n+1}^k - lam_{n+1}^{k-1}).
+pe_status coarse_adj_initial(pe_problem p, int B, double* Lk, const double* cs) {
+    const int Dp = p->Dp, N = p->N;
+    const long ldX = (long)(N + 1) * Dp;
+    PE_HIP(place(Lk + (long)N * Dp, ldX, 0, 0, cs + (long)N * Dp, ldX, B, Dp, 1.0, 0, p->st));
+    for (int n = N - 1; n >= 0; --n) {
+        Epi e;
+        e.mode = EPI_COARSE_INIT;
+        e.xout = Lk + (long)n * Dp;
+        e.ldxo = ldX;
+        e.cs = cs + (long)n * Dp;
+        e.ldcs = ldX;
+        PE_TRY(gemm<double>(p, shape(B, Dp, Lk + (long)(n + 1) * Dp, ldX, p->PhiGT64, Dp, 0, Dp), e, 0,
+                            PE_PROF_COARSE));
+    }
+    return PE_OK;
+}
+
+pe_status coarse_adj_correct(pe_problem p, int B, double* Lk, const double* Lprev, const int* active) {
+    const int Dp = p->Dp, N = p->N;
+    const long ldX = (long)(N + 1) * Dp;
+    const bool mixed = p->prec == PE_MIXED;
+    PE_HIP(place(Lk + (long)N * Dp, ldX, 0, 0, Lprev + (long)N * Dp, ldX, B, Dp, 1.0, 0, p->st));
+    PE_HIP(zero_fill(mixed ? nullptr : p->Dl64[0], mixed ? p->Dl32[0] : nullptr, (long)B * Dp, p->st));
+    int c = 0;
+    for (int n = N - 1; n >= 0; --n) {
+        Epi e;
+        e.mode = EPI_COARSE_DELTA;
+        e.xout = Lk + (long)n * Dp;
+        e.ldxo = ldX;
+        e.xprev = Lprev + (long)n * Dp;
+        e.fbuf = p->Fbuf + (long)n * Dp;
+        e.ldfb = (long)N * Dp;
+        e.dl64 = mixed ? nullptr : p->Dl64[1 - c];
+        e.dl32 = mixed ? p->Dl32[1 - c] : nullptr;
+        e.ldl = Dp;
+        e.active = active;
+        if (mixed)
+            PE_TRY(gemm<float>(p, shape(B, Dp, p->Dl32[c], Dp, p->PhiGT32, Dp, 0, Dp), e, 0, PE_PROF_COARSE));
+        else
+            PE_TRY(gemm<double>(p, shape(B, Dp, p->Dl64[c], Dp, p->PhiGT64, Dp, 0, Dp), e, 0, PE_PROF_COARSE));
+        c = 1 - c;
+    }
+    return PE_OK;
+}
+
+// Euclidean jumps J_b = max_{j < nr} |Lk[b][n0+j] - Lp[b][n0+j]|_2 (Lp null: norms)
+pe_status adj_jumps_launch(pe_problem p, int B, const double* Lk, const double* Lp, int n0, int nr) {
+    const int Dp = p->Dp;
+    const long ldX = (long)(p->N + 1) * Dp;
+    PE_HIP(jump_diff(Lk, Lp, ldX, n0, nr, B, Dp, p->E, p->st));
+    PE_HIP(jump_reduce(p->E, p->E, B, nr, Dp, p->Jd, p->nrm, p->st));
+    return PE_OK;
+}
+
+// Fine levels of the tracked trajectory y (boundary states packed in Yb,
+// source amplitudes dH or none) into Ytraj, and Inj = beta dt_fine M y
+// (whitened mass in PE_MIXED, where Ytraj holds whitened states).
+pe_status tracking_levels(pe_problem p, int B, const double* dH, double beta) {
+    const int Dp = p->Dp, N = p->N, P = p->P;
+    SrcView sv;
+    if (dH && p->src_set && p->src_kind != 0) {
+        sv.kind = p->src_kind;
+        sv.Hs = dH;
+        if (p->src_kind == 2) {
+            PE_TRY(interval_table(p, B, dH, p->Fdh, p->prec == PE_MIXED ? p->Fdh_w : nullptr));
+            sv.Fint = p->Fdh;
+            sv.Fint_w = p->Fdh_w;
+        }
+    }
+    PE_TRY(fine_sweep(p, B, p->Yb, (long)(N + 1) * Dp, p->Fbuf, true, 0, false, &sv, p->Ytraj));
+    const double* Mx = p->prec == PE_MIXED ? p->Mw64 : p->M64;
+    PE_TRY(gemm<double>(p, shape(B * N * P, Dp, p->Ytraj, Dp, Mx, Dp, 0, Dp),
+                        store_epi(p->Inj, Dp, beta * p->dtf), 0, -1, SITE_TRAJ));
+    return PE_OK;
+}
+
 pe_status check_handle(pe_problem p) {
     if (!p) return fail(PE_ERR_ARG, "null problem handle");
     return PE_OK;
@@ -927,6 +1229,7 @@ pe_status pe_problem_destroy(pe_problem p) {
     (void)hipStreamSynchronize(p->st);
     graphs_clear(p);
     free_list(p->ws_allocs);
+    free_list(p->adj_allocs);
     free_list(p->op_allocs);
     for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
     if (p->gw.part) (void)hipFree(p->gw.part);
@@ -1166,10 +1469,21 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         CK(dalloc_t(p, OL, &p->PhiG32, (size_t)Dp * Dp));
         CKH(to_f32(p->PhiG64, p->PhiG32, (long)Dp * Dp, p->st));
     }
+    // transposed coarse step (adjoint sweeps)
+    CK(dalloc_t(p, OL, &p->PhiGT64, (size_t)Dp * Dp));
+    CKH(place(p->PhiGT64, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
+    if (precision == PE_MIXED) {
+        CK(dalloc_t(p, OL, &p->PhiGT32, (size_t)Dp * Dp));
+        CKH(to_f32(p->PhiGT64, p->PhiGT32, (long)Dp * Dp, p->st));
+    }
     if (precision == PE_FP64) {
         CK(dalloc_t(p, OL, &p->Zf64, (size_t)Dp * Dp));
         CK(dalloc_t(p, OL, &p->Wf64, (size_t)Dp * 2 * Dp));
         CK(build_step_ops(p, dt_fine, pM11, pM12, M22inv, pA11, pA12, pA21, pA22, p->Zf64, p->Wf64));
+        CK(dalloc_t(p, OL, &p->ZT64, (size_t)Dp * Dp));
+        CKH(place(p->ZT64, Dp, 0, 0, p->Zf64, Dp, Dp, Dp, 1.0, 1, p->st));
+        CK(dalloc_t(p, OL, &p->Yop64, (size_t)2 * Dp * Dp));
+        CK(build_adj_state_op(p, p->A64, pM12, d2p, dt_fine, p->Yop64));
     } else {
         double *wM12, *wA11, *wA12, *wA21, *wA22, *I11, *I22inv, *Z64, *W64;
         CK(whiten(p, tmp, pM11, pM12, pM22, pA11, pA12, pA21, pA22, &wM12, &wA11, &wA12, &wA21, &wA22,
@@ -1181,6 +1495,27 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         CK(dalloc_t(p, OL, &p->Wf32, (size_t)Dp * 2 * Dp));
         CKH(to_f32(Z64, p->Zf32, (long)Dp * Dp, p->st));
         CKH(to_f32(W64, p->Wf32, (long)Dp * 2 * Dp, p->st));
+        // adjoint operators in whitened coordinates
+        double *ZT64w, *Y64w;
+        CK(dalloc_t(p, tmp, &ZT64w, (size_t)Dp * Dp));
+        CK(dalloc_t(p, tmp, &Y64w, (size_t)2 * Dp * Dp));
+        CKH(place(ZT64w, Dp, 0, 0, Z64, Dp, Dp, Dp, 1.0, 1, p->st));
+        CK(build_adj_state_op(p, p->Aw64, wM12, d2p, dt_fine, Y64w));
+        CK(dalloc_t(p, OL, &p->ZT32, (size_t)Dp * Dp));
+        CK(dalloc_t(p, OL, &p->Yop32, (size_t)2 * Dp * Dp));
+        CKH(to_f32(ZT64w, p->ZT32, (long)Dp * Dp, p->st));
+        CKH(to_f32(Y64w, p->Yop32, (long)2 * Dp * Dp, p->st));
+        CK(dalloc_t(p, OL, &p->TinT64, (size_t)Dp * Dp));
+        CKH(place(p->TinT64, Dp, 0, 0, p->Tin64, Dp, Dp, Dp, 1.0, 1, p->st));
+        // whitened mass [[I, M~12], [M~21, I]]
+        CK(dalloc_t(p, OL, &p->Mw64, (size_t)Dp * Dp));
+        CKH(hipMemsetAsync(p->Mw64, 0, sizeof(double) * Dp * Dp, p->st));
+        CKH(place(p->Mw64, Dp, 0, 0, I11, d1p, d1, d1, 1.0, 0, p->st));
+        if (d2 > 0) {
+            CKH(place(p->Mw64, Dp, d1p, d1p, I22inv, nf2, d2, d2, 1.0, 0, p->st));
+            CKH(place(p->Mw64, Dp, 0, d1p, wM12, d2p, d1, d2, 1.0, 0, p->st));
+            CKH(place(p->Mw64, Dp, d1p, 0, wM12, d2p, d2, d1, 1.0, 1, p->st));
+        }
     }
     CKH(hipStreamSynchronize(p->st));
     free_list(tmp);
@@ -1199,13 +1534,14 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
     if (time_mode == PE_T_FINE && R > 64) return fail(PE_ERR_ARG, "PE_T_FINE supports R <= 64");
     PE_HIP(hipStreamSynchronize(p->st));
     graphs_clear(p);
-    for (void* v : {(void*)p->Gs, (void*)p->Hs, (void*)p->Fint, (void*)p->Gs_w, (void*)p->Fint_w, (void*)p->CS}) {
+    for (void* v : {(void*)p->Gs, (void*)p->Hs, (void*)p->Fint, (void*)p->Gs_w, (void*)p->Fint_w, (void*)p->CS,
+                    (void*)p->GT, (void*)p->GwT}) {
         if (!v) continue;
         auto it = std::find(p->op_allocs.begin(), p->op_allocs.end(), v);
         if (it != p->op_allocs.end()) p->op_allocs.erase(it);
         (void)hipFree(v);
     }
-    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = p->CS = nullptr;
+    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = p->CS = p->GT = p->GwT = nullptr;
     p->src_set = 1;
     p->B_src = B;
     p->R = R;
@@ -1225,24 +1561,15 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
     PE_TRY(dalloc_t(p, p->op_allocs, &p->Hs, (size_t)B * R * p->Tlen));
     PE_HIP(hipMemcpyAsync(p->Hs, H, sizeof(double) * B * R * p->Tlen, hipMemcpyDeviceToDevice, p->st));
     if (dense) {
-        // Fint[(b, n)][s] = sum_r G[s][r] H[b][r][n]
-        double* Ht = nullptr;
-        std::vector<void*> tmp;
-        PE_TRY(dalloc_t(p, tmp, &Ht, (size_t)B * p->N * p->Rp));
-        PE_HIP(hipMemsetAsync(Ht, 0, sizeof(double) * B * p->N * p->Rp, p->st));
-        for (int b = 0; b < B; ++b)
-            PE_HIP(place(Ht + (long)b * p->N * p->Rp, p->Rp, 0, 0, p->Hs + (long)b * R * p->N, p->N, p->N, R,
-                         1.0, 1, p->st));
         PE_TRY(dalloc_t(p, p->op_allocs, &p->Fint, (size_t)B * p->N * Dp));
-        pe_status s = gemm<double>(p, shape(B * p->N, Dp, Ht, p->Rp, p->Gs, p->Rp, 0, p->Rp),
-                                   store_epi(p->Fint, Dp));
-        (void)hipStreamSynchronize(p->st);
-        free_list(tmp);
-        if (s < 0) return s;
+        PE_TRY(interval_table(p, B, p->Hs, p->Fint, nullptr));
         p->src_kind = 2;
     } else {
         p->src_kind = 1;
     }
+    // G^T for the source adjoint
+    PE_TRY(dalloc_t(p, p->op_allocs, &p->GT, (size_t)p->Rp * Dp));
+    PE_HIP(place(p->GT, Dp, 0, 0, p->Gs, p->Rp, p->Rp, Dp, 1.0, 1, p->st));
     {
         // coarse source term c_n = Z_dt F(t_{n+1}) for every (sample, interval)
         double* Fc = nullptr;
@@ -1269,24 +1596,17 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
         if (s < 0) return s;
     }
     if (p->prec == PE_MIXED) {
-        // whitened source for the mixed fine sweep: F~ = Tout^T F = Linv F
+        // whitened source for the mixed fine sweep: F~ = Tout^T F = Linv F,
+        // G~ = Linv G (kept transposed for the source adjoint)
+        PE_TRY(dalloc_t(p, p->op_allocs, &p->GwT, (size_t)p->Rp * Dp));
+        PE_TRY(gemm<double>(p, shape(p->Rp, Dp, p->GT, Dp, p->Linv64, Dp, 0, Dp), store_epi(p->GwT, Dp)));
         if (p->src_kind == 2) {
             PE_TRY(dalloc_t(p, p->op_allocs, &p->Fint_w, (size_t)B * p->N * Dp));
             PE_TRY(gemm<double>(p, shape(B * p->N, Dp, p->Fint, Dp, p->Linv64, Dp, 0, Dp),
                                 store_epi(p->Fint_w, Dp)));
         } else {
-            double *GT = nullptr, *GwT = nullptr;
-            std::vector<void*> tmp;
-            PE_TRY(dalloc_t(p, tmp, &GT, (size_t)p->Rp * Dp));
-            PE_TRY(dalloc_t(p, tmp, &GwT, (size_t)p->Rp * Dp));
-            PE_HIP(place(GT, Dp, 0, 0, p->Gs, p->Rp, p->Rp, Dp, 1.0, 1, p->st));
-            pe_status s = gemm<double>(p, shape(p->Rp, Dp, GT, Dp, p->Linv64, Dp, 0, Dp), store_epi(GwT, Dp));
-            if (s == PE_OK) s = dalloc_t(p, p->op_allocs, &p->Gs_w, (size_t)Dp * p->Rp);
-            if (s == PE_OK && place(p->Gs_w, p->Rp, 0, 0, GwT, Dp, Dp, p->Rp, 1.0, 1, p->st) != hipSuccess)
-                s = fail(PE_ERR_HIP, "source transpose failed");
-            (void)hipStreamSynchronize(p->st);
-            free_list(tmp);
-            if (s < 0) return s;
+            PE_TRY(dalloc_t(p, p->op_allocs, &p->Gs_w, (size_t)Dp * p->Rp));
+            PE_HIP(place(p->Gs_w, p->Rp, 0, 0, p->GwT, Dp, Dp, p->Rp, 1.0, 1, p->st));
         }
     }
     PE_HIP(hipStreamSynchronize(p->st));
@@ -1426,6 +1746,146 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
             PE_HIP(hipMemcpyAsync(p->active_d, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, p->st));
     }
     PE_HIP(unpack_states(p->Xk[cur], X, (long)B * (N + 1), p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    PE_TRY(prof_collect(p));
+    return n_active > 0 ? PE_WARN_NOT_CONVERGED : PE_OK;
+}
+
+pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH, double beta, double* J) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1 || !Ybnd || !J) return fail(PE_ERR_ARG, "bad arguments");
+    if (!(beta >= 0)) return fail(PE_ERR_ARG, "need beta >= 0");
+    if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    const bool fdh = dH && p->src_set && p->src_kind == 2;
+    PE_TRY(ensure_workspace(p, B));
+    PE_TRY(ensure_adj_workspace(p, B, true, false, fdh));
+    const long rowsX = (long)B * (p->N + 1);
+    PE_HIP(pack_states(Ybnd, p->Yb, rowsX, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_TRY(tracking_levels(p, B, dH, beta));
+    PE_HIP(sample_dot_sums(p->Ytraj, p->Inj, B, (long)p->N * p->P, p->Dp, 0.5, p->rowtmp, p->Jd, p->st));
+    PE_HIP(hipMemcpyAsync(J, p->Jd, sizeof(double) * B, hipMemcpyDeviceToHost, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    PE_TRY(prof_collect(p));
+    return PE_OK;
+}
+
+pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const double* Ybnd, const double* dH,
+                     double tol, int k_max, double* x0bar, double* Hbar, double* Lam, int* iters,
+                     double* jump_hist) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1 || !x0bar) return fail(PE_ERR_ARG, "bad arguments");
+    if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    if (!(tol >= 0) || k_max < 0 || k_max > p->N) return fail(PE_ERR_ARG, "need tol >= 0 and 0 <= k_max <= N");
+    if (!(beta >= 0)) return fail(PE_ERR_ARG, "need beta >= 0");
+    if (beta > 0 && !Ybnd) return fail(PE_ERR_ARG, "beta > 0 needs the tracked trajectory Ybnd");
+    const bool track = beta > 0;
+    const bool want_h = Hbar && p->src_set && p->R > 0;
+    const bool rho_all = want_h && p->time_mode == PE_T_FINE;
+    const bool fdh = track && dH && p->src_set && p->src_kind == 2;
+    const bool mixed = p->prec == PE_MIXED;
+    PE_TRY(ensure_workspace(p, B));
+    PE_TRY(ensure_adj_workspace(p, B, track, rho_all, fdh));
+    const int N = p->N, Dp = p->Dp;
+    const long ldX = (long)(N + 1) * Dp;
+    const long rowsX = (long)B * (N + 1);
+
+    if (Xbar)
+        PE_HIP(pack_states(Xbar, p->Xb, rowsX, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    else
+        PE_HIP(zero_fill(p->Xb, nullptr, rowsX * Dp, p->st));
+    const double* inj = nullptr;
+    if (track) {
+        PE_HIP(pack_states(Ybnd, p->Yb, rowsX, p->d1, p->d2, p->d1p, p->d2p, p->st));
+        PE_TRY(tracking_levels(p, B, dH, beta));
+        inj = p->Inj;
+        // coarse stand-in for interval n's tracking term in the initial
+        // sweep: beta dt M y_{n+1} at the interval end
+        PE_TRY(gemm<double>(p, shape((int)rowsX, Dp, p->Yb, Dp, p->M64, Dp, 0, Dp),
+                            store_epi(p->Qb, Dp, beta * p->dt)));
+        PE_HIP(zero_row0(p->Qb, ldX, B, Dp, p->st));
+    } else {
+        PE_HIP(zero_fill(p->Qb, nullptr, rowsX * Dp, p->st));
+    }
+
+    std::vector<int> active(B, 1);
+    std::vector<double> thr(B, tol), J(B, 0.0);
+    if (iters)
+        for (int b = 0; b < B; ++b) iters[b] = 0;
+    if (jump_hist)
+        for (long i = 0; i < (long)B * k_max; ++i) jump_hist[i] = 0.0;
+    PE_HIP(hipMemcpyAsync(p->active_d, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, p->st));
+
+    // initial backward coarse sweep on mu = lambda + Q: mu_n = Xbar_n + Q_n + Phi_G^T mu_{n+1}
+    int cur = 0;
+    PE_HIP(hipMemcpyAsync(p->io, p->Xb, sizeof(double) * rowsX * Dp, hipMemcpyDeviceToDevice, p->st));
+    PE_HIP(axpy(p->io, p->Qb, 1.0, rowsX * Dp, p->st));
+    PE_TRY(coarse_adj_initial(p, B, p->Xk[0], p->io));
+    PE_HIP(axpy(p->Xk[0], p->Qb, -1.0, rowsX * Dp, p->st));
+    PE_TRY(adj_jumps_launch(p, B, p->Xk[0], nullptr, 0, N + 1));
+    PE_TRY(jumps_read(p, B, thr.data()));
+    for (int b = 0; b < B; ++b) thr[b] *= tol;
+
+    int n_active = B;
+    for (int k = 1; k <= k_max && n_active > 0; ++k) {
+        const int nxt = 1 - cur;
+        if (mixed && k >= 2) {
+            // the transposed fine map is linear: add its action on the change
+            // lam^{k-1} - lam^{k-2} (rows n = 0..N-1 in E) to the stored values
+            PE_TRY(graph_run(p, {10, B, 2}, [&]() {
+                return fine_adjoint_sweep(p, B, p->E, (long)N * Dp, N, nullptr, p->Fbuf, true, 0);
+            }));
+        } else {
+            PE_TRY(graph_run(p, {10, B, cur, track ? 1 : 0}, [&]() -> pe_status {
+                PE_TRY(fine_adjoint_sweep(p, B, p->Xk[cur], ldX, N + 1, inj, p->Fbuf, false, 0));
+                PE_HIP(add_rows(p->Fbuf, p->Xb, B, N, Dp, p->st));
+                return PE_OK;
+            }));
+        }
+        if (n_active < B) PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, ldX, B, p->st));
+        PE_TRY(graph_run(p, {11, B, cur}, [&]() -> pe_status {
+            PE_TRY(coarse_adj_correct(p, B, p->Xk[nxt], p->Xk[cur], p->active_d));
+            PE_TRY(adj_jumps_launch(p, B, p->Xk[nxt], p->Xk[cur], 0, N));
+            return PE_OK;
+        }));
+        PE_TRY(jumps_read(p, B, J.data()));
+        cur = nxt;
+        for (int b = 0; b < B; ++b) {
+            if (!active[b]) continue;
+            if (!std::isfinite(J[b]))
+                return fail(PE_ERR_NONFINITE, "non-finite adjoint jump for sample " + std::to_string(b) +
+                                                  " at iteration " + std::to_string(k));
+            if (jump_hist) jump_hist[(long)b * k_max + (k - 1)] = J[b];
+            if (iters) iters[b] = k;
+            if (J[b] <= thr[b]) {
+                active[b] = 0;
+                --n_active;
+            }
+        }
+        if (n_active > 0 && n_active < B)
+            PE_HIP(hipMemcpyAsync(p->active_d, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, p->st));
+    }
+    const double* Lf = p->Xk[cur];
+    // gradient with respect to the initial state: lambda_0
+    PE_HIP(place(p->x0p, Dp, 0, 0, Lf, ldX, B, Dp, 1.0, 0, p->st));
+    PE_HIP(unpack_states(p->x0p, x0bar, B, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    if (Lam) PE_HIP(unpack_states(Lf, Lam, rowsX, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    if (want_h) {
+        // source adjoint: one transposed fine sweep from the final lambda,
+        // rho summed per interval (or kept per step), then G^T rho
+        PE_TRY(graph_run(p, {12, B, cur, track ? 1 : 0, rho_all ? 1 : 0}, [&]() {
+            return fine_adjoint_sweep(p, B, Lf, ldX, N + 1, inj, p->Fbuf, false, rho_all ? 2 : 1);
+        }));
+        const int Rp = p->Rp;
+        const long tl = p->Tlen;
+        const long rows_h = (long)B * tl;
+        PE_TRY(gemm<double>(p, shape((int)rows_h, Rp, rho_all ? p->Rho : p->Sacc, Dp, mixed ? p->GwT : p->GT, Dp, 0, Dp),
+                            store_epi(p->Hb, Rp)));
+        for (int b = 0; b < B; ++b)
+            PE_HIP(place(Hbar + (long)b * p->R * tl, tl, 0, 0, p->Hb + (long)b * tl * Rp, Rp, p->R, (int)tl, 1.0, 1,
+                         p->st));
+    }
     PE_HIP(hipStreamSynchronize(p->st));
     PE_TRY(prof_collect(p));
     return n_active > 0 ? PE_WARN_NOT_CONVERGED : PE_OK;

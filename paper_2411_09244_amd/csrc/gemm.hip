@@ -12,6 +12,8 @@
 // (the coarse sweep) use a row-parallel GEMV kernel instead.
 #include "pe_internal.h"
 
+#include <type_traits>
+
 namespace pe {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -66,67 +68,93 @@ __device__ inline double source_value(const Epi& e, int r, int s) {
     return v;
 }
 
-__device__ inline void epilogue(const Epi& e, int r, int s, double acc) {
-    switch (e.mode) {
-        case EPI_STORE: {
-            double v = e.alpha * acc;
-            if (e.beta != 0.0) v += e.beta * e.C0[(long)r * e.ldc0 + s];
-            if (e.diag_add != 0.0 && r == s + e.diag_off) v += e.diag_add;
-            e.C[(long)r * e.ldc + s] = v;
-            break;
-        }
-        case EPI_RESID: {
-            double v = source_value(e, r, s) - acc;
-            if (e.base) v -= e.base[(long)r * e.ldb + s];
-            e.R64[(long)r * e.ldr + s] = v;
-            if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
-            break;
-        }
-        case EPI_STEP: {
-            // state layout per column: [du_prev | u - u_a | w - w_a | dw_prev]
-            double* d = e.dev64 + (long)r * e.ldd;
-            float* d32 = e.dev32 ? e.dev32 + (long)r * e.ldd : nullptr;
-            if (s < e.d1p) {
-                const double u = d[e.d1p + s] + acc;
-                d[s] = acc;
-                d[e.d1p + s] = u;
-                if (d32) {
-                    d32[s] = (float)acc;
-                    d32[e.d1p + s] = (float)u;
-                }
-            } else {
-                const int j = s - e.d1p;
-                const long ow = 2L * e.d1p + j, oh = 2L * e.d1p + e.d2p + j;
-                const double w = d[ow] + acc;
-                d[ow] = w;
-                d[oh] = acc;
-                if (d32) {
-                    d32[ow] = (float)w;
-                    d32[oh] = (float)acc;
-                }
+// one epilogue per mode (the product kernel emits one unrolled store loop per
+// mode, which keeps each loop small enough to unroll with static accumulator
+// indexing)
+template <int MODE>
+__device__ inline void epi_apply(const Epi& e, int r, int s, double acc) {
+    if constexpr (MODE == EPI_STORE) {
+        double v = e.alpha * acc;
+        if (e.beta != 0.0) v += e.beta * e.C0[(long)r * e.ldc0 + s];
+        if (e.diag_add != 0.0 && r == s + e.diag_off) v += e.diag_add;
+        e.C[(long)r * e.ldc + s] = v;
+    } else if constexpr (MODE == EPI_RESID) {
+        double v = source_value(e, r, s) - acc;
+        if (e.base) v -= e.base[(long)r * e.ldb + s];
+        e.R64[(long)r * e.ldr + s] = v;
+        if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
+    } else if constexpr (MODE == EPI_STEP) {
+        // state layout per column: [du_prev | u - u_a | w - w_a | dw_prev]
+        double* d = e.dev64 + (long)r * e.ldd;
+        float* d32 = e.dev32 ? e.dev32 + (long)r * e.ldd : nullptr;
+        double full_dev;
+        if (s < e.d1p) {
+            const double u = d[e.d1p + s] + acc;
+            d[s] = acc;
+            d[e.d1p + s] = u;
+            if (d32) {
+                d32[s] = (float)acc;
+                d32[e.d1p + s] = (float)u;
             }
-            break;
+            full_dev = u;
+        } else {
+            const int j = s - e.d1p;
+            const long ow = 2L * e.d1p + j, oh = 2L * e.d1p + e.d2p + j;
+            const double w = d[ow] + acc;
+            d[ow] = w;
+            d[oh] = acc;
+            if (d32) {
+                d32[ow] = (float)w;
+                d32[oh] = (float)acc;
+            }
+            full_dev = w;
         }
-        case EPI_COARSE_INIT: {
-            const int b = r;
-            double x = acc;
-            if (e.cs) x += e.cs[(long)b * e.ldcs + s];
-            e.xout[(long)b * e.ldxo + s] = x;
-            break;
-        }
-        case EPI_COARSE_DELTA: {
-            const int b = r;
-            if (e.active && !e.active[b]) break;
-            const double x = e.fbuf[(long)b * e.ldfb + s] + acc;
-            e.xout[(long)b * e.ldxo + s] = x;
-            const double d = x - e.xprev[(long)b * e.ldxo + s];
-            if (e.dl64) e.dl64[(long)b * e.ldl + s] = d;
-            if (e.dl32) e.dl32[(long)b * e.ldl + s] = (float)d;
-            break;
-        }
-        default:
-            break;
+        if (e.traj) e.traj[(long)r * e.ldtraj + s] = e.xa[(long)r * (e.d1p + e.d2p) + s] + full_dev;
+    } else if constexpr (MODE == EPI_COARSE_INIT) {
+        const int b = r;
+        double x = acc;
+        if (e.cs) x += e.cs[(long)b * e.ldcs + s];
+        e.xout[(long)b * e.ldxo + s] = x;
+    } else if constexpr (MODE == EPI_COARSE_DELTA) {
+        const int b = r;
+        if (e.active && !e.active[b]) return;
+        const double x = e.fbuf[(long)b * e.ldfb + s] + acc;
+        e.xout[(long)b * e.ldxo + s] = x;
+        const double d = x - e.xprev[(long)b * e.ldxo + s];
+        if (e.dl64) e.dl64[(long)b * e.ldl + s] = d;
+        if (e.dl32) e.dl32[(long)b * e.ldl + s] = (float)d;
+    } else if constexpr (MODE == EPI_ADJ_RHO) {
+        if (e.R64) e.R64[(long)r * e.ldr + s] = acc;
+        if (e.R32) e.R32[(long)r * e.ldr + s] = (float)acc;
+        if (e.sacc) e.sacc[(long)r * e.ldr + s] += acc;
+        if (e.rho_all) e.rho_all[((long)r * e.P + e.m_step) * e.ldr + s] = acc;
+    } else if constexpr (MODE == EPI_ADJ_STATE) {
+        const long D = e.ldr;
+        const int j = s < D ? s : (int)(s - D);
+        double v = e.s_cur[(long)r * 2 * D + j] - acc;
+        if (e.inj) v += e.inj[(long)r * e.ldinj + j];
+        e.s_nxt[(long)r * 2 * D + s] = v;
+        if (s >= D && e.nu32) e.nu32[(long)r * D + j] = (float)v;
     }
+}
+
+// call f(integral_constant<mode>) for the runtime mode
+template <typename F>
+__device__ inline void epi_dispatch(int mode, F&& f) {
+    switch (mode) {
+        case EPI_STORE: f(std::integral_constant<int, EPI_STORE>{}); break;
+        case EPI_RESID: f(std::integral_constant<int, EPI_RESID>{}); break;
+        case EPI_STEP: f(std::integral_constant<int, EPI_STEP>{}); break;
+        case EPI_COARSE_INIT: f(std::integral_constant<int, EPI_COARSE_INIT>{}); break;
+        case EPI_COARSE_DELTA: f(std::integral_constant<int, EPI_COARSE_DELTA>{}); break;
+        case EPI_ADJ_RHO: f(std::integral_constant<int, EPI_ADJ_RHO>{}); break;
+        case EPI_ADJ_STATE: f(std::integral_constant<int, EPI_ADJ_STATE>{}); break;
+        default: break;
+    }
+}
+
+__device__ inline void epilogue(const Epi& e, int r, int s, double acc) {
+    epi_dispatch(e.mode, [&](auto m) { epi_apply<decltype(m)::value>(e, r, s, acc); });
 }
 
 // ---------------------------------------------------------------------------
@@ -267,16 +295,19 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
     // output coordinates of this lane: 16x16 block (i, j), element q ->
     // row Op::row(lane, q), column lane % 16 of the block
     if (splitk == 1) {
+        epi_dispatch(epi.mode, [&](auto m) {
+            constexpr int MODE = decltype(m)::value;
 #pragma unroll
-        for (int i = 0; i < MI; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-            for (int j = 0; j < MJ; ++j)
+                for (int j = 0; j < MJ; ++j)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = r0 + wr * (BR / 2) + i * 16 + Op::row(lane, q);
-                    const int s = s0 + wsi * (BS / 2) + j * 16 + (lane & 15);
-                    if (r < sh.Mr && s < sh.Ns) epilogue(epi, r, s, (double)acc[i][j][q]);
-                }
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = r0 + wr * (BR / 2) + i * 16 + Op::row(lane, q);
+                        const int s = s0 + wsi * (BS / 2) + j * 16 + (lane & 15);
+                        if (r < sh.Mr && s < sh.Ns) epi_apply<MODE>(epi, r, s, (double)acc[i][j][q]);
+                    }
+        });
         return;
     }
 

@@ -58,19 +58,21 @@ hipError_t unpack_states(const double* src, double* dst, long rows, int d1, int 
 }
 
 // ---------------------------------------------------------------------------
-// fine sweep: gather anchors X[b][n - n_shift] (zero for n < n_shift) into
-// Xa[b*N + n], zero the deviation state; afterwards Y (+)= Xa + deviation.
+// fine sweep: gather anchors X[b][n + row_off] (zero unless
+// 0 <= n + row_off < nvalid) into Xa[b*N + n], zero the deviation state;
+// afterwards Y (+)= Xa + deviation.
 // ---------------------------------------------------------------------------
-__global__ void k_fine_init(const double* __restrict__ X, long ldXb, int n_shift, double* __restrict__ Xa,
-                            double* __restrict__ dev64, float* __restrict__ dev32, int B, int N,
-                            int Dp) {
+__global__ void k_fine_init(const double* __restrict__ X, long ldXb, int row_off, int nvalid,
+                            double* __restrict__ Xa, double* __restrict__ dev64, float* __restrict__ dev32,
+                            int B, int N, int Dp) {
     const long rows = (long)B * N;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
          i += (long)gridDim.x * blockDim.x) {
         const long r = i / Dp;
         const int s = (int)(i - r * Dp);
         const long b = r / N, n = r - b * N;
-        Xa[i] = (n >= n_shift) ? X[b * ldXb + (n - n_shift) * Dp + s] : 0.0;
+        const long j = n + row_off;
+        Xa[i] = (j >= 0 && j < nvalid) ? X[b * ldXb + j * Dp + s] : 0.0;
         dev64[r * 2 * Dp + s] = 0.0;
         dev64[r * 2 * Dp + Dp + s] = 0.0;
         if (dev32) {
@@ -80,9 +82,9 @@ __global__ void k_fine_init(const double* __restrict__ X, long ldXb, int n_shift
     }
 }
 
-hipError_t fine_init(const double* X, long ldXb, int n_shift, double* Xa, double* dev64, float* dev32,
-                     int B, int N, int Dp, hipStream_t st) {
-    hipLaunchKernelGGL(k_fine_init, grid1((long)B * N * Dp), dim3(256), 0, st, X, ldXb, n_shift, Xa,
+hipError_t fine_init(const double* X, long ldXb, int row_off, int nvalid, double* Xa, double* dev64,
+                     float* dev32, int B, int N, int Dp, hipStream_t st) {
+    hipLaunchKernelGGL(k_fine_init, grid1((long)B * N * Dp), dim3(256), 0, st, X, ldXb, row_off, nvalid, Xa,
                        dev64, dev32, B, N, Dp);
     return hipGetLastError();
 }
@@ -182,6 +184,139 @@ hipError_t zero_fill(double* a, float* b, long n, hipStream_t st) {
     return hipGetLastError();
 }
 
+// adjoint sweep state [a | nu] (2Dp per column): a = nu = src (+ add, a
+// row of stride ld_add, when given); FP32 copy of nu when nu32 is given
+__global__ void k_adj_init(const double* __restrict__ src, const double* __restrict__ add, long ld_add,
+                           double* __restrict__ S, float* __restrict__ nu32, long rows, int Dp) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        double v = src[i];
+        if (add) v += add[r * ld_add + s];
+        S[r * 2 * Dp + s] = v;
+        S[r * 2 * Dp + Dp + s] = v;
+        if (nu32) nu32[i] = (float)v;
+    }
+}
+
+hipError_t adj_init(const double* src, const double* add, long ld_add, double* S, float* nu32, long rows, int Dp,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_init, grid1(rows * Dp), dim3(256), 0, st, src, add, ld_add, S, nu32, rows, Dp);
+    return hipGetLastError();
+}
+
+// y += a * x (n elements)
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
+hipError_t axpy(double* y, const double* x, double a, long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, grid1(n), dim3(256), 0, st, y, x, a, n);
+    return hipGetLastError();
+}
+
+// X[b][0][s] = 0 for every sample (rows of Dp, sample stride ldb)
+__global__ void k_zero_row0(double* __restrict__ X, long ldb, int B, int Dp) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)B * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long b = i / Dp;
+        X[b * ldb + (i - b * Dp)] = 0.0;
+    }
+}
+
+hipError_t zero_row0(double* X, long ldb, int B, int Dp, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_row0, grid1((long)B * Dp), dim3(256), 0, st, X, ldb, B, Dp);
+    return hipGetLastError();
+}
+
+// J[b] = scale * sum over the rows_per_b rows of sample b of dot(Y_row, Z_row):
+// one block per row for the dots, then one block per sample sums them in a
+// fixed order
+__global__ __launch_bounds__(256) void k_row_dots(const double* __restrict__ Y, const double* __restrict__ Z,
+                                                  int Dp, double* __restrict__ out) {
+    __shared__ double red[4];
+    const long r = blockIdx.x;
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < Dp; s += 256) acc += Y[r * Dp + s] * Z[r * Dp + s];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[r] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_sample_sum(const double* __restrict__ v, long rows_per_b, double scale,
+                                                    double* __restrict__ J) {
+    __shared__ double red[4];
+    const long b = blockIdx.x;
+    double acc = 0.0;
+    for (long j = threadIdx.x; j < rows_per_b; j += 256) acc += v[b * rows_per_b + j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) J[b] = scale * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+hipError_t sample_dot_sums(const double* Y, const double* Z, int B, long rows_per_b, int Dp, double scale,
+                           double* tmp_rows, double* J, hipStream_t st) {
+    const long rows = (long)B * rows_per_b;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_dots, dim3((unsigned)rows), dim3(256), 0, st, Y, Z, Dp, tmp_rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sample_sum, dim3((unsigned)B), dim3(256), 0, st, tmp_rows, rows_per_b, scale, J);
+    return hipGetLastError();
+}
+
+// Y[r][s] (+)= S[r][s]  (the a-part of the adjoint state)
+__global__ void k_take_a(const double* __restrict__ S, double* __restrict__ Y, long rows, int Dp, int accumulate) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const double v = S[r * 2 * Dp + s];
+        Y[i] = accumulate ? Y[i] + v : v;
+    }
+}
+
+hipError_t take_a(const double* S, double* Y, long rows, int Dp, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_take_a, grid1(rows * Dp), dim3(256), 0, st, S, Y, rows, Dp, accumulate);
+    return hipGetLastError();
+}
+
+// Y[b][n][s] += X[b][n][s] for n < N (X has N+1 rows per sample, Y has N)
+__global__ void k_add_rows(double* __restrict__ Y, const double* __restrict__ X, int B, int N, int Dp) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)B * N * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const long b = r / N, n = r - b * N;
+        Y[i] += X[(b * (N + 1) + n) * Dp + s];
+    }
+}
+
+hipError_t add_rows(double* Y, const double* X, int B, int N, int Dp, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_rows, grid1((long)B * N * Dp), dim3(256), 0, st, Y, X, B, N, Dp);
+    return hipGetLastError();
+}
+
+// X[b][row] = src[b][row] for every sample (rows of length Dp, strides ldb)
+__global__ void k_copy_row(const double* __restrict__ src, double* __restrict__ dst, long ldb, int B, int Dp) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)B * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long b = i / Dp;
+        const int s = (int)(i - b * Dp);
+        dst[b * ldb + s] = src[b * ldb + s];
+    }
+}
+
+hipError_t copy_row(const double* src, double* dst, long ldb, int B, int Dp, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_row, grid1((long)B * Dp), dim3(256), 0, st, src, dst, ldb, B, Dp);
+    return hipGetLastError();
+}
+
 // copy Xsrc[b] -> Xdst[b] for samples that stopped iterating
 __global__ void k_freeze(const double* __restrict__ Xsrc, double* __restrict__ Xdst,
                          const int* __restrict__ active, long ldXb, int B) {
@@ -219,20 +354,21 @@ hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStr
 // ---------------------------------------------------------------------------
 // generic placement: dst[(ro + i) * ldd + co + j] = scale * (trans ? src[j*lds + i] : src[i*lds + j])
 __global__ void k_place(double* __restrict__ dst, long ldd, int ro, int co, const double* __restrict__ src,
-                        long lds, int rows, int cols, double scale, int trans) {
+                        long lds, int rows, int cols, double scale, int trans, int accumulate) {
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)rows * cols;
          t += (long)gridDim.x * blockDim.x) {
         const int i = (int)(t / cols), j = (int)(t - (long)i * cols);
         const double v = trans ? src[(long)j * lds + i] : src[(long)i * lds + j];
-        dst[(long)(ro + i) * ldd + co + j] = scale * v;
+        double* d = dst + (long)(ro + i) * ldd + co + j;
+        *d = accumulate ? *d + scale * v : scale * v;
     }
 }
 
 hipError_t place(double* dst, long ldd, int ro, int co, const double* src, long lds, int rows, int cols,
-                 double scale, int trans, hipStream_t st) {
+                 double scale, int trans, hipStream_t st, int accumulate) {
     if (rows <= 0 || cols <= 0 || !src) return hipSuccess;
     hipLaunchKernelGGL(k_place, grid1((long)rows * cols), dim3(256), 0, st, dst, ldd, ro, co, src, lds,
-                       rows, cols, scale, trans);
+                       rows, cols, scale, trans, accumulate);
     return hipGetLastError();
 }
 

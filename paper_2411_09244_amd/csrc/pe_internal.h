@@ -31,6 +31,8 @@ enum EpiMode : int {
     EPI_STEP = 2,    // increment -> state/history update    (fine step)
     EPI_COARSE_INIT = 3,   // initial coarse sweep: x_{n+1} = Phi_G x_n + c_n
     EPI_COARSE_DELTA = 4,  // correction of eq. (2.7): x_{n+1}^k = F_n + Phi_G (x_n^k - x_n^{k-1})
+    EPI_ADJ_RHO = 5,       // adjoint step, first product: rho = Z^T nu (+ source adjoint)
+    EPI_ADJ_STATE = 6,     // adjoint step, second product: [a; nu] <- a - [A; A + Mh] rho
 };
 
 struct Epi {
@@ -66,6 +68,9 @@ struct Epi {
     float* dev32 = nullptr;
     long ldd = 0;
     int d1p = 0, d2p = 0;
+    double* traj = nullptr;         // STEP (nullable): full new state xa + deviation at traj + r*ldtraj
+    const double* xa = nullptr;     // STEP: anchors, ld d1p + d2p
+    long ldtraj = 0;
     // EPI_COARSE_*  (column r is sample r)
     double* xout = nullptr;         // X^k[b][n+1] = xout + b*ldxo
     long ldxo = 0;
@@ -78,6 +83,16 @@ struct Epi {
     float* dl32 = nullptr;
     long ldl = 0;
     const int* active = nullptr;
+    // EPI_ADJ_RHO: rho -> R64/R32 (ldr, each nullable); source adjoint accumulation
+    double* sacc = nullptr;         // += rho (per-interval source adjoint), ld ldr
+    double* rho_all = nullptr;      // rho of step m at row r*P + m (per-step source adjoint), ld ldr
+    int m_step = 0;
+    // EPI_ADJ_STATE: adjoint state [a | nu], 2*ldr per column
+    const double* s_cur = nullptr;
+    double* s_nxt = nullptr;
+    float* nu32 = nullptr;          // FP32 copy of nu, ld ldr
+    const double* inj = nullptr;    // nullable: cotangent added to both parts, at inj + r*ldinj
+    long ldinj = 0;
 };
 
 // Tile configuration of one GEMM launch.

@@ -7,8 +7,17 @@ hipError_t pack_states(const double* src, double* dst, long rows, int d1, int d2
                        hipStream_t st);
 hipError_t unpack_states(const double* src, double* dst, long rows, int d1, int d2, int d1p, int d2p,
                          hipStream_t st);
-hipError_t fine_init(const double* X, long ldXb, int n_shift, double* Xa, double* dev64, float* dev32,
-                     int B, int N, int Dp, hipStream_t st);
+hipError_t fine_init(const double* X, long ldXb, int row_off, int nvalid, double* Xa, double* dev64,
+                     float* dev32, int B, int N, int Dp, hipStream_t st);
+hipError_t adj_init(const double* src, const double* add, long ld_add, double* S, float* nu32, long rows, int Dp,
+                    hipStream_t st);
+hipError_t axpy(double* y, const double* x, double a, long n, hipStream_t st);
+hipError_t zero_row0(double* X, long ldb, int B, int Dp, hipStream_t st);
+hipError_t sample_dot_sums(const double* Y, const double* Z, int B, long rows_per_b, int Dp, double scale,
+                           double* tmp_rows, double* J, hipStream_t st);
+hipError_t take_a(const double* S, double* Y, long rows, int Dp, int accumulate, hipStream_t st);
+hipError_t add_rows(double* Y, const double* X, int B, int N, int Dp, hipStream_t st);
+hipError_t copy_row(const double* src, double* dst, long ldb, int B, int Dp, hipStream_t st);
 hipError_t fine_final(const double* Xa, const double* dev64, double* Y, long rows, int Dp, int d1p,
                       int accumulate, hipStream_t st);
 hipError_t jump_diff(const double* Xk, const double* Xp, long ldXb, int n0, int nr, int B, int Dp,
@@ -20,7 +29,7 @@ hipError_t freeze_inactive(const double* Xsrc, double* Xdst, const int* active, 
 hipError_t zero_fill(double* a, float* b, long n, hipStream_t st);
 hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st);
 hipError_t place(double* dst, long ldd, int ro, int co, const double* src, long lds, int rows, int cols,
-                 double scale, int trans, hipStream_t st);
+                 double scale, int trans, hipStream_t st, int accumulate = 0);
 hipError_t shifted_embed(double* dst, int n, const double* A, const double* Bm, long lds, int d,
                          double cb, hipStream_t st);
 hipError_t tril(double* A, int n, hipStream_t st);

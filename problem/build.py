@@ -185,6 +185,29 @@ def cfg_key(cfg):
     return hashlib.sha256(json.dumps(cfg, sort_keys=True).encode()).hexdigest()[:16]
 
 
+# fields that fix the medium and the multiscale spaces (workloads that differ
+# only in source, initial state or time grid share them)
+_SPACE_FIELDS = ("n", "n_c", "layers", "J1", "J2", "medium", "sigma", "corr", "n_h", "n_v", "contrast",
+                 "incl", "seed")
+_last_spaces = {}
+
+
+def _spaces(cfg, checks):
+    """build_spaces + blocks + diagnostics, memoised for the last space key
+    in this process."""
+    skey = cfg_key({k: cfg.get(k) for k in _SPACE_FIELDS})
+    if not checks and _last_spaces.get("key") == skey:
+        return _last_spaces["val"]
+    fine, cg, Psi1, Psi2, info = build_spaces(cfg, checks=checks)
+    bl = project_blocks(fine, Psi1, Psi2)
+    diag = diagnostics(bl, with_cond=Psi1.shape[1] <= 2000)
+    val = (fine, cg, Psi1, Psi2, info, bl, diag)
+    _last_spaces.clear()
+    if not checks:
+        _last_spaces.update(key=skey, val=val)
+    return val
+
+
 def build_problem(name_or_cfg, use_cache=True, keep_spaces=False, verbose=False):
     """Build (or load from cache) a workload. Returns a dict with the blocks,
     source factors, initial states, step sizes and diagnostics."""
@@ -197,9 +220,7 @@ def build_problem(name_or_cfg, use_cache=True, keep_spaces=False, verbose=False)
         prob.update(json.loads(str(z["meta"])))
         return prob
     t0 = time.perf_counter()
-    fine, cg, Psi1, Psi2, info = build_spaces(cfg, checks=keep_spaces)
-    bl = project_blocks(fine, Psi1, Psi2)
-    diag = diagnostics(bl, with_cond=Psi1.shape[1] <= 2000)
+    fine, cg, Psi1, Psi2, info, bl, diag = _spaces(cfg, keep_spaces)
     N, P, B = cfg["N"], cfg["P"], cfg["B"]
     T = cfg.get("T")
     if T is None or T / N > diag["dt_max"]:

@@ -206,6 +206,35 @@ pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const
  */
 pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH, double beta, double* J);
 
+/*
+ * Batches of different problems (different d1, d2, N, sources and sample
+ * counts; same precision and step ratio P), solved together: every
+ * product of a fine step runs as one grouped MFMA launch over all problems'
+ * interval columns, every coarse step n as one grouped launch over the
+ * problems with N > n, and each sweep is replayed from a captured HIP graph
+ * after its first visits. Each problem keeps its own stopping test
+ * (eq. (2.8)) and iteration count; finished samples are frozen.
+ *
+ * pe_batch_create - borrow `count` problem handles (they must outlive the
+ *   batch and keep their sources; a later pe_source_set or a pe_solve with
+ *   more samples is picked up at the next pe_batch_solve). hip_stream: the
+ *   stream for all batch work (NULL: the batch creates its own).
+ * pe_batch_solve - Algorithm 1 for every problem of the batch.
+ *   x0          host array of `count` device pointers, x0[i]: B_i x D_i
+ *               (B_i the sample count of problem i's source, 1 without one).
+ *   tol, norm_mode   as in pe_solve, per sample.
+ *   k_max       maximum iterations (each problem also stops at its own N).
+ *   X           host array of `count` device pointers, X[i]: B_i x (N_i+1) x D_i.
+ *   iters       host, sum_i B_i ints (problem-major, nullable).
+ *   Returns PE_WARN_NOT_CONVERGED if some sample did not meet its test.
+ * pe_batch_destroy - release the batch (not the problems).
+ */
+typedef struct pe_batch_s* pe_batch;
+pe_status pe_batch_create(pe_batch* out, int count, const pe_problem* problems, void* hip_stream);
+pe_status pe_batch_solve(pe_batch b, const double* const* x0, double tol, int norm_mode, int k_max,
+                         double* const* X, int* iters);
+pe_status pe_batch_destroy(pe_batch b);
+
 /* launch classes timed by pe_profile */
 enum {
     PE_PROF_FINE_RESIDUAL = 0,  /* fine step, R = F - A x_a - W dev (steps 2..P)  */

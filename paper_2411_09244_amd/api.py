@@ -185,6 +185,52 @@ class Problem:
             pass
 
 
+class Batch:
+    """Different problems (sizes, interval counts, sources; same precision
+    and step ratio) solved together by grouped launches (pe_batch_*). The
+    problems must outlive the batch."""
+
+    def __init__(self, problems, device="cuda"):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.problems = list(problems)
+        self.stream = torch.cuda.Stream(device=self.device)
+        arr = (ctypes.c_void_p * len(self.problems))(*[p.handle.value for p in self.problems])
+        h = ctypes.c_void_p()
+        L.check(self.lib.pe_batch_create(ctypes.byref(h), len(self.problems), arr,
+                                         ctypes.c_void_p(self.stream.cuda_stream)))
+        self.handle = h
+
+    def solve(self, x0s, tol, norm="abs", k_max=None):
+        """x0s: one (B_i, D_i) initial-state array per problem. Returns
+        (list of X_i (B_i, N_i+1, D_i), list of iteration arrays, status)."""
+        x0s = [_dev(x, self.device).reshape(-1, p.D) for x, p in zip(x0s, self.problems)]
+        Xs = [torch.empty((x.shape[0], p.N + 1, p.D), dtype=torch.float64, device=self.device)
+              for x, p in zip(x0s, self.problems)]
+        nb = [x.shape[0] for x in x0s]
+        k_max = max(p.N for p in self.problems) if k_max is None else int(k_max)
+        iters = np.zeros(sum(nb), dtype=np.int32)
+        xa = (ctypes.c_void_p * len(x0s))(*[x.data_ptr() for x in x0s])
+        Xa = (ctypes.c_void_p * len(Xs))(*[X.data_ptr() for X in Xs])
+        mode = {"abs": L.PE_NORM_M_ABS, "rel": L.PE_NORM_M_REL}[norm]
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        st = L.check(self.lib.pe_batch_solve(self.handle, xa, float(tol), mode, k_max, Xa,
+                                             iters.ctypes.data_as(ctypes.c_void_p)))
+        off = np.cumsum([0] + nb)
+        return Xs, [iters[off[i]:off[i + 1]] for i in range(len(nb))], st
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pe_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def problem_from(prob, precision="fp64", device="cuda"):
     """Problem + source from a workload dict (blocks, G, H, time_mode)."""
     blocks = {k: prob[k] for k in ("M11", "M12", "M22", "A11", "A12", "A22")}

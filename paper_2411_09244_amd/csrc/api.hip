@@ -63,6 +63,20 @@ inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
 }  // namespace
 
+// captured HIP graphs of repeated launch sequences, keyed by what fixes
+// their pointers (first visit eager, second captured, later replayed)
+struct GraphCache {
+    int use_graphs = 1;
+    std::map<std::vector<long>, hipGraphExec_t> graphs;
+    std::set<std::vector<long>> seen, bad;
+    void clear() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+        seen.clear();
+        bad.clear();
+    }
+};
+
 struct pe_problem_s {
     int d1 = 0, d2 = 0, D = 0, d1p = 0, d2p = 0, Dp = 0, N = 0, P = 0;
     double dt = 0, dtf = 0;
@@ -100,6 +114,8 @@ struct pe_problem_s {
     float* PhiGT32 = nullptr;
     double* TinT64 = nullptr;
     double* Mw64 = nullptr;
+    int adj_ops = 0;           // adjoint operators built (on first use)
+    double* M12k = nullptr;    // d1p x d2p (ld d2p): M12 in the fine sweep's coordinates
 
     // source
     int src_set = 0, B_src = 0, R = 0, Rp = 0, time_mode = 0, src_kind = 0;
@@ -148,9 +164,7 @@ struct pe_problem_s {
     std::map<std::vector<int>, pe::TileCfg> tuned;
 
     // captured HIP graphs of the sweeps, keyed by (kind, B, buffer parity)
-    int use_graphs = 1;
-    std::map<std::vector<long>, hipGraphExec_t> graphs;
-    std::set<std::vector<long>> graph_seen, graph_bad;
+    GraphCache gc;
 
     std::vector<void*> op_allocs, ws_allocs;
 };
@@ -242,53 +256,53 @@ pe_status prof_collect(pe_problem p) {
 // captures. Graphs hold only kernel nodes (no memset nodes). Pointer changes
 // (workspace growth, a new source) drop every graph.
 // ---------------------------------------------------------------------------
-void graphs_clear(pe_problem p) {
-    for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
-    p->graphs.clear();
-    p->graph_seen.clear();
-    p->graph_bad.clear();
-}
+void graphs_clear(pe_problem p) { p->gc.clear(); }
 
 template <typename Fn>
-pe_status graph_run(pe_problem p, const std::vector<long>& key, Fn&& fn) {
-    if (!p->use_graphs || p->prof_on || p->graph_bad.count(key) || !p->st) return fn();
-    auto it = p->graphs.find(key);
-    if (it != p->graphs.end()) {
-        PE_HIP(hipGraphLaunch(it->second, p->st));
+pe_status graph_run_on(GraphCache& gc, hipStream_t st, bool eager, const std::vector<long>& key, Fn&& fn) {
+    if (!gc.use_graphs || eager || gc.bad.count(key) || !st) return fn();
+    auto it = gc.graphs.find(key);
+    if (it != gc.graphs.end()) {
+        PE_HIP(hipGraphLaunch(it->second, st));
         return PE_OK;
     }
-    if (!p->graph_seen.count(key)) {
-        p->graph_seen.insert(key);
+    if (!gc.seen.count(key)) {
+        gc.seen.insert(key);
         return fn();
     }
     hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(p->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
-        p->use_graphs = 0;  // this stream cannot be captured: stay eager
+        gc.use_graphs = 0;  // this stream cannot be captured: stay eager
         return fn();
     }
     const pe_status s = fn();
-    const hipError_t e = hipStreamEndCapture(p->st, &g);
+    const hipError_t e = hipStreamEndCapture(st, &g);
     hipGraphExec_t ex = nullptr;
     hipError_t ei = hipErrorUnknown;
     if (s == PE_OK && e == hipSuccess && g) ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     if (s != PE_OK || e != hipSuccess || ei != hipSuccess) {
-        // not capturable: keep this sweep eager
+        // not capturable: keep this sequence eager
         (void)hipGetLastError();
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(p->st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
             hipGraph_t g2 = nullptr;
-            (void)hipStreamEndCapture(p->st, &g2);
+            (void)hipStreamEndCapture(st, &g2);
             if (g2) (void)hipGraphDestroy(g2);
         }
-        p->graph_bad.insert(key);
+        gc.bad.insert(key);
         g_err.clear();
         return fn();
     }
-    p->graphs[key] = ex;
-    PE_HIP(hipGraphLaunch(ex, p->st));
+    gc.graphs[key] = ex;
+    PE_HIP(hipGraphLaunch(ex, st));
     return PE_OK;
+}
+
+template <typename Fn>
+pe_status graph_run(pe_problem p, const std::vector<long>& key, Fn&& fn) {
+    return graph_run_on(p->gc, p->st, p->prof_on != 0, key, fn);
 }
 
 // ---------------------------------------------------------------------------
@@ -1008,6 +1022,58 @@ pe_status jumps(pe_problem p, int B, const double* Xk, const double* Xp, long ld
 // the fresh history does not depend on the state, so F^T lambda = a there.
 // A cotangent of an intermediate state adds to both a and nu.
 
+// Adjoint operators, built at the first adjoint call: Z^T, [A; A + Mh] and
+// Phi_G^T in the fine sweep's precision and coordinates; PE_MIXED also
+// Tin^T and the whitened mass [[I, M~12], [M~21, I]].
+pe_status ensure_adj_ops(pe_problem p) {
+    if (p->adj_ops) return PE_OK;
+    const int d1 = p->d1, d2 = p->d2, d1p = p->d1p, d2p = p->d2p, Dp = p->Dp;
+    auto& OL = p->op_allocs;
+    std::vector<void*> tmp;
+    auto done = [&](pe_status r) {
+        (void)hipStreamSynchronize(p->st);
+        free_list(tmp);
+        return r;
+    };
+    pe_status s;
+    if ((s = dalloc_t(p, OL, &p->PhiGT64, (size_t)Dp * Dp)) < 0) return done(s);
+    PE_HIP(place(p->PhiGT64, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
+    if (p->prec == PE_FP64) {
+        if ((s = dalloc_t(p, OL, &p->ZT64, (size_t)Dp * Dp)) < 0 ||
+            (s = dalloc_t(p, OL, &p->Yop64, (size_t)2 * Dp * Dp)) < 0)
+            return done(s);
+        PE_HIP(place(p->ZT64, Dp, 0, 0, p->Zf64, Dp, Dp, Dp, 1.0, 1, p->st));
+        if ((s = build_adj_state_op(p, p->A64, p->M12k, d2p, p->dtf, p->Yop64)) < 0) return done(s);
+    } else {
+        double *Y64w = nullptr, *I = nullptr;
+        const int dm = std::max(d1p, d2p);
+        if ((s = dalloc_t(p, OL, &p->PhiGT32, (size_t)Dp * Dp)) < 0 ||
+            (s = dalloc_t(p, OL, &p->ZT32, (size_t)Dp * Dp)) < 0 ||
+            (s = dalloc_t(p, OL, &p->Yop32, (size_t)2 * Dp * Dp)) < 0 ||
+            (s = dalloc_t(p, OL, &p->TinT64, (size_t)Dp * Dp)) < 0 ||
+            (s = dalloc_t(p, OL, &p->Mw64, (size_t)Dp * Dp)) < 0 ||
+            (s = dalloc_t(p, tmp, &Y64w, (size_t)2 * Dp * Dp)) < 0 || (s = dalloc_t(p, tmp, &I, (size_t)dm * dm)) < 0)
+            return done(s);
+        PE_HIP(to_f32(p->PhiGT64, p->PhiGT32, (long)Dp * Dp, p->st));
+        // the FP32 step operator transposed (exact)
+        PE_HIP(transpose_f32(p->Zf32, Dp, p->ZT32, Dp, Dp, Dp, p->st));
+        if ((s = build_adj_state_op(p, p->Aw64, p->M12k, d2p, p->dtf, Y64w)) < 0) return done(s);
+        PE_HIP(to_f32(Y64w, p->Yop32, (long)2 * Dp * Dp, p->st));
+        PE_HIP(place(p->TinT64, Dp, 0, 0, p->Tin64, Dp, Dp, Dp, 1.0, 1, p->st));
+        PE_HIP(hipMemsetAsync(p->Mw64, 0, sizeof(double) * Dp * Dp, p->st));
+        PE_HIP(eye(I, dm, d1, p->st));
+        PE_HIP(place(p->Mw64, Dp, 0, 0, I, dm, d1, d1, 1.0, 0, p->st));
+        if (d2 > 0) {
+            PE_HIP(eye(I, dm, d2, p->st));
+            PE_HIP(place(p->Mw64, Dp, d1p, d1p, I, dm, d2, d2, 1.0, 0, p->st));
+            PE_HIP(place(p->Mw64, Dp, 0, d1p, p->M12k, d2p, d1, d2, 1.0, 0, p->st));
+            PE_HIP(place(p->Mw64, Dp, d1p, 0, p->M12k, d2p, d2, d1, 1.0, 1, p->st));
+        }
+    }
+    p->adj_ops = 1;
+    return done(PE_OK);
+}
+
 pe_status ensure_adj_workspace(pe_problem p, int B, bool traj, bool rho, bool fdh) {
     const bool grow = B > p->adj_B || std::max(p->Rp, 1) > p->adj_Rp || (traj && !p->adj_traj) ||
                       (rho && !p->adj_rho) || (fdh && !p->adj_fdh);
@@ -1208,6 +1274,344 @@ pe_status tracking_levels(pe_problem p, int B, const double* dH, double beta) {
     return PE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batches of different problems
+// ---------------------------------------------------------------------------
+struct GroupPlan {
+    GemmItem* items = nullptr;  // device
+    const int* wg_item = nullptr;
+    const int* wg_tile = nullptr;
+    int n_wg = 0;
+};
+
+}  // namespace
+
+struct pe_batch_s {
+    int count = 0, prec = PE_FP64, P = 0, N_max = 0;
+    std::vector<pe_problem> pr;
+    std::vector<int> Bs, J_off;
+    int J_total = 0;
+    hipStream_t st = nullptr;
+    int own_stream = 0;
+    // launch plans (built at the first solve; rebuilt when a problem's
+    // workspace or sample count changes)
+    int planned = 0;
+    std::vector<const void*> plan_keys;
+    TileCfg cfg;
+    std::vector<void*> allocs;
+    GroupPlan anc1, anc2, inc, fin[2], nrm_rel, nrm_k;
+    std::vector<GroupPlan> resid[2];  // [with source][fine step]
+    CoarseItem* c_init = nullptr;
+    CoarseItem* c_corr[2] = {nullptr, nullptr};
+    int *c_wg_item = nullptr, *c_wg_row = nullptr;
+    std::vector<int> c_nwg;  // coarse step n: work-groups of the problems with N > n
+    std::vector<int> order;  // problems by decreasing N
+    double* J_all = nullptr;
+    GraphCache gc;
+};
+
+namespace {
+
+template <typename T>
+pe_status upload(pe_batch bt, const std::vector<T>& v, T** out) {
+    *out = nullptr;
+    if (v.empty()) return PE_OK;
+    void* d = nullptr;
+    if (hipMalloc(&d, sizeof(T) * v.size()) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PE_ERR_NOMEM, "device allocation for a batch plan failed");
+    }
+    bt->allocs.push_back(d);
+    PE_HIP(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    *out = (T*)d;
+    return PE_OK;
+}
+
+// work-group tables of a grouped product family (one product per problem)
+pe_status group_tables(pe_batch bt, const std::vector<GemmShape>& shapes, const int** wg_item, const int** wg_tile,
+                       int* n_wg) {
+    std::vector<int> wi, wt;
+    for (size_t g = 0; g < shapes.size(); ++g) {
+        const long tiles = (long)((shapes[g].Mr + bt->cfg.br - 1) / bt->cfg.br) *
+                           ((shapes[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
+        for (long t = 0; t < tiles; ++t) {
+            wi.push_back((int)g);
+            wt.push_back((int)t);
+        }
+    }
+    int *a = nullptr, *b = nullptr;
+    PE_TRY(upload(bt, wi, &a));
+    PE_TRY(upload(bt, wt, &b));
+    *wg_item = a;
+    *wg_tile = b;
+    *n_wg = (int)wi.size();
+    return PE_OK;
+}
+
+pe_status group_plan(pe_batch bt, const std::vector<GemmShape>& sh, const std::vector<Epi>& ep, size_t elem,
+                     const int* wg_item, const int* wg_tile, int n_wg, GroupPlan* out) {
+    std::vector<GemmItem> items(sh.size());
+    for (size_t g = 0; g < sh.size(); ++g) {
+        if (!gemm_shape_ok(sh[g], elem)) return fail(PE_ERR_ARG, "batch product operands are not 16-byte aligned");
+        items[g].sh = sh[g];
+        items[g].epi = ep[g];
+        items[g].tiles_r = (sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br;
+    }
+    PE_TRY(upload(bt, items, &out->items));
+    out->wg_item = wg_item;
+    out->wg_tile = wg_tile;
+    out->n_wg = n_wg;
+    return PE_OK;
+}
+
+std::vector<const void*> batch_plan_keys(pe_batch bt) {
+    std::vector<const void*> k;
+    for (int i = 0; i < bt->count; ++i) {
+        pe_problem p = bt->pr[i];
+        k.push_back(p->Xk[0]);
+        k.push_back(p->CS);
+        k.push_back(p->Gs);
+        k.push_back(p->Fint);
+        k.push_back((const void*)(long)bt->Bs[i]);
+    }
+    return k;
+}
+
+pe_status batch_plan(pe_batch bt) {
+    PE_HIP(hipStreamSynchronize(bt->st));
+    bt->gc.clear();
+    for (void* v : bt->allocs) (void)hipFree(v);
+    bt->allocs.clear();
+    bt->planned = 0;
+    const bool mixed = bt->prec == PE_MIXED;
+    const size_t el = mixed ? sizeof(float) : sizeof(double);
+    const int G = bt->count;
+    std::vector<GemmShape> fine_sh(G), nrel_sh(G), nk_sh(G);
+    std::vector<GemmShape> a1(G), a2(G), g2s(G), fsh(G);
+    std::vector<Epi> e_a1(G), e_a2(G), e_inc(G), e_fin[2], e_nrel(G), e_nk(G);
+    e_fin[0].resize(G);
+    e_fin[1].resize(G);
+    std::vector<std::vector<GemmShape>> r_sh(bt->P, std::vector<GemmShape>(G));
+    std::vector<std::vector<Epi>> r_ep[2];
+    for (int w = 0; w < 2; ++w) r_ep[w].assign(bt->P, std::vector<Epi>(G));
+    for (int g = 0; g < G; ++g) {
+        pe_problem p = bt->pr[g];
+        const int B = bt->Bs[g], N = p->N, Dp = p->Dp, d1p = p->d1p, d2p = p->d2p, rows = B * N;
+        const long ldS = 2L * Dp;
+        fine_sh[g] = shape(rows, Dp, nullptr, Dp, nullptr, Dp, 0, Dp);
+        // anchors
+        a1[g] = shape(rows, Dp, p->R64, Dp, p->Tin64, Dp, 0, d1p);
+        a1[g].s_split = d1p;
+        a1[g].k0b = d1p;
+        a1[g].k1b = Dp;
+        e_a1[g] = store_epi(p->Xa, Dp);
+        a2[g] = shape(rows, Dp, p->Xa, Dp, mixed ? p->Aw64 : p->A64, Dp, 0, Dp);
+        e_a2[g] = store_epi(p->Ya, Dp);
+        // fine steps
+        for (int step = 0; step < bt->P; ++step) {
+            GemmShape g1 = shape(rows, Dp, mixed ? (const void*)p->dev32 : (const void*)p->dev64, ldS,
+                                 mixed ? (const void*)p->Wf32 : (const void*)p->Wf64, ldS, 0, 0);
+            g1.s_split = d1p;
+            if (step > 0) {
+                g1.k0a = d1p;
+                g1.k1a = 2 * Dp;
+                g1.k0b = 0;
+                g1.k1b = 2 * d1p + d2p;
+            }
+            r_sh[step][g] = g1;
+            for (int w = 0; w < 2; ++w) {
+                Epi e1;
+                e1.mode = EPI_RESID;
+                e1.R64 = p->R64;
+                e1.R32 = mixed ? p->R32 : nullptr;
+                e1.ldr = Dp;
+                e1.base = p->Ya;
+                e1.ldb = Dp;
+                source_fields(p, e1, mixed);
+                if (!w) e1.src_kind = 0;
+                e1.cols_per_b = N;
+                e1.n_fixed = -1;
+                e1.p_step = step;
+                r_ep[w][step][g] = e1;
+            }
+        }
+        g2s[g] = shape(rows, Dp, mixed ? (const void*)p->R32 : (const void*)p->R64, Dp,
+                       mixed ? (const void*)p->Zf32 : (const void*)p->Zf64, Dp, 0, d1p);
+        g2s[g].s_split = d1p;
+        g2s[g].k0b = 0;
+        g2s[g].k1b = Dp;
+        Epi e2;
+        e2.mode = EPI_STEP;
+        e2.dev64 = p->dev64;
+        e2.dev32 = mixed ? p->dev32 : nullptr;
+        e2.ldd = ldS;
+        e2.d1p = d1p;
+        e2.d2p = d2p;
+        e_inc[g] = e2;
+        // back to the caller's coordinates (mixed)
+        fsh[g] = shape(rows, Dp, p->R64, Dp, p->Tout64, Dp, 0, d1p);
+        fsh[g].s_split = d1p;
+        fsh[g].k0b = d1p;
+        fsh[g].k1b = Dp;
+        e_fin[0][g] = store_epi(p->Fbuf, Dp);
+        e_fin[1][g] = store_epi(p->Fbuf, Dp, 1.0, p->Fbuf, Dp, 1.0);
+        // jump norms
+        nrel_sh[g] = shape(B * (N + 1), Dp, p->E, Dp, p->M64, Dp, 0, Dp);
+        nk_sh[g] = shape(B * N, Dp, p->E, Dp, p->M64, Dp, 0, Dp);
+        e_nrel[g] = store_epi(p->Yn, Dp);
+        e_nk[g] = store_epi(p->Yn, Dp);
+    }
+    const int *fi, *ft, *ri, *rt, *ki, *kt;
+    int fn, rn, kn;
+    PE_TRY(group_tables(bt, fine_sh, &fi, &ft, &fn));
+    PE_TRY(group_tables(bt, nrel_sh, &ri, &rt, &rn));
+    PE_TRY(group_tables(bt, nk_sh, &ki, &kt, &kn));
+    if (mixed) {
+        PE_TRY(group_plan(bt, a1, e_a1, sizeof(double), fi, ft, fn, &bt->anc1));
+        PE_TRY(group_plan(bt, fsh, e_fin[0], sizeof(double), fi, ft, fn, &bt->fin[0]));
+        PE_TRY(group_plan(bt, fsh, e_fin[1], sizeof(double), fi, ft, fn, &bt->fin[1]));
+    }
+    PE_TRY(group_plan(bt, a2, e_a2, sizeof(double), fi, ft, fn, &bt->anc2));
+    PE_TRY(group_plan(bt, g2s, e_inc, el, fi, ft, fn, &bt->inc));
+    for (int w = 0; w < 2; ++w) {
+        bt->resid[w].assign(bt->P, GroupPlan());
+        if (!mixed && !w) continue;  // the FP64 path always sweeps with the source
+        for (int step = 0; step < bt->P; ++step)
+            PE_TRY(group_plan(bt, r_sh[step], r_ep[w][step], el, fi, ft, fn, &bt->resid[w][step]));
+    }
+    PE_TRY(group_plan(bt, nrel_sh, e_nrel, sizeof(double), ri, rt, rn, &bt->nrm_rel));
+    PE_TRY(group_plan(bt, nk_sh, e_nk, sizeof(double), ki, kt, kn, &bt->nrm_k));
+
+    // coarse steps: problems by decreasing N, so the problems still running
+    // at step n are a prefix of the row table
+    bt->order.resize(G);
+    for (int g = 0; g < G; ++g) bt->order[g] = g;
+    std::stable_sort(bt->order.begin(), bt->order.end(),
+                     [&](int a, int b) { return bt->pr[a]->N > bt->pr[b]->N; });
+    std::vector<CoarseItem> ci(G), cc[2];
+    cc[0].resize(G);
+    cc[1].resize(G);
+    std::vector<int> wi, wr, first(G + 1, 0);
+    for (int j = 0; j < G; ++j) {
+        pe_problem p = bt->pr[bt->order[j]];
+        CoarseItem c;
+        c.Phi64 = p->PhiG64;
+        c.Phi32 = p->PhiG32;
+        c.Dp = p->Dp;
+        c.B = bt->Bs[bt->order[j]];
+        c.N = p->N;
+        c.ldX = (long)(p->N + 1) * p->Dp;
+        c.Fbuf = p->Fbuf;
+        for (int q = 0; q < 2; ++q) {
+            c.Dl64[q] = p->Dl64[q];
+            c.Dl32[q] = p->Dl32[q];
+        }
+        CoarseItem a = c;
+        a.Xk = p->Xk[0];
+        a.cs = p->CS;
+        ci[j] = a;
+        for (int cur = 0; cur < 2; ++cur) {
+            CoarseItem d = c;
+            d.Xk = p->Xk[1 - cur];
+            d.Xprev = p->Xk[cur];
+            d.active = p->active_d;
+            cc[cur][j] = d;
+        }
+        first[j] = (int)wi.size();
+        for (int r = 0; r < (p->Dp + 3) / 4; ++r) {
+            wi.push_back(j);
+            wr.push_back(r);
+        }
+    }
+    first[G] = (int)wi.size();
+    PE_TRY(upload(bt, ci, &bt->c_init));
+    PE_TRY(upload(bt, cc[0], &bt->c_corr[0]));
+    PE_TRY(upload(bt, cc[1], &bt->c_corr[1]));
+    PE_TRY(upload(bt, wi, &bt->c_wg_item));
+    PE_TRY(upload(bt, wr, &bt->c_wg_row));
+    bt->c_nwg.assign(bt->N_max, 0);
+    for (int n = 0; n < bt->N_max; ++n) {
+        int j = 0;
+        while (j < G && bt->pr[bt->order[j]]->N > n) ++j;
+        bt->c_nwg[n] = first[j];
+    }
+    // jump values of every (problem, sample)
+    bt->J_off.assign(G, 0);
+    bt->J_total = 0;
+    for (int g = 0; g < G; ++g) {
+        bt->J_off[g] = bt->J_total;
+        bt->J_total += bt->Bs[g];
+    }
+    void* jd = nullptr;
+    if (hipMalloc(&jd, sizeof(double) * bt->J_total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PE_ERR_NOMEM, "device allocation for batch jumps failed");
+    }
+    bt->allocs.push_back(jd);
+    bt->J_all = (double*)jd;
+    bt->plan_keys = batch_plan_keys(bt);
+    bt->planned = 1;
+    return PE_OK;
+}
+
+template <typename T>
+pe_status grouped(pe_batch bt, const GroupPlan& g) {
+    TileCfg c = bt->cfg;
+    if (sizeof(T) == 8) c.bk2 = 0;
+    const hipError_t e = gemm_grouped_launch<T>(g.items, g.wg_item, g.wg_tile, g.n_wg, c, bt->st);
+    if (e != hipSuccess) return fail(PE_ERR_HIP, std::string("grouped product launch failed: ") + hipGetErrorString(e));
+    return PE_OK;
+}
+
+// F on every interval of every problem (as fine_sweep, one grouped launch per product)
+pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
+    const bool mixed = bt->prec == PE_MIXED;
+    for (int g = 0; g < bt->count; ++g) {
+        pe_problem p = bt->pr[g];
+        const int B = bt->Bs[g], N = p->N, Dp = p->Dp;
+        const double* Xs = incremental ? p->E : p->Xk[cur];
+        const long ld = incremental ? (long)N * Dp : (long)(N + 1) * Dp;
+        PE_HIP(fine_init(Xs, ld, incremental ? -1 : 0, N, mixed ? p->R64 : p->Xa, p->dev64,
+                         mixed ? p->dev32 : nullptr, B, N, Dp, bt->st));
+    }
+    if (mixed) PE_TRY(grouped<double>(bt, bt->anc1));
+    PE_TRY(grouped<double>(bt, bt->anc2));
+    for (int step = 0; step < bt->P; ++step) {
+        const GroupPlan& r = bt->resid[incremental ? 0 : 1][step];
+        if (mixed) {
+            PE_TRY(grouped<float>(bt, r));
+            PE_TRY(grouped<float>(bt, bt->inc));
+        } else {
+            PE_TRY(grouped<double>(bt, r));
+            PE_TRY(grouped<double>(bt, bt->inc));
+        }
+    }
+    for (int g = 0; g < bt->count; ++g) {
+        pe_problem p = bt->pr[g];
+        const long rows = (long)bt->Bs[g] * p->N;
+        PE_HIP(fine_final(p->Xa, p->dev64, mixed ? p->R64 : p->Fbuf, rows, p->Dp, p->d1p, 0, bt->st));
+    }
+    if (mixed) PE_TRY(grouped<double>(bt, bt->fin[incremental ? 1 : 0]));
+    return PE_OK;
+}
+
+// jumps of every problem into J_all: rel (X^0 norms over n = 0..N) or the
+// change of iterate xk against 1 - xk over n = 1..N
+pe_status batch_jumps(pe_batch bt, int xk, bool rel) {
+    for (int g = 0; g < bt->count; ++g) {
+        pe_problem p = bt->pr[g];
+        const int N = p->N;
+        PE_HIP(jump_diff(p->Xk[xk], rel ? nullptr : p->Xk[1 - xk], (long)(N + 1) * p->Dp, rel ? 0 : 1,
+                         rel ? N + 1 : N, bt->Bs[g], p->Dp, p->E, bt->st));
+    }
+    PE_TRY(grouped<double>(bt, rel ? bt->nrm_rel : bt->nrm_k));
+    for (int g = 0; g < bt->count; ++g) {
+        pe_problem p = bt->pr[g];
+        PE_HIP(jump_reduce(p->E, p->Yn, bt->Bs[g], rel ? p->N + 1 : p->N, p->Dp, bt->J_all + bt->J_off[g], p->nrm,
+                           bt->st));
+    }
+    return PE_OK;
+}
 pe_status check_handle(pe_problem p) {
     if (!p) return fail(PE_ERR_ARG, "null problem handle");
     return PE_OK;
@@ -1342,7 +1746,7 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         const char* at = getenv("PE_AUTOTUNE");
         p->autotune = (at && at[0] == '0') ? 0 : 1;
         const char* gr = getenv("PE_GRAPHS");
-        p->use_graphs = (gr && gr[0] == '0') ? 0 : 1;
+        p->gc.use_graphs = (gr && gr[0] == '0') ? 0 : 1;
         tune_cache_load(p);
     }
     int dev = 0;
@@ -1469,21 +1873,13 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         CK(dalloc_t(p, OL, &p->PhiG32, (size_t)Dp * Dp));
         CKH(to_f32(p->PhiG64, p->PhiG32, (long)Dp * Dp, p->st));
     }
-    // transposed coarse step (adjoint sweeps)
-    CK(dalloc_t(p, OL, &p->PhiGT64, (size_t)Dp * Dp));
-    CKH(place(p->PhiGT64, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
-    if (precision == PE_MIXED) {
-        CK(dalloc_t(p, OL, &p->PhiGT32, (size_t)Dp * Dp));
-        CKH(to_f32(p->PhiGT64, p->PhiGT32, (long)Dp * Dp, p->st));
-    }
+    const size_t m12n = (size_t)d1p * std::max(d2p, 8);
+    CK(dalloc_t(p, OL, &p->M12k, m12n));
     if (precision == PE_FP64) {
         CK(dalloc_t(p, OL, &p->Zf64, (size_t)Dp * Dp));
         CK(dalloc_t(p, OL, &p->Wf64, (size_t)Dp * 2 * Dp));
         CK(build_step_ops(p, dt_fine, pM11, pM12, M22inv, pA11, pA12, pA21, pA22, p->Zf64, p->Wf64));
-        CK(dalloc_t(p, OL, &p->ZT64, (size_t)Dp * Dp));
-        CKH(place(p->ZT64, Dp, 0, 0, p->Zf64, Dp, Dp, Dp, 1.0, 1, p->st));
-        CK(dalloc_t(p, OL, &p->Yop64, (size_t)2 * Dp * Dp));
-        CK(build_adj_state_op(p, p->A64, pM12, d2p, dt_fine, p->Yop64));
+        CKH(hipMemcpyAsync(p->M12k, pM12, sizeof(double) * m12n, hipMemcpyDeviceToDevice, p->st));
     } else {
         double *wM12, *wA11, *wA12, *wA21, *wA22, *I11, *I22inv, *Z64, *W64;
         CK(whiten(p, tmp, pM11, pM12, pM22, pA11, pA12, pA21, pA22, &wM12, &wA11, &wA12, &wA21, &wA22,
@@ -1495,27 +1891,7 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         CK(dalloc_t(p, OL, &p->Wf32, (size_t)Dp * 2 * Dp));
         CKH(to_f32(Z64, p->Zf32, (long)Dp * Dp, p->st));
         CKH(to_f32(W64, p->Wf32, (long)Dp * 2 * Dp, p->st));
-        // adjoint operators in whitened coordinates
-        double *ZT64w, *Y64w;
-        CK(dalloc_t(p, tmp, &ZT64w, (size_t)Dp * Dp));
-        CK(dalloc_t(p, tmp, &Y64w, (size_t)2 * Dp * Dp));
-        CKH(place(ZT64w, Dp, 0, 0, Z64, Dp, Dp, Dp, 1.0, 1, p->st));
-        CK(build_adj_state_op(p, p->Aw64, wM12, d2p, dt_fine, Y64w));
-        CK(dalloc_t(p, OL, &p->ZT32, (size_t)Dp * Dp));
-        CK(dalloc_t(p, OL, &p->Yop32, (size_t)2 * Dp * Dp));
-        CKH(to_f32(ZT64w, p->ZT32, (long)Dp * Dp, p->st));
-        CKH(to_f32(Y64w, p->Yop32, (long)2 * Dp * Dp, p->st));
-        CK(dalloc_t(p, OL, &p->TinT64, (size_t)Dp * Dp));
-        CKH(place(p->TinT64, Dp, 0, 0, p->Tin64, Dp, Dp, Dp, 1.0, 1, p->st));
-        // whitened mass [[I, M~12], [M~21, I]]
-        CK(dalloc_t(p, OL, &p->Mw64, (size_t)Dp * Dp));
-        CKH(hipMemsetAsync(p->Mw64, 0, sizeof(double) * Dp * Dp, p->st));
-        CKH(place(p->Mw64, Dp, 0, 0, I11, d1p, d1, d1, 1.0, 0, p->st));
-        if (d2 > 0) {
-            CKH(place(p->Mw64, Dp, d1p, d1p, I22inv, nf2, d2, d2, 1.0, 0, p->st));
-            CKH(place(p->Mw64, Dp, 0, d1p, wM12, d2p, d1, d2, 1.0, 0, p->st));
-            CKH(place(p->Mw64, Dp, d1p, 0, wM12, d2p, d2, d1, 1.0, 1, p->st));
-        }
+        CKH(hipMemcpyAsync(p->M12k, wM12, sizeof(double) * m12n, hipMemcpyDeviceToDevice, p->st));
     }
     CKH(hipStreamSynchronize(p->st));
     free_list(tmp);
@@ -1759,6 +2135,7 @@ pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH,
     if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
     const bool fdh = dH && p->src_set && p->src_kind == 2;
     PE_TRY(ensure_workspace(p, B));
+    PE_TRY(ensure_adj_ops(p));
     PE_TRY(ensure_adj_workspace(p, B, true, false, fdh));
     const long rowsX = (long)B * (p->N + 1);
     PE_HIP(pack_states(Ybnd, p->Yb, rowsX, p->d1, p->d2, p->d1p, p->d2p, p->st));
@@ -1786,6 +2163,7 @@ pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const
     const bool fdh = track && dH && p->src_set && p->src_kind == 2;
     const bool mixed = p->prec == PE_MIXED;
     PE_TRY(ensure_workspace(p, B));
+    PE_TRY(ensure_adj_ops(p));
     PE_TRY(ensure_adj_workspace(p, B, track, rho_all, fdh));
     const int N = p->N, Dp = p->Dp;
     const long ldX = (long)(N + 1) * Dp;
@@ -1889,6 +2267,181 @@ pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const
     PE_HIP(hipStreamSynchronize(p->st));
     PE_TRY(prof_collect(p));
     return n_active > 0 ? PE_WARN_NOT_CONVERGED : PE_OK;
+}
+
+pe_status pe_batch_create(pe_batch* out, int count, const pe_problem* problems, void* hip_stream) {
+    g_err.clear();
+    if (!out || count < 1 || !problems) return fail(PE_ERR_ARG, "bad arguments");
+    *out = nullptr;
+    for (int i = 0; i < count; ++i)
+        if (!problems[i]) return fail(PE_ERR_ARG, "null problem handle in the batch");
+    const int prec = problems[0]->prec, P = problems[0]->P;
+    for (int i = 1; i < count; ++i) {
+        if (problems[i]->prec != prec) return fail(PE_ERR_ARG, "all problems of a batch need the same precision");
+        if (problems[i]->P != P) return fail(PE_ERR_ARG, "all problems of a batch need the same step ratio P");
+    }
+    pe_batch bt = new pe_batch_s();
+    bt->count = count;
+    bt->prec = prec;
+    bt->P = P;
+    bt->pr.assign(problems, problems + count);
+    for (pe_problem p : bt->pr) bt->N_max = std::max(bt->N_max, p->N);
+    const char* gr = getenv("PE_GRAPHS");
+    bt->gc.use_graphs = (gr && gr[0] == '0') ? 0 : 1;
+    bt->cfg.br = 64;
+    bt->cfg.bs = 64;
+    bt->cfg.splitk = 1;
+    bt->cfg.bk2 = prec == PE_MIXED ? 1 : 0;
+    if (const char* t = getenv("PE_BATCH_TILE")) {
+        int br = 0, bs = 0, bk2 = 0;
+        if (sscanf(t, "%d %d %d", &br, &bs, &bk2) == 3 && (br == 32 || br == 64) && bs == 64) {
+            bt->cfg.br = br;
+            bt->cfg.bk2 = bk2 ? 1 : 0;
+        }
+    }
+    if (hip_stream) {
+        bt->st = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&bt->st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            delete bt;
+            return fail(PE_ERR_HIP, "stream creation failed");
+        }
+        bt->own_stream = 1;
+    }
+    *out = bt;
+    return PE_OK;
+}
+
+pe_status pe_batch_destroy(pe_batch bt) {
+    if (!bt) return PE_OK;
+    (void)hipStreamSynchronize(bt->st);
+    bt->gc.clear();
+    for (void* v : bt->allocs) (void)hipFree(v);
+    if (bt->own_stream) (void)hipStreamDestroy(bt->st);
+    delete bt;
+    return PE_OK;
+}
+
+pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int norm_mode, int k_max,
+                         double* const* X, int* iters) {
+    g_err.clear();
+    if (!bt || !x0 || !X) return fail(PE_ERR_ARG, "bad arguments");
+    if (!(tol >= 0) || k_max < 0) return fail(PE_ERR_ARG, "need tol >= 0 and k_max >= 0");
+    if (norm_mode != PE_NORM_M_ABS && norm_mode != PE_NORM_M_REL) return fail(PE_ERR_ARG, "unknown norm_mode");
+    const int G = bt->count;
+    for (int g = 0; g < G; ++g)
+        if (!x0[g] || !X[g]) return fail(PE_ERR_ARG, "null state pointer for problem " + std::to_string(g));
+    // samples per problem: the B of its source (1 without a source)
+    bt->Bs.assign(G, 1);
+    for (int g = 0; g < G; ++g) {
+        pe_problem p = bt->pr[g];
+        if (p->src_set) bt->Bs[g] = p->B_src;
+        PE_TRY(ensure_workspace(p, bt->Bs[g]));
+        PE_HIP(hipStreamSynchronize(p->st));
+    }
+    if (!bt->planned || batch_plan_keys(bt) != bt->plan_keys) PE_TRY(batch_plan(bt));
+    const bool mixed = bt->prec == PE_MIXED;
+    const long rel = norm_mode == PE_NORM_M_REL ? 1 : 0;
+    std::vector<int> act(bt->J_total, 1), conv(bt->J_total, 0), kcap(G);
+    std::vector<double> thr(bt->J_total, tol), J(bt->J_total, 0.0);
+    if (iters)
+        for (int i = 0; i < bt->J_total; ++i) iters[i] = 0;
+    for (int g = 0; g < G; ++g) {
+        pe_problem p = bt->pr[g];
+        kcap[g] = std::min(k_max, p->N);
+        PE_HIP(pack_states(x0[g], p->x0p, bt->Bs[g], p->d1, p->d2, p->d1p, p->d2p, bt->st));
+        PE_HIP(hipMemcpyAsync(p->active_d, act.data(), sizeof(int) * bt->Bs[g], hipMemcpyHostToDevice, bt->st));
+    }
+    int cur = 0;
+    PE_TRY(graph_run_on(bt->gc, bt->st, false, {0, rel}, [&]() -> pe_status {
+        for (int g = 0; g < G; ++g) {
+            pe_problem p = bt->pr[g];
+            PE_HIP(set_x0(p->x0p, p->Xk[0], (long)(p->N + 1) * p->Dp, bt->Bs[g], p->Dp, bt->st));
+        }
+        for (int n = 0; n < bt->N_max; ++n)
+            PE_HIP(coarse_grouped_launch<double>(bt->c_init, bt->c_wg_item, bt->c_wg_row, bt->c_nwg[n], n, 0, 0,
+                                                 bt->st));
+        if (rel) PE_TRY(batch_jumps(bt, 0, true));
+        return PE_OK;
+    }));
+    if (rel) {
+        PE_HIP(hipMemcpyAsync(thr.data(), bt->J_all, sizeof(double) * bt->J_total, hipMemcpyDeviceToHost, bt->st));
+        PE_HIP(hipStreamSynchronize(bt->st));
+        for (double& t : thr) t *= tol;
+    }
+    // samples of problems with no iteration allowed are done at once
+    for (int g = 0; g < G; ++g)
+        if (kcap[g] == 0)
+            for (int b = 0; b < bt->Bs[g]; ++b) act[bt->J_off[g] + b] = 0;
+    auto n_act = [&]() { return (int)std::count(act.begin(), act.end(), 1); };
+    std::vector<int> pushed(act);
+    for (int k = 1; n_act() > 0; ++k) {
+        const int nxt = 1 - cur;
+        // active flags to the device where they changed
+        for (int g = 0; g < G; ++g) {
+            const int o = bt->J_off[g];
+            if (!std::equal(act.begin() + o, act.begin() + o + bt->Bs[g], pushed.begin() + o)) {
+                PE_HIP(hipMemcpyAsync(bt->pr[g]->active_d, act.data() + o, sizeof(int) * bt->Bs[g],
+                                      hipMemcpyHostToDevice, bt->st));
+                std::copy(act.begin() + o, act.begin() + o + bt->Bs[g], pushed.begin() + o);
+            }
+        }
+        if (mixed && k >= 2)
+            PE_TRY(graph_run_on(bt->gc, bt->st, false, {1, 2}, [&]() { return batch_fine_sweep(bt, cur, true); }));
+        else
+            PE_TRY(graph_run_on(bt->gc, bt->st, false, {1, cur}, [&]() { return batch_fine_sweep(bt, cur, false); }));
+        for (int g = 0; g < G; ++g) {
+            pe_problem p = bt->pr[g];
+            const int o = bt->J_off[g];
+            if (std::count(act.begin() + o, act.begin() + o + bt->Bs[g], 1) < bt->Bs[g])
+                PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, (long)(p->N + 1) * p->Dp, bt->Bs[g],
+                                       bt->st));
+        }
+        PE_TRY(graph_run_on(bt->gc, bt->st, false, {2, cur}, [&]() -> pe_status {
+            for (int g = 0; g < G; ++g) {
+                pe_problem p = bt->pr[g];
+                PE_HIP(set_x0(p->x0p, p->Xk[nxt], (long)(p->N + 1) * p->Dp, bt->Bs[g], p->Dp, bt->st));
+                PE_HIP(zero_fill(mixed ? nullptr : p->Dl64[0], mixed ? p->Dl32[0] : nullptr, (long)bt->Bs[g] * p->Dp,
+                                 bt->st));
+            }
+            for (int n = 0; n < bt->N_max; ++n) {
+                if (mixed)
+                    PE_HIP(coarse_grouped_launch<float>(bt->c_corr[cur], bt->c_wg_item, bt->c_wg_row, bt->c_nwg[n], n,
+                                                        1, n & 1, bt->st));
+                else
+                    PE_HIP(coarse_grouped_launch<double>(bt->c_corr[cur], bt->c_wg_item, bt->c_wg_row, bt->c_nwg[n],
+                                                         n, 1, n & 1, bt->st));
+            }
+            PE_TRY(batch_jumps(bt, nxt, false));
+            return PE_OK;
+        }));
+        PE_HIP(hipMemcpyAsync(J.data(), bt->J_all, sizeof(double) * bt->J_total, hipMemcpyDeviceToHost, bt->st));
+        PE_HIP(hipStreamSynchronize(bt->st));
+        cur = nxt;
+        for (int g = 0; g < G; ++g) {
+            for (int b = 0; b < bt->Bs[g]; ++b) {
+                const int i = bt->J_off[g] + b;
+                if (!act[i]) continue;
+                if (!std::isfinite(J[i]))
+                    return fail(PE_ERR_NONFINITE, "non-finite parareal jump for problem " + std::to_string(g) +
+                                                      " sample " + std::to_string(b) + " at iteration " +
+                                                      std::to_string(k));
+                if (iters) iters[i] = k;
+                if (J[i] <= thr[i]) conv[i] = 1;
+                if (conv[i] || k >= kcap[g]) act[i] = 0;
+            }
+        }
+    }
+    bool all_conv = true;
+    for (int g = 0; g < G; ++g) {
+        pe_problem p = bt->pr[g];
+        PE_HIP(unpack_states(p->Xk[cur], X[g], (long)bt->Bs[g] * (p->N + 1), p->d1, p->d2, p->d1p, p->d2p, bt->st));
+    }
+    for (int i = 0; i < bt->J_total; ++i)
+        if (!conv[i]) all_conv = false;
+    PE_HIP(hipStreamSynchronize(bt->st));
+    return all_conv ? PE_OK : PE_WARN_NOT_CONVERGED;
 }
 
 }  // extern "C"

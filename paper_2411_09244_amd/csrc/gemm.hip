@@ -160,10 +160,10 @@ __device__ inline void epilogue(const Epi& e, int r, int s, double acc) {
 // ---------------------------------------------------------------------------
 // kernel
 // ---------------------------------------------------------------------------
+// one BR x BS output tile (or its split-K part) of C = epi(A B^T)
 template <typename T, int BR, int BS, int BK>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const Epi epi,
-                                                      const int tiles_r, const int splitk,
-                                                      T* __restrict__ part) {
+__device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, const int tiles_r, const int tile,
+                                          const int split, const int splitk, T* __restrict__ part) {
     using Op = MfmaOp<T>;
     using acc_t = typename Op::acc_t;
     using vec_t = typename Op::vec_t;
@@ -184,8 +184,6 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wr = wave & 1, wsi = wave >> 1;
-    const int tile = blockIdx.x;
-    const int split = blockIdx.y;
     const int tr = tile % tiles_r, ts = tile / tiles_r;
     const int r0 = tr * BR, s0 = ts * BS;
     const int s1 = min(s0 + BS, sh.Ns);
@@ -325,6 +323,22 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
             }
 }
 
+template <typename T, int BR, int BS, int BK>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const Epi epi, const int tiles_r,
+                                                      const int splitk, T* __restrict__ part) {
+    gemm_tile<T, BR, BS, BK>(sh, epi, tiles_r, blockIdx.x, blockIdx.y, splitk, part);
+}
+
+// grouped products: work-group w computes tile wg_tile[w] of product
+// wg_item[w] (each product with its own shape, operands and epilogue)
+template <typename T, int BR, int BS, int BK>
+__global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmItem* __restrict__ items,
+                                                           const int* __restrict__ wg_item,
+                                                           const int* __restrict__ wg_tile) {
+    const GemmItem& it = items[wg_item[blockIdx.x]];
+    gemm_tile<T, BR, BS, BK>(it.sh, it.epi, it.tiles_r, wg_tile[blockIdx.x], 0, 1, nullptr);
+}
+
 // sum of the split-K planes in split order, then the epilogue; one thread per element
 template <typename T>
 __global__ __launch_bounds__(256) void splitk_epilogue_kernel(const int Mr, const int Ns, const int splitk,
@@ -444,15 +458,17 @@ static hipError_t launch_gemv(const GemmShape& sh, const Epi& epi, hipStream_t s
     return hipGetLastError();
 }
 
+bool gemm_shape_ok(const GemmShape& sh, size_t elem) {
+    const long vw = 16 / (long)elem;
+    return !((sh.lda % vw) || (sh.ldb % vw) || (sh.k0a % vw) || (sh.k0b % vw) || (sh.k1a % vw) ||
+             (sh.k1b % vw) || (((uintptr_t)sh.A) % 16) || (((uintptr_t)sh.B) % 16));
+}
+
 template <typename T>
 hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, GemmWork& ws,
                        hipStream_t stream) {
     if (sh.Mr <= 0 || sh.Ns <= 0) return hipSuccess;
-    // operand offsets and strides must keep 16-byte vector loads aligned
-    const long vw = 16 / sizeof(T);
-    if ((sh.lda % vw) || (sh.ldb % vw) || (sh.k0a % vw) || (sh.k0b % vw) || (sh.k1a % vw) ||
-        (sh.k1b % vw) || (((uintptr_t)sh.A) % 16) || (((uintptr_t)sh.B) % 16))
-        return hipErrorInvalidValue;
+    if (!gemm_shape_ok(sh, sizeof(T))) return hipErrorInvalidValue;
     if (sh.Mr <= 4) return launch_gemv<T>(sh, epi, stream);
     const int sk = cfg.splitk < 1 ? 1 : cfg.splitk;
     constexpr int B0 = MfmaOp<T>::BK;  // base K depth: 32 (FP32), 16 (FP64)
@@ -470,6 +486,108 @@ hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, 
 #undef PE_CFG
     return hipErrorInvalidValue;
 }
+
+template <typename T>
+hipError_t gemm_grouped_launch(const GemmItem* items, const int* wg_item, const int* wg_tile, int n_wg,
+                               const TileCfg& cfg, hipStream_t stream) {
+    if (n_wg <= 0) return hipSuccess;
+    constexpr int B0 = MfmaOp<T>::BK;
+    const bool deep = cfg.bk2 != 0;
+#define PE_GCFG(R, S)                                                                                      \
+    if (cfg.br == R && cfg.bs == S) {                                                                     \
+        if (deep)                                                                                          \
+            hipLaunchKernelGGL((gemm_grouped_kernel<T, R, S, 2 * B0>), dim3((unsigned)n_wg), dim3(256), 0, \
+                               stream, items, wg_item, wg_tile);                                           \
+        else                                                                                               \
+            hipLaunchKernelGGL((gemm_grouped_kernel<T, R, S, B0>), dim3((unsigned)n_wg), dim3(256), 0,     \
+                               stream, items, wg_item, wg_tile);                                           \
+        return hipGetLastError();                                                                          \
+    }
+    PE_GCFG(64, 64)
+    PE_GCFG(32, 64)
+#undef PE_GCFG
+    return hipErrorInvalidValue;
+}
+
+// grouped coarse step: one wave per operator row of one problem, its samples
+// in chunks of 4, wave reduction, epilogue by lane 0
+template <typename T>
+__global__ __launch_bounds__(256) void coarse_grouped_kernel(const CoarseItem* __restrict__ items,
+                                                             const int* __restrict__ wg_item,
+                                                             const int* __restrict__ wg_row, const int n,
+                                                             const int delta, const int c) {
+    using vec_t = typename MfmaOp<T>::vec_t;
+    constexpr int VW = 16 / sizeof(T);
+    const CoarseItem& it = items[wg_item[blockIdx.x]];
+    if (n >= it.N) return;
+    const int lane = threadIdx.x & 63;
+    const int s = wg_row[blockIdx.x] * 4 + (threadIdx.x >> 6);
+    if (s >= it.Dp) return;
+    const int Dp = it.Dp;
+    const T* __restrict__ Phi = (const T*)(sizeof(T) == 4 ? (const void*)it.Phi32 : (const void*)it.Phi64) +
+                                (long)s * Dp;
+    const T* Dl = (const T*)(sizeof(T) == 4 ? (const void*)it.Dl32[c] : (const void*)it.Dl64[c]);
+    for (int b0 = 0; b0 < it.B; b0 += 4) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = VW * lane; k < Dp; k += 64 * VW) {
+            const vec_t w = *(const vec_t*)(Phi + k);
+            const T* wp = (const T*)&w;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int b = b0 + r;
+                if (b < it.B) {
+                    const T* v = delta ? Dl + (long)b * Dp : (const T*)(it.Xk + (long)b * it.ldX + (long)n * Dp);
+                    const vec_t x = *(const vec_t*)(v + k);
+                    const T* xp = (const T*)&x;
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) acc[r] += (double)wp[q] * (double)xp[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off, 64);
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int b = b0 + r;
+                if (b >= it.B) break;
+                const long ox = (long)b * it.ldX + (long)(n + 1) * Dp + s;
+                const long of = ((long)b * it.N + n) * Dp + s;
+                if (!delta) {
+                    it.Xk[ox] = acc[r] + (it.cs ? it.cs[of] : 0.0);
+                } else {
+                    if (it.active && !it.active[b]) continue;
+                    const double x = it.Fbuf[of] + acc[r];
+                    it.Xk[ox] = x;
+                    const double d = x - it.Xprev[ox];
+                    if (sizeof(T) == 4)
+                        it.Dl32[1 - c][(long)b * Dp + s] = (float)d;
+                    else
+                        it.Dl64[1 - c][(long)b * Dp + s] = d;
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t coarse_grouped_launch(const CoarseItem* items, const int* wg_item, const int* wg_row, int n_wg, int n,
+                                 int delta, int c, hipStream_t stream) {
+    if (n_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL((coarse_grouped_kernel<T>), dim3((unsigned)n_wg), dim3(256), 0, stream, items, wg_item,
+                       wg_row, n, delta, c);
+    return hipGetLastError();
+}
+
+template hipError_t gemm_grouped_launch<float>(const GemmItem*, const int*, const int*, int, const TileCfg&,
+                                               hipStream_t);
+template hipError_t gemm_grouped_launch<double>(const GemmItem*, const int*, const int*, int, const TileCfg&,
+                                                hipStream_t);
+template hipError_t coarse_grouped_launch<float>(const CoarseItem*, const int*, const int*, int, int, int, int,
+                                                 hipStream_t);
+template hipError_t coarse_grouped_launch<double>(const CoarseItem*, const int*, const int*, int, int, int, int,
+                                                  hipStream_t);
 
 template hipError_t gemm_launch<float>(const GemmShape&, const Epi&, const TileCfg&, GemmWork&,
                                        hipStream_t);

@@ -111,11 +111,51 @@ struct GemmWork {
     void* between_arg = nullptr;
 };
 
+// One product of a grouped launch (device-resident array of these).
+struct GemmItem {
+    GemmShape sh;
+    Epi epi;
+    int tiles_r = 1;  // row tiles of this product for the launch's tile shape
+};
+
+// One problem of a grouped coarse step (device-resident array of these):
+// x_{n+1} = Phi x_n + c_n (initial sweep, FP64) or the delta-form correction
+// x_{n+1}^k = F_n + Phi (x_n^k - x_n^{k-1}) in the path's precision.
+struct CoarseItem {
+    const double* Phi64 = nullptr;  // Dp x Dp
+    const float* Phi32 = nullptr;
+    int Dp = 0, B = 0, N = 0;
+    long ldX = 0;                   // (N+1) * Dp
+    double* Xk = nullptr;           // X^k (B x (N+1) x Dp)
+    const double* Xprev = nullptr;  // X^{k-1}
+    const double* cs = nullptr;     // B x N x Dp coarse source terms (nullable)
+    const double* Fbuf = nullptr;   // B x N x Dp fine values
+    double* Dl64[2] = {nullptr, nullptr};  // B x Dp changes (ping-pong)
+    float* Dl32[2] = {nullptr, nullptr};
+    const int* active = nullptr;    // B flags (nullable: all active)
+};
+
 // Launch C = epi(A * B^T) in precision T (float: FP32 MFMA, double: FP64
 // MFMA). Returns hipSuccess or an error; throws nothing.
 template <typename T>
 hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, GemmWork& ws,
                        hipStream_t stream);
+
+// Grouped launch of n_wg work-groups over device-resident items (tile shape
+// cfg.br x cfg.bs, K depth per cfg.bk2; no split-K).
+template <typename T>
+hipError_t gemm_grouped_launch(const GemmItem* items, const int* wg_item, const int* wg_tile, int n_wg,
+                               const TileCfg& cfg, hipStream_t stream);
+
+// Grouped coarse step n over the first n_wg work-groups of the row table
+// (4 operator rows per work-group). delta = 0: initial sweep (FP64),
+// delta = 1: correction in precision T, reading changes Dl[c], writing Dl[1-c].
+template <typename T>
+hipError_t coarse_grouped_launch(const CoarseItem* items, const int* wg_item, const int* wg_row, int n_wg, int n,
+                                 int delta, int c, hipStream_t stream);
+
+// operand offsets, strides and addresses keep 16-byte vector loads aligned
+bool gemm_shape_ok(const GemmShape& sh, size_t elem);
 
 // Choose a tile configuration for a product of this shape.
 TileCfg choose_tiles(const GemmShape& sh, bool fp32, int n_cu);

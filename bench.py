@@ -149,6 +149,110 @@ def adjoint_leg(args, torch, pe, build_problem, precs):
     return res
 
 
+C2_WORKLOAD = ("256 independent solves in one batch: 8 generated media/space pairs (n_c at the octiles of "
+               "U{8..32}, n = 10 n_c, kappa = 1 + floor(n_c/4) horizontal and vertical channels of contrast "
+               "10^U(4,6), CEM-GMsFEM d1 = 2 n_c^2, d2 = 3 n_c^2), per solve N ~ U{16..128} intervals x P = 32, "
+               "8 Fourier modes with N(0,1) time-constant amplitudes, u0 = 0, rel tol 1e-7")
+
+
+def batch_main(args, torch, pe):
+    """Ragged batch: all solves advance together; each fine step is one
+    grouped launch per product over every solve's interval columns."""
+    import numpy as np
+    from problem.build import c2_workload
+    t0 = time.perf_counter()
+    pool, solves = c2_workload()
+    log(f"c2 pool of {len(pool)} built in {time.perf_counter() - t0:.1f}s; {len(solves)} solves, "
+        f"sum N = {sum(s['N'] for s in solves)}")
+    tol = 1e-7
+    keys = ("M11", "M12", "M22", "A11", "A12", "A22")
+    d1 = [pool[s["pool"]]["d1"] for s in solves]
+    d2 = [pool[s["pool"]]["d2"] for s in solves]
+    flops_res = sum(2.0 * (a * a + 4.0 * a * b + b * b) * s["N"] for a, b, s in zip(d1, d2, solves))
+    res = {}
+    precs = ["mixed"] if args.no_fp64 else ["mixed", "fp64"]
+    for prec in precs:
+        stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        handles = []
+        for s in solves:
+            p = pool[s["pool"]]
+            pr = pe.Problem({k: p[k] for k in keys}, p["dt"], p["dt_fine"], s["N"], precision=prec, stream=stream)
+            pr.set_source(p["G"], s["H"], "interval")
+            handles.append(pr)
+            if len(handles) % 64 == 0:
+                log(f"c2 {prec}: {len(handles)} problems set up ({time.perf_counter() - ts:.1f}s)")
+        bt = pe.Batch(handles)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - ts
+        x0s = [torch.zeros((1, h.D), dtype=torch.float64, device="cuda") for h in handles]
+        for _ in range(args.warmup):
+            bt.solve(x0s, tol=tol, norm="rel")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            Xs, its, st = bt.solve(x0s, tol=tol, norm="rel")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        bt.profile(True)
+        for _ in range(max(1, args.steps // 2)):
+            bt.solve(x0s, tol=tol, norm="rel")
+        prof = bt.profile_read()
+        bt.profile(False)
+        it = np.array([int(i[0]) for i in its])
+        res[prec] = dict(seconds=dt, setup=setup, prof=prof, iters=it, status=st,
+                         X={b: Xs[b][0].cpu().numpy() for b in range(len(solves)) if solves[b]["pool"] == 0})
+        log(f"c2 {prec}: {args.steps} batch solves in {dt:.3f}s ({len(solves) * args.steps / dt:.1f} solves/s), "
+            f"set-up {setup:.1f}s, iterations mean {it.mean():.2f} max {it.max()}; launch timing: " +
+            ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in prof.items() if v[1]))
+        bt.close()
+        for h in handles:
+            h.close()
+        del handles, bt, Xs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    mixed = res["mixed"]
+    ms, n = mixed["prof"]["fine_residual"]
+    avg = (ms / n) * 1e-3
+    out = {"metric": "batched parareal solves/sec (ragged batch)", "value": round(len(solves) * args.steps /
+           mixed["seconds"], 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * mixed["seconds"] / args.steps, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": C2_WORKLOAD, "name": "c2", "solves": len(solves),
+                      "sum_N": sum(s["N"] for s in solves), "P": 32, "precision": "FP32 MFMA grouped products",
+                      "iterations_mean": float(mixed["iters"].mean()), "iterations_max": int(mixed["iters"].max()),
+                      "setup_s": round(mixed["setup"], 2)},
+           "roofline": dict(kernel="gemm_grouped_kernel<float,64,64,64> fine-step residual products of all solves",
+                            bound="mfma", achieved=round(flops_res / avg / 1e12, 3), peak=PEAK_FP32_MFMA,
+                            unit="TFLOP/s", frac=round(flops_res / avg / 1e12 / PEAK_FP32_MFMA, 5), traffic=None,
+                            avg_launch_us=round(avg * 1e6, 3), launches=n, flops_per_launch=flops_res)}
+    if "fp64" in res:
+        f64 = res["fp64"]
+        out["fp64"] = {"value": round(len(solves) * args.steps / f64["seconds"], 3), "unit": "solves/s",
+                       "iterations_mean": float(f64["iters"].mean()), "setup_s": round(f64["setup"], 2)}
+        out["speedup_mixed_vs_fp64"] = round(f64["seconds"] / mixed["seconds"], 4)
+    if not args.no_cpu_baseline:
+        import oracle.scheme as S
+        sample = [b for b in range(len(solves)) if solves[b]["pool"] == 0][:2]
+        p0 = pool[0]
+        bl = S.Blocks.from_problem(p0)
+        t2 = time.perf_counter()
+        errs = {k: [] for k in res}
+        for b in sample:
+            bl_b = S.Blocks.from_problem(dict(p0, N=solves[b]["N"]))
+            src = S.Source(p0["G"], solves[b]["H"], S.TIME_INTERVAL, solves[b]["N"], bl_b.P)
+            r = S.parareal(bl_b, src, np.zeros(bl.D), tol, rel=True)
+            for k in res:
+                errs[k].append(S.rel_l2_M(bl_b, res[k]["X"][b], r["X"][r["K"]]))
+        dt_cpu = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": round(len(sample) / dt_cpu, 5), "unit": "solves/s", "cores": os.cpu_count(),
+                               "kind": "oracle", "sample": f"{len(sample)} solves of the smallest pool entry "
+                               f"(D = {bl.D}), FP64 NumPy/SciPy parareal, {dt_cpu:.1f}s"}
+        out["rel_l2_vs_oracle_sampled"] = {k: float(f"{max(v):.3e}") for k, v in errs.items()}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(p, tol):
     """The FP64 oracle's plain parareal on the same workload, one solve."""
     import numpy as np
@@ -173,6 +277,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c1")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2"],
+                    help="c1: one 200x200 problem (default line); c2: ragged batch of 256 solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint workload")
@@ -194,6 +300,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c2":
+        return batch_main(args, torch, pe)
     tol = 1e-7
     t0 = time.perf_counter()
     p = build_problem(args.config, verbose=False)

@@ -235,6 +235,12 @@ pe_status pe_batch_solve(pe_batch b, const double* const* x0, double tol, int no
                          double* const* X, int* iters);
 pe_status pe_batch_destroy(pe_batch b);
 
+/* pe_batch_profile / pe_batch_profile_read - launch timing of a batch's
+   grouped launches by class (PE_PROF_*), as pe_profile / pe_profile_read:
+   HIP event pairs on the batch's stream; sweeps run eagerly while enabled. */
+pe_status pe_batch_profile(pe_batch b, int enable);
+pe_status pe_batch_profile_read(pe_batch b, int kind, double* total_ms, long long* launches);
+
 /* launch classes timed by pe_profile */
 enum {
     PE_PROF_FINE_RESIDUAL = 0,  /* fine step, R = F - A x_a - W dev (steps 2..P)  */

@@ -26,7 +26,7 @@ PE_NORM_M_REL = 1
 # every entry point declared in include/pe.h
 EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate",
            "pe_coarse_propagate", "pe_mass_norms", "pe_adjoint", "pe_tracking", "pe_batch_create", "pe_batch_solve",
-           "pe_batch_destroy", "pe_profile", "pe_profile_read",
+           "pe_batch_destroy", "pe_batch_profile", "pe_batch_profile_read", "pe_profile", "pe_profile_read",
            "pe_autotune", "pe_last_tiles", "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
 PROFILE_KINDS = {"fine_residual": 0, "fine_increment": 1, "fine_first": 2, "anchor": 3,
@@ -65,6 +65,8 @@ def load():
     lib.pe_batch_create.argtypes = [ctypes.POINTER(vp), ci, vp, vp]
     lib.pe_batch_solve.argtypes = [vp, vp, cd, ci, ci, vp, vp]
     lib.pe_batch_destroy.argtypes = [vp]
+    lib.pe_batch_profile.argtypes = [vp, ci]
+    lib.pe_batch_profile_read.argtypes = [vp, ci, vp, vp]
     lib.pe_problem_info.argtypes = [vp, vp, vp, vp, vp]
     lib.pe_profile.argtypes = [vp, ci]
     lib.pe_autotune.argtypes = [vp, ci]

@@ -219,6 +219,20 @@ class Batch:
         off = np.cumsum([0] + nb)
         return Xs, [iters[off[i]:off[i + 1]] for i in range(len(nb))], st
 
+    def profile(self, enable=True):
+        """Enable/disable per-launch HIP-event timing of the grouped launches."""
+        L.check(self.lib.pe_batch_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kind: (total GPU ms, launches)} since the last profile() call."""
+        out = {}
+        for name, k in L.PROFILE_KINDS.items():
+            ms = ctypes.c_double()
+            n = ctypes.c_longlong()
+            L.check(self.lib.pe_batch_profile_read(self.handle, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.pe_batch_destroy(self.handle)

@@ -77,6 +77,28 @@ struct GraphCache {
     }
 };
 
+// launch timing: HIP event pairs around each launch of a class, recorded on
+// the owner's stream, folded into per-class totals when the stream is idle
+struct Prof {
+    int on = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> pending;  // (kind, index of first event)
+    double ms[PE_PROF_KINDS] = {0};
+    long long n[PE_PROF_KINDS] = {0};
+    void reset() {
+        pending.clear();
+        used = 0;
+        for (int k = 0; k < PE_PROF_KINDS; ++k) {
+            ms[k] = 0.0;
+            n[k] = 0;
+        }
+    }
+    ~Prof() {
+        for (hipEvent_t ev : pool) (void)hipEventDestroy(ev);
+    }
+};
+
 struct pe_problem_s {
     int d1 = 0, d2 = 0, D = 0, d1p = 0, d2p = 0, Dp = 0, N = 0, P = 0;
     double dt = 0, dtf = 0;
@@ -149,12 +171,7 @@ struct pe_problem_s {
 
     // launch timing (pe_profile): HIP event pairs around each launch of a
     // kernel class, on the handle's stream
-    int prof_on = 0;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    std::vector<std::pair<int, size_t>> ev_pending;  // (kind, index of first event)
-    double prof_ms[PE_PROF_KINDS] = {0};
-    long long prof_n[PE_PROF_KINDS] = {0};
+    Prof prof;
 
     // tile configuration of the last launch of each profiled class
     int last_cfg[PE_PROF_KINDS][4] = {{0}};
@@ -215,39 +232,45 @@ pe_status ensure_gemm_work(pe_problem p, size_t part_bytes) {
     return PE_OK;
 }
 
-pe_status prof_begin(pe_problem p, int kind, size_t* slot) {
+pe_status prof_begin_on(Prof& pf, hipStream_t st, int kind, size_t* slot) {
     *slot = (size_t)-1;
-    if (!p->prof_on || kind < 0) return PE_OK;
-    while (p->ev_pool.size() < p->ev_used + 2) {
+    if (!pf.on || kind < 0) return PE_OK;
+    while (pf.pool.size() < pf.used + 2) {
         hipEvent_t ev;
         PE_HIP(hipEventCreate(&ev));
-        p->ev_pool.push_back(ev);
+        pf.pool.push_back(ev);
     }
-    *slot = p->ev_used;
-    p->ev_used += 2;
-    PE_HIP(hipEventRecord(p->ev_pool[*slot], p->st));
-    p->ev_pending.emplace_back(kind, *slot);
+    *slot = pf.used;
+    pf.used += 2;
+    PE_HIP(hipEventRecord(pf.pool[*slot], st));
+    pf.pending.emplace_back(kind, *slot);
     return PE_OK;
 }
 
-pe_status prof_end(pe_problem p, size_t slot) {
+pe_status prof_end_on(Prof& pf, hipStream_t st, size_t slot) {
     if (slot == (size_t)-1) return PE_OK;
-    PE_HIP(hipEventRecord(p->ev_pool[slot + 1], p->st));
+    PE_HIP(hipEventRecord(pf.pool[slot + 1], st));
     return PE_OK;
 }
+
+pe_status prof_collect_on(Prof& pf) {
+    for (auto& kv : pf.pending) {
+        float ms = 0.f;
+        PE_HIP(hipEventElapsedTime(&ms, pf.pool[kv.second], pf.pool[kv.second + 1]));
+        pf.ms[kv.first] += ms;
+        pf.n[kv.first] += 1;
+    }
+    pf.pending.clear();
+    pf.used = 0;
+    return PE_OK;
+}
+
+pe_status prof_begin(pe_problem p, int kind, size_t* slot) { return prof_begin_on(p->prof, p->st, kind, slot); }
+
+pe_status prof_end(pe_problem p, size_t slot) { return prof_end_on(p->prof, p->st, slot); }
 
 // fold completed event pairs into the per-kind totals (stream must be idle)
-pe_status prof_collect(pe_problem p) {
-    for (auto& kv : p->ev_pending) {
-        float ms = 0.f;
-        PE_HIP(hipEventElapsedTime(&ms, p->ev_pool[kv.second], p->ev_pool[kv.second + 1]));
-        p->prof_ms[kv.first] += ms;
-        p->prof_n[kv.first] += 1;
-    }
-    p->ev_pending.clear();
-    p->ev_used = 0;
-    return PE_OK;
-}
+pe_status prof_collect(pe_problem p) { return prof_collect_on(p->prof); }
 
 // ---------------------------------------------------------------------------
 // HIP graphs: a sweep's launches are recorded once (stream capture) and
@@ -302,7 +325,7 @@ pe_status graph_run_on(GraphCache& gc, hipStream_t st, bool eager, const std::ve
 
 template <typename Fn>
 pe_status graph_run(pe_problem p, const std::vector<long>& key, Fn&& fn) {
-    return graph_run_on(p->gc, p->st, p->prof_on != 0, key, fn);
+    return graph_run_on(p->gc, p->st, p->prof.on != 0, key, fn);
 }
 
 // ---------------------------------------------------------------------------
@@ -1308,6 +1331,7 @@ struct pe_batch_s {
     std::vector<int> order;  // problems by decreasing N
     double* J_all = nullptr;
     GraphCache gc;
+    Prof prof;
 };
 
 namespace {
@@ -1555,11 +1579,23 @@ pe_status batch_plan(pe_batch bt) {
 }
 
 template <typename T>
-pe_status grouped(pe_batch bt, const GroupPlan& g) {
+pe_status grouped(pe_batch bt, const GroupPlan& g, int kind) {
     TileCfg c = bt->cfg;
     if (sizeof(T) == 8) c.bk2 = 0;
+    size_t slot;
+    PE_TRY(prof_begin_on(bt->prof, bt->st, kind, &slot));
     const hipError_t e = gemm_grouped_launch<T>(g.items, g.wg_item, g.wg_tile, g.n_wg, c, bt->st);
     if (e != hipSuccess) return fail(PE_ERR_HIP, std::string("grouped product launch failed: ") + hipGetErrorString(e));
+    PE_TRY(prof_end_on(bt->prof, bt->st, slot));
+    return PE_OK;
+}
+
+template <typename T>
+pe_status coarse_grouped(pe_batch bt, const CoarseItem* items, int n, int delta, int c) {
+    size_t slot;
+    PE_TRY(prof_begin_on(bt->prof, bt->st, PE_PROF_COARSE, &slot));
+    PE_HIP(coarse_grouped_launch<T>(items, bt->c_wg_item, bt->c_wg_row, bt->c_nwg[n], n, delta, c, bt->st));
+    PE_TRY(prof_end_on(bt->prof, bt->st, slot));
     return PE_OK;
 }
 
@@ -1574,16 +1610,17 @@ pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
         PE_HIP(fine_init(Xs, ld, incremental ? -1 : 0, N, mixed ? p->R64 : p->Xa, p->dev64,
                          mixed ? p->dev32 : nullptr, B, N, Dp, bt->st));
     }
-    if (mixed) PE_TRY(grouped<double>(bt, bt->anc1));
-    PE_TRY(grouped<double>(bt, bt->anc2));
+    if (mixed) PE_TRY(grouped<double>(bt, bt->anc1, PE_PROF_ANCHOR));
+    PE_TRY(grouped<double>(bt, bt->anc2, PE_PROF_ANCHOR));
     for (int step = 0; step < bt->P; ++step) {
         const GroupPlan& r = bt->resid[incremental ? 0 : 1][step];
+        const int k1 = step > 0 ? PE_PROF_FINE_RESIDUAL : PE_PROF_FINE_FIRST;
         if (mixed) {
-            PE_TRY(grouped<float>(bt, r));
-            PE_TRY(grouped<float>(bt, bt->inc));
+            PE_TRY(grouped<float>(bt, r, k1));
+            PE_TRY(grouped<float>(bt, bt->inc, PE_PROF_FINE_INCREMENT));
         } else {
-            PE_TRY(grouped<double>(bt, r));
-            PE_TRY(grouped<double>(bt, bt->inc));
+            PE_TRY(grouped<double>(bt, r, k1));
+            PE_TRY(grouped<double>(bt, bt->inc, PE_PROF_FINE_INCREMENT));
         }
     }
     for (int g = 0; g < bt->count; ++g) {
@@ -1591,7 +1628,7 @@ pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
         const long rows = (long)bt->Bs[g] * p->N;
         PE_HIP(fine_final(p->Xa, p->dev64, mixed ? p->R64 : p->Fbuf, rows, p->Dp, p->d1p, 0, bt->st));
     }
-    if (mixed) PE_TRY(grouped<double>(bt, bt->fin[incremental ? 1 : 0]));
+    if (mixed) PE_TRY(grouped<double>(bt, bt->fin[incremental ? 1 : 0], PE_PROF_ANCHOR));
     return PE_OK;
 }
 
@@ -1604,7 +1641,7 @@ pe_status batch_jumps(pe_batch bt, int xk, bool rel) {
         PE_HIP(jump_diff(p->Xk[xk], rel ? nullptr : p->Xk[1 - xk], (long)(N + 1) * p->Dp, rel ? 0 : 1,
                          rel ? N + 1 : N, bt->Bs[g], p->Dp, p->E, bt->st));
     }
-    PE_TRY(grouped<double>(bt, rel ? bt->nrm_rel : bt->nrm_k));
+    PE_TRY(grouped<double>(bt, rel ? bt->nrm_rel : bt->nrm_k, PE_PROF_NORM));
     for (int g = 0; g < bt->count; ++g) {
         pe_problem p = bt->pr[g];
         PE_HIP(jump_reduce(p->E, p->Yn, bt->Bs[g], rel ? p->N + 1 : p->N, p->Dp, bt->J_all + bt->J_off[g], p->nrm,
@@ -1635,7 +1672,6 @@ pe_status pe_problem_destroy(pe_problem p) {
     free_list(p->ws_allocs);
     free_list(p->adj_allocs);
     free_list(p->op_allocs);
-    for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
     if (p->gw.part) (void)hipFree(p->gw.part);
     if (p->own_stream) (void)hipStreamDestroy(p->st);
     delete p;
@@ -1646,13 +1682,8 @@ pe_status pe_profile(pe_problem p, int enable) {
     g_err.clear();
     PE_TRY(check_handle(p));
     PE_HIP(hipStreamSynchronize(p->st));
-    p->ev_pending.clear();
-    p->ev_used = 0;
-    for (int k = 0; k < PE_PROF_KINDS; ++k) {
-        p->prof_ms[k] = 0.0;
-        p->prof_n[k] = 0;
-    }
-    p->prof_on = enable ? 1 : 0;
+    p->prof.reset();
+    p->prof.on = enable ? 1 : 0;
     return PE_OK;
 }
 
@@ -1662,8 +1693,8 @@ pe_status pe_profile_read(pe_problem p, int kind, double* total_ms, long long* l
     if (kind < 0 || kind >= PE_PROF_KINDS) return fail(PE_ERR_ARG, "unknown profile kind");
     PE_HIP(hipStreamSynchronize(p->st));
     PE_TRY(prof_collect(p));
-    if (total_ms) *total_ms = p->prof_ms[kind];
-    if (launches) *launches = p->prof_n[kind];
+    if (total_ms) *total_ms = p->prof.ms[kind];
+    if (launches) *launches = p->prof.n[kind];
     return PE_OK;
 }
 
@@ -1681,8 +1712,8 @@ pe_status pe_autotune(pe_problem p, int B) {
     if (s == PE_OK) s = jumps(p, B, p->Xk[0], nullptr, (long)(p->N + 1) * p->Dp, 1, p->N, nullptr, nullptr);
     p->autotune = save;
     PE_HIP(hipStreamSynchronize(p->st));
-    p->ev_pending.clear();
-    p->ev_used = 0;
+    p->prof.pending.clear();
+    p->prof.used = 0;
     return s;
 }
 
@@ -2313,6 +2344,26 @@ pe_status pe_batch_create(pe_batch* out, int count, const pe_problem* problems, 
     return PE_OK;
 }
 
+pe_status pe_batch_profile(pe_batch bt, int enable) {
+    g_err.clear();
+    if (!bt) return fail(PE_ERR_ARG, "null batch handle");
+    PE_HIP(hipStreamSynchronize(bt->st));
+    bt->prof.reset();
+    bt->prof.on = enable ? 1 : 0;
+    return PE_OK;
+}
+
+pe_status pe_batch_profile_read(pe_batch bt, int kind, double* total_ms, long long* launches) {
+    g_err.clear();
+    if (!bt) return fail(PE_ERR_ARG, "null batch handle");
+    if (kind < 0 || kind >= PE_PROF_KINDS) return fail(PE_ERR_ARG, "unknown profile kind");
+    PE_HIP(hipStreamSynchronize(bt->st));
+    PE_TRY(prof_collect_on(bt->prof));
+    if (total_ms) *total_ms = bt->prof.ms[kind];
+    if (launches) *launches = bt->prof.n[kind];
+    return PE_OK;
+}
+
 pe_status pe_batch_destroy(pe_batch bt) {
     if (!bt) return PE_OK;
     (void)hipStreamSynchronize(bt->st);
@@ -2354,14 +2405,12 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
         PE_HIP(hipMemcpyAsync(p->active_d, act.data(), sizeof(int) * bt->Bs[g], hipMemcpyHostToDevice, bt->st));
     }
     int cur = 0;
-    PE_TRY(graph_run_on(bt->gc, bt->st, false, {0, rel}, [&]() -> pe_status {
+    PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {0, rel}, [&]() -> pe_status {
         for (int g = 0; g < G; ++g) {
             pe_problem p = bt->pr[g];
             PE_HIP(set_x0(p->x0p, p->Xk[0], (long)(p->N + 1) * p->Dp, bt->Bs[g], p->Dp, bt->st));
         }
-        for (int n = 0; n < bt->N_max; ++n)
-            PE_HIP(coarse_grouped_launch<double>(bt->c_init, bt->c_wg_item, bt->c_wg_row, bt->c_nwg[n], n, 0, 0,
-                                                 bt->st));
+        for (int n = 0; n < bt->N_max; ++n) PE_TRY(coarse_grouped<double>(bt, bt->c_init, n, 0, 0));
         if (rel) PE_TRY(batch_jumps(bt, 0, true));
         return PE_OK;
     }));
@@ -2388,9 +2437,9 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
             }
         }
         if (mixed && k >= 2)
-            PE_TRY(graph_run_on(bt->gc, bt->st, false, {1, 2}, [&]() { return batch_fine_sweep(bt, cur, true); }));
+            PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {1, 2}, [&]() { return batch_fine_sweep(bt, cur, true); }));
         else
-            PE_TRY(graph_run_on(bt->gc, bt->st, false, {1, cur}, [&]() { return batch_fine_sweep(bt, cur, false); }));
+            PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {1, cur}, [&]() { return batch_fine_sweep(bt, cur, false); }));
         for (int g = 0; g < G; ++g) {
             pe_problem p = bt->pr[g];
             const int o = bt->J_off[g];
@@ -2398,7 +2447,7 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
                 PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, (long)(p->N + 1) * p->Dp, bt->Bs[g],
                                        bt->st));
         }
-        PE_TRY(graph_run_on(bt->gc, bt->st, false, {2, cur}, [&]() -> pe_status {
+        PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {2, cur}, [&]() -> pe_status {
             for (int g = 0; g < G; ++g) {
                 pe_problem p = bt->pr[g];
                 PE_HIP(set_x0(p->x0p, p->Xk[nxt], (long)(p->N + 1) * p->Dp, bt->Bs[g], p->Dp, bt->st));
@@ -2407,17 +2456,16 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
             }
             for (int n = 0; n < bt->N_max; ++n) {
                 if (mixed)
-                    PE_HIP(coarse_grouped_launch<float>(bt->c_corr[cur], bt->c_wg_item, bt->c_wg_row, bt->c_nwg[n], n,
-                                                        1, n & 1, bt->st));
+                    PE_TRY(coarse_grouped<float>(bt, bt->c_corr[cur], n, 1, n & 1));
                 else
-                    PE_HIP(coarse_grouped_launch<double>(bt->c_corr[cur], bt->c_wg_item, bt->c_wg_row, bt->c_nwg[n],
-                                                         n, 1, n & 1, bt->st));
+                    PE_TRY(coarse_grouped<double>(bt, bt->c_corr[cur], n, 1, n & 1));
             }
             PE_TRY(batch_jumps(bt, nxt, false));
             return PE_OK;
         }));
         PE_HIP(hipMemcpyAsync(J.data(), bt->J_all, sizeof(double) * bt->J_total, hipMemcpyDeviceToHost, bt->st));
         PE_HIP(hipStreamSynchronize(bt->st));
+        PE_TRY(prof_collect_on(bt->prof));
         cur = nxt;
         for (int g = 0; g < G; ++g) {
             for (int b = 0; b < bt->Bs[g]; ++b) {
@@ -2441,6 +2489,7 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
     for (int i = 0; i < bt->J_total; ++i)
         if (!conv[i]) all_conv = false;
     PE_HIP(hipStreamSynchronize(bt->st));
+    PE_TRY(prof_collect_on(bt->prof));
     return all_conv ? PE_OK : PE_WARN_NOT_CONVERGED;
 }
 

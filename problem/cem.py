@@ -100,10 +100,11 @@ def cem_basis(cg, J, layers, spsi, return_checks=False):
     j < J find phi in H^1_0(K_i^+) and multipliers mu with
         a(phi, v) + s(mu, v) = 0  for all v,
         s(phi, nu) = s(psi_j^(i), nu)  for all nu in V_aux(K_i^+).
-    Discretely [A+ C^T; C 0][phi; mu] = [0; e_(i,j)], solved by a Schur
-    complement on the multipliers. Returns a list (per element) of
-    (full-grid node ids of the patch interior, (n_free, J) array of phi),
-    and optionally the constraint residuals."""
+    Discretely [A+ C^T; C 0][phi; mu] = [0; e_(i,j)], solved for the J
+    right-hand sides of element i with one sparse LU of the saddle-point
+    matrix of the patch. Returns a list (per element) of (full-grid node ids
+    of the patch interior, (n_free, J) array of phi), and optionally the
+    constraint residuals."""
     fine = cg.fine
     Kfull = fine.K_full.tocsr()
     n_nodes = fine.n_nodes
@@ -111,24 +112,30 @@ def cem_basis(cg, J, layers, spsi, return_checks=False):
     out, checks = [], []
     for i in range(cg.n_elem):
         elems, free_ids = cg.patch(i, layers)
-        lookup[free_ids] = np.arange(free_ids.size)
-        Ap = Kfull[free_ids][:, free_ids].tocsc()
-        n_aux = elems.size * J
-        C = np.zeros((n_aux, free_ids.size))
+        nf = free_ids.size
+        lookup[free_ids] = np.arange(nf)
+        Ap = Kfull[free_ids][:, free_ids]
+        rows, cols, vals = [], [], []
         for a, k in enumerate(elems):
             loc = lookup[cg.element_nodes(k)]
             keep = loc >= 0
-            C[a * J:(a + 1) * J, loc[keep]] = spsi[k][keep].T
-        lu = spla.splu(Ap)
-        Y = lu.solve(np.ascontiguousarray(C.T))
-        schur = C @ Y
+            for j in range(J):
+                rows.append(np.full(int(keep.sum()), a * J + j))
+                cols.append(loc[keep])
+                vals.append(spsi[k][keep, j])
+        n_aux = elems.size * J
+        C = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(n_aux, nf))
+        lu = spla.splu(sp.bmat([[Ap, C.T], [C, None]], format="csc"), permc_spec="MMD_AT_PLUS_A",
+                       diag_pivot_thresh=0.01, options=dict(SymmetricMode=True))
         a_i = int(np.flatnonzero(elems == i)[0])
-        E = np.zeros((n_aux, J))
-        E[a_i * J:(a_i + 1) * J, :] = np.eye(J)
-        mu = sla.solve(schur, E, assume_a="pos")
-        phi = Y @ mu
+        rhs = np.zeros((nf + n_aux, J))
+        rhs[nf + a_i * J + np.arange(J), np.arange(J)] = 1.0
+        phi = lu.solve(rhs)[:nf]
         out.append((free_ids.copy(), phi))
         if return_checks:
+            E = np.zeros((n_aux, J))
+            E[a_i * J:(a_i + 1) * J, :] = np.eye(J)
             checks.append(np.abs(C @ phi - E).max())
         lookup[free_ids] = -1
     return (out, checks) if return_checks else out

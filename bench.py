@@ -168,7 +168,10 @@ def batch_main(args, torch, pe):
     keys = ("M11", "M12", "M22", "A11", "A12", "A22")
     d1 = [pool[s["pool"]]["d1"] for s in solves]
     d2 = [pool[s["pool"]]["d2"] for s in solves]
-    flops_res = sum(2.0 * (a * a + 4.0 * a * b + b * b) * s["N"] for a, b, s in zip(d1, d2, solves))
+    # residual flops of one fine step of each solve (the launches only cover
+    # the solves still iterating: a solve takes part in (P - 1) residual
+    # launches per iteration it runs)
+    f_step = [2.0 * (a * a + 4.0 * a * b + b * b) * s["N"] for a, b, s in zip(d1, d2, solves)]
     res = {}
     precs = ["mixed"] if args.no_fp64 else ["mixed", "fp64"]
     for prec in precs:
@@ -196,12 +199,13 @@ def batch_main(args, torch, pe):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         bt.profile(True)
-        for _ in range(max(1, args.steps // 2)):
+        n_prof = max(1, args.steps // 2)
+        for _ in range(n_prof):
             bt.solve(x0s, tol=tol, norm="rel")
         prof = bt.profile_read()
         bt.profile(False)
         it = np.array([int(i[0]) for i in its])
-        res[prec] = dict(seconds=dt, setup=setup, prof=prof, iters=it, status=st,
+        res[prec] = dict(seconds=dt, setup=setup, prof=prof, iters=it, status=st, n_prof=n_prof,
                          X={b: Xs[b][0].cpu().numpy() for b in range(len(solves)) if solves[b]["pool"] == 0})
         log(f"c2 {prec}: {args.steps} batch solves in {dt:.3f}s ({len(solves) * args.steps / dt:.1f} solves/s), "
             f"set-up {setup:.1f}s, iterations mean {it.mean():.2f} max {it.max()}; launch timing: " +
@@ -215,6 +219,8 @@ def batch_main(args, torch, pe):
     mixed = res["mixed"]
     ms, n = mixed["prof"]["fine_residual"]
     avg = (ms / n) * 1e-3
+    flops_total = mixed["n_prof"] * sum(f * (32 - 1) * int(k) for f, k in zip(f_step, mixed["iters"]))
+    flops_res = flops_total / n
     out = {"metric": "batched parareal solves/sec (ragged batch)", "value": round(len(solves) * args.steps /
            mixed["seconds"], 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(1e3 * mixed["seconds"] / args.steps, 3), "higher_is_better": True,
@@ -226,7 +232,9 @@ def batch_main(args, torch, pe):
            "roofline": dict(kernel="gemm_grouped_kernel<float,64,64,64> fine-step residual products of all solves",
                             bound="mfma", achieved=round(flops_res / avg / 1e12, 3), peak=PEAK_FP32_MFMA,
                             unit="TFLOP/s", frac=round(flops_res / avg / 1e12 / PEAK_FP32_MFMA, 5), traffic=None,
-                            avg_launch_us=round(avg * 1e6, 3), launches=n, flops_per_launch=flops_res)}
+                            avg_launch_us=round(avg * 1e6, 3), launches=n, flops_per_launch=round(flops_res),
+                            flops_note="algorithmic residual flops of the solves each launch covered, "
+                                       "averaged over the launches of one profiled batch solve")}
     if "fp64" in res:
         f64 = res["fp64"]
         out["fp64"] = {"value": round(len(solves) * args.steps / f64["seconds"], 3), "unit": "solves/s",

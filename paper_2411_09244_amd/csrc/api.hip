@@ -1332,6 +1332,12 @@ struct pe_batch_s {
     double* J_all = nullptr;
     GraphCache gc;
     Prof prof;
+    // problems still iterating: finished ones leave the launch tables
+    std::vector<int> pact, fin_buf;
+    std::vector<long> t_fine, t_nk;  // tiles per problem of the fine and jump product families
+    int *fi_d = nullptr, *ft_d = nullptr, *ki_d = nullptr, *kt_d = nullptr;
+    int tables_all = 1;
+    long act_hash = 0;
 };
 
 namespace {
@@ -1400,6 +1406,8 @@ std::vector<const void*> batch_plan_keys(pe_batch bt) {
     }
     return k;
 }
+
+pe_status batch_tables(pe_batch bt);
 
 pe_status batch_plan(pe_batch bt) {
     PE_HIP(hipStreamSynchronize(bt->st));
@@ -1505,6 +1513,16 @@ pe_status batch_plan(pe_batch bt) {
     }
     PE_TRY(group_plan(bt, nrel_sh, e_nrel, sizeof(double), ri, rt, rn, &bt->nrm_rel));
     PE_TRY(group_plan(bt, nk_sh, e_nk, sizeof(double), ki, kt, kn, &bt->nrm_k));
+    bt->fi_d = (int*)fi;
+    bt->ft_d = (int*)ft;
+    bt->ki_d = (int*)ki;
+    bt->kt_d = (int*)kt;
+    bt->t_fine.assign(G, 0);
+    bt->t_nk.assign(G, 0);
+    for (int g = 0; g < G; ++g) {
+        bt->t_fine[g] = (long)((fine_sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br) * ((fine_sh[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
+        bt->t_nk[g] = (long)((nk_sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br) * ((nk_sh[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
+    }
 
     // coarse steps: problems by decreasing N, so the problems still running
     // at step n are a prefix of the row table
@@ -1575,6 +1593,63 @@ pe_status batch_plan(pe_batch bt) {
     bt->J_all = (double*)jd;
     bt->plan_keys = batch_plan_keys(bt);
     bt->planned = 1;
+    bt->pact.assign(G, 1);
+    PE_TRY(batch_tables(bt));
+    return PE_OK;
+}
+
+// Rebuild the work-group tables of the fine, jump and coarse launches for
+// the problems still iterating (bt->pact); the stream must be idle.
+pe_status batch_tables(pe_batch bt) {
+    const int G = bt->count;
+    std::vector<int> fi, ft, ki, kt, wi, wr;
+    for (int g = 0; g < G; ++g) {
+        if (!bt->pact[g]) continue;
+        for (long t = 0; t < bt->t_fine[g]; ++t) {
+            fi.push_back(g);
+            ft.push_back((int)t);
+        }
+        for (long t = 0; t < bt->t_nk[g]; ++t) {
+            ki.push_back(g);
+            kt.push_back((int)t);
+        }
+    }
+    std::vector<int> rows_upto(G + 1, 0);
+    for (int j = 0; j < G; ++j) {
+        const int g = bt->order[j];
+        if (bt->pact[g])
+            for (int r = 0; r < (bt->pr[g]->Dp + 3) / 4; ++r) {
+                wi.push_back(j);
+                wr.push_back(r);
+            }
+        rows_upto[j + 1] = (int)wi.size();
+    }
+    for (int n = 0; n < bt->N_max; ++n) {
+        int j = 0;
+        while (j < G && bt->pr[bt->order[j]]->N > n) ++j;
+        bt->c_nwg[n] = rows_upto[j];
+    }
+    auto put = [&](int* d, const std::vector<int>& v) -> pe_status {
+        if (!v.empty()) PE_HIP(hipMemcpy(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
+        return PE_OK;
+    };
+    PE_TRY(put(bt->fi_d, fi));
+    PE_TRY(put(bt->ft_d, ft));
+    PE_TRY(put(bt->ki_d, ki));
+    PE_TRY(put(bt->kt_d, kt));
+    PE_TRY(put(bt->c_wg_item, wi));
+    PE_TRY(put(bt->c_wg_row, wr));
+    const int fn = (int)fi.size(), kn = (int)ki.size();
+    for (GroupPlan* g : {&bt->anc1, &bt->anc2, &bt->inc, &bt->fin[0], &bt->fin[1]}) g->n_wg = fn;
+    for (int w = 0; w < 2; ++w)
+        for (GroupPlan& g : bt->resid[w]) g.n_wg = fn;
+    bt->nrm_k.n_wg = kn;
+    bt->tables_all = std::count(bt->pact.begin(), bt->pact.end(), 1) == G;
+    // graphs are keyed by the active set (the tables' content); repeated
+    // solves that pass through the same sets replay them
+    unsigned long long h = 1469598103934665603ULL;
+    for (int a : bt->pact) h = (h ^ (unsigned long long)(a + 1)) * 1099511628211ULL;
+    bt->act_hash = (long)(h >> 1);
     return PE_OK;
 }
 
@@ -1603,6 +1678,7 @@ pe_status coarse_grouped(pe_batch bt, const CoarseItem* items, int n, int delta,
 pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
     const bool mixed = bt->prec == PE_MIXED;
     for (int g = 0; g < bt->count; ++g) {
+        if (!bt->pact[g]) continue;
         pe_problem p = bt->pr[g];
         const int B = bt->Bs[g], N = p->N, Dp = p->Dp;
         const double* Xs = incremental ? p->E : p->Xk[cur];
@@ -1624,6 +1700,7 @@ pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
         }
     }
     for (int g = 0; g < bt->count; ++g) {
+        if (!bt->pact[g]) continue;
         pe_problem p = bt->pr[g];
         const long rows = (long)bt->Bs[g] * p->N;
         PE_HIP(fine_final(p->Xa, p->dev64, mixed ? p->R64 : p->Fbuf, rows, p->Dp, p->d1p, 0, bt->st));
@@ -1636,6 +1713,7 @@ pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
 // change of iterate xk against 1 - xk over n = 1..N
 pe_status batch_jumps(pe_batch bt, int xk, bool rel) {
     for (int g = 0; g < bt->count; ++g) {
+        if (!bt->pact[g]) continue;
         pe_problem p = bt->pr[g];
         const int N = p->N;
         PE_HIP(jump_diff(p->Xk[xk], rel ? nullptr : p->Xk[1 - xk], (long)(N + 1) * p->Dp, rel ? 0 : 1,
@@ -1643,6 +1721,7 @@ pe_status batch_jumps(pe_batch bt, int xk, bool rel) {
     }
     PE_TRY(grouped<double>(bt, rel ? bt->nrm_rel : bt->nrm_k, PE_PROF_NORM));
     for (int g = 0; g < bt->count; ++g) {
+        if (!bt->pact[g]) continue;
         pe_problem p = bt->pr[g];
         PE_HIP(jump_reduce(p->E, p->Yn, bt->Bs[g], rel ? p->N + 1 : p->N, p->Dp, bt->J_all + bt->J_off[g], p->nrm,
                            bt->st));
@@ -2392,6 +2471,10 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
         PE_HIP(hipStreamSynchronize(p->st));
     }
     if (!bt->planned || batch_plan_keys(bt) != bt->plan_keys) PE_TRY(batch_plan(bt));
+    PE_HIP(hipStreamSynchronize(bt->st));
+    bt->pact.assign(G, 1);
+    bt->fin_buf.assign(G, 0);
+    if (!bt->tables_all) PE_TRY(batch_tables(bt));
     const bool mixed = bt->prec == PE_MIXED;
     const long rel = norm_mode == PE_NORM_M_REL ? 1 : 0;
     std::vector<int> act(bt->J_total, 1), conv(bt->J_total, 0), kcap(G);
@@ -2420,15 +2503,21 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
         for (double& t : thr) t *= tol;
     }
     // samples of problems with no iteration allowed are done at once
+    bool shrink = false;
     for (int g = 0; g < G; ++g)
-        if (kcap[g] == 0)
+        if (kcap[g] == 0) {
             for (int b = 0; b < bt->Bs[g]; ++b) act[bt->J_off[g] + b] = 0;
+            bt->pact[g] = 0;
+            shrink = true;
+        }
     auto n_act = [&]() { return (int)std::count(act.begin(), act.end(), 1); };
+    if (shrink && n_act() > 0) PE_TRY(batch_tables(bt));
     std::vector<int> pushed(act);
     for (int k = 1; n_act() > 0; ++k) {
         const int nxt = 1 - cur;
         // active flags to the device where they changed
         for (int g = 0; g < G; ++g) {
+            if (!bt->pact[g]) continue;
             const int o = bt->J_off[g];
             if (!std::equal(act.begin() + o, act.begin() + o + bt->Bs[g], pushed.begin() + o)) {
                 PE_HIP(hipMemcpyAsync(bt->pr[g]->active_d, act.data() + o, sizeof(int) * bt->Bs[g],
@@ -2436,19 +2525,24 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
                 std::copy(act.begin() + o, act.begin() + o + bt->Bs[g], pushed.begin() + o);
             }
         }
+        const long ah = bt->act_hash;
         if (mixed && k >= 2)
-            PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {1, 2}, [&]() { return batch_fine_sweep(bt, cur, true); }));
+            PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {1, 2, ah},
+                                [&]() { return batch_fine_sweep(bt, cur, true); }));
         else
-            PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {1, cur}, [&]() { return batch_fine_sweep(bt, cur, false); }));
+            PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {1, cur, ah},
+                                [&]() { return batch_fine_sweep(bt, cur, false); }));
         for (int g = 0; g < G; ++g) {
+            if (!bt->pact[g]) continue;
             pe_problem p = bt->pr[g];
             const int o = bt->J_off[g];
             if (std::count(act.begin() + o, act.begin() + o + bt->Bs[g], 1) < bt->Bs[g])
                 PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, (long)(p->N + 1) * p->Dp, bt->Bs[g],
                                        bt->st));
         }
-        PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {2, cur}, [&]() -> pe_status {
+        PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {2, cur, ah}, [&]() -> pe_status {
             for (int g = 0; g < G; ++g) {
+                if (!bt->pact[g]) continue;
                 pe_problem p = bt->pr[g];
                 PE_HIP(set_x0(p->x0p, p->Xk[nxt], (long)(p->N + 1) * p->Dp, bt->Bs[g], p->Dp, bt->st));
                 PE_HIP(zero_fill(mixed ? nullptr : p->Dl64[0], mixed ? p->Dl32[0] : nullptr, (long)bt->Bs[g] * p->Dp,
@@ -2480,11 +2574,25 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
                 if (conv[i] || k >= kcap[g]) act[i] = 0;
             }
         }
+        // problems with no sample left leave the launches; their last
+        // iterate stays in buffer fin_buf
+        shrink = false;
+        for (int g = 0; g < G; ++g) {
+            if (!bt->pact[g]) continue;
+            const int o = bt->J_off[g];
+            if (std::count(act.begin() + o, act.begin() + o + bt->Bs[g], 1) == 0) {
+                bt->pact[g] = 0;
+                bt->fin_buf[g] = cur;
+                shrink = true;
+            }
+        }
+        if (shrink && n_act() > 0) PE_TRY(batch_tables(bt));
     }
     bool all_conv = true;
     for (int g = 0; g < G; ++g) {
         pe_problem p = bt->pr[g];
-        PE_HIP(unpack_states(p->Xk[cur], X[g], (long)bt->Bs[g] * (p->N + 1), p->d1, p->d2, p->d1p, p->d2p, bt->st));
+        const int fb = bt->pact[g] ? cur : bt->fin_buf[g];
+        PE_HIP(unpack_states(p->Xk[fb], X[g], (long)bt->Bs[g] * (p->N + 1), p->d1, p->d2, p->d1p, p->d2p, bt->st));
     }
     for (int i = 0; i < bt->J_total; ++i)
         if (!conv[i]) all_conv = false;

@@ -261,6 +261,94 @@ def batch_main(args, torch, pe):
     print(json.dumps(out), flush=True)
 
 
+C4_WORKLOAD = ("400x400 Q1 fine grid, 40x40 coarse, kappa = 1 with 10 horizontal + 10 vertical channels of 1e6, "
+               "CEM-GMsFEM d1 = 3200, d2 = 4800, N = 256 intervals x P = 128, 32 samples of 8 Fourier modes with "
+               "N(0,1) per-interval amplitudes, u0 = 0; forward parareal and transposed parareal (loss "
+               "1/2 |x_N|_M^2 + 1/2 sum_n dt |x_n|_M^2) per step, both to rel tol 1e-7")
+
+
+def large_main(args, torch, pe):
+    """Large batched forward + adjoint: B = 32 samples share one problem;
+    every fine-step product covers 32 x 256 = 8192 interval columns."""
+    import numpy as np
+    from problem import build_problem
+    t0 = time.perf_counter()
+    p = build_problem("c4")
+    d1, d2, N, P, B = p["d1"], p["d2"], p["N"], p["P"], p["H"].shape[0]
+    D = d1 + d2
+    log(f"c4 built in {time.perf_counter() - t0:.1f}s: d1={d1} d2={d2} N={N} P={P} B={B}")
+    tol = 1e-7
+    M = np.block([[p["M11"], p["M12"]], [p["M12"].T, p["M22"]]])
+    Mt = torch.tensor(M, device="cuda")
+    x0 = torch.zeros((B, D), dtype=torch.float64, device="cuda")
+    res = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        ts = time.perf_counter()
+        pr = pe.problem_from(p, prec)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - ts
+
+        def step():
+            X, itf, _, _ = pr.solve(x0, tol=tol, norm="rel")
+            Xbar = p["dt"] * (X @ Mt)
+            Xbar[:, 0] = 0.0
+            Xbar[:, -1] += X[:, -1] @ Mt
+            r = pr.adjoint(Xbar=Xbar, tol=tol)
+            log(f"c4 {prec}: step done ({time.perf_counter() - ts:.1f}s since set-up began)")
+            return itf, r
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            itf, r = step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        pr.profile(True)
+        step()
+        torch.cuda.synchronize()
+        prof = pr.profile_read()
+        pr.profile(False)
+        res[prec] = dict(seconds=dt, setup=setup, prof=prof, it_f=int(itf.max()), it_a=int(r["iters"].max()),
+                         tiles=pr.last_tiles("fine_residual"), tiles_adj=pr.last_tiles("adj_state"),
+                         grad=np.concatenate([r["x0bar"].cpu().numpy().ravel(), r["Hbar"].cpu().numpy().ravel()]))
+        log(f"c4 {prec}: {args.steps} forward+adjoint steps in {dt:.2f}s, iterations fwd {itf.max()} adj "
+            f"{r['iters'].max()}, set-up {setup:.1f}s; launch timing: " +
+            ", ".join(f"{k} {v[0]:.1f}ms/{v[1]}" for k, v in prof.items() if v[1]))
+        pr.close()
+        torch.cuda.empty_cache()
+    mixed = res["mixed"]
+    rf = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + d2 * d2) * N * B
+    ms, n = mixed["prof"]["fine_residual"]
+    ams, an = mixed["prof"]["adj_state"]
+    avg, aavg = ms / n * 1e-3, ams / an * 1e-3
+    af = 4.0 * D * D * N * B
+    out = {"metric": "forward+adjoint parareal solves/sec (batched samples)",
+           "value": round(B * args.steps / mixed["seconds"], 4), "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * mixed["seconds"] / args.steps, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": C4_WORKLOAD, "name": "c4", "d1": d1, "d2": d2, "N": N, "P": P, "samples": B,
+                      "iterations": {"forward": mixed["it_f"], "adjoint": mixed["it_a"]},
+                      "setup_s": round(mixed["setup"], 2)},
+           "roofline": dict(kernel="gemm_nt_kernel<float,%d,%d,%d> fine-step residual product, split-K %d"
+                            % tuple(mixed["tiles"]), bound="mfma", achieved=round(rf / avg / 1e12, 3),
+                            peak=PEAK_FP32_MFMA, unit="TFLOP/s", frac=round(rf / avg / 1e12 / PEAK_FP32_MFMA, 5),
+                            traffic=None, avg_launch_us=round(avg * 1e6, 2), launches=n, flops_per_launch=rf),
+           "adjoint_roofline": dict(kernel="gemm_nt_kernel<float,%d,%d,%d> adjoint state update, split-K %d"
+                                    % tuple(mixed["tiles_adj"]), achieved=round(af / aavg / 1e12, 3),
+                                    peak=PEAK_FP32_MFMA, frac=round(af / aavg / 1e12 / PEAK_FP32_MFMA, 5),
+                                    avg_launch_us=round(aavg * 1e6, 2), launches=an, flops_per_launch=af)}
+    if "fp64" in res:
+        f64 = res["fp64"]
+        out["fp64"] = {"value": round(B * args.steps / f64["seconds"], 4), "unit": "solves/s",
+                       "iterations": {"forward": f64["it_f"], "adjoint": f64["it_a"]}}
+        out["speedup_mixed_vs_fp64"] = round(f64["seconds"] / mixed["seconds"], 4)
+        out["grad_rel_diff_mixed_vs_fp64"] = float("%.3e" % (np.linalg.norm(mixed["grad"] - f64["grad"]) /
+                                                            np.linalg.norm(f64["grad"])))
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(p, tol):
     """The FP64 oracle's plain parareal on the same workload, one solve."""
     import numpy as np
@@ -285,8 +373,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c1")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2"],
-                    help="c1: one 200x200 problem (default line); c2: ragged batch of 256 solves")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c4"],
+                    help="c1: one 200x200 problem (default line); c2: ragged batch of 256 solves; "
+                         "c4: 400x400, 32 samples, forward + adjoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint workload")
@@ -310,6 +399,8 @@ def main():
         sys.exit(2)
     if args.workload == "c2":
         return batch_main(args, torch, pe)
+    if args.workload == "c4":
+        return large_main(args, torch, pe)
     tol = 1e-7
     t0 = time.perf_counter()
     p = build_problem(args.config, verbose=False)

@@ -36,7 +36,7 @@ PEAK_FP64_MFMA = 78.6
 # copy reads for the same counters), keyed by workload and the kernel's tile
 # configuration (state-tile rows, operator-tile rows, K depth, split-K).
 # Reported only when the timed run used that configuration.
-MEASURED_TRAFFIC = {("c1", (64, 32, 64, 8)): 2.0 * 15685.2 * 1024 + 1.0 * 4000.0 * 1024}
+MEASURED_TRAFFIC = {}
 
 
 def time_solves(pr, x0, tol, steps, warmup, torch):
@@ -168,10 +168,10 @@ def batch_main(args, torch, pe):
     keys = ("M11", "M12", "M22", "A11", "A12", "A22")
     d1 = [pool[s["pool"]]["d1"] for s in solves]
     d2 = [pool[s["pool"]]["d2"] for s in solves]
-    # residual flops of one fine step of each solve (the launches only cover
-    # the solves still iterating: a solve takes part in (P - 1) residual
+    # fused-step flops of one fine step of each solve (the launches only
+    # cover the solves still iterating: a solve takes part in (P - 1) step
     # launches per iteration it runs)
-    f_step = [2.0 * (a * a + 4.0 * a * b + b * b) * s["N"] for a, b, s in zip(d1, d2, solves)]
+    f_step = [2.0 * (a * a + 4.0 * a * b + 2.0 * b * b) * s["N"] for a, b, s in zip(d1, d2, solves)]
     res = {}
     precs = ["mixed"] if args.no_fp64 else ["mixed", "fp64"]
     for prec in precs:
@@ -217,7 +217,7 @@ def batch_main(args, torch, pe):
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     mixed = res["mixed"]
-    ms, n = mixed["prof"]["fine_residual"]
+    ms, n = mixed["prof"]["fine_step"]
     avg = (ms / n) * 1e-3
     flops_total = mixed["n_prof"] * sum(f * (32 - 1) * int(k) for f, k in zip(f_step, mixed["iters"]))
     flops_res = flops_total / n
@@ -229,11 +229,11 @@ def batch_main(args, torch, pe):
                       "sum_N": sum(s["N"] for s in solves), "P": 32, "precision": "FP32 MFMA grouped products",
                       "iterations_mean": float(mixed["iters"].mean()), "iterations_max": int(mixed["iters"].max()),
                       "setup_s": round(mixed["setup"], 2)},
-           "roofline": dict(kernel="gemm_grouped_kernel<float,64,64,64> fine-step residual products of all solves",
+           "roofline": dict(kernel="gemm_grouped_kernel<float,64,64,64> fused fine-step products of all solves",
                             bound="mfma", achieved=round(flops_res / avg / 1e12, 3), peak=PEAK_FP32_MFMA,
                             unit="TFLOP/s", frac=round(flops_res / avg / 1e12 / PEAK_FP32_MFMA, 5), traffic=None,
                             avg_launch_us=round(avg * 1e6, 3), launches=n, flops_per_launch=round(flops_res),
-                            flops_note="algorithmic residual flops of the solves each launch covered, "
+                            flops_note="algorithmic fused-step flops of the solves each launch covered, "
                                        "averaged over the launches of one profiled batch solve")}
     if "fp64" in res:
         f64 = res["fp64"]
@@ -311,7 +311,7 @@ def large_main(args, torch, pe):
         prof = pr.profile_read()
         pr.profile(False)
         res[prec] = dict(seconds=dt, setup=setup, prof=prof, it_f=int(itf.max()), it_a=int(r["iters"].max()),
-                         tiles=pr.last_tiles("fine_residual"), tiles_adj=pr.last_tiles("adj_state"),
+                         tiles=pr.last_tiles("fine_step"), tiles_adj=pr.last_tiles("adj_state"),
                          grad=np.concatenate([r["x0bar"].cpu().numpy().ravel(), r["Hbar"].cpu().numpy().ravel()]))
         log(f"c4 {prec}: {args.steps} forward+adjoint steps in {dt:.2f}s, iterations fwd {itf.max()} adj "
             f"{r['iters'].max()}, set-up {setup:.1f}s; launch timing: " +
@@ -319,8 +319,8 @@ def large_main(args, torch, pe):
         pr.close()
         torch.cuda.empty_cache()
     mixed = res["mixed"]
-    rf = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + d2 * d2) * N * B
-    ms, n = mixed["prof"]["fine_residual"]
+    rf = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * N * B
+    ms, n = mixed["prof"]["fine_step"]
     ams, an = mixed["prof"]["adj_state"]
     avg, aavg = ms / n * 1e-3, ams / an * 1e-3
     af = 4.0 * D * D * N * B
@@ -331,7 +331,7 @@ def large_main(args, torch, pe):
            "config": {"workload": C4_WORKLOAD, "name": "c4", "d1": d1, "d2": d2, "N": N, "P": P, "samples": B,
                       "iterations": {"forward": mixed["it_f"], "adjoint": mixed["it_a"]},
                       "setup_s": round(mixed["setup"], 2)},
-           "roofline": dict(kernel="gemm_nt_kernel<float,%d,%d,%d> fine-step residual product, split-K %d"
+           "roofline": dict(kernel="gemm_nt_kernel<float,%d,%d,%d> fused fine-step product, split-K %d"
                             % tuple(mixed["tiles"]), bound="mfma", achieved=round(rf / avg / 1e12, 3),
                             peak=PEAK_FP32_MFMA, unit="TFLOP/s", frac=round(rf / avg / 1e12 / PEAK_FP32_MFMA, 5),
                             traffic=None, avg_launch_us=round(avg * 1e6, 2), launches=n, flops_per_launch=rf),
@@ -420,7 +420,7 @@ def main():
         dt, X, iters, hist, st, prof, dt_prof = time_solves(pr, x0, tol, args.steps, args.warmup, torch)
         res[prec] = dict(seconds=dt, X=X[0].cpu().numpy(), iters=int(iters[0]), status=st,
                          setup=setup, prof=prof, seconds_profiled=dt_prof,
-                         tiles=pr.last_tiles("fine_residual"))
+                         tiles=pr.last_tiles("fine_step"))
         log(f"{prec}: {args.steps} solves in {dt:.3f}s ({1e3 * dt / args.steps:.2f} ms/solve), "
             f"iterations {iters[0]}, set-up {setup:.2f}s; event-timed pass {1e3 * dt_prof / args.steps:.2f} ms/solve")
         log(f"{prec} launch timing: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in prof.items()))
@@ -440,27 +440,28 @@ def main():
     ms_per_step = 1e3 * mixed["seconds"] / args.steps
     value = args.steps / mixed["seconds"]
 
-    # roofline of the dominant kernel: the fine-step residual product
-    # R = F - A x_a - W dev, algorithmic 2*(d1^2 + 4 d1 d2 + d2^2) flops per
-    # column (the scheme's products (i) and (iii)), N columns per launch. The
-    # product kernel is timed alone; its split-K reduction kernel (shared by
-    # both fine-step products) is reported beside it.
-    ms_tot, n_launch = mixed["prof"]["fine_residual"]
+    # roofline of the dominant kernel: the fused fine-step product
+    # Z_h W_h dev (the scheme's residual products (i), (iii) and the solves
+    # (ii), (iv) folded into one operator), algorithmic
+    # 2*(d1^2 + 4 d1 d2 + 2 d2^2) flops per column (its nonzero blocks), N
+    # columns per launch. The product kernel is timed alone; its split-K
+    # reduction kernel is reported beside it.
+    ms_tot, n_launch = mixed["prof"]["fine_step"]
     ms_red, n_red = mixed["prof"]["splitk_reduce"]
-    flops_per_launch = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + d2 * d2) * N
+    flops_per_launch = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * N
     avg_s = (ms_tot / n_launch) * 1e-3 if n_launch else float("nan")
     avg_red = (ms_red / n_red) * 1e-3 if n_red else 0.0
     achieved = flops_per_launch / avg_s / 1e12
     tiles = tuple(mixed["tiles"])
     traffic = MEASURED_TRAFFIC.get((args.config, tiles))
-    roofline = dict(kernel="gemm_nt_kernel<float,%d,%d,%d> fine-step residual product (W * dev), split-K %d"
+    roofline = dict(kernel="gemm_nt_kernel<float,%d,%d,%d> fused fine-step product (Z W dev), split-K %d"
                     % tiles, bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP32_MFMA, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_MFMA, 5),
                     traffic=None if traffic is None else round(traffic),
                     avg_launch_us=round(avg_s * 1e6, 3), launches=n_launch,
                     flops_per_launch=flops_per_launch,
                     traffic_unit="bytes per launch (HBM, FETCH_SIZE+WRITE_SIZE, calibrated)",
-                    algorithmic_bytes=round((d1 * d1 + 4.0 * d1 * d2 + d2 * d2) * 4 + N * 2 * (d1 + d2) * 4),
+                    algorithmic_bytes=round((d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * 4 + N * 2 * (d1 + d2) * 4),
                     splitk_reduce_avg_us=round(avg_red * 1e6, 3),
                     achieved_with_reduce=round(flops_per_launch / (avg_s + avg_red) / 1e12, 3))
 
@@ -481,7 +482,7 @@ def main():
                        "ms_per_step": round(1e3 * f64["seconds"] / args.steps, 4),
                        "iterations": f64["iters"], "setup_s": round(f64["setup"], 3)}
         out["speedup_mixed_vs_fp64"] = round(f64["seconds"] / mixed["seconds"], 4)
-        ms64, n64 = f64["prof"]["fine_residual"]
+        ms64, n64 = f64["prof"]["fine_step"]
         if n64:
             a64 = flops_per_launch / ((ms64 / n64) * 1e-3) / 1e12
             out["fp64"]["roofline"] = dict(bound="mfma", achieved=round(a64, 3), peak=PEAK_FP64_MFMA,

@@ -243,16 +243,17 @@ pe_status pe_batch_profile_read(pe_batch b, int kind, double* total_ms, long lon
 
 /* launch classes timed by pe_profile */
 enum {
-    PE_PROF_FINE_RESIDUAL = 0,  /* fine step, R = F - A x_a - W dev (steps 2..P)  */
-    PE_PROF_FINE_INCREMENT = 1, /* fine step, [du; dw] = Z R and state update     */
-    PE_PROF_FINE_FIRST = 2,     /* fine step 1 residual (zero deviation: source only) */
-    PE_PROF_ANCHOR = 3,         /* fine sweep anchors: A x_a and coordinate changes */
-    PE_PROF_COARSE = 4,         /* coarse step + parareal correction              */
-    PE_PROF_NORM = 5,           /* mass products of the stopping test             */
-    PE_PROF_SPLITK_REDUCE = 6,  /* split-K reduction + epilogue kernels of the above */
-    PE_PROF_ADJ_RHO = 7,        /* transposed fine step, rho = Z^T nu                */
-    PE_PROF_ADJ_STATE = 8,      /* transposed fine step, adjoint state update        */
-    PE_PROF_KINDS = 9
+    PE_PROF_FINE_STEP = 0,      /* fine step (steps 2..P): the increment
+                                   Z F - (Z A) x_a - (Z W) dev as one product,
+                                   with the state/history update fused        */
+    PE_PROF_FINE_FIRST = 1,     /* fine step 1 (zero deviation: source and anchor) */
+    PE_PROF_ANCHOR = 2,         /* fine sweep anchors: Z A x_a and coordinate changes */
+    PE_PROF_COARSE = 3,         /* coarse step + parareal correction              */
+    PE_PROF_NORM = 4,           /* mass products of the stopping test             */
+    PE_PROF_SPLITK_REDUCE = 5,  /* split-K reduction + epilogue kernels of the above */
+    PE_PROF_ADJ_RHO = 6,        /* transposed fine step, rho = Z^T nu                */
+    PE_PROF_ADJ_STATE = 7,      /* transposed fine step, adjoint state update        */
+    PE_PROF_KINDS = 8
 };
 
 /*

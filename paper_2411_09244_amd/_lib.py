@@ -29,8 +29,8 @@ EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate"
            "pe_batch_destroy", "pe_batch_profile", "pe_batch_profile_read", "pe_profile", "pe_profile_read",
            "pe_autotune", "pe_last_tiles", "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
-PROFILE_KINDS = {"fine_residual": 0, "fine_increment": 1, "fine_first": 2, "anchor": 3,
-                 "coarse": 4, "norm": 5, "splitk_reduce": 6, "adj_rho": 7, "adj_state": 8}
+PROFILE_KINDS = {"fine_step": 0, "fine_first": 1, "anchor": 2, "coarse": 3, "norm": 4, "splitk_reduce": 5,
+                 "adj_rho": 6, "adj_state": 7}
 
 
 class PeError(RuntimeError):

@@ -166,7 +166,7 @@ class Problem:
             out[name] = (ms.value, n.value)
         return out
 
-    def last_tiles(self, kind="fine_residual"):
+    def last_tiles(self, kind="fine_step"):
         """(state-tile rows, operator-tile rows, K depth, split-K) of the last
         launch of a product class."""
         out = (ctypes.c_int * 4)()

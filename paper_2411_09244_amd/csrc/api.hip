@@ -110,10 +110,13 @@ struct pe_problem_s {
     // operators (padded, row-major)
     double* A64 = nullptr;   // Dp x Dp   full stiffness
     double* M64 = nullptr;   // Dp x Dp   full mass
-    double* Wf64 = nullptr;  // Dp x 2Dp  fine residual operator
-    double* Zf64 = nullptr;  // Dp x Dp   fine increment operator
-    float* Wf32 = nullptr;
-    float* Zf32 = nullptr;
+    // fine step (eqs. (2.5)-(2.6) at dt_fine): increment Z_h R with the
+    // residual R = F - A x_a - W_h dev, fused into one product per step:
+    // Z_h R = Z_h F - (Z_h A) x_a - (Z_h W_h) dev
+    double* Zf64 = nullptr;  // Dp x Dp   Z_h (FP64; whitened coordinates in PE_MIXED)
+    double* ZW64 = nullptr;  // Dp x 2Dp  Z_h W_h (PE_FP64)
+    float* ZW32 = nullptr;   // Dp x 2Dp  Z_h W_h in FP32, whitened (PE_MIXED)
+    double* ZA64 = nullptr;  // Dp x Dp   Z_h A (FP64; whitened in PE_MIXED)
     double* Zc64 = nullptr;  // Dp x Dp   coarse increment operator
     double* PhiG64 = nullptr;  // Dp x Dp   coarse step matrix I - Z_dt A
     float* PhiG32 = nullptr;
@@ -149,6 +152,8 @@ struct pe_problem_s {
     double* Fint_w = nullptr;
     double* CS = nullptr;      // (B*N) x Dp: Z_dt F(t_{n+1}), the coarse step's source term
     double* GT = nullptr;      // Rp x Dp: G^T (source adjoint)
+    double* ZGs = nullptr;     // Dp x Rp: Z_h G (whitened in PE_MIXED), the fused step's source
+    double* ZFint = nullptr;   // (B*N) x Dp: Z_h F per interval (dense tables)
     double* GwT = nullptr;     // Rp x Dp: whitened G^T (PE_MIXED)
 
     // iteration workspace (sized for B_cap samples)
@@ -157,15 +162,16 @@ struct pe_problem_s {
     double *Fbuf = nullptr, *Xa = nullptr, *Ya = nullptr, *R64 = nullptr;
     double* Dl64[2] = {nullptr, nullptr};  // B x Dp: x_n^k - x_n^{k-1} along the coarse sweep
     float* Dl32[2] = {nullptr, nullptr};
-    double* dev64 = nullptr;
-    float *dev32 = nullptr, *R32 = nullptr;
+    double* dev64[2] = {nullptr, nullptr};  // fine-step state, ping-pong (N*B x 2Dp)
+    float* dev32[2] = {nullptr, nullptr};
+    float* R32 = nullptr;
     double *E = nullptr, *Yn = nullptr, *Jd = nullptr, *x0p = nullptr, *io = nullptr, *nrm = nullptr;
     int* active_d = nullptr;
     GemmWork gw;
 
     // adjoint workspace (pe_adjoint / pe_tracking), sized for adj_B samples
     int adj_B = 0, adj_Rp = 0, adj_traj = 0, adj_rho = 0, adj_fdh = 0;
-    double *S2 = nullptr, *Xb = nullptr, *Qb = nullptr, *Yb = nullptr, *Sacc = nullptr, *Hb = nullptr;
+    double *Xb = nullptr, *Qb = nullptr, *Yb = nullptr, *Sacc = nullptr, *Hb = nullptr;
     double *Rho = nullptr, *Ytraj = nullptr, *Inj = nullptr, *Fdh = nullptr, *Fdh_w = nullptr, *rowtmp = nullptr;
     std::vector<void*> adj_allocs;
 
@@ -445,8 +451,7 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
 
 enum {
     SITE_NONE = -1,
-    SITE_FINE_RES = 0,
-    SITE_FINE_INC = 1,
+    SITE_FINE_STEP = 7,
     SITE_ANCHOR = 2,
     SITE_NORM = 3,
     SITE_ADJ_RHO = 4,
@@ -791,9 +796,11 @@ pe_status ensure_workspace(pe_problem p, int B) {
     PE_TRY(dalloc_t(p, L, &p->Xa, Bs * N * Dp));
     PE_TRY(dalloc_t(p, L, &p->Ya, Bs * N * Dp));
     PE_TRY(dalloc_t(p, L, &p->R64, Bs * N * Dp));
-    PE_TRY(dalloc_t(p, L, &p->dev64, Bs * N * 2 * Dp));
+    PE_TRY(dalloc_t(p, L, &p->dev64[0], Bs * N * 2 * Dp));
+    PE_TRY(dalloc_t(p, L, &p->dev64[1], Bs * N * 2 * Dp));
     if (p->prec == PE_MIXED) {
-        PE_TRY(dalloc_t(p, L, &p->dev32, Bs * N * 2 * Dp));
+        PE_TRY(dalloc_t(p, L, &p->dev32[0], Bs * N * 2 * Dp));
+        PE_TRY(dalloc_t(p, L, &p->dev32[1], Bs * N * 2 * Dp));
         PE_TRY(dalloc_t(p, L, &p->R32, Bs * N * Dp));
     }
     PE_TRY(dalloc_t(p, L, &p->E, Bs * (N + 1) * Dp));
@@ -829,14 +836,28 @@ pe_status interval_table(pe_problem p, int B, const double* H, double* out, doub
     return s;
 }
 
-// source fields of a fine-sweep residual epilogue; sv (nullable) replaces
-// the handle's amplitudes (same G, same time layout)
+// source of the fused fine step with other amplitudes (same G, same time
+// layout): kind, amplitudes and, for dense tables, the per-interval Z_h F
+// in the sweep's coordinates
 struct SrcView {
     int kind = 0;
     const double* Hs = nullptr;
-    const double* Fint = nullptr;
-    const double* Fint_w = nullptr;
+    const double* ZFint = nullptr;
 };
+
+// source fields of the fused fine step: Z_h G (or the per-interval Z_h F)
+void source_fields_step(pe_problem p, Epi& e) {
+    e.src_kind = p->src_set ? p->src_kind : 0;
+    e.Gs = p->ZGs;
+    e.Hs = p->Hs;
+    e.R = p->Rp;
+    e.Tlen = p->Tlen;
+    e.time_mode = p->time_mode;
+    e.P = p->P;
+    e.N = p->N;
+    e.Fint = p->ZFint;
+    e.ldf = p->Dp;
+}
 
 void source_fields(pe_problem p, Epi& e, bool whitened = false) {
     e.src_kind = p->src_set ? p->src_kind : 0;
@@ -867,81 +888,70 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     const int rows = B * p->N;
     const bool mixed = p->prec == PE_MIXED;
     if (!mixed) {
-        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->Xa, p->dev64, nullptr, B, p->N, Dp, p->st));
-        PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->A64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
-                            PE_PROF_ANCHOR, SITE_ANCHOR));
+        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->Xa, p->dev64[0], nullptr, B, p->N, Dp, p->st));
     } else {
         // anchors into whitened coordinates: Xa = Tin x (block diagonal)
-        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->R64, p->dev64, p->dev32, B, p->N, Dp, p->st));
+        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->R64, p->dev64[0], p->dev32[0], B, p->N, Dp, p->st));
         GemmShape gt = shape(rows, Dp, p->R64, Dp, p->Tin64, Dp, 0, d1p);
         gt.s_split = d1p;
         gt.k0b = d1p;
         gt.k1b = Dp;
         PE_TRY(gemm<double>(p, gt, store_epi(p->Xa, Dp), 0, PE_PROF_ANCHOR, SITE_ANCHOR));
-        PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->Aw64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
-                            PE_PROF_ANCHOR, SITE_ANCHOR));
     }
+    // anchor term Z_h A x_a (FP64, once per sweep)
+    PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->ZA64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
+                        PE_PROF_ANCHOR, SITE_ANCHOR));
     const long ldS = 2L * Dp;
     for (int step = 0; step < p->P; ++step) {
-        GemmShape g1 = shape(rows, Dp, mixed ? (const void*)p->dev32 : (const void*)p->dev64, ldS,
-                             mixed ? (const void*)p->Wf32 : (const void*)p->Wf64, ldS, 0, 0);
-        g1.s_split = d1p;
-        if (step > 0) {  // the deviation is zero at the first step
-            g1.k0a = d1p;
-            g1.k1a = 2 * Dp;
-            g1.k0b = 0;
-            g1.k1b = 2 * d1p + d2p;
+        const int c = step & 1;
+        // the state deviation is zero at the first step (empty K ranges);
+        // u-rows of Z_h W_h have no du_prev columns
+        GemmShape g = shape(rows, Dp, mixed ? (const void*)p->dev32[c] : (const void*)p->dev64[c], ldS,
+                            mixed ? (const void*)p->ZW32 : (const void*)p->ZW64, ldS, 0, 0);
+        g.s_split = d1p;
+        if (step > 0) {
+            g.k0a = d1p;
+            g.k1a = 2 * Dp;
+            g.k0b = 0;
+            g.k1b = 2 * Dp;
         }
-        Epi e1;
-        e1.mode = EPI_RESID;
-        e1.R64 = p->R64;
-        e1.R32 = mixed ? p->R32 : nullptr;
-        e1.ldr = Dp;
-        e1.base = p->Ya;
-        e1.ldb = Dp;
-        source_fields(p, e1, mixed);
+        Epi e;
+        e.mode = EPI_FSTEP;
+        e.base = p->Ya;
+        e.ldb = Dp;
+        source_fields_step(p, e);
         if (sv) {
-            e1.src_kind = sv->kind;
-            e1.Hs = sv->Hs;
-            e1.Fint = mixed ? sv->Fint_w : sv->Fint;
+            e.src_kind = sv->kind;
+            e.Hs = sv->Hs;
+            e.Fint = sv->ZFint;
         }
-        if (!with_source) e1.src_kind = 0;
-        e1.cols_per_b = p->N;
-        e1.n_fixed = -1;
-        e1.p_step = step;
-        const int k1 = step > 0 ? PE_PROF_FINE_RESIDUAL : PE_PROF_FINE_FIRST;
-        if (mixed)
-            PE_TRY(gemm<float>(p, g1, e1, 0, k1, SITE_FINE_RES));
-        else
-            PE_TRY(gemm<double>(p, g1, e1, 0, k1, SITE_FINE_RES));
-
-        GemmShape g2 = shape(rows, Dp, mixed ? (const void*)p->R32 : (const void*)p->R64, Dp,
-                             mixed ? (const void*)p->Zf32 : (const void*)p->Zf64, Dp, 0, d1p);
-        g2.s_split = d1p;
-        g2.k0b = 0;
-        g2.k1b = Dp;
-        Epi e2;
-        e2.mode = EPI_STEP;
-        e2.dev64 = p->dev64;
-        e2.dev32 = mixed ? p->dev32 : nullptr;
-        e2.ldd = ldS;
-        e2.d1p = d1p;
-        e2.d2p = d2p;
+        if (!with_source) e.src_kind = 0;
+        e.cols_per_b = p->N;
+        e.n_fixed = -1;
+        e.p_step = step;
+        e.din = p->dev64[c];
+        e.dev64 = p->dev64[1 - c];
+        e.dev32 = mixed ? p->dev32[1 - c] : nullptr;
+        e.ldd = ldS;
+        e.d1p = d1p;
+        e.d2p = d2p;
         if (traj) {
-            e2.traj = traj + (long)step * Dp;
-            e2.ldtraj = (long)p->P * Dp;
-            e2.xa = p->Xa;
+            e.traj = traj + (long)step * Dp;
+            e.ldtraj = (long)p->P * Dp;
+            e.xa = p->Xa;
         }
+        const int kind = step > 0 ? PE_PROF_FINE_STEP : PE_PROF_FINE_FIRST;
         if (mixed)
-            PE_TRY(gemm<float>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT, SITE_FINE_INC));
+            PE_TRY(gemm<float>(p, g, e, 0, kind, SITE_FINE_STEP));
         else
-            PE_TRY(gemm<double>(p, g2, e2, 0, PE_PROF_FINE_INCREMENT, SITE_FINE_INC));
+            PE_TRY(gemm<double>(p, g, e, 0, kind, SITE_FINE_STEP));
     }
+    const double* dfin = p->dev64[p->P & 1];
     if (!mixed) {
-        PE_HIP(fine_final(p->Xa, p->dev64, Y, rows, Dp, d1p, accumulate ? 1 : 0, p->st));
+        PE_HIP(fine_final(p->Xa, dfin, Y, rows, Dp, d1p, accumulate ? 1 : 0, p->st));
     } else {
         // back to the caller's coordinates: Y (+)= Tout (Xa + dev)
-        PE_HIP(fine_final(p->Xa, p->dev64, p->R64, rows, Dp, d1p, 0, p->st));
+        PE_HIP(fine_final(p->Xa, dfin, p->R64, rows, Dp, d1p, 0, p->st));
         GemmShape gt = shape(rows, Dp, p->R64, Dp, p->Tout64, Dp, 0, d1p);
         gt.s_split = d1p;
         gt.k0b = d1p;
@@ -1078,8 +1088,9 @@ pe_status ensure_adj_ops(pe_problem p) {
             (s = dalloc_t(p, tmp, &Y64w, (size_t)2 * Dp * Dp)) < 0 || (s = dalloc_t(p, tmp, &I, (size_t)dm * dm)) < 0)
             return done(s);
         PE_HIP(to_f32(p->PhiGT64, p->PhiGT32, (long)Dp * Dp, p->st));
-        // the FP32 step operator transposed (exact)
-        PE_HIP(transpose_f32(p->Zf32, Dp, p->ZT32, Dp, Dp, Dp, p->st));
+        // the whitened step operator, transposed, in FP32
+        PE_HIP(place(Y64w, Dp, 0, 0, p->Zf64, Dp, Dp, Dp, 1.0, 1, p->st));
+        PE_HIP(to_f32(Y64w, p->ZT32, (long)Dp * Dp, p->st));
         if ((s = build_adj_state_op(p, p->Aw64, p->M12k, d2p, p->dtf, Y64w)) < 0) return done(s);
         PE_HIP(to_f32(Y64w, p->Yop32, (long)2 * Dp * Dp, p->st));
         PE_HIP(place(p->TinT64, Dp, 0, 0, p->Tin64, Dp, Dp, Dp, 1.0, 1, p->st));
@@ -1108,12 +1119,11 @@ pe_status ensure_adj_workspace(pe_problem p, int B, bool traj, bool rho, bool fd
     PE_HIP(hipStreamSynchronize(p->st));
     graphs_clear(p);
     free_list(p->adj_allocs);
-    p->S2 = p->Xb = p->Qb = p->Yb = p->Sacc = p->Hb = p->Rho = p->Ytraj = p->Inj = p->Fdh = p->Fdh_w = p->rowtmp =
+    p->Xb = p->Qb = p->Yb = p->Sacc = p->Hb = p->Rho = p->Ytraj = p->Inj = p->Fdh = p->Fdh_w = p->rowtmp =
         nullptr;
     p->adj_B = p->adj_Rp = p->adj_traj = p->adj_rho = p->adj_fdh = 0;
     const size_t N = p->N, P = p->P, Dp = p->Dp, Bs = B, Rp = std::max(p->Rp, 1);
     auto& L = p->adj_allocs;
-    PE_TRY(dalloc_t(p, L, &p->S2, Bs * N * 2 * Dp));
     PE_TRY(dalloc_t(p, L, &p->Xb, Bs * (N + 1) * Dp));
     PE_TRY(dalloc_t(p, L, &p->Qb, Bs * (N + 1) * Dp));
     PE_TRY(dalloc_t(p, L, &p->Yb, Bs * (N + 1) * Dp));
@@ -1127,7 +1137,7 @@ pe_status ensure_adj_workspace(pe_problem p, int B, bool traj, bool rho, bool fd
     }
     if (fdh) {
         PE_TRY(dalloc_t(p, L, &p->Fdh, Bs * N * Dp));
-        if (p->prec == PE_MIXED) PE_TRY(dalloc_t(p, L, &p->Fdh_w, Bs * N * Dp));
+        PE_TRY(dalloc_t(p, L, &p->Fdh_w, Bs * N * Dp));
     }
     p->adj_B = B;
     p->adj_Rp = (int)Rp;
@@ -1148,8 +1158,8 @@ pe_status fine_adjoint_sweep(pe_problem p, int B, const double* L, long ldLb, in
     const int rows = B * N;
     const long ldS = 2L * Dp;
     const bool mixed = p->prec == PE_MIXED;
-    float* nu32 = mixed ? p->dev32 : nullptr;
-    PE_HIP(fine_init(L, ldLb, 1, nvalid, p->Xa, p->dev64, nullptr, B, N, Dp, p->st));
+    float* nu32 = mixed ? p->dev32[0] : nullptr;
+    PE_HIP(fine_init(L, ldLb, 1, nvalid, p->Xa, p->dev64[0], nullptr, B, N, Dp, p->st));
     const double* lam0 = p->Xa;
     if (mixed) {
         // lambda~ = Tout^T lambda = Linv lambda (block diagonal)
@@ -1161,9 +1171,9 @@ pe_status fine_adjoint_sweep(pe_problem p, int B, const double* L, long ldLb, in
         lam0 = p->R64;
     }
     const long ldinj = (long)P * Dp;
-    PE_HIP(adj_init(lam0, inj ? inj + (long)(P - 1) * Dp : nullptr, ldinj, p->dev64, nu32, rows, Dp, p->st));
+    PE_HIP(adj_init(lam0, inj ? inj + (long)(P - 1) * Dp : nullptr, ldinj, p->dev64[0], nu32, rows, Dp, p->st));
     if (srcadj == 1) PE_HIP(zero_fill(p->Sacc, nullptr, (long)rows * Dp, p->st));
-    double* Sb[2] = {p->dev64, p->S2};
+    double* Sb[2] = {p->dev64[0], p->dev64[1]};
     int c = 0;
     for (int step = P - 1; step >= 0; --step) {
         // rho = Z^T nu: u-rows of Z^T use K over [0, Dp), w-rows [d1p, Dp)
@@ -1285,9 +1295,13 @@ pe_status tracking_levels(pe_problem p, int B, const double* dH, double beta) {
         sv.kind = p->src_kind;
         sv.Hs = dH;
         if (p->src_kind == 2) {
-            PE_TRY(interval_table(p, B, dH, p->Fdh, p->prec == PE_MIXED ? p->Fdh_w : nullptr));
-            sv.Fint = p->Fdh;
-            sv.Fint_w = p->Fdh_w;
+            // per-interval Z_h F of the amplitudes dH, in the sweep's coordinates
+            const bool mixed = p->prec == PE_MIXED;
+            PE_TRY(interval_table(p, B, dH, p->Fdh, mixed ? p->Fdh_w : nullptr));
+            const double* src = mixed ? p->Fdh_w : p->Fdh;
+            double* dst = mixed ? p->Fdh : p->Fdh_w;
+            PE_TRY(gemm<double>(p, shape(B * N, Dp, src, Dp, p->Zf64, Dp, 0, Dp), store_epi(dst, Dp)));
+            sv.ZFint = dst;
         }
     }
     PE_TRY(fine_sweep(p, B, p->Yb, (long)(N + 1) * Dp, p->Fbuf, true, 0, false, &sv, p->Ytraj));
@@ -1322,7 +1336,7 @@ struct pe_batch_s {
     std::vector<const void*> plan_keys;
     TileCfg cfg;
     std::vector<void*> allocs;
-    GroupPlan anc1, anc2, inc, fin[2], nrm_rel, nrm_k;
+    GroupPlan anc1, anc2, fin[2], nrm_rel, nrm_k;
     std::vector<GroupPlan> resid[2];  // [with source][fine step]
     CoarseItem* c_init = nullptr;
     CoarseItem* c_corr[2] = {nullptr, nullptr};
@@ -1419,8 +1433,8 @@ pe_status batch_plan(pe_batch bt) {
     const size_t el = mixed ? sizeof(float) : sizeof(double);
     const int G = bt->count;
     std::vector<GemmShape> fine_sh(G), nrel_sh(G), nk_sh(G);
-    std::vector<GemmShape> a1(G), a2(G), g2s(G), fsh(G);
-    std::vector<Epi> e_a1(G), e_a2(G), e_inc(G), e_fin[2], e_nrel(G), e_nk(G);
+    std::vector<GemmShape> a1(G), a2(G), fsh(G);
+    std::vector<Epi> e_a1(G), e_a2(G), e_fin[2], e_nrel(G), e_nk(G);
     e_fin[0].resize(G);
     e_fin[1].resize(G);
     std::vector<std::vector<GemmShape>> r_sh(bt->P, std::vector<GemmShape>(G));
@@ -1437,49 +1451,40 @@ pe_status batch_plan(pe_batch bt) {
         a1[g].k0b = d1p;
         a1[g].k1b = Dp;
         e_a1[g] = store_epi(p->Xa, Dp);
-        a2[g] = shape(rows, Dp, p->Xa, Dp, mixed ? p->Aw64 : p->A64, Dp, 0, Dp);
+        a2[g] = shape(rows, Dp, p->Xa, Dp, p->ZA64, Dp, 0, Dp);
         e_a2[g] = store_epi(p->Ya, Dp);
-        // fine steps
+        // fused fine steps (state ping-pong: step p reads buffer p & 1)
         for (int step = 0; step < bt->P; ++step) {
-            GemmShape g1 = shape(rows, Dp, mixed ? (const void*)p->dev32 : (const void*)p->dev64, ldS,
-                                 mixed ? (const void*)p->Wf32 : (const void*)p->Wf64, ldS, 0, 0);
+            const int c = step & 1;
+            GemmShape g1 = shape(rows, Dp, mixed ? (const void*)p->dev32[c] : (const void*)p->dev64[c], ldS,
+                                 mixed ? (const void*)p->ZW32 : (const void*)p->ZW64, ldS, 0, 0);
             g1.s_split = d1p;
             if (step > 0) {
                 g1.k0a = d1p;
                 g1.k1a = 2 * Dp;
                 g1.k0b = 0;
-                g1.k1b = 2 * d1p + d2p;
+                g1.k1b = 2 * Dp;
             }
             r_sh[step][g] = g1;
             for (int w = 0; w < 2; ++w) {
                 Epi e1;
-                e1.mode = EPI_RESID;
-                e1.R64 = p->R64;
-                e1.R32 = mixed ? p->R32 : nullptr;
-                e1.ldr = Dp;
+                e1.mode = EPI_FSTEP;
                 e1.base = p->Ya;
                 e1.ldb = Dp;
-                source_fields(p, e1, mixed);
+                source_fields_step(p, e1);
                 if (!w) e1.src_kind = 0;
                 e1.cols_per_b = N;
                 e1.n_fixed = -1;
                 e1.p_step = step;
+                e1.din = p->dev64[c];
+                e1.dev64 = p->dev64[1 - c];
+                e1.dev32 = mixed ? p->dev32[1 - c] : nullptr;
+                e1.ldd = ldS;
+                e1.d1p = d1p;
+                e1.d2p = d2p;
                 r_ep[w][step][g] = e1;
             }
         }
-        g2s[g] = shape(rows, Dp, mixed ? (const void*)p->R32 : (const void*)p->R64, Dp,
-                       mixed ? (const void*)p->Zf32 : (const void*)p->Zf64, Dp, 0, d1p);
-        g2s[g].s_split = d1p;
-        g2s[g].k0b = 0;
-        g2s[g].k1b = Dp;
-        Epi e2;
-        e2.mode = EPI_STEP;
-        e2.dev64 = p->dev64;
-        e2.dev32 = mixed ? p->dev32 : nullptr;
-        e2.ldd = ldS;
-        e2.d1p = d1p;
-        e2.d2p = d2p;
-        e_inc[g] = e2;
         // back to the caller's coordinates (mixed)
         fsh[g] = shape(rows, Dp, p->R64, Dp, p->Tout64, Dp, 0, d1p);
         fsh[g].s_split = d1p;
@@ -1504,7 +1509,6 @@ pe_status batch_plan(pe_batch bt) {
         PE_TRY(group_plan(bt, fsh, e_fin[1], sizeof(double), fi, ft, fn, &bt->fin[1]));
     }
     PE_TRY(group_plan(bt, a2, e_a2, sizeof(double), fi, ft, fn, &bt->anc2));
-    PE_TRY(group_plan(bt, g2s, e_inc, el, fi, ft, fn, &bt->inc));
     for (int w = 0; w < 2; ++w) {
         bt->resid[w].assign(bt->P, GroupPlan());
         if (!mixed && !w) continue;  // the FP64 path always sweeps with the source
@@ -1640,7 +1644,7 @@ pe_status batch_tables(pe_batch bt) {
     PE_TRY(put(bt->c_wg_item, wi));
     PE_TRY(put(bt->c_wg_row, wr));
     const int fn = (int)fi.size(), kn = (int)ki.size();
-    for (GroupPlan* g : {&bt->anc1, &bt->anc2, &bt->inc, &bt->fin[0], &bt->fin[1]}) g->n_wg = fn;
+    for (GroupPlan* g : {&bt->anc1, &bt->anc2, &bt->fin[0], &bt->fin[1]}) g->n_wg = fn;
     for (int w = 0; w < 2; ++w)
         for (GroupPlan& g : bt->resid[w]) g.n_wg = fn;
     bt->nrm_k.n_wg = kn;
@@ -1683,27 +1687,24 @@ pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
         const int B = bt->Bs[g], N = p->N, Dp = p->Dp;
         const double* Xs = incremental ? p->E : p->Xk[cur];
         const long ld = incremental ? (long)N * Dp : (long)(N + 1) * Dp;
-        PE_HIP(fine_init(Xs, ld, incremental ? -1 : 0, N, mixed ? p->R64 : p->Xa, p->dev64,
-                         mixed ? p->dev32 : nullptr, B, N, Dp, bt->st));
+        PE_HIP(fine_init(Xs, ld, incremental ? -1 : 0, N, mixed ? p->R64 : p->Xa, p->dev64[0],
+                         mixed ? p->dev32[0] : nullptr, B, N, Dp, bt->st));
     }
     if (mixed) PE_TRY(grouped<double>(bt, bt->anc1, PE_PROF_ANCHOR));
     PE_TRY(grouped<double>(bt, bt->anc2, PE_PROF_ANCHOR));
     for (int step = 0; step < bt->P; ++step) {
         const GroupPlan& r = bt->resid[incremental ? 0 : 1][step];
-        const int k1 = step > 0 ? PE_PROF_FINE_RESIDUAL : PE_PROF_FINE_FIRST;
-        if (mixed) {
+        const int k1 = step > 0 ? PE_PROF_FINE_STEP : PE_PROF_FINE_FIRST;
+        if (mixed)
             PE_TRY(grouped<float>(bt, r, k1));
-            PE_TRY(grouped<float>(bt, bt->inc, PE_PROF_FINE_INCREMENT));
-        } else {
+        else
             PE_TRY(grouped<double>(bt, r, k1));
-            PE_TRY(grouped<double>(bt, bt->inc, PE_PROF_FINE_INCREMENT));
-        }
     }
     for (int g = 0; g < bt->count; ++g) {
         if (!bt->pact[g]) continue;
         pe_problem p = bt->pr[g];
         const long rows = (long)bt->Bs[g] * p->N;
-        PE_HIP(fine_final(p->Xa, p->dev64, mixed ? p->R64 : p->Fbuf, rows, p->Dp, p->d1p, 0, bt->st));
+        PE_HIP(fine_final(p->Xa, p->dev64[bt->P & 1], mixed ? p->R64 : p->Fbuf, rows, p->Dp, p->d1p, 0, bt->st));
     }
     if (mixed) PE_TRY(grouped<double>(bt, bt->fin[incremental ? 1 : 0], PE_PROF_ANCHOR));
     return PE_OK;
@@ -1985,23 +1986,37 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
     }
     const size_t m12n = (size_t)d1p * std::max(d2p, 8);
     CK(dalloc_t(p, OL, &p->M12k, m12n));
-    if (precision == PE_FP64) {
-        CK(dalloc_t(p, OL, &p->Zf64, (size_t)Dp * Dp));
-        CK(dalloc_t(p, OL, &p->Wf64, (size_t)Dp * 2 * Dp));
-        CK(build_step_ops(p, dt_fine, pM11, pM12, M22inv, pA11, pA12, pA21, pA22, p->Zf64, p->Wf64));
-        CKH(hipMemcpyAsync(p->M12k, pM12, sizeof(double) * m12n, hipMemcpyDeviceToDevice, p->st));
-    } else {
-        double *wM12, *wA11, *wA12, *wA21, *wA22, *I11, *I22inv, *Z64, *W64;
-        CK(whiten(p, tmp, pM11, pM12, pM22, pA11, pA12, pA21, pA22, &wM12, &wA11, &wA12, &wA21, &wA22,
-                  &I11, &I22inv));
-        CK(dalloc_t(p, tmp, &Z64, (size_t)Dp * Dp));
+    // fine step operators: Z_h (kept in FP64), the fused Z_h W_h and Z_h A
+    CK(dalloc_t(p, OL, &p->Zf64, (size_t)Dp * Dp));
+    CK(dalloc_t(p, OL, &p->ZA64, (size_t)Dp * Dp));
+    {
+        double *W64, *WT, *ZW;
+        const double* Aop = p->A64;
         CK(dalloc_t(p, tmp, &W64, (size_t)Dp * 2 * Dp));
-        CK(build_step_ops(p, dt_fine, I11, wM12, I22inv, wA11, wA12, wA21, wA22, Z64, W64));
-        CK(dalloc_t(p, OL, &p->Zf32, (size_t)Dp * Dp));
-        CK(dalloc_t(p, OL, &p->Wf32, (size_t)Dp * 2 * Dp));
-        CKH(to_f32(Z64, p->Zf32, (long)Dp * Dp, p->st));
-        CKH(to_f32(W64, p->Wf32, (long)Dp * 2 * Dp, p->st));
-        CKH(hipMemcpyAsync(p->M12k, wM12, sizeof(double) * m12n, hipMemcpyDeviceToDevice, p->st));
+        CK(dalloc_t(p, tmp, &WT, (size_t)Dp * 2 * Dp));
+        if (precision == PE_FP64) {
+            CK(build_step_ops(p, dt_fine, pM11, pM12, M22inv, pA11, pA12, pA21, pA22, p->Zf64, W64));
+            CKH(hipMemcpyAsync(p->M12k, pM12, sizeof(double) * m12n, hipMemcpyDeviceToDevice, p->st));
+            CK(dalloc_t(p, OL, &p->ZW64, (size_t)Dp * 2 * Dp));
+            ZW = p->ZW64;
+        } else {
+            double *wM12, *wA11, *wA12, *wA21, *wA22, *I11, *I22inv;
+            CK(whiten(p, tmp, pM11, pM12, pM22, pA11, pA12, pA21, pA22, &wM12, &wA11, &wA12, &wA21, &wA22,
+                      &I11, &I22inv));
+            CK(build_step_ops(p, dt_fine, I11, wM12, I22inv, wA11, wA12, wA21, wA22, p->Zf64, W64));
+            CKH(hipMemcpyAsync(p->M12k, wM12, sizeof(double) * m12n, hipMemcpyDeviceToDevice, p->st));
+            CK(dalloc_t(p, tmp, &ZW, (size_t)Dp * 2 * Dp));
+            Aop = p->Aw64;
+        }
+        // Z_h W_h = Z_h (W_h^T)^T: NT product with W_h^T as the operator rows
+        CKH(place(WT, Dp, 0, 0, W64, 2L * Dp, 2 * Dp, Dp, 1.0, 1, p->st));
+        CK(gemm<double>(p, shape(Dp, 2 * Dp, p->Zf64, Dp, WT, Dp, 0, Dp), store_epi(ZW, 2L * Dp)));
+        // Z_h A (A symmetric: its rows serve as the operator rows)
+        CK(gemm<double>(p, shape(Dp, Dp, p->Zf64, Dp, Aop, Dp, 0, Dp), store_epi(p->ZA64, Dp)));
+        if (precision == PE_MIXED) {
+            CK(dalloc_t(p, OL, &p->ZW32, (size_t)Dp * 2 * Dp));
+            CKH(to_f32(ZW, p->ZW32, 2L * Dp * Dp, p->st));
+        }
     }
     CKH(hipStreamSynchronize(p->st));
     free_list(tmp);
@@ -2021,13 +2036,13 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
     PE_HIP(hipStreamSynchronize(p->st));
     graphs_clear(p);
     for (void* v : {(void*)p->Gs, (void*)p->Hs, (void*)p->Fint, (void*)p->Gs_w, (void*)p->Fint_w, (void*)p->CS,
-                    (void*)p->GT, (void*)p->GwT}) {
+                    (void*)p->GT, (void*)p->GwT, (void*)p->ZGs, (void*)p->ZFint}) {
         if (!v) continue;
         auto it = std::find(p->op_allocs.begin(), p->op_allocs.end(), v);
         if (it != p->op_allocs.end()) p->op_allocs.erase(it);
         (void)hipFree(v);
     }
-    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = p->CS = p->GT = p->GwT = nullptr;
+    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = p->CS = p->GT = p->GwT = p->ZGs = p->ZFint = nullptr;
     p->src_set = 1;
     p->B_src = B;
     p->R = R;
@@ -2094,6 +2109,17 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
             PE_TRY(dalloc_t(p, p->op_allocs, &p->Gs_w, (size_t)Dp * p->Rp));
             PE_HIP(place(p->Gs_w, p->Rp, 0, 0, p->GwT, Dp, Dp, p->Rp, 1.0, 1, p->st));
         }
+    }
+    // the fused fine step's source: Z_h G, or Z_h F per interval (in the
+    // sweep's coordinates)
+    const bool mixed = p->prec == PE_MIXED;
+    PE_TRY(dalloc_t(p, p->op_allocs, &p->ZGs, (size_t)Dp * p->Rp));
+    PE_TRY(gemm<double>(p, shape(Dp, p->Rp, p->Zf64, Dp, mixed ? p->GwT : p->GT, Dp, 0, Dp),
+                        store_epi(p->ZGs, p->Rp)));
+    if (p->src_kind == 2) {
+        PE_TRY(dalloc_t(p, p->op_allocs, &p->ZFint, (size_t)B * p->N * Dp));
+        PE_TRY(gemm<double>(p, shape(B * p->N, Dp, mixed ? p->Fint_w : p->Fint, Dp, p->Zf64, Dp, 0, Dp),
+                            store_epi(p->ZFint, Dp)));
     }
     PE_HIP(hipStreamSynchronize(p->st));
     return PE_OK;

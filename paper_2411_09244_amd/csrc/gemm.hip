@@ -83,29 +83,33 @@ __device__ inline void epi_apply(const Epi& e, int r, int s, double acc) {
         if (e.base) v -= e.base[(long)r * e.ldb + s];
         e.R64[(long)r * e.ldr + s] = v;
         if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
-    } else if constexpr (MODE == EPI_STEP) {
-        // state layout per column: [du_prev | u - u_a | w - w_a | dw_prev]
+    } else if constexpr (MODE == EPI_FSTEP) {
+        // increment of the fused step, then the state/history update from
+        // the input state (layout per column: [du_prev | u - u_a | w - w_a | dw_prev])
+        double v = source_value(e, r, s) - acc;
+        if (e.base) v -= e.base[(long)r * e.ldb + s];
+        const double* di = e.din + (long)r * e.ldd;
         double* d = e.dev64 + (long)r * e.ldd;
         float* d32 = e.dev32 ? e.dev32 + (long)r * e.ldd : nullptr;
         double full_dev;
         if (s < e.d1p) {
-            const double u = d[e.d1p + s] + acc;
-            d[s] = acc;
+            const double u = di[e.d1p + s] + v;
+            d[s] = v;
             d[e.d1p + s] = u;
             if (d32) {
-                d32[s] = (float)acc;
+                d32[s] = (float)v;
                 d32[e.d1p + s] = (float)u;
             }
             full_dev = u;
         } else {
             const int j = s - e.d1p;
             const long ow = 2L * e.d1p + j, oh = 2L * e.d1p + e.d2p + j;
-            const double w = d[ow] + acc;
+            const double w = di[ow] + v;
             d[ow] = w;
-            d[oh] = acc;
+            d[oh] = v;
             if (d32) {
                 d32[ow] = (float)w;
-                d32[oh] = (float)acc;
+                d32[oh] = (float)v;
             }
             full_dev = w;
         }
@@ -144,7 +148,7 @@ __device__ inline void epi_dispatch(int mode, F&& f) {
     switch (mode) {
         case EPI_STORE: f(std::integral_constant<int, EPI_STORE>{}); break;
         case EPI_RESID: f(std::integral_constant<int, EPI_RESID>{}); break;
-        case EPI_STEP: f(std::integral_constant<int, EPI_STEP>{}); break;
+        case EPI_FSTEP: f(std::integral_constant<int, EPI_FSTEP>{}); break;
         case EPI_COARSE_INIT: f(std::integral_constant<int, EPI_COARSE_INIT>{}); break;
         case EPI_COARSE_DELTA: f(std::integral_constant<int, EPI_COARSE_DELTA>{}); break;
         case EPI_ADJ_RHO: f(std::integral_constant<int, EPI_ADJ_RHO>{}); break;

@@ -427,22 +427,6 @@ hipError_t eye(double* A, int n, int d, hipStream_t st) {
     return hipGetLastError();
 }
 
-// dst[j][i] = src[i][j] for a rows x cols FP32 block
-__global__ void k_transpose_f32(const float* __restrict__ src, long lds, float* __restrict__ dst, long ldd,
-                                int rows, int cols) {
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)rows * cols;
-         t += (long)gridDim.x * blockDim.x) {
-        const int i = (int)(t / cols), j = (int)(t - (long)i * cols);
-        dst[(long)j * ldd + i] = src[(long)i * lds + j];
-    }
-}
-
-hipError_t transpose_f32(const float* src, long lds, float* dst, long ldd, int rows, int cols, hipStream_t st) {
-    if (rows <= 0 || cols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_transpose_f32, grid1((long)rows * cols), dim3(256), 0, st, src, lds, dst, ldd, rows, cols);
-    return hipGetLastError();
-}
-
 hipError_t to_f32(const double* src, float* dst, long n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_to_f32, grid1(n), dim3(256), 0, st, src, dst, n);

@@ -28,7 +28,7 @@ struct GemmShape {
 enum EpiMode : int {
     EPI_STORE = 0,   // C = alpha*acc + beta*C0 (+ diag_add on r == s + diag_off)
     EPI_RESID = 1,   // R = f(t) - base - acc               (residual of a step)
-    EPI_STEP = 2,    // increment -> state/history update    (fine step)
+    EPI_FSTEP = 2,   // fused fine step: d = ZF(t) - base - acc -> state/history update (ping-pong)
     EPI_COARSE_INIT = 3,   // initial coarse sweep: x_{n+1} = Phi_G x_n + c_n
     EPI_COARSE_DELTA = 4,  // correction of eq. (2.7): x_{n+1}^k = F_n + Phi_G (x_n^k - x_n^{k-1})
     EPI_ADJ_RHO = 5,       // adjoint step, first product: rho = Z^T nu (+ source adjoint)
@@ -63,13 +63,15 @@ struct Epi {
     int N = 1;
     const double* Fint = nullptr;  // (B*N) x Dp table of per-interval sources
     long ldf = 0;
-    // EPI_STEP / EPI_COARSE
-    double* dev64 = nullptr;
-    float* dev32 = nullptr;
+    // EPI_FSTEP (source fields as for EPI_RESID, with the step operator
+    // applied: Gs = Z G, Fint = per-interval Z F; base = Z A x_a)
+    const double* din = nullptr;    // state in  [du_prev | u - u_a | w - w_a | dw_prev], ld ldd
+    double* dev64 = nullptr;        // state out (FP64), ld ldd
+    float* dev32 = nullptr;         // state out (FP32 copy, nullable)
     long ldd = 0;
     int d1p = 0, d2p = 0;
-    double* traj = nullptr;         // STEP (nullable): full new state xa + deviation at traj + r*ldtraj
-    const double* xa = nullptr;     // STEP: anchors, ld d1p + d2p
+    double* traj = nullptr;         // nullable: full new state xa + deviation at traj + r*ldtraj
+    const double* xa = nullptr;     // anchors, ld d1p + d2p
     long ldtraj = 0;
     // EPI_COARSE_*  (column r is sample r)
     double* xout = nullptr;         // X^k[b][n+1] = xout + b*ldxo

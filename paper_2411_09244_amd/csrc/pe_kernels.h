@@ -34,7 +34,6 @@ hipError_t shifted_embed(double* dst, int n, const double* A, const double* Bm, 
                          double cb, hipStream_t st);
 hipError_t tril(double* A, int n, hipStream_t st);
 hipError_t eye(double* A, int n, int d, hipStream_t st);
-hipError_t transpose_f32(const float* src, long lds, float* dst, long ldd, int rows, int cols, hipStream_t st);
 hipError_t to_f32(const double* src, float* dst, long n, hipStream_t st);
 hipError_t asym(const double* X, const double* Y, long ldx, long ldy, int rows, int cols,
                 unsigned long long* out2, hipStream_t st);

@@ -118,20 +118,20 @@ def adjoint_leg(args, torch, pe, build_problem, precs):
         pr.profile(False)
         out[prec] = dict(seconds=dt, it_fwd=int(itf[0]), it_adj=int(r["iters"][0]), prof=prof,
                          grad=np.concatenate([r["x0bar"].cpu().numpy().ravel(), r["Hbar"].cpu().numpy().ravel()]),
-                         tiles=pr.last_tiles("adj_state"))
+                         tiles=pr.last_tiles("adj_step"))
         log(f"adjoint {prec}: {args.steps} forward+adjoint solves in {dt:.3f}s, iterations fwd {itf[0]} "
             f"adj {r['iters'][0]}; launch timing: " +
             ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in prof.items() if v[1]))
         pr.close()
     mixed = out[precs[0]]
-    ms, n = mixed["prof"]["adj_state"]
+    ms, n = mixed["prof"]["adj_step"]
     flops = 4.0 * D * D * N
     avg = (ms / n) * 1e-3 if n else float("nan")
     res = {"workload": ADJ_WORKLOAD, "name": "c3", "metric": "forward+adjoint solves/s (gradient wrt theta, x0)",
            "value": round(args.steps / mixed["seconds"], 4), "unit": "solves/s",
            "ms_per_step": round(1e3 * mixed["seconds"] / args.steps, 4), "precision": precs[0],
            "iterations": {"forward": mixed["it_fwd"], "adjoint": mixed["it_adj"]},
-           "roofline": dict(kernel="gemm_nt_kernel<%s,%d,%d,%d> adjoint state update ([A; A+Mh] rho), split-K %d"
+           "roofline": dict(kernel="gemm_nt_kernel<%s,%d,%d,%d> fused adjoint step ([A; A+Mh] Z^T nu), split-K %d"
                             % (("float" if precs[0] == "mixed" else "double",) + tuple(mixed["tiles"])),
                             bound="mfma", achieved=round(flops / avg / 1e12, 3),
                             peak=PEAK_FP32_MFMA if precs[0] == "mixed" else PEAK_FP64_MFMA, unit="TFLOP/s",
@@ -311,7 +311,7 @@ def large_main(args, torch, pe):
         prof = pr.profile_read()
         pr.profile(False)
         res[prec] = dict(seconds=dt, setup=setup, prof=prof, it_f=int(itf.max()), it_a=int(r["iters"].max()),
-                         tiles=pr.last_tiles("fine_step"), tiles_adj=pr.last_tiles("adj_state"),
+                         tiles=pr.last_tiles("fine_step"), tiles_adj=pr.last_tiles("adj_step"),
                          grad=np.concatenate([r["x0bar"].cpu().numpy().ravel(), r["Hbar"].cpu().numpy().ravel()]))
         log(f"c4 {prec}: {args.steps} forward+adjoint steps in {dt:.2f}s, iterations fwd {itf.max()} adj "
             f"{r['iters'].max()}, set-up {setup:.1f}s; launch timing: " +
@@ -321,7 +321,7 @@ def large_main(args, torch, pe):
     mixed = res["mixed"]
     rf = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * N * B
     ms, n = mixed["prof"]["fine_step"]
-    ams, an = mixed["prof"]["adj_state"]
+    ams, an = mixed["prof"]["adj_step"]
     avg, aavg = ms / n * 1e-3, ams / an * 1e-3
     af = 4.0 * D * D * N * B
     out = {"metric": "forward+adjoint parareal solves/sec (batched samples)",
@@ -335,7 +335,7 @@ def large_main(args, torch, pe):
                             % tuple(mixed["tiles"]), bound="mfma", achieved=round(rf / avg / 1e12, 3),
                             peak=PEAK_FP32_MFMA, unit="TFLOP/s", frac=round(rf / avg / 1e12 / PEAK_FP32_MFMA, 5),
                             traffic=None, avg_launch_us=round(avg * 1e6, 2), launches=n, flops_per_launch=rf),
-           "adjoint_roofline": dict(kernel="gemm_nt_kernel<float,%d,%d,%d> adjoint state update, split-K %d"
+           "adjoint_roofline": dict(kernel="gemm_nt_kernel<float,%d,%d,%d> fused adjoint step, split-K %d"
                                     % tuple(mixed["tiles_adj"]), achieved=round(af / aavg / 1e12, 3),
                                     peak=PEAK_FP32_MFMA, frac=round(af / aavg / 1e12 / PEAK_FP32_MFMA, 5),
                                     avg_launch_us=round(aavg * 1e6, 2), launches=an, flops_per_launch=af)}

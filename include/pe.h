@@ -251,9 +251,9 @@ enum {
     PE_PROF_COARSE = 3,         /* coarse step + parareal correction              */
     PE_PROF_NORM = 4,           /* mass products of the stopping test             */
     PE_PROF_SPLITK_REDUCE = 5,  /* split-K reduction + epilogue kernels of the above */
-    PE_PROF_ADJ_RHO = 6,        /* transposed fine step, rho = Z^T nu                */
-    PE_PROF_ADJ_STATE = 7,      /* transposed fine step, adjoint state update        */
-    PE_PROF_KINDS = 8
+    PE_PROF_ADJ_STEP = 6,       /* transposed fine step: [a; nu] <- a - ([A; A + Mh] Z^T) nu
+                                   as one product                                 */
+    PE_PROF_KINDS = 7
 };
 
 /*

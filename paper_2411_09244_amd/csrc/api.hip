@@ -128,13 +128,10 @@ struct pe_problem_s {
     double* Tout64 = nullptr;  // Dp x Dp
     double* Linv64 = nullptr;  // Dp x Dp
     // adjoint (transposed) operators, in the fine sweep's precision and
-    // coordinates: Z^T of the fine step, Yop = [A; A + Mh] (2Dp x Dp, Mh the
-    // off-diagonal mass coupling over dt_fine), Phi_G^T; PE_MIXED also keeps
-    // Tin^T and the whitened mass
-    double* ZT64 = nullptr;
-    double* Yop64 = nullptr;
-    float* ZT32 = nullptr;
-    float* Yop32 = nullptr;
+    // coordinates: [A; A + Mh] Z_h^T (Mh the off-diagonal mass coupling over
+    // dt_fine), Phi_G^T; PE_MIXED also keeps Tin^T and the whitened mass
+    double* YZ64 = nullptr;    // 2Dp x Dp  [A; A + Mh] Z_h^T: the fused transposed step (PE_FP64)
+    float* YZ32 = nullptr;     //            its FP32 copy in whitened coordinates (PE_MIXED)
     double* PhiGT64 = nullptr;
     float* PhiGT32 = nullptr;
     double* TinT64 = nullptr;
@@ -153,6 +150,7 @@ struct pe_problem_s {
     double* CS = nullptr;      // (B*N) x Dp: Z_dt F(t_{n+1}), the coarse step's source term
     double* GT = nullptr;      // Rp x Dp: G^T (source adjoint)
     double* ZGs = nullptr;     // Dp x Rp: Z_h G (whitened in PE_MIXED), the fused step's source
+    double* ZGT = nullptr;     // Rp x Dp: its transpose (source adjoint (Z_h G)^T nu)
     double* ZFint = nullptr;   // (B*N) x Dp: Z_h F per interval (dense tables)
     double* GwT = nullptr;     // Rp x Dp: whitened G^T (PE_MIXED)
 
@@ -164,7 +162,6 @@ struct pe_problem_s {
     float* Dl32[2] = {nullptr, nullptr};
     double* dev64[2] = {nullptr, nullptr};  // fine-step state, ping-pong (N*B x 2Dp)
     float* dev32[2] = {nullptr, nullptr};
-    float* R32 = nullptr;
     double *E = nullptr, *Yn = nullptr, *Jd = nullptr, *x0p = nullptr, *io = nullptr, *nrm = nullptr;
     int* active_d = nullptr;
     GemmWork gw;
@@ -454,9 +451,8 @@ enum {
     SITE_FINE_STEP = 7,
     SITE_ANCHOR = 2,
     SITE_NORM = 3,
-    SITE_ADJ_RHO = 4,
-    SITE_ADJ_STATE = 5,
-    SITE_TRAJ = 6
+    SITE_TRAJ = 6,
+    SITE_ADJ_STEP = 8
 };
 
 template <typename T>
@@ -801,7 +797,6 @@ pe_status ensure_workspace(pe_problem p, int B) {
     if (p->prec == PE_MIXED) {
         PE_TRY(dalloc_t(p, L, &p->dev32[0], Bs * N * 2 * Dp));
         PE_TRY(dalloc_t(p, L, &p->dev32[1], Bs * N * 2 * Dp));
-        PE_TRY(dalloc_t(p, L, &p->R32, Bs * N * Dp));
     }
     PE_TRY(dalloc_t(p, L, &p->E, Bs * (N + 1) * Dp));
     PE_TRY(dalloc_t(p, L, &p->Yn, Bs * (N + 1) * Dp));
@@ -1069,30 +1064,30 @@ pe_status ensure_adj_ops(pe_problem p) {
         return r;
     };
     pe_status s;
-    if ((s = dalloc_t(p, OL, &p->PhiGT64, (size_t)Dp * Dp)) < 0) return done(s);
+    const bool mixed = p->prec == PE_MIXED;
+    double *Y64 = nullptr, *YZ = nullptr;
+    if ((s = dalloc_t(p, OL, &p->PhiGT64, (size_t)Dp * Dp)) < 0 || (s = dalloc_t(p, tmp, &Y64, (size_t)2 * Dp * Dp)) < 0)
+        return done(s);
     PE_HIP(place(p->PhiGT64, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
-    if (p->prec == PE_FP64) {
-        if ((s = dalloc_t(p, OL, &p->ZT64, (size_t)Dp * Dp)) < 0 ||
-            (s = dalloc_t(p, OL, &p->Yop64, (size_t)2 * Dp * Dp)) < 0)
-            return done(s);
-        PE_HIP(place(p->ZT64, Dp, 0, 0, p->Zf64, Dp, Dp, Dp, 1.0, 1, p->st));
-        if ((s = build_adj_state_op(p, p->A64, p->M12k, d2p, p->dtf, p->Yop64)) < 0) return done(s);
+    // [A; A + Mh] Z_h^T (NT product with the rows of Z_h as operator rows)
+    if ((s = build_adj_state_op(p, mixed ? p->Aw64 : p->A64, p->M12k, d2p, p->dtf, Y64)) < 0) return done(s);
+    if (mixed) {
+        if ((s = dalloc_t(p, tmp, &YZ, (size_t)2 * Dp * Dp)) < 0) return done(s);
     } else {
-        double *Y64w = nullptr, *I = nullptr;
+        if ((s = dalloc_t(p, OL, &p->YZ64, (size_t)2 * Dp * Dp)) < 0) return done(s);
+        YZ = p->YZ64;
+    }
+    if ((s = gemm<double>(p, shape(2 * Dp, Dp, Y64, Dp, p->Zf64, Dp, 0, Dp), store_epi(YZ, Dp))) < 0) return done(s);
+    if (mixed) {
+        double* I = nullptr;
         const int dm = std::max(d1p, d2p);
         if ((s = dalloc_t(p, OL, &p->PhiGT32, (size_t)Dp * Dp)) < 0 ||
-            (s = dalloc_t(p, OL, &p->ZT32, (size_t)Dp * Dp)) < 0 ||
-            (s = dalloc_t(p, OL, &p->Yop32, (size_t)2 * Dp * Dp)) < 0 ||
+            (s = dalloc_t(p, OL, &p->YZ32, (size_t)2 * Dp * Dp)) < 0 ||
             (s = dalloc_t(p, OL, &p->TinT64, (size_t)Dp * Dp)) < 0 ||
-            (s = dalloc_t(p, OL, &p->Mw64, (size_t)Dp * Dp)) < 0 ||
-            (s = dalloc_t(p, tmp, &Y64w, (size_t)2 * Dp * Dp)) < 0 || (s = dalloc_t(p, tmp, &I, (size_t)dm * dm)) < 0)
+            (s = dalloc_t(p, OL, &p->Mw64, (size_t)Dp * Dp)) < 0 || (s = dalloc_t(p, tmp, &I, (size_t)dm * dm)) < 0)
             return done(s);
         PE_HIP(to_f32(p->PhiGT64, p->PhiGT32, (long)Dp * Dp, p->st));
-        // the whitened step operator, transposed, in FP32
-        PE_HIP(place(Y64w, Dp, 0, 0, p->Zf64, Dp, Dp, Dp, 1.0, 1, p->st));
-        PE_HIP(to_f32(Y64w, p->ZT32, (long)Dp * Dp, p->st));
-        if ((s = build_adj_state_op(p, p->Aw64, p->M12k, d2p, p->dtf, Y64w)) < 0) return done(s);
-        PE_HIP(to_f32(Y64w, p->Yop32, (long)2 * Dp * Dp, p->st));
+        PE_HIP(to_f32(YZ, p->YZ32, 2L * Dp * Dp, p->st));
         PE_HIP(place(p->TinT64, Dp, 0, 0, p->Tin64, Dp, Dp, Dp, 1.0, 1, p->st));
         PE_HIP(hipMemsetAsync(p->Mw64, 0, sizeof(double) * Dp * Dp, p->st));
         PE_HIP(eye(I, dm, d1, p->st));
@@ -1158,7 +1153,7 @@ pe_status fine_adjoint_sweep(pe_problem p, int B, const double* L, long ldLb, in
     const int rows = B * N;
     const long ldS = 2L * Dp;
     const bool mixed = p->prec == PE_MIXED;
-    float* nu32 = mixed ? p->dev32[0] : nullptr;
+    float* nu32[2] = {mixed ? p->dev32[0] : nullptr, mixed ? p->dev32[1] : nullptr};
     PE_HIP(fine_init(L, ldLb, 1, nvalid, p->Xa, p->dev64[0], nullptr, B, N, Dp, p->st));
     const double* lam0 = p->Xa;
     if (mixed) {
@@ -1170,48 +1165,39 @@ pe_status fine_adjoint_sweep(pe_problem p, int B, const double* L, long ldLb, in
         PE_TRY(gemm<double>(p, gt, store_epi(p->R64, Dp), 0, PE_PROF_ANCHOR, SITE_ANCHOR));
         lam0 = p->R64;
     }
+    // the source adjoint of step p is Z_h^T nu_p: keep the sum of the nu_p
+    // over the interval (srcadj 1) or each nu_p (srcadj 2); nu_{P-1} = a
     const long ldinj = (long)P * Dp;
-    PE_HIP(adj_init(lam0, inj ? inj + (long)(P - 1) * Dp : nullptr, ldinj, p->dev64[0], nu32, rows, Dp, p->st));
-    if (srcadj == 1) PE_HIP(zero_fill(p->Sacc, nullptr, (long)rows * Dp, p->st));
+    double* nset = srcadj == 1 ? p->Sacc : (srcadj == 2 ? p->Rho + (long)(P - 1) * Dp : nullptr);
+    const long ldset = srcadj == 2 ? (long)P * Dp : Dp;
+    PE_HIP(adj_init(lam0, inj ? inj + (long)(P - 1) * Dp : nullptr, ldinj, p->dev64[0], nu32[0], nset, ldset, rows,
+                    Dp, p->st));
     double* Sb[2] = {p->dev64[0], p->dev64[1]};
     int c = 0;
     for (int step = P - 1; step >= 0; --step) {
-        // rho = Z^T nu: u-rows of Z^T use K over [0, Dp), w-rows [d1p, Dp)
-        GemmShape g1 = shape(rows, Dp, mixed ? (const void*)nu32 : (const void*)(Sb[c] + Dp), mixed ? Dp : ldS,
-                             mixed ? (const void*)p->ZT32 : (const void*)p->ZT64, Dp, 0, Dp);
-        g1.s_split = d1p;
-        g1.k0b = d1p;
-        g1.k1b = Dp;
-        Epi e1;
-        e1.mode = EPI_ADJ_RHO;
-        e1.R64 = mixed ? nullptr : p->R64;
-        e1.R32 = mixed ? p->R32 : nullptr;
-        e1.ldr = Dp;
-        e1.sacc = srcadj == 1 ? p->Sacc : nullptr;
-        e1.rho_all = srcadj == 2 ? p->Rho : nullptr;
-        e1.P = P;
-        e1.m_step = step;
-        if (mixed)
-            PE_TRY(gemm<float>(p, g1, e1, 0, PE_PROF_ADJ_RHO, SITE_ADJ_RHO));
-        else
-            PE_TRY(gemm<double>(p, g1, e1, 0, PE_PROF_ADJ_RHO, SITE_ADJ_RHO));
-        // [a; nu] <- a - [A; A + Mh] rho (+ cotangent of the state before this step)
-        GemmShape g2 = shape(rows, 2 * Dp, mixed ? (const void*)p->R32 : (const void*)p->R64, Dp,
-                             mixed ? (const void*)p->Yop32 : (const void*)p->Yop64, Dp, 0, Dp);
-        Epi e2;
-        e2.mode = EPI_ADJ_STATE;
-        e2.ldr = Dp;
-        e2.s_cur = Sb[c];
-        e2.s_nxt = Sb[1 - c];
-        e2.nu32 = nu32;
-        if (inj && step > 0) {
-            e2.inj = inj + (long)(step - 1) * Dp;
-            e2.ldinj = ldinj;
+        // [a; nu] <- a - [A; A + Mh] Z_h^T nu  (+ cotangent of the state before this step)
+        GemmShape g = shape(rows, 2 * Dp, mixed ? (const void*)nu32[c] : (const void*)(Sb[c] + Dp), mixed ? Dp : ldS,
+                            mixed ? (const void*)p->YZ32 : (const void*)p->YZ64, Dp, 0, Dp);
+        Epi e;
+        e.mode = EPI_ADJ_STATE;
+        e.ldr = Dp;
+        e.s_cur = Sb[c];
+        e.s_nxt = Sb[1 - c];
+        e.nu32 = nu32[1 - c];
+        e.P = P;
+        if (step > 0) {
+            if (inj) {
+                e.inj = inj + (long)(step - 1) * Dp;
+                e.ldinj = ldinj;
+            }
+            e.sacc = srcadj == 1 ? p->Sacc : nullptr;
+            e.rho_all = srcadj == 2 ? p->Rho : nullptr;
+            e.m_step = step - 1;
         }
         if (mixed)
-            PE_TRY(gemm<float>(p, g2, e2, 0, PE_PROF_ADJ_STATE, SITE_ADJ_STATE));
+            PE_TRY(gemm<float>(p, g, e, 0, PE_PROF_ADJ_STEP, SITE_ADJ_STEP));
         else
-            PE_TRY(gemm<double>(p, g2, e2, 0, PE_PROF_ADJ_STATE, SITE_ADJ_STATE));
+            PE_TRY(gemm<double>(p, g, e, 0, PE_PROF_ADJ_STEP, SITE_ADJ_STEP));
         c = 1 - c;
     }
     if (!mixed) {
@@ -2036,13 +2022,13 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
     PE_HIP(hipStreamSynchronize(p->st));
     graphs_clear(p);
     for (void* v : {(void*)p->Gs, (void*)p->Hs, (void*)p->Fint, (void*)p->Gs_w, (void*)p->Fint_w, (void*)p->CS,
-                    (void*)p->GT, (void*)p->GwT, (void*)p->ZGs, (void*)p->ZFint}) {
+                    (void*)p->GT, (void*)p->GwT, (void*)p->ZGs, (void*)p->ZGT, (void*)p->ZFint}) {
         if (!v) continue;
         auto it = std::find(p->op_allocs.begin(), p->op_allocs.end(), v);
         if (it != p->op_allocs.end()) p->op_allocs.erase(it);
         (void)hipFree(v);
     }
-    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = p->CS = p->GT = p->GwT = p->ZGs = p->ZFint = nullptr;
+    p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = p->CS = p->GT = p->GwT = p->ZGs = p->ZGT = p->ZFint = nullptr;
     p->src_set = 1;
     p->B_src = B;
     p->R = R;
@@ -2116,6 +2102,8 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
     PE_TRY(dalloc_t(p, p->op_allocs, &p->ZGs, (size_t)Dp * p->Rp));
     PE_TRY(gemm<double>(p, shape(Dp, p->Rp, p->Zf64, Dp, mixed ? p->GwT : p->GT, Dp, 0, Dp),
                         store_epi(p->ZGs, p->Rp)));
+    PE_TRY(dalloc_t(p, p->op_allocs, &p->ZGT, (size_t)p->Rp * Dp));
+    PE_HIP(place(p->ZGT, Dp, 0, 0, p->ZGs, p->Rp, p->Rp, Dp, 1.0, 1, p->st));
     if (p->src_kind == 2) {
         PE_TRY(dalloc_t(p, p->op_allocs, &p->ZFint, (size_t)B * p->N * Dp));
         PE_TRY(gemm<double>(p, shape(B * p->N, Dp, mixed ? p->Fint_w : p->Fint, Dp, p->Zf64, Dp, 0, Dp),
@@ -2387,14 +2375,14 @@ pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const
     if (Lam) PE_HIP(unpack_states(Lf, Lam, rowsX, p->d1, p->d2, p->d1p, p->d2p, p->st));
     if (want_h) {
         // source adjoint: one transposed fine sweep from the final lambda,
-        // rho summed per interval (or kept per step), then G^T rho
+        // the nu summed per interval (or kept per step), then (Z_h G)^T nu
         PE_TRY(graph_run(p, {12, B, cur, track ? 1 : 0, rho_all ? 1 : 0}, [&]() {
             return fine_adjoint_sweep(p, B, Lf, ldX, N + 1, inj, p->Fbuf, false, rho_all ? 2 : 1);
         }));
         const int Rp = p->Rp;
         const long tl = p->Tlen;
         const long rows_h = (long)B * tl;
-        PE_TRY(gemm<double>(p, shape((int)rows_h, Rp, rho_all ? p->Rho : p->Sacc, Dp, mixed ? p->GwT : p->GT, Dp, 0, Dp),
+        PE_TRY(gemm<double>(p, shape((int)rows_h, Rp, rho_all ? p->Rho : p->Sacc, Dp, p->ZGT, Dp, 0, Dp),
                             store_epi(p->Hb, Rp)));
         for (int b = 0; b < B; ++b)
             PE_HIP(place(Hbar + (long)b * p->R * tl, tl, 0, 0, p->Hb + (long)b * tl * Rp, Rp, p->R, (int)tl, 1.0, 1,

@@ -127,18 +127,17 @@ __device__ inline void epi_apply(const Epi& e, int r, int s, double acc) {
         const double d = x - e.xprev[(long)b * e.ldxo + s];
         if (e.dl64) e.dl64[(long)b * e.ldl + s] = d;
         if (e.dl32) e.dl32[(long)b * e.ldl + s] = (float)d;
-    } else if constexpr (MODE == EPI_ADJ_RHO) {
-        if (e.R64) e.R64[(long)r * e.ldr + s] = acc;
-        if (e.R32) e.R32[(long)r * e.ldr + s] = (float)acc;
-        if (e.sacc) e.sacc[(long)r * e.ldr + s] += acc;
-        if (e.rho_all) e.rho_all[((long)r * e.P + e.m_step) * e.ldr + s] = acc;
     } else if constexpr (MODE == EPI_ADJ_STATE) {
         const long D = e.ldr;
         const int j = s < D ? s : (int)(s - D);
         double v = e.s_cur[(long)r * 2 * D + j] - acc;
         if (e.inj) v += e.inj[(long)r * e.ldinj + j];
         e.s_nxt[(long)r * 2 * D + s] = v;
-        if (s >= D && e.nu32) e.nu32[(long)r * D + j] = (float)v;
+        if (s >= D) {
+            if (e.nu32) e.nu32[(long)r * D + j] = (float)v;
+            if (e.sacc) e.sacc[(long)r * D + j] += v;
+            if (e.rho_all) e.rho_all[((long)r * e.P + e.m_step) * D + j] = v;
+        }
     }
 }
 
@@ -151,7 +150,6 @@ __device__ inline void epi_dispatch(int mode, F&& f) {
         case EPI_FSTEP: f(std::integral_constant<int, EPI_FSTEP>{}); break;
         case EPI_COARSE_INIT: f(std::integral_constant<int, EPI_COARSE_INIT>{}); break;
         case EPI_COARSE_DELTA: f(std::integral_constant<int, EPI_COARSE_DELTA>{}); break;
-        case EPI_ADJ_RHO: f(std::integral_constant<int, EPI_ADJ_RHO>{}); break;
         case EPI_ADJ_STATE: f(std::integral_constant<int, EPI_ADJ_STATE>{}); break;
         default: break;
     }

@@ -185,9 +185,11 @@ hipError_t zero_fill(double* a, float* b, long n, hipStream_t st) {
 }
 
 // adjoint sweep state [a | nu] (2Dp per column): a = nu = src (+ add, a
-// row of stride ld_add, when given); FP32 copy of nu when nu32 is given
+// row of stride ld_add, when given); FP32 copy of nu when nu32 is given; a
+// copy of nu at nu_set + r*ld_set when given
 __global__ void k_adj_init(const double* __restrict__ src, const double* __restrict__ add, long ld_add,
-                           double* __restrict__ S, float* __restrict__ nu32, long rows, int Dp) {
+                           double* __restrict__ S, float* __restrict__ nu32, double* __restrict__ nu_set,
+                           long ld_set, long rows, int Dp) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
          i += (long)gridDim.x * blockDim.x) {
         const long r = i / Dp;
@@ -197,12 +199,14 @@ __global__ void k_adj_init(const double* __restrict__ src, const double* __restr
         S[r * 2 * Dp + s] = v;
         S[r * 2 * Dp + Dp + s] = v;
         if (nu32) nu32[i] = (float)v;
+        if (nu_set) nu_set[r * ld_set + s] = v;
     }
 }
 
-hipError_t adj_init(const double* src, const double* add, long ld_add, double* S, float* nu32, long rows, int Dp,
-                    hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_init, grid1(rows * Dp), dim3(256), 0, st, src, add, ld_add, S, nu32, rows, Dp);
+hipError_t adj_init(const double* src, const double* add, long ld_add, double* S, float* nu32, double* nu_set,
+                    long ld_set, long rows, int Dp, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_init, grid1(rows * Dp), dim3(256), 0, st, src, add, ld_add, S, nu32, nu_set, ld_set,
+                       rows, Dp);
     return hipGetLastError();
 }
 

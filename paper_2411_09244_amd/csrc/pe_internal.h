@@ -31,8 +31,7 @@ enum EpiMode : int {
     EPI_FSTEP = 2,   // fused fine step: d = ZF(t) - base - acc -> state/history update (ping-pong)
     EPI_COARSE_INIT = 3,   // initial coarse sweep: x_{n+1} = Phi_G x_n + c_n
     EPI_COARSE_DELTA = 4,  // correction of eq. (2.7): x_{n+1}^k = F_n + Phi_G (x_n^k - x_n^{k-1})
-    EPI_ADJ_RHO = 5,       // adjoint step, first product: rho = Z^T nu (+ source adjoint)
-    EPI_ADJ_STATE = 6,     // adjoint step, second product: [a; nu] <- a - [A; A + Mh] rho
+    EPI_ADJ_STATE = 6,     // fused adjoint step: [a; nu] <- a - [A; A + Mh] Z^T nu (+ cotangent)
 };
 
 struct Epi {
@@ -85,11 +84,12 @@ struct Epi {
     float* dl32 = nullptr;
     long ldl = 0;
     const int* active = nullptr;
-    // EPI_ADJ_RHO: rho -> R64/R32 (ldr, each nullable); source adjoint accumulation
-    double* sacc = nullptr;         // += rho (per-interval source adjoint), ld ldr
-    double* rho_all = nullptr;      // rho of step m at row r*P + m (per-step source adjoint), ld ldr
+    // EPI_ADJ_STATE: adjoint state [a | nu], 2*ldr per column; the new nu
+    // is also summed into sacc or stored at row r*P + m_step of rho_all
+    // (both nullable, ld ldr): the source adjoint is Z^T applied to them
+    double* sacc = nullptr;
+    double* rho_all = nullptr;
     int m_step = 0;
-    // EPI_ADJ_STATE: adjoint state [a | nu], 2*ldr per column
     const double* s_cur = nullptr;
     double* s_nxt = nullptr;
     float* nu32 = nullptr;          // FP32 copy of nu, ld ldr

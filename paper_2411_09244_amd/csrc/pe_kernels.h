@@ -9,8 +9,8 @@ hipError_t unpack_states(const double* src, double* dst, long rows, int d1, int 
                          hipStream_t st);
 hipError_t fine_init(const double* X, long ldXb, int row_off, int nvalid, double* Xa, double* dev64,
                      float* dev32, int B, int N, int Dp, hipStream_t st);
-hipError_t adj_init(const double* src, const double* add, long ld_add, double* S, float* nu32, long rows, int Dp,
-                    hipStream_t st);
+hipError_t adj_init(const double* src, const double* add, long ld_add, double* S, float* nu32, double* nu_set,
+                    long ld_set, long rows, int Dp, hipStream_t st);
 hipError_t axpy(double* y, const double* x, double a, long n, hipStream_t st);
 hipError_t zero_row0(double* X, long ldb, int B, int Dp, hipStream_t st);
 hipError_t sample_dot_sums(const double* Y, const double* Z, int B, long rows_per_b, int Dp, double scale,

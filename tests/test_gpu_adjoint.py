@@ -298,3 +298,35 @@ def test_full_size_adjoint_c3(prec, bar):
     assert r["status"] == 0
     assert e <= bar
     np.testing.assert_allclose(J[0], c["J"], rtol=max(bar, 1e-12))
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", TOL64), ("mixed", TOLMIX)])
+def test_adjoint_full_space_no_explicit_part(prec, bar):
+    """d2 = 0 (V_H1 = the whole fine Q1 space): the transposed scheme is
+    transposed backward Euler; boundary cotangents plus fine-step tracking."""
+    pe = _pe()
+    from problem.fem import FineGrid
+    n, P, N = 12, 5, 4
+    rng = np.random.default_rng(23)
+    fine = FineGrid(np.exp(2 * rng.standard_normal((n, n))))
+    M, A = fine.M.toarray(), fine.A.toarray()
+    d1 = M.shape[0]
+    dt = 1e-2
+    z = np.zeros((d1, 0))
+    bl = S.Blocks(M, z, np.zeros((0, 0)), A, z, np.zeros((0, 0)), dt, dt / P, N)
+    G = fine.load_smooth(lambda x, y: np.sin(np.pi * x) * y)[:, None]
+    H = rng.standard_normal((1, 1, N))
+    Xbar = rng.standard_normal((1, N + 1, d1))
+    dH = rng.standard_normal((1, 1, N))
+    Yf = ADJ.fine_trajectory(bl, S.Source(G, dH, S.TIME_INTERVAL, N, P), 0.1 * rng.standard_normal(d1))
+    src = S.Source(G, H, S.TIME_INTERVAL, N, P)
+    x0b, Hb, lam = ADJ.adjoint(bl, src, Xbar[0], Xbar_fine=ADJ.tracking_cotangents(bl, Yf, 1.0))
+    pr = pe.Problem(dict(M11=M, M12=z, M22=np.zeros((0, 0)), A11=A, A12=z, A22=np.zeros((0, 0))),
+                    dt, dt / P, N, prec)
+    pr.set_source(G, H, "interval")
+    r = pr.adjoint(Xbar=Xbar, beta=1.0, Ybnd=Yf[::P][None], dH=dH, lam=True)
+    pr.close()
+    e = _rel([r["x0bar"].cpu().numpy()[0], r["Hbar"].cpu().numpy()[0]], [x0b, Hb])
+    el = _rel([r["lam"].cpu().numpy()[0]], [lam])
+    print(f"d2 = 0 {prec}: grad rel err {e:.3e}, lambda rel err {el:.3e}")
+    assert e <= bar and el <= bar

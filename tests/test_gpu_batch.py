@@ -140,3 +140,35 @@ def test_batch_errors():
     prs2 = [pe.problem_from(probs[0], "fp64"), pe.problem_from(probs[0], "mixed")]
     with pytest.raises(pe.PeError, match="precision"):
         pe.Batch(prs2)
+
+
+def test_batch_with_full_space_problem():
+    """A d2 = 0 problem (V_H1 = the whole fine space) inside a ragged batch."""
+    pe = _pe()
+    from problem.fem import FineGrid
+    n, P, N = 12, 4, 5
+    rng = np.random.default_rng(29)
+    fine = FineGrid(np.exp(2 * rng.standard_normal((n, n))))
+    M, A = fine.M.toarray(), fine.A.toarray()
+    d1 = M.shape[0]
+    dt = 1e-2
+    z = np.zeros((d1, 0))
+    bl0 = S.Blocks(M, z, np.zeros((0, 0)), A, z, np.zeros((0, 0)), dt, dt / P, N)
+    G = fine.load_smooth(lambda x, y: np.sin(np.pi * x) * y)[:, None]
+    H = rng.standard_normal((1, 1, N))
+    x0 = rng.standard_normal(d1) * 0.1
+    for prec, bar in (("fp64", TOL64), ("mixed", TOLMIX)):
+        pr0 = pe.Problem(dict(M11=M, M12=z, M22=np.zeros((0, 0)), A11=A, A12=z, A22=np.zeros((0, 0))),
+                         dt, dt / P, N, prec)
+        pr0.set_source(G, H, "interval")
+        probs, prs = _setup(pe, prec, BATCH[:3])
+        bt = pe.Batch([pr0] + prs)
+        Xs, its, st = bt.solve([x0[None]] + [p["x0"] for p in probs], tol=0.0)
+        ref = S.fine_composition(bl0, S.Source(G, H, S.TIME_INTERVAL, N, P), x0)
+        e0 = _rel(bl0, Xs[0][0].cpu().numpy(), ref)
+        print(f"{prec}: d2 = 0 member rel err {e0:.3e}, iterations {its[0]}")
+        assert e0 <= bar
+        for p, X in zip(probs, Xs[1:]):
+            bl, src = S.Blocks.from_problem(p), S.Source.from_problem(p)
+            assert _rel(bl, X[0].cpu().numpy(), S.fine_composition(bl, src, p["x0"][0], 0)) <= bar
+        bt.close()

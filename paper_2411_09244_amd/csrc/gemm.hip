@@ -12,6 +12,7 @@
 // (the coarse sweep) use a row-parallel GEMV kernel instead.
 #include "pe_internal.h"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace pe {
@@ -341,55 +342,89 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmItem* __res
     gemm_tile<T, BR, BS, BK>(it.sh, it.epi, it.tiles_r, wg_tile[blockIdx.x], 0, 1, nullptr);
 }
 
-// sum of the split-K planes in split order, then the epilogue; one thread per element
-template <typename T>
+// sum of the split-K planes, then the epilogue. TPE threads per element:
+// thread t of an element sums planes t, t + TPE, ... in order, the TPE
+// partial sums are combined by a fixed butterfly (bitwise reproducible), and
+// the first thread runs the epilogue. More threads per element keep more
+// loads in flight (the kernel is latency-bound at small sizes).
+template <typename T, int TPE>
 __global__ __launch_bounds__(256) void splitk_epilogue_kernel(const int Mr, const int Ns, const int splitk,
                                                               const T* __restrict__ part, const Epi epi) {
     const long total = (long)Mr * Ns;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const int t = threadIdx.x % TPE;
+    const long first = (blockIdx.x * (long)blockDim.x + threadIdx.x) / TPE;
+    const long stride = (long)gridDim.x * blockDim.x / TPE;
+    for (long i = first; i < total; i += stride) {
         double v = 0.0;
-        for (int sp = 0; sp < splitk; ++sp) v += (double)part[(long)sp * total + i];
-        const int r = (int)(i / Ns), s = (int)(i - (long)r * Ns);
-        epilogue(epi, r, s, v);
+        for (int sp = t; sp < splitk; sp += TPE) v += (double)part[(long)sp * total + i];
+        if (TPE > 1)
+            for (int off = TPE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, TPE);
+        if (t == 0) {
+            const int r = (int)(i / Ns), s = (int)(i - (long)r * Ns);
+            epilogue(epi, r, s, v);
+        }
     }
 }
 
-// y[r][s] = sum_k A[r][k] B[s][k] for MR <= 4 state columns: one wave per
-// operator row, 16-byte loads along K, wave reduction, epilogue by lane 0
-template <typename T, int MR>
+// y[r][s] = sum_k A[r][k] B[s][k] for MR <= 4 state columns: WPR waves per
+// operator row (4 / WPR rows per work-group), each wave taking every WPR-th
+// 64-lane chunk of K with 16-byte loads; wave reductions, then the WPR
+// partial sums are added in wave order (bitwise reproducible) and the
+// epilogue runs once per (r, s)
+template <typename T, int MR, int WPR>
 __global__ __launch_bounds__(256) void gemv_kernel(const GemmShape sh, const Epi epi) {
     using vec_t = typename MfmaOp<T>::vec_t;
     constexpr int VW = 16 / sizeof(T);
+    __shared__ double red[4][MR];
     const int lane = threadIdx.x & 63;
-    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (s >= sh.Ns) return;
-    const int k0 = s < sh.s_split ? sh.k0a : sh.k0b;
-    const int k1 = s < sh.s_split ? sh.k1a : sh.k1b;
-    const T* __restrict__ B = (const T*)sh.B + (long)s * sh.ldb;
-    const T* __restrict__ A = (const T*)sh.A;
+    const int wave = threadIdx.x >> 6;
+    const int sub = wave % WPR;
+    const int s = blockIdx.x * (4 / WPR) + wave / WPR;
     double acc[MR];
 #pragma unroll
     for (int r = 0; r < MR; ++r) acc[r] = 0.0;
-    for (int k = k0 + VW * lane; k < k1; k += 64 * VW) {
-        const vec_t w = *(const vec_t*)(B + k);
-        const T* wp = (const T*)&w;
+    if (s < sh.Ns) {
+        const int k0 = s < sh.s_split ? sh.k0a : sh.k0b;
+        const int k1 = s < sh.s_split ? sh.k1a : sh.k1b;
+        const T* __restrict__ B = (const T*)sh.B + (long)s * sh.ldb;
+        const T* __restrict__ A = (const T*)sh.A;
+        for (int k = k0 + VW * (lane + 64 * sub); k < k1; k += 64 * VW * WPR) {
+            const vec_t w = *(const vec_t*)(B + k);
+            const T* wp = (const T*)&w;
 #pragma unroll
-        for (int r = 0; r < MR; ++r) {
-            if (r < sh.Mr) {
-                const vec_t x = *(const vec_t*)(A + (long)r * sh.lda + k);
-                const T* xp = (const T*)&x;
+            for (int r = 0; r < MR; ++r) {
+                if (r < sh.Mr) {
+                    const vec_t x = *(const vec_t*)(A + (long)r * sh.lda + k);
+                    const T* xp = (const T*)&x;
 #pragma unroll
-                for (int q = 0; q < VW; ++q) acc[r] += (double)wp[q] * (double)xp[q];
+                    for (int q = 0; q < VW; ++q) acc[r] += (double)wp[q] * (double)xp[q];
+                }
             }
         }
     }
 #pragma unroll
     for (int r = 0; r < MR; ++r)
         for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off, 64);
+    if (WPR == 1) {
+        if (lane == 0 && s < sh.Ns)
+#pragma unroll
+            for (int r = 0; r < MR; ++r)
+                if (r < sh.Mr) epilogue(epi, r, s, acc[r]);
+        return;
+    }
     if (lane == 0)
 #pragma unroll
-        for (int r = 0; r < MR; ++r)
-            if (r < sh.Mr) epilogue(epi, r, s, acc[r]);
+        for (int r = 0; r < MR; ++r) red[wave][r] = acc[r];
+    __syncthreads();
+    if (lane == 0 && sub == 0 && s < sh.Ns) {
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            if (r >= sh.Mr) break;
+            double v = red[wave][r];
+            for (int w = 1; w < WPR; ++w) v += red[wave + w][r];
+            epilogue(epi, r, s, v);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -427,6 +462,20 @@ TileCfg choose_tiles(const GemmShape& sh, bool fp32, int n_cu) {
     return c;
 }
 
+// threads per element of the split-K reduction (PE_SPLITK_TPE = 1, 2 or 4;
+// never more than the split count)
+static int splitk_tpe(int splitk) {
+    static int w = -1;
+    if (w < 0) {
+        const char* e = getenv("PE_SPLITK_TPE");
+        w = e ? atoi(e) : 1;
+        if (w != 1 && w != 2 && w != 4) w = 1;
+    }
+    int t = w;
+    while (t > 1 && t > splitk) t >>= 1;
+    return t;
+}
+
 template <typename T, int BR, int BS, int BK>
 static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, GemmWork& ws,
                              hipStream_t stream) {
@@ -442,20 +491,47 @@ static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, Ge
     if (e != hipSuccess || splitk == 1) return e;
     if (ws.between) ws.between(ws.between_arg);
     const long total = (long)sh.Mr * sh.Ns;
-    long blocks = (total + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL((splitk_epilogue_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, stream, sh.Mr,
-                       sh.Ns, splitk, (const T*)ws.part, epi);
+    const int tpe = splitk_tpe(splitk);
+    long blocks = (total * tpe + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    const dim3 g((unsigned)blocks), b(256);
+    const T* part = (const T*)ws.part;
+    switch (tpe) {
+        case 4: hipLaunchKernelGGL((splitk_epilogue_kernel<T, 4>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
+        case 2: hipLaunchKernelGGL((splitk_epilogue_kernel<T, 2>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
+        default: hipLaunchKernelGGL((splitk_epilogue_kernel<T, 1>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
+    }
     return hipGetLastError();
+}
+
+template <typename T, int WPR>
+static void launch_gemv_w(const GemmShape& sh, const Epi& epi, hipStream_t stream) {
+    dim3 grid((unsigned)cdiv(sh.Ns, 4 / WPR));
+    switch (sh.Mr) {
+        case 1: hipLaunchKernelGGL((gemv_kernel<T, 1, WPR>), grid, dim3(256), 0, stream, sh, epi); break;
+        case 2: hipLaunchKernelGGL((gemv_kernel<T, 2, WPR>), grid, dim3(256), 0, stream, sh, epi); break;
+        default: hipLaunchKernelGGL((gemv_kernel<T, 4, WPR>), grid, dim3(256), 0, stream, sh, epi); break;
+    }
+}
+
+// waves per operator row of the coarse-step products (PE_GEMV_WPR = 1, 2 or
+// 4; 2 measured fastest on MI355X at d = 2000)
+static int gemv_wpr() {
+    static int w = -1;
+    if (w < 0) {
+        const char* e = getenv("PE_GEMV_WPR");
+        w = e ? atoi(e) : 2;
+        if (w != 1 && w != 2 && w != 4) w = 2;
+    }
+    return w;
 }
 
 template <typename T>
 static hipError_t launch_gemv(const GemmShape& sh, const Epi& epi, hipStream_t stream) {
-    dim3 grid((unsigned)cdiv(sh.Ns, 4));
-    switch (sh.Mr) {
-        case 1: hipLaunchKernelGGL((gemv_kernel<T, 1>), grid, dim3(256), 0, stream, sh, epi); break;
-        case 2: hipLaunchKernelGGL((gemv_kernel<T, 2>), grid, dim3(256), 0, stream, sh, epi); break;
-        default: hipLaunchKernelGGL((gemv_kernel<T, 4>), grid, dim3(256), 0, stream, sh, epi); break;
+    switch (gemv_wpr()) {
+        case 4: launch_gemv_w<T, 4>(sh, epi, stream); break;
+        case 2: launch_gemv_w<T, 2>(sh, epi, stream); break;
+        default: launch_gemv_w<T, 1>(sh, epi, stream); break;
     }
     return hipGetLastError();
 }

@@ -30,6 +30,7 @@ WORKLOAD = ("200x200 Q1 fine grid, 20x20 coarse grid, lognormal kappa (sigma 1, 
 METRIC = "parareal solves/sec to 1e-6 rel L2: batched FP32-MFMA+refine vs plain FP64"
 PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6
+PEAK_HBM_TBPS = 8.0      # MI355X HBM3E
 
 # HBM bytes per launch of the fine residual product, from two rocprofv3 --pmc
 # passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0: the factors a 256 MiB device
@@ -464,6 +465,11 @@ def main():
                     algorithmic_bytes=round((d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * 4 + N * 2 * (d1 + d2) * 4),
                     splitk_reduce_avg_us=round(avg_red * 1e6, 3),
                     achieved_with_reduce=round(flops_per_launch / (avg_s + avg_red) / 1e12, 3))
+    if traffic is not None:
+        # HBM side of the same kernel: measured bytes per launch over the
+        # live average duration, against the 8 TB/s HBM3E peak
+        roofline["hbm_achieved_TBps"] = round(traffic / avg_s / 1e12, 3)
+        roofline["hbm_frac"] = round(traffic / avg_s / 1e12 / PEAK_HBM_TBPS, 5)
 
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1,

@@ -217,6 +217,22 @@ void free_list(std::vector<void*>& list) {
     list.clear();
 }
 
+// temporary device allocations of one call: released (after the stream has
+// drained) when the owner goes out of scope, on every return path
+struct TmpList {
+    hipStream_t st;
+    std::vector<void*> v;
+    explicit TmpList(hipStream_t s) : st(s) {}
+    ~TmpList() {
+        if (!v.empty()) {
+            (void)hipStreamSynchronize(st);
+            free_list(v);
+        }
+    }
+    TmpList(const TmpList&) = delete;
+    TmpList& operator=(const TmpList&) = delete;
+};
+
 void graphs_clear(pe_problem p);
 
 // grow the split-K workspace if a launch needs more (synchronises first)
@@ -546,7 +562,8 @@ Epi store_epi(double* C, long ldc, double alpha = 1.0, const double* C0 = nullpt
 pe_status factor_inverse(pe_problem p, double* Aemb, int nf, double* Kinv, const char* name, int d,
                          double* Zt_out = nullptr) {
     const int nb = 64, nblk = nf / nb;
-    std::vector<void*> tmp;
+    TmpList tmpl(p->st);
+    std::vector<void*>& tmp = tmpl.v;
     double *Dinv = nullptr, *Zt = nullptr, *T = nullptr;
     int* info = nullptr;
     auto cleanup = [&]() {
@@ -618,7 +635,8 @@ pe_status build_step_ops(pe_problem p, double h, const double* M11, const double
                          const double* A21, const double* A22, double* Z, double* W) {
     const int d1 = p->d1, d2 = p->d2, d1p = p->d1p, d2p = p->d2p, Dp = p->Dp;
     const int nf1 = roundup(d1, 64);
-    std::vector<void*> tmp;
+    TmpList tmpl(p->st);
+    std::vector<void*>& tmp = tmpl.v;
     double *K = nullptr, *Kinv = nullptr, *Q = nullptr;
     pe_status s;
     if ((s = dalloc_t(p, tmp, &K, (size_t)nf1 * nf1)) < 0 || (s = dalloc_t(p, tmp, &Kinv, (size_t)nf1 * nf1)) < 0 ||
@@ -815,7 +833,8 @@ pe_status ensure_workspace(pe_problem p, int B) {
 pe_status interval_table(pe_problem p, int B, const double* H, double* out, double* out_w) {
     const int Dp = p->Dp, N = p->N, R = p->R, Rp = p->Rp;
     double* Ht = nullptr;
-    std::vector<void*> tmp;
+    TmpList tmpl(p->st);
+    std::vector<void*>& tmp = tmpl.v;
     PE_TRY(dalloc_t(p, tmp, &Ht, (size_t)B * N * Rp));
     pe_status s = PE_OK;
     if (hipMemsetAsync(Ht, 0, sizeof(double) * B * N * Rp, p->st) != hipSuccess)
@@ -1057,7 +1076,8 @@ pe_status ensure_adj_ops(pe_problem p) {
     if (p->adj_ops) return PE_OK;
     const int d1 = p->d1, d2 = p->d2, d1p = p->d1p, d2p = p->d2p, Dp = p->Dp;
     auto& OL = p->op_allocs;
-    std::vector<void*> tmp;
+    TmpList tmpl(p->st);
+    std::vector<void*>& tmp = tmpl.v;
     auto done = [&](pe_status r) {
         (void)hipStreamSynchronize(p->st);
         free_list(tmp);
@@ -2060,7 +2080,8 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
     {
         // coarse source term c_n = Z_dt F(t_{n+1}) for every (sample, interval)
         double* Fc = nullptr;
-        std::vector<void*> tmp;
+        TmpList tmpl(p->st);
+        std::vector<void*>& tmp = tmpl.v;
         PE_TRY(dalloc_t(p, tmp, &Fc, (size_t)B * p->N * Dp));
         Epi e;
         e.mode = EPI_RESID;

@@ -36,8 +36,8 @@ PEAK_HBM_TBPS = 8.0      # MI355X HBM3E
 # passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0: the factors a 256 MiB device
 # copy reads for the same counters), keyed by workload and the kernel's tile
 # configuration (state-tile rows, operator-tile rows, K depth, split-K).
-# Reported only when the timed run used that configuration.
-MEASURED_TRAFFIC = {("c1", (64, 32, 64, 8)): 2.0 * 18546.8 * 1024 + 1.0 * 4000.0 * 1024}
+# Reported only when the timed run used that kernel class and configuration.
+MEASURED_TRAFFIC = {("c1", "fine_step", (64, 32, 64, 8)): 2.0 * 18546.8 * 1024 + 1.0 * 4000.0 * 1024}
 
 
 def time_solves(pr, x0, tol, steps, warmup, torch):
@@ -421,7 +421,7 @@ def main():
         dt, X, iters, hist, st, prof, dt_prof = time_solves(pr, x0, tol, args.steps, args.warmup, torch)
         res[prec] = dict(seconds=dt, X=X[0].cpu().numpy(), iters=int(iters[0]), status=st,
                          setup=setup, prof=prof, seconds_profiled=dt_prof,
-                         tiles=pr.last_tiles("fine_step"))
+                         tiles=pr.last_tiles("fine_step"), tiles_sweep=pr.last_tiles("fine_sweep"))
         log(f"{prec}: {args.steps} solves in {dt:.3f}s ({1e3 * dt / args.steps:.2f} ms/solve), "
             f"iterations {iters[0]}, set-up {setup:.2f}s; event-timed pass {1e3 * dt_prof / args.steps:.2f} ms/solve")
         log(f"{prec} launch timing: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in prof.items()))
@@ -445,26 +445,38 @@ def main():
     # Z_h W_h dev (the scheme's residual products (i), (iii) and the solves
     # (ii), (iv) folded into one operator), algorithmic
     # 2*(d1^2 + 4 d1 d2 + 2 d2^2) flops per column (its nonzero blocks), N
-    # columns per launch. The product kernel is timed alone; its split-K
-    # reduction kernel is reported beside it.
-    ms_tot, n_launch = mixed["prof"]["fine_step"]
+    # columns per step. With per-step launches the product kernel is timed
+    # alone and its split-K reduction kernel beside it; the persistent sweep
+    # (one cooperative launch for the P steps of a sweep, reductions and grid
+    # synchronisations included) is timed per sweep: (P - 1) steps of flops.
+    step_flops = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * N
+    step_bytes = (d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * 4 + N * 2 * (d1 + d2) * 4
     ms_red, n_red = mixed["prof"]["splitk_reduce"]
-    flops_per_launch = 2.0 * (d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * N
-    avg_s = (ms_tot / n_launch) * 1e-3 if n_launch else float("nan")
     avg_red = (ms_red / n_red) * 1e-3 if n_red else 0.0
+    if mixed["prof"]["fine_sweep"][1]:
+        ms_tot, n_launch = mixed["prof"]["fine_sweep"]
+        cls, tiles = "fine_sweep", tuple(mixed["tiles_sweep"])
+        flops_per_launch, bytes_per_launch = (P - 1) * step_flops, (P - 1) * step_bytes
+        kname = ("fine_sweep_persistent_kernel<float,%d,%d,%d> persistent fine sweep (%d fused steps, "
+                 "split-K %%d, in-kernel reductions)" % (tiles[:3] + (P,))) % tiles[3]
+    else:
+        ms_tot, n_launch = mixed["prof"]["fine_step"]
+        cls, tiles = "fine_step", tuple(mixed["tiles"])
+        flops_per_launch, bytes_per_launch = step_flops, step_bytes
+        kname = "gemm_nt_kernel<float,%d,%d,%d> fused fine-step product (Z W dev), split-K %d" % tiles
+    avg_s = (ms_tot / n_launch) * 1e-3 if n_launch else float("nan")
     achieved = flops_per_launch / avg_s / 1e12
-    tiles = tuple(mixed["tiles"])
-    traffic = MEASURED_TRAFFIC.get((args.config, tiles))
-    roofline = dict(kernel="gemm_nt_kernel<float,%d,%d,%d> fused fine-step product (Z W dev), split-K %d"
-                    % tiles, bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP32_MFMA, unit="TFLOP/s",
+    traffic = MEASURED_TRAFFIC.get((args.config, cls, tiles))
+    roofline = dict(kernel=kname, bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP32_MFMA, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_MFMA, 5),
                     traffic=None if traffic is None else round(traffic),
                     avg_launch_us=round(avg_s * 1e6, 3), launches=n_launch,
                     flops_per_launch=flops_per_launch,
                     traffic_unit="bytes per launch (HBM, FETCH_SIZE+WRITE_SIZE, calibrated)",
-                    algorithmic_bytes=round((d1 * d1 + 4.0 * d1 * d2 + 2.0 * d2 * d2) * 4 + N * 2 * (d1 + d2) * 4),
-                    splitk_reduce_avg_us=round(avg_red * 1e6, 3),
-                    achieved_with_reduce=round(flops_per_launch / (avg_s + avg_red) / 1e12, 3))
+                    algorithmic_bytes=round(bytes_per_launch))
+    if cls == "fine_step":
+        roofline["splitk_reduce_avg_us"] = round(avg_red * 1e6, 3)
+        roofline["achieved_with_reduce"] = round(flops_per_launch / (avg_s + avg_red) / 1e12, 3)
     if traffic is not None:
         # HBM side of the same kernel: measured bytes per launch over the
         # live average duration, against the 8 TB/s HBM3E peak
@@ -488,7 +500,7 @@ def main():
                        "ms_per_step": round(1e3 * f64["seconds"] / args.steps, 4),
                        "iterations": f64["iters"], "setup_s": round(f64["setup"], 3)}
         out["speedup_mixed_vs_fp64"] = round(f64["seconds"] / mixed["seconds"], 4)
-        ms64, n64 = f64["prof"]["fine_step"]
+        ms64, n64 = f64["prof"][cls]
         if n64:
             a64 = flops_per_launch / ((ms64 / n64) * 1e-3) / 1e12
             out["fp64"]["roofline"] = dict(bound="mfma", achieved=round(a64, 3), peak=PEAK_FP64_MFMA,

@@ -253,7 +253,13 @@ enum {
     PE_PROF_SPLITK_REDUCE = 5,  /* split-K reduction + epilogue kernels of the above */
     PE_PROF_ADJ_STEP = 6,       /* transposed fine step: [a; nu] <- a - ([A; A + Mh] Z^T) nu
                                    as one product                                 */
-    PE_PROF_KINDS = 7
+    PE_PROF_FINE_SWEEP = 7,     /* persistent fine sweep: all P fused steps of a sweep
+                                   in one cooperative launch with grid barriers
+                                   between them; used when PE_PERSISTENT=1 is in the
+                                   environment at problem creation and the N*B
+                                   interval columns fit one 64-row tile (by default
+                                   each step is its own launch, replayed from a graph) */
+    PE_PROF_KINDS = 8
 };
 
 /*

@@ -30,7 +30,7 @@ EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate"
            "pe_autotune", "pe_last_tiles", "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
 PROFILE_KINDS = {"fine_step": 0, "fine_first": 1, "anchor": 2, "coarse": 3, "norm": 4, "splitk_reduce": 5,
-                 "adj_step": 6}
+                 "adj_step": 6, "fine_sweep": 7}
 
 
 class PeError(RuntimeError):

@@ -179,6 +179,11 @@ struct pe_problem_s {
     // tile configuration of the last launch of each profiled class
     int last_cfg[PE_PROF_KINDS][4] = {{0}};
 
+    // persistent fine sweep (one cooperative launch per sweep, opt-in) when
+    // the interval columns fit one row tile; co-resident grid per precision
+    int persistent = 0;
+    int pers_grid[2] = {-1, -1};
+
     // autotuned tile configurations per product site and shape
     int autotune = 1;
     std::map<std::vector<int>, pe::TileCfg> tuned;
@@ -916,44 +921,96 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->ZA64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
                         PE_PROF_ANCHOR, SITE_ANCHOR));
     const long ldS = 2L * Dp;
-    for (int step = 0; step < p->P; ++step) {
+    // the fused step's epilogue fields (step index and state buffers are per step)
+    Epi eb;
+    eb.mode = EPI_FSTEP;
+    eb.base = p->Ya;
+    eb.ldb = Dp;
+    source_fields_step(p, eb);
+    if (sv) {
+        eb.src_kind = sv->kind;
+        eb.Hs = sv->Hs;
+        eb.Fint = sv->ZFint;
+    }
+    if (!with_source) eb.src_kind = 0;
+    eb.cols_per_b = p->N;
+    eb.n_fixed = -1;
+    eb.ldd = ldS;
+    eb.d1p = d1p;
+    eb.d2p = d2p;
+    eb.xa = p->Xa;
+    eb.ldtraj = (long)p->P * Dp;
+    // u-rows of Z_h W_h have no du_prev columns
+    GemmShape gs = shape(rows, Dp, mixed ? (const void*)p->dev32[0] : (const void*)p->dev64[0], ldS,
+                         mixed ? (const void*)p->ZW32 : (const void*)p->ZW64, ldS, 0, 0);
+    gs.s_split = d1p;
+    gs.k0a = d1p;
+    gs.k1a = 2 * Dp;
+    gs.k0b = 0;
+    gs.k1b = 2 * Dp;
+    bool done = false;
+    if (p->persistent && rows <= 64) {
+        int& grid = p->pers_grid[mixed ? 1 : 0];
+        if (grid < 0) {
+            grid = mixed ? fine_sweep_persistent_grid<float>() : fine_sweep_persistent_grid<double>();
+            // optional cap on the co-resident grid (fewer work-groups per grid barrier)
+            if (const char* gc = getenv("PE_PERSISTENT_GRID")) {
+                const int cap = atoi(gc);
+                if (cap > 0 && cap < grid) grid = cap;
+            }
+        }
+        if (grid > 0) {
+            // split count: about one (tile, split) item per co-resident work-group,
+            // at least two K tiles per split
+            const int n_tiles = (Dp + 31) / 32;
+            const int bk = mixed ? 64 : 32;
+            const int ktiles = (2 * Dp + bk - 1) / bk;
+            int sk = std::max(1, std::min(16, grid / n_tiles));
+            while (sk > 1 && ktiles / sk < 2) --sk;
+            const size_t elem = mixed ? sizeof(float) : sizeof(double);
+            PE_TRY(ensure_gemm_work(p, (size_t)sk * rows * Dp * elem));
+            p->last_cfg[PE_PROF_FINE_SWEEP][0] = 64;
+            p->last_cfg[PE_PROF_FINE_SWEEP][1] = 32;
+            p->last_cfg[PE_PROF_FINE_SWEEP][2] = bk;
+            p->last_cfg[PE_PROF_FINE_SWEEP][3] = sk;
+            size_t slot;
+            PE_TRY(prof_begin(p, PE_PROF_FINE_SWEEP, &slot));
+            const void* A1 = mixed ? (const void*)p->dev32[1] : (const void*)p->dev64[1];
+            hipError_t e = mixed ? fine_sweep_persistent<float>(gs, A1, eb, p->dev64[0], p->dev64[1], p->dev32[0],
+                                                                p->dev32[1], traj, p->P, grid, sk, p->gw.part,
+                                                                p->gw.part_bytes, p->st)
+                                 : fine_sweep_persistent<double>(gs, A1, eb, p->dev64[0], p->dev64[1], nullptr,
+                                                                 nullptr, traj, p->P, grid, sk, p->gw.part,
+                                                                 p->gw.part_bytes, p->st);
+            if (e == hipSuccess) {
+                PE_TRY(prof_end(p, slot));
+                done = true;
+            } else {
+                (void)hipGetLastError();
+                hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+                if (hipStreamIsCapturing(p->st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+                    // not capturable: the caller keeps this sweep eager, so
+                    // replays and eager runs take the same path
+                    return fail(PE_ERR_HIP, "persistent fine sweep cannot be captured");
+                // not launchable on this device: per-step launches from now on
+                p->persistent = 0;
+                if (slot != (size_t)-1) PE_TRY(prof_end(p, slot));
+            }
+        }
+    }
+    for (int step = 0; step < p->P && !done; ++step) {
         const int c = step & 1;
-        // the state deviation is zero at the first step (empty K ranges);
-        // u-rows of Z_h W_h have no du_prev columns
-        GemmShape g = shape(rows, Dp, mixed ? (const void*)p->dev32[c] : (const void*)p->dev64[c], ldS,
-                            mixed ? (const void*)p->ZW32 : (const void*)p->ZW64, ldS, 0, 0);
-        g.s_split = d1p;
-        if (step > 0) {
-            g.k0a = d1p;
-            g.k1a = 2 * Dp;
-            g.k0b = 0;
-            g.k1b = 2 * Dp;
+        GemmShape g = gs;
+        g.A = mixed ? (const void*)p->dev32[c] : (const void*)p->dev64[c];
+        if (step == 0) {  // zero deviation: empty K ranges
+            g.k0a = g.k1a = g.k0b = g.k1b = 0;
         }
-        Epi e;
-        e.mode = EPI_FSTEP;
-        e.base = p->Ya;
-        e.ldb = Dp;
-        source_fields_step(p, e);
-        if (sv) {
-            e.src_kind = sv->kind;
-            e.Hs = sv->Hs;
-            e.Fint = sv->ZFint;
-        }
-        if (!with_source) e.src_kind = 0;
-        e.cols_per_b = p->N;
-        e.n_fixed = -1;
+        Epi e = eb;
         e.p_step = step;
         e.din = p->dev64[c];
         e.dev64 = p->dev64[1 - c];
         e.dev32 = mixed ? p->dev32[1 - c] : nullptr;
-        e.ldd = ldS;
-        e.d1p = d1p;
-        e.d2p = d2p;
-        if (traj) {
-            e.traj = traj + (long)step * Dp;
-            e.ldtraj = (long)p->P * Dp;
-            e.xa = p->Xa;
-        }
+        e.traj = traj ? traj + (long)step * Dp : nullptr;
         const int kind = step > 0 ? PE_PROF_FINE_STEP : PE_PROF_FINE_FIRST;
         if (mixed)
             PE_TRY(gemm<float>(p, g, e, 0, kind, SITE_FINE_STEP));
@@ -1864,6 +1921,10 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         p->autotune = (at && at[0] == '0') ? 0 : 1;
         const char* gr = getenv("PE_GRAPHS");
         p->gc.use_graphs = (gr && gr[0] == '0') ? 0 : 1;
+        // persistent fine sweep: opt-in (measured slower than per-step launches
+        // replayed from graphs on MI355X: each grid-wide barrier costs tens of µs)
+        const char* pz = getenv("PE_PERSISTENT");
+        p->persistent = (pz && pz[0] == '1') ? 1 : 0;
         tune_cache_load(p);
     }
     int dev = 0;

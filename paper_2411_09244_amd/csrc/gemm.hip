@@ -12,6 +12,8 @@
 // (the coarse sweep) use a row-parallel GEMV kernel instead.
 #include "pe_internal.h"
 
+#include <hip/hip_cooperative_groups.h>
+
 #include <cstdlib>
 #include <type_traits>
 
@@ -50,7 +52,7 @@ struct MfmaOp<double> {
 // ---------------------------------------------------------------------------
 // epilogue
 // ---------------------------------------------------------------------------
-__device__ inline double source_value(const Epi& e, int r, int s) {
+__device__ inline double source_value_p(const Epi& e, int r, int s, int p_step) {
     if (e.src_kind == 0) return 0.0;
     int b, n;
     if (e.n_fixed >= 0) {
@@ -61,12 +63,49 @@ __device__ inline double source_value(const Epi& e, int r, int s) {
         n = r - b * e.cols_per_b;
     }
     if (e.src_kind == 2) return e.Fint[((long)b * e.N + n) * e.ldf + s];
-    const long tau = (e.time_mode == 0) ? (long)n * e.P + e.p_step : (long)n;
+    const long tau = (e.time_mode == 0) ? (long)n * e.P + p_step : (long)n;
     const double* g = e.Gs + (long)s * e.R;
     const double* h = e.Hs + (long)b * e.R * e.Tlen + tau;
     double v = 0.0;
     for (int q = 0; q < e.R; ++q) v += g[q] * h[(long)q * e.Tlen];
     return v;
+}
+
+__device__ inline double source_value(const Epi& e, int r, int s) { return source_value_p(e, r, s, e.p_step); }
+
+// fused fine step (EPI_FSTEP) with the step index and state buffers given
+// explicitly: increment d = Z F(t) - base - acc, then the state/history
+// update from din into dout (layout per column: [du_prev | u - u_a | w - w_a | dw_prev])
+__device__ inline void fstep_apply(const Epi& e, int r, int s, double acc, int p_step, const double* __restrict__ din,
+                                   double* __restrict__ dout, float* __restrict__ dout32, double* __restrict__ traj) {
+    double v = source_value_p(e, r, s, p_step) - acc;
+    if (e.base) v -= e.base[(long)r * e.ldb + s];
+    const double* di = din + (long)r * e.ldd;
+    double* d = dout + (long)r * e.ldd;
+    float* d32 = dout32 ? dout32 + (long)r * e.ldd : nullptr;
+    double full_dev;
+    if (s < e.d1p) {
+        const double u = di[e.d1p + s] + v;
+        d[s] = v;
+        d[e.d1p + s] = u;
+        if (d32) {
+            d32[s] = (float)v;
+            d32[e.d1p + s] = (float)u;
+        }
+        full_dev = u;
+    } else {
+        const int j = s - e.d1p;
+        const long ow = 2L * e.d1p + j, oh = 2L * e.d1p + e.d2p + j;
+        const double w = di[ow] + v;
+        d[ow] = w;
+        d[oh] = v;
+        if (d32) {
+            d32[ow] = (float)w;
+            d32[oh] = (float)v;
+        }
+        full_dev = w;
+    }
+    if (traj) traj[(long)r * e.ldtraj + s] = e.xa[(long)r * (e.d1p + e.d2p) + s] + full_dev;
 }
 
 // one epilogue per mode (the product kernel emits one unrolled store loop per
@@ -85,36 +124,7 @@ __device__ inline void epi_apply(const Epi& e, int r, int s, double acc) {
         e.R64[(long)r * e.ldr + s] = v;
         if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
     } else if constexpr (MODE == EPI_FSTEP) {
-        // increment of the fused step, then the state/history update from
-        // the input state (layout per column: [du_prev | u - u_a | w - w_a | dw_prev])
-        double v = source_value(e, r, s) - acc;
-        if (e.base) v -= e.base[(long)r * e.ldb + s];
-        const double* di = e.din + (long)r * e.ldd;
-        double* d = e.dev64 + (long)r * e.ldd;
-        float* d32 = e.dev32 ? e.dev32 + (long)r * e.ldd : nullptr;
-        double full_dev;
-        if (s < e.d1p) {
-            const double u = di[e.d1p + s] + v;
-            d[s] = v;
-            d[e.d1p + s] = u;
-            if (d32) {
-                d32[s] = (float)v;
-                d32[e.d1p + s] = (float)u;
-            }
-            full_dev = u;
-        } else {
-            const int j = s - e.d1p;
-            const long ow = 2L * e.d1p + j, oh = 2L * e.d1p + e.d2p + j;
-            const double w = di[ow] + v;
-            d[ow] = w;
-            d[oh] = v;
-            if (d32) {
-                d32[ow] = (float)w;
-                d32[oh] = (float)v;
-            }
-            full_dev = w;
-        }
-        if (e.traj) e.traj[(long)r * e.ldtraj + s] = e.xa[(long)r * (e.d1p + e.d2p) + s] + full_dev;
+        fstep_apply(e, r, s, acc, e.p_step, e.din, e.dev64, e.dev32, e.traj);
     } else if constexpr (MODE == EPI_COARSE_INIT) {
         const int b = r;
         double x = acc;
@@ -166,7 +176,8 @@ __device__ inline void epilogue(const Epi& e, int r, int s, double acc) {
 // one BR x BS output tile (or its split-K part) of C = epi(A B^T)
 template <typename T, int BR, int BS, int BK>
 __device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, const int tiles_r, const int tile,
-                                          const int split, const int splitk, T* __restrict__ part) {
+                                          const int split, const int splitk, T* __restrict__ part,
+                                          const bool planes_only = false) {
     using Op = MfmaOp<T>;
     using acc_t = typename Op::acc_t;
     using vec_t = typename Op::vec_t;
@@ -295,7 +306,7 @@ __device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, c
 
     // output coordinates of this lane: 16x16 block (i, j), element q ->
     // row Op::row(lane, q), column lane % 16 of the block
-    if (splitk == 1) {
+    if (splitk == 1 && !planes_only) {
         epi_dispatch(epi.mode, [&](auto m) {
             constexpr int MODE = decltype(m)::value;
 #pragma unroll
@@ -330,6 +341,49 @@ template <typename T, int BR, int BS, int BK>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const Epi epi, const int tiles_r,
                                                       const int splitk, T* __restrict__ part) {
     gemm_tile<T, BR, BS, BK>(sh, epi, tiles_r, blockIdx.x, blockIdx.y, splitk, part);
+}
+
+// Persistent fine sweep: every fused step of one sweep in one cooperative
+// launch, for products whose state columns fit one row tile (Mr <= BR).
+// Step p: the work-groups compute the split-K partial tiles of Z W dev into
+// the planes, the grid synchronises, every thread sums its elements' planes
+// in split order (bitwise reproducible) and runs the step epilogue (state
+// ping-pong: even steps read state buffer a, odd steps b), and the grid
+// synchronises again. Step 0 has no product (zero deviation).
+template <typename T, int BR, int BS, int BK>
+__global__ __launch_bounds__(256) void fine_sweep_persistent_kernel(const GemmShape sh, const void* A1, const Epi epi,
+                                                                    double* d64a, double* d64b, float* d32a,
+                                                                    float* d32b, double* traj, const int P,
+                                                                    const int n_tiles, const int splitk,
+                                                                    T* __restrict__ part) {
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    const long total = (long)sh.Mr * sh.Ns;
+    const int G = gridDim.x;
+    const long nthreads = (long)G * blockDim.x;
+    const int Dp = epi.d1p + epi.d2p;
+    for (int p = 0; p < P; ++p) {
+        const int c = p & 1;
+        if (p > 0) {
+            GemmShape s2 = sh;
+            if (c) s2.A = A1;
+            for (int item = blockIdx.x; item < n_tiles * splitk; item += G)
+                gemm_tile<T, BR, BS, BK>(s2, epi, 1, item % n_tiles, item / n_tiles, splitk, part, true);
+            grid.sync();
+        }
+        const double* din = c ? d64b : d64a;
+        double* dout = c ? d64a : d64b;
+        float* dout32 = c ? d32a : d32b;
+        double* tr = traj ? traj + (long)p * Dp : nullptr;
+        for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += nthreads) {
+            double v = 0.0;
+            if (p > 0)
+                for (int sp = 0; sp < splitk; ++sp) v += (double)part[(long)sp * total + i];
+            const int r = (int)(i / sh.Ns), s = (int)(i - (long)r * sh.Ns);
+            fstep_apply(epi, r, s, v, p, din, dout, dout32, tr);
+        }
+        grid.sync();
+    }
 }
 
 // grouped products: work-group w computes tile wg_tile[w] of product
@@ -657,6 +711,53 @@ hipError_t coarse_grouped_launch(const CoarseItem* items, const int* wg_item, co
                        wg_row, n, delta, c);
     return hipGetLastError();
 }
+
+template <typename T>
+static auto persistent_fn() {
+    return fine_sweep_persistent_kernel<T, 64, 32, 2 * MfmaOp<T>::BK>;
+}
+
+template <typename T>
+int fine_sweep_persistent_grid() {
+    int per_cu = 0, n_cu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_fn<T>(), 256, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * n_cu;
+}
+
+template <typename T>
+hipError_t fine_sweep_persistent(const GemmShape& sh, const void* A1, const Epi& epi, double* d64a, double* d64b,
+                                 float* d32a, float* d32b, double* traj, int P, int grid, int splitk, void* part,
+                                 size_t part_bytes, hipStream_t stream) {
+    if (sh.Mr > 64 || sh.Mr <= 0 || grid <= 0 || splitk < 1) return hipErrorInvalidValue;
+    if (!gemm_shape_ok(sh, sizeof(T)) || (((uintptr_t)A1) % 16)) return hipErrorInvalidValue;
+    if ((size_t)splitk * sh.Mr * sh.Ns * sizeof(T) > part_bytes) return hipErrorInvalidValue;
+    int n_tiles = cdiv(sh.Ns, 32);
+    GemmShape s0 = sh;
+    const void* a1 = A1;
+    Epi e = epi;
+    T* pt = (T*)part;
+    void* args[] = {(void*)&s0, (void*)&a1, (void*)&e, (void*)&d64a, (void*)&d64b, (void*)&d32a, (void*)&d32b,
+                    (void*)&traj, (void*)&P, (void*)&n_tiles, (void*)&splitk, (void*)&pt};
+    return hipLaunchCooperativeKernel((const void*)persistent_fn<T>(), dim3((unsigned)grid), dim3(256), args, 0,
+                                      stream);
+}
+
+template int fine_sweep_persistent_grid<float>();
+template int fine_sweep_persistent_grid<double>();
+template hipError_t fine_sweep_persistent<float>(const GemmShape&, const void*, const Epi&, double*, double*, float*,
+                                                 float*, double*, int, int, int, void*, size_t, hipStream_t);
+template hipError_t fine_sweep_persistent<double>(const GemmShape&, const void*, const Epi&, double*, double*,
+                                                  float*, float*, double*, int, int, int, void*, size_t, hipStream_t);
 
 template hipError_t gemm_grouped_launch<float>(const GemmItem*, const int*, const int*, int, const TileCfg&,
                                                hipStream_t);

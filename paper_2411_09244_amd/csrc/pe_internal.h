@@ -156,6 +156,20 @@ template <typename T>
 hipError_t coarse_grouped_launch(const CoarseItem* items, const int* wg_item, const int* wg_row, int n_wg, int n,
                                  int delta, int c, hipStream_t stream);
 
+// Persistent fine sweep (one cooperative launch for all P fused steps of a
+// sweep; state columns Mr <= 64). sh: the step > 0 product with A = the even
+// steps' FP32 (or FP64) state, A1 the odd steps'; epi: EPI_FSTEP source,
+// anchor and layout fields; d64a/d64b, d32a/d32b: the state ping-pong (step 0
+// reads a); traj (nullable): per-step states, row (r*P + p). grid: from
+// fine_sweep_persistent_grid (the co-resident work-group count; 0 if
+// cooperative launches are unavailable).
+template <typename T>
+int fine_sweep_persistent_grid();
+template <typename T>
+hipError_t fine_sweep_persistent(const GemmShape& sh, const void* A1, const Epi& epi, double* d64a, double* d64b,
+                                 float* d32a, float* d32b, double* traj, int P, int grid, int splitk, void* part,
+                                 size_t part_bytes, hipStream_t stream);
+
 // operand offsets, strides and addresses keep 16-byte vector loads aligned
 bool gemm_shape_ok(const GemmShape& sh, size_t elem);
 

@@ -234,3 +234,27 @@ def test_full_size_c1(c1_reference, prec, tol):
     print(f"c1 {prec}: iterations {iters[0]}, rel L2 vs sequential fine solution {err:.3e}, "
           f"jumps {hist[0][:iters[0]]}")
     assert err < tol
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", TOL64), ("mixed", TOLMIX)])
+def test_persistent_fine_sweep(prec, bar, monkeypatch):
+    """The opt-in persistent fine sweep (one cooperative launch per sweep,
+    grid barriers between the steps) against the oracle: the fine propagator
+    and a full solve, including the full-size 64-column workload."""
+    pe = _pe()
+    monkeypatch.setenv("PE_PERSISTENT", "1")
+    for name in ("t1", "c1"):
+        p = _prob(name)
+        bl, src = S.Blocks.from_problem(p), S.Source.from_problem(p)
+        pr = pe.problem_from(p, prec)
+        X, iters, hist, st = pr.solve(p["x0"], tol=0.0, k_max=2)
+        prof = None
+        pr.profile(True)
+        Y = pr.fine(X[:, :-1].contiguous())
+        prof = pr.profile_read()
+        pr.close()
+        assert prof["fine_sweep"][1] == 1 and prof["fine_step"][1] == 0, prof
+        ref = S.fine_propagator_cols(bl, src, X[0, :-1].cpu().numpy().T, list(range(bl.N)), [0] * bl.N).T
+        e = _colwise_rel(bl, Y[0].cpu().numpy(), ref)
+        print(f"{name} {prec}: persistent F vs oracle {e:.3e}")
+        assert e <= bar

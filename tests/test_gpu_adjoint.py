@@ -247,6 +247,20 @@ def test_autograd_tracked_solve(prec, bar):
 
 
 _C3 = {}
+_C3IN = {}
+
+
+def _c3_inputs():
+    """The full-size adjoint workload's problem and evaluation point."""
+    if not _C3IN:
+        p = build_problem("c3")
+        bl = S.Blocks.from_problem(p)
+        rng = np.random.default_rng(3)
+        theta_ref = p["H"][0]
+        theta = theta_ref + 0.1 * rng.standard_normal(theta_ref.shape)
+        x0 = 0.1 * rng.standard_normal(bl.D) / np.sqrt(bl.D)
+        _C3IN.update(p=p, bl=bl, theta=theta, theta_ref=theta_ref, x0=x0)
+    return _C3IN
 
 
 def _c3_oracle():
@@ -255,12 +269,8 @@ def _c3_oracle():
     (the scheme is linear), the loss 1/2 |y_NP|_M^2 + 1/2 sum_m dt_fine
     |y_m|_M^2 (beta = 1)."""
     if not _C3:
-        p = build_problem("c3")
-        bl = S.Blocks.from_problem(p)
-        rng = np.random.default_rng(3)
-        theta_ref = p["H"][0]
-        theta = theta_ref + 0.1 * rng.standard_normal(theta_ref.shape)
-        x0 = 0.1 * rng.standard_normal(bl.D) / np.sqrt(bl.D)
+        c = _c3_inputs()
+        p, bl, theta, theta_ref, x0 = c["p"], c["bl"], c["theta"], c["theta_ref"], c["x0"]
         Yf = ADJ.forward_fine_linear(bl, p["G"], p["time_mode"], x0, theta - theta_ref)
         Xbar = np.zeros((bl.N + 1, bl.D))
         Xbar[-1] = bl.M @ Yf[-1]
@@ -330,3 +340,54 @@ def test_adjoint_full_space_no_explicit_part(prec, bar):
     el = _rel([r["lam"].cpu().numpy()[0]], [lam])
     print(f"d2 = 0 {prec}: grad rel err {e:.3e}, lambda rel err {el:.3e}")
     assert e <= bar and el <= bar
+
+
+def test_full_size_adjoint_finite_differences_fp64():
+    """The GPU gradient of the full-size adjoint workload's loss against
+    central differences (h = 1e-6) of that loss evaluated by GPU forward
+    solves (k = N: the sequential fine solution) and pe_tracking, along 8
+    random unit directions and 16 random coordinates of (x0, theta); the
+    loss is quadratic, so only rounding separates the two."""
+    pe = _pe()
+    c = _c3_inputs()
+    p, bl = c["p"], c["bl"]
+    dth0 = c["theta"] - c["theta_ref"]
+    Mt = torch.tensor(bl.M, device="cuda")
+    pr = pe.problem_from(dict(p, H=dth0[None]), "fp64")
+
+    def loss(dx0, dth):
+        pr.set_source(p["G"], (dth0 + dth)[None], "interval")
+        Y, _, _, _ = pr.solve((c["x0"] + dx0)[None], tol=0.0)
+        J = pr.tracking(Y, torch.tensor((dth0 + dth)[None], device="cuda"), 1.0)[0]
+        yN = Y[0, -1]
+        return 0.5 * float(yN @ (Mt @ yN)) + J, Y
+
+    L0, Y = loss(np.zeros(bl.D), np.zeros(dth0.shape))
+    Xbar = torch.zeros_like(Y)
+    Xbar[:, -1] = Y[:, -1] @ Mt
+    r = pr.adjoint(Xbar=Xbar, beta=1.0, Ybnd=Y, dH=torch.tensor(dth0[None], device="cuda"))
+    gx, gh = r["x0bar"].cpu().numpy()[0], r["Hbar"].cpu().numpy()[0]
+    rng = np.random.default_rng(31)
+    dirs = []
+    for _ in range(8):
+        dx, dH = rng.standard_normal(bl.D), rng.standard_normal(dth0.shape)
+        nrm = np.sqrt(np.sum(dx ** 2) + np.sum(dH ** 2))
+        dirs.append((dx / nrm, dH / nrm))
+    for idx in rng.choice(bl.D + dth0.size, size=16, replace=False):
+        dx, dH = np.zeros(bl.D), np.zeros(dth0.shape)
+        if idx < bl.D:
+            dx[idx] = 1.0
+        else:
+            dH.flat[idx - bl.D] = 1.0
+        dirs.append((dx, dH))
+    h = 1e-6
+    fd, ad = [], []
+    for dx, dH in dirs:
+        lp, _ = loss(h * dx, h * dH)
+        lm, _ = loss(-h * dx, -h * dH)
+        fd.append((lp - lm) / (2 * h))
+        ad.append(float(np.sum(dx * gx) + np.sum(dH * gh)))
+    pr.close()
+    fd, ad = np.array(fd), np.array(ad)
+    print("FD vs adjoint, max rel diff %.3e (L = %.3e)" % (np.max(np.abs(fd - ad) / np.abs(ad).max()), L0))
+    np.testing.assert_allclose(fd, ad, rtol=1e-5, atol=1e-5 * np.abs(ad).max())

@@ -167,3 +167,62 @@ def test_planted_tracking_mistake_is_caught():
     np.testing.assert_allclose(fd, ad, rtol=1e-6)
     fd, ad = ADJ.fd_check(bl, p["G"], p["time_mode"], x0, H, loss, bad[0], bad[1], dirs, h=1e-3, fine=True)
     assert abs(fd[0] - ad[0]) > 1e-4 * abs(fd[0])
+
+
+def test_finite_differences_h_1e6_directions_and_coordinates():
+    """Central differences at h = 1e-6 of the terminal + fine-step tracking
+    loss along 8 random unit directions and 16 random coordinates of
+    (x0, H): the loss is quadratic, so the only FD error is rounding,
+    about eps |L| / h."""
+    p = build_problem("t2")
+    bl = S.Blocks.from_problem(p)
+    rng = np.random.default_rng(15)
+    H_ref = rng.standard_normal(p["H"].shape[1:])
+    ref = ADJ.forward_fine_linear(bl, p["G"], p["time_mode"], np.zeros(bl.D), H_ref)
+    H = H_ref + 0.1 * rng.standard_normal(H_ref.shape)
+    x0 = 0.1 * rng.standard_normal(bl.D) / np.sqrt(bl.D)
+    M = bl.M
+
+    def loss(Xf):
+        e = Xf - ref
+        q = np.einsum("nd,de,ne->n", e, M, e)
+        return 0.5 * q[-1] + 0.5 * bl.dt_fine * q[1:].sum()
+
+    Y = ADJ.forward_fine_linear(bl, p["G"], p["time_mode"], x0, H - H_ref)
+    Xbar = np.zeros((bl.N + 1, bl.D))
+    Xbar[-1] = M @ Y[-1]
+    sbar = S.Source(p["G"], H[None], p["time_mode"], bl.N, bl.P)
+    x0b, Hb, _ = ADJ.adjoint(bl, sbar, Xbar, Xbar_fine=ADJ.tracking_cotangents(bl, Y, 1.0))
+    dirs = []
+    for _ in range(8):
+        dx, dH = rng.standard_normal(bl.D), rng.standard_normal(H.shape)
+        nrm = np.sqrt(np.sum(dx ** 2) + np.sum(dH ** 2))
+        dirs.append((dx / nrm, dH / nrm))
+    n_x0, n_h = bl.D, H.size
+    for idx in rng.choice(n_x0 + n_h, size=16, replace=False):
+        dx, dH = np.zeros(bl.D), np.zeros(H.shape)
+        if idx < n_x0:
+            dx[idx] = 1.0
+        else:
+            dH.flat[idx - n_x0] = 1.0
+        dirs.append((dx, dH))
+    fd, ad = ADJ.fd_check(bl, p["G"], p["time_mode"], x0, H, loss, x0b, Hb, dirs, h=1e-6, fine=True)
+    L = loss(ADJ.forward_fine_linear(bl, p["G"], p["time_mode"], x0, H))
+    np.testing.assert_allclose(fd, ad, rtol=1e-5, atol=1e3 * np.finfo(float).eps * abs(L) / 1e-6)
+
+
+def test_gradient_vanishes_at_the_reference():
+    """At (x0, H) = (x0_ref, H_ref) the tracking error is zero, so every
+    cotangent and the gradient are exactly zero."""
+    p = build_problem("t1")
+    bl = S.Blocks.from_problem(p)
+    rng = np.random.default_rng(21)
+    H_ref = rng.standard_normal(p["H"].shape[1:])
+    x0_ref = rng.standard_normal(bl.D)
+    Y = ADJ.forward_fine_linear(bl, p["G"], p["time_mode"], x0_ref - x0_ref, H_ref - H_ref)
+    assert not Y.any()
+    Xbar = np.zeros((bl.N + 1, bl.D))
+    Xbar[-1] = bl.M @ Y[-1]
+    sbar = S.Source(p["G"], H_ref[None], p["time_mode"], bl.N, bl.P)
+    x0b, Hb, lam = ADJ.adjoint(bl, sbar, Xbar, Xbar_fine=ADJ.tracking_cotangents(bl, Y, 1.0))
+    assert not x0b.any() and not Hb.any() and not lam.any()

@@ -66,8 +66,21 @@ __device__ inline double source_value_p(const Epi& e, int r, int s, int p_step) 
     const long tau = (e.time_mode == 0) ? (long)n * e.P + p_step : (long)n;
     const double* g = e.Gs + (long)s * e.R;
     const double* h = e.Hs + (long)b * e.R * e.Tlen + tau;
+    // blocks of QB terms: all loads of a block (indices clamped, surplus
+    // terms weighted by zero) before any use, so a block costs one round trip
+    constexpr int QB = 8;
     double v = 0.0;
-    for (int q = 0; q < e.R; ++q) v += g[q] * h[(long)q * e.Tlen];
+    for (int q0 = 0; q0 < e.R; q0 += QB) {
+        double gq[QB], hq[QB];
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int qq = min(q0 + q, e.R - 1);
+            gq[q] = g[qq];
+            hq[q] = h[(long)qq * e.Tlen];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) v = fma(q0 + q < e.R ? gq[q] : 0.0, hq[q], v);
+    }
     return v;
 }
 
@@ -108,48 +121,119 @@ __device__ inline void fstep_apply(const Epi& e, int r, int s, double acc, int p
     if (traj) traj[(long)r * e.ldtraj + s] = e.xa[(long)r * (e.d1p + e.d2p) + s] + full_dev;
 }
 
+// Each epilogue is split into a load phase (everything it reads besides the
+// accumulated value) and a finish phase. Kernels whose accumulation is short
+// (the split-K reduction, the coarse-step matrix-vector products) issue the
+// load phase together with their operand loads, so an output costs one memory
+// round trip instead of two. The arithmetic, and its order, is the same as
+// in a single-phase epilogue.
+struct EpiIn {
+    double a = 0.0, b = 0.0, c = 0.0;
+    bool ok = true;
+};
+
+template <int MODE>
+__device__ inline EpiIn epi_load(const Epi& e, int r, int s) {
+    EpiIn in;
+    if constexpr (MODE == EPI_STORE) {
+        if (e.beta != 0.0) in.a = e.C0[(long)r * e.ldc0 + s];
+    } else if constexpr (MODE == EPI_RESID) {
+        if (e.base) in.b = e.base[(long)r * e.ldb + s];
+        in.a = source_value(e, r, s);
+    } else if constexpr (MODE == EPI_FSTEP) {
+        // branch-free load first, the source term (branches, waits) last
+        in.c = e.din[(long)r * e.ldd + (s < e.d1p ? e.d1p + s : 2L * e.d1p + (s - e.d1p))];
+        if (e.base) in.b = e.base[(long)r * e.ldb + s];
+        in.a = source_value_p(e, r, s, e.p_step);
+    } else if constexpr (MODE == EPI_COARSE_INIT) {
+        if (e.cs) in.a = e.cs[(long)r * e.ldcs + s];
+    } else if constexpr (MODE == EPI_COARSE_DELTA) {
+        in.ok = !(e.active && !e.active[r]);
+        in.a = e.fbuf[(long)r * e.ldfb + s];
+        in.b = e.xprev[(long)r * e.ldxo + s];
+    } else if constexpr (MODE == EPI_ADJ_STATE) {
+        const long D = e.ldr;
+        const int j = s < D ? s : (int)(s - D);
+        in.a = e.s_cur[(long)r * 2 * D + j];
+        if (e.inj) in.b = e.inj[(long)r * e.ldinj + j];
+        if (s >= D && e.sacc) in.c = e.sacc[(long)r * D + j];
+    }
+    return in;
+}
+
+template <int MODE>
+__device__ inline void epi_finish(const Epi& e, int r, int s, double acc, const EpiIn& in) {
+    if constexpr (MODE == EPI_STORE) {
+        double v = e.alpha * acc;
+        if (e.beta != 0.0) v += e.beta * in.a;
+        if (e.diag_add != 0.0 && r == s + e.diag_off) v += e.diag_add;
+        e.C[(long)r * e.ldc + s] = v;
+    } else if constexpr (MODE == EPI_RESID) {
+        double v = in.a - acc;
+        if (e.base) v -= in.b;
+        e.R64[(long)r * e.ldr + s] = v;
+        if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
+    } else if constexpr (MODE == EPI_FSTEP) {
+        // increment d = Z F(t) - base - acc, then the state/history update
+        // (layout per column: [du_prev | u - u_a | w - w_a | dw_prev])
+        double v = in.a - acc;
+        if (e.base) v -= in.b;
+        double* d = e.dev64 + (long)r * e.ldd;
+        float* d32 = e.dev32 ? e.dev32 + (long)r * e.ldd : nullptr;
+        double full_dev;
+        if (s < e.d1p) {
+            const double u = in.c + v;
+            d[s] = v;
+            d[e.d1p + s] = u;
+            if (d32) {
+                d32[s] = (float)v;
+                d32[e.d1p + s] = (float)u;
+            }
+            full_dev = u;
+        } else {
+            const int j = s - e.d1p;
+            const long ow = 2L * e.d1p + j, oh = 2L * e.d1p + e.d2p + j;
+            const double w = in.c + v;
+            d[ow] = w;
+            d[oh] = v;
+            if (d32) {
+                d32[ow] = (float)w;
+                d32[oh] = (float)v;
+            }
+            full_dev = w;
+        }
+        if (e.traj) e.traj[(long)r * e.ldtraj + s] = e.xa[(long)r * (e.d1p + e.d2p) + s] + full_dev;
+    } else if constexpr (MODE == EPI_COARSE_INIT) {
+        double x = acc;
+        if (e.cs) x += in.a;
+        e.xout[(long)r * e.ldxo + s] = x;
+    } else if constexpr (MODE == EPI_COARSE_DELTA) {
+        if (!in.ok) return;
+        const double x = in.a + acc;
+        e.xout[(long)r * e.ldxo + s] = x;
+        const double d = x - in.b;
+        if (e.dl64) e.dl64[(long)r * e.ldl + s] = d;
+        if (e.dl32) e.dl32[(long)r * e.ldl + s] = (float)d;
+    } else if constexpr (MODE == EPI_ADJ_STATE) {
+        const long D = e.ldr;
+        const int j = s < D ? s : (int)(s - D);
+        double v = in.a - acc;
+        if (e.inj) v += in.b;
+        e.s_nxt[(long)r * 2 * D + s] = v;
+        if (s >= D) {
+            if (e.nu32) e.nu32[(long)r * D + j] = (float)v;
+            if (e.sacc) e.sacc[(long)r * D + j] = in.c + v;
+            if (e.rho_all) e.rho_all[((long)r * e.P + e.m_step) * D + j] = v;
+        }
+    }
+}
+
 // one epilogue per mode (the product kernel emits one unrolled store loop per
 // mode, which keeps each loop small enough to unroll with static accumulator
 // indexing)
 template <int MODE>
 __device__ inline void epi_apply(const Epi& e, int r, int s, double acc) {
-    if constexpr (MODE == EPI_STORE) {
-        double v = e.alpha * acc;
-        if (e.beta != 0.0) v += e.beta * e.C0[(long)r * e.ldc0 + s];
-        if (e.diag_add != 0.0 && r == s + e.diag_off) v += e.diag_add;
-        e.C[(long)r * e.ldc + s] = v;
-    } else if constexpr (MODE == EPI_RESID) {
-        double v = source_value(e, r, s) - acc;
-        if (e.base) v -= e.base[(long)r * e.ldb + s];
-        e.R64[(long)r * e.ldr + s] = v;
-        if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
-    } else if constexpr (MODE == EPI_FSTEP) {
-        fstep_apply(e, r, s, acc, e.p_step, e.din, e.dev64, e.dev32, e.traj);
-    } else if constexpr (MODE == EPI_COARSE_INIT) {
-        const int b = r;
-        double x = acc;
-        if (e.cs) x += e.cs[(long)b * e.ldcs + s];
-        e.xout[(long)b * e.ldxo + s] = x;
-    } else if constexpr (MODE == EPI_COARSE_DELTA) {
-        const int b = r;
-        if (e.active && !e.active[b]) return;
-        const double x = e.fbuf[(long)b * e.ldfb + s] + acc;
-        e.xout[(long)b * e.ldxo + s] = x;
-        const double d = x - e.xprev[(long)b * e.ldxo + s];
-        if (e.dl64) e.dl64[(long)b * e.ldl + s] = d;
-        if (e.dl32) e.dl32[(long)b * e.ldl + s] = (float)d;
-    } else if constexpr (MODE == EPI_ADJ_STATE) {
-        const long D = e.ldr;
-        const int j = s < D ? s : (int)(s - D);
-        double v = e.s_cur[(long)r * 2 * D + j] - acc;
-        if (e.inj) v += e.inj[(long)r * e.ldinj + j];
-        e.s_nxt[(long)r * 2 * D + s] = v;
-        if (s >= D) {
-            if (e.nu32) e.nu32[(long)r * D + j] = (float)v;
-            if (e.sacc) e.sacc[(long)r * D + j] += v;
-            if (e.rho_all) e.rho_all[((long)r * e.P + e.m_step) * D + j] = v;
-        }
-    }
+    epi_finish<MODE>(e, r, s, acc, epi_load<MODE>(e, r, s));
 }
 
 // call f(integral_constant<mode>) for the runtime mode
@@ -396,44 +480,60 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmItem* __res
     gemm_tile<T, BR, BS, BK>(it.sh, it.epi, it.tiles_r, wg_tile[blockIdx.x], 0, 1, nullptr);
 }
 
-// sum of the split-K planes, then the epilogue. TPE threads per element:
-// thread t of an element sums planes t, t + TPE, ... in order, the TPE
-// partial sums are combined by a fixed butterfly (bitwise reproducible), and
-// the first thread runs the epilogue. More threads per element keep more
-// loads in flight (the kernel is latency-bound at small sizes).
-template <typename T, int TPE>
+// split-K reduction with the epilogue: out[i] = epi(sum_sp part[sp][i]),
+// partial tiles summed in split order (bitwise reproducible). The epilogue's
+// loads are issued together with the SK plane loads.
+template <typename T, int MODE, int SK>
 __global__ __launch_bounds__(256) void splitk_epilogue_kernel(const int Mr, const int Ns, const int splitk,
                                                               const T* __restrict__ part, const Epi epi) {
     const long total = (long)Mr * Ns;
-    const int t = threadIdx.x % TPE;
-    const long first = (blockIdx.x * (long)blockDim.x + threadIdx.x) / TPE;
-    const long stride = (long)gridDim.x * blockDim.x / TPE;
-    for (long i = first; i < total; i += stride) {
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int r = (int)(i / Ns), s = (int)(i - (long)r * Ns);
         double v = 0.0;
-        for (int sp = t; sp < splitk; sp += TPE) v += (double)part[(long)sp * total + i];
-        if (TPE > 1)
-            for (int off = TPE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, TPE);
-        if (t == 0) {
-            const int r = (int)(i / Ns), s = (int)(i - (long)r * Ns);
-            epilogue(epi, r, s, v);
+        if constexpr (SK > 0) {
+            // plane loads first (no branches), then the epilogue's loads
+            T pv[SK];
+#pragma unroll
+            for (int sp = 0; sp < SK; ++sp) pv[sp] = part[(long)sp * total + i];
+            const EpiIn in = epi_load<MODE>(epi, r, s);
+#pragma unroll
+            for (int sp = 0; sp < SK; ++sp) v += (double)pv[sp];
+            epi_finish<MODE>(epi, r, s, v, in);
+        } else {
+            const EpiIn in = epi_load<MODE>(epi, r, s);
+            for (int sp = 0; sp < splitk; ++sp) v += (double)part[(long)sp * total + i];
+            epi_finish<MODE>(epi, r, s, v, in);
         }
     }
 }
 
-// y[r][s] = sum_k A[r][k] B[s][k] for MR <= 4 state columns: WPR waves per
-// operator row (4 / WPR rows per work-group), each wave taking every WPR-th
-// 64-lane chunk of K with 16-byte loads; wave reductions, then the WPR
-// partial sums are added in wave order (bitwise reproducible) and the
-// epilogue runs once per (r, s)
-template <typename T, int MR, int WPR>
+// y[r][s] = sum_k A[r][k] B[s][k] for MR <= 4 state columns: two waves per
+// operator row (two rows per work-group), each wave taking every other
+// 64-lane chunk of K with 16-byte loads. A lane loads CH chunks before it
+// multiplies any of them (addresses clamped into the operands, chunks past
+// the end zeroed by a select, so no load sits under a branch), and the lane
+// that runs the epilogue requests the epilogue's inputs first: at the
+// 2000-row size every load of the kernel is in flight at once. Wave
+// reductions, then the two partial sums are added in wave order (bitwise
+// reproducible) and the epilogue runs once per (r, s).
+template <typename T, int MR, int MODE>
 __global__ __launch_bounds__(256) void gemv_kernel(const GemmShape sh, const Epi epi) {
     using vec_t = typename MfmaOp<T>::vec_t;
     constexpr int VW = 16 / sizeof(T);
+    constexpr int WPR = 2, CH = 4;
     __shared__ double red[4][MR];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int sub = wave % WPR;
     const int s = blockIdx.x * (4 / WPR) + wave / WPR;
+    const bool epi_lane = lane == 0 && sub == 0 && s < sh.Ns;
+    EpiIn in[MR];
+    if (epi_lane) {
+#pragma unroll
+        for (int r = 0; r < MR; ++r)
+            if (r < sh.Mr) in[r] = epi_load<MODE>(epi, r, s);
+    }
     double acc[MR];
 #pragma unroll
     for (int r = 0; r < MR; ++r) acc[r] = 0.0;
@@ -442,16 +542,25 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemmShape sh, const Epi
         const int k1 = s < sh.s_split ? sh.k1a : sh.k1b;
         const T* __restrict__ B = (const T*)sh.B + (long)s * sh.ldb;
         const T* __restrict__ A = (const T*)sh.A;
-        for (int k = k0 + VW * (lane + 64 * sub); k < k1; k += 64 * VW * WPR) {
-            const vec_t w = *(const vec_t*)(B + k);
-            const T* wp = (const T*)&w;
+        constexpr int step = 64 * VW * WPR;
+        for (int kb = k0 + VW * (lane + 64 * sub); kb < k1; kb += CH * step) {
+            vec_t w[CH], x[CH][MR];
 #pragma unroll
-            for (int r = 0; r < MR; ++r) {
-                if (r < sh.Mr) {
-                    const vec_t x = *(const vec_t*)(A + (long)r * sh.lda + k);
-                    const T* xp = (const T*)&x;
+            for (int c = 0; c < CH; ++c) {
+                const int kc = min(kb + c * step, k1 - VW);
+                w[c] = *(const vec_t*)(B + kc);
 #pragma unroll
-                    for (int q = 0; q < VW; ++q) acc[r] += (double)wp[q] * (double)xp[q];
+                for (int r = 0; r < MR; ++r) x[c][r] = *(const vec_t*)(A + (long)min(r, sh.Mr - 1) * sh.lda + kc);
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const bool ok = kb + c * step < k1;
+                const T* wp = (const T*)&w[c];
+#pragma unroll
+                for (int r = 0; r < MR; ++r) {
+                    const T* xp = (const T*)&x[c][r];
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) acc[r] = fma(ok ? (double)wp[q] : 0.0, (double)xp[q], acc[r]);
                 }
             }
         }
@@ -459,24 +568,17 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemmShape sh, const Epi
 #pragma unroll
     for (int r = 0; r < MR; ++r)
         for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off, 64);
-    if (WPR == 1) {
-        if (lane == 0 && s < sh.Ns)
-#pragma unroll
-            for (int r = 0; r < MR; ++r)
-                if (r < sh.Mr) epilogue(epi, r, s, acc[r]);
-        return;
-    }
     if (lane == 0)
 #pragma unroll
         for (int r = 0; r < MR; ++r) red[wave][r] = acc[r];
     __syncthreads();
-    if (lane == 0 && sub == 0 && s < sh.Ns) {
+    if (epi_lane) {
 #pragma unroll
         for (int r = 0; r < MR; ++r) {
             if (r >= sh.Mr) break;
             double v = red[wave][r];
             for (int w = 1; w < WPR; ++w) v += red[wave + w][r];
-            epilogue(epi, r, s, v);
+            epi_finish<MODE>(epi, r, s, v, in[r]);
         }
     }
 }
@@ -516,18 +618,18 @@ TileCfg choose_tiles(const GemmShape& sh, bool fp32, int n_cu) {
     return c;
 }
 
-// threads per element of the split-K reduction (PE_SPLITK_TPE = 1, 2 or 4;
-// never more than the split count)
-static int splitk_tpe(int splitk) {
-    static int w = -1;
-    if (w < 0) {
-        const char* e = getenv("PE_SPLITK_TPE");
-        w = e ? atoi(e) : 1;
-        if (w != 1 && w != 2 && w != 4) w = 1;
+// split-K reduction launch for one epilogue mode, with the split count as a
+// compile-time constant for the common counts
+template <typename T, int MODE>
+static void launch_reduce(dim3 g, dim3 b, hipStream_t stream, const GemmShape& sh, int splitk, const T* part,
+                          const Epi& epi) {
+    switch (splitk) {
+        case 2: hipLaunchKernelGGL((splitk_epilogue_kernel<T, MODE, 2>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
+        case 4: hipLaunchKernelGGL((splitk_epilogue_kernel<T, MODE, 4>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
+        case 8: hipLaunchKernelGGL((splitk_epilogue_kernel<T, MODE, 8>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
+        case 16: hipLaunchKernelGGL((splitk_epilogue_kernel<T, MODE, 16>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
+        default: hipLaunchKernelGGL((splitk_epilogue_kernel<T, MODE, 0>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
     }
-    int t = w;
-    while (t > 1 && t > splitk) t >>= 1;
-    return t;
 }
 
 template <typename T, int BR, int BS, int BK>
@@ -545,47 +647,42 @@ static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, Ge
     if (e != hipSuccess || splitk == 1) return e;
     if (ws.between) ws.between(ws.between_arg);
     const long total = (long)sh.Mr * sh.Ns;
-    const int tpe = splitk_tpe(splitk);
-    long blocks = (total * tpe + 255) / 256;
+    long blocks = (total + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     const dim3 g((unsigned)blocks), b(256);
     const T* part = (const T*)ws.part;
-    switch (tpe) {
-        case 4: hipLaunchKernelGGL((splitk_epilogue_kernel<T, 4>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
-        case 2: hipLaunchKernelGGL((splitk_epilogue_kernel<T, 2>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
-        default: hipLaunchKernelGGL((splitk_epilogue_kernel<T, 1>), g, b, 0, stream, sh.Mr, sh.Ns, splitk, part, epi); break;
+    switch (epi.mode) {
+        case EPI_STORE: launch_reduce<T, EPI_STORE>(g, b, stream, sh, splitk, part, epi); break;
+        case EPI_RESID: launch_reduce<T, EPI_RESID>(g, b, stream, sh, splitk, part, epi); break;
+        case EPI_FSTEP: launch_reduce<T, EPI_FSTEP>(g, b, stream, sh, splitk, part, epi); break;
+        case EPI_COARSE_INIT: launch_reduce<T, EPI_COARSE_INIT>(g, b, stream, sh, splitk, part, epi); break;
+        case EPI_COARSE_DELTA: launch_reduce<T, EPI_COARSE_DELTA>(g, b, stream, sh, splitk, part, epi); break;
+        case EPI_ADJ_STATE: launch_reduce<T, EPI_ADJ_STATE>(g, b, stream, sh, splitk, part, epi); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename T, int WPR>
-static void launch_gemv_w(const GemmShape& sh, const Epi& epi, hipStream_t stream) {
-    dim3 grid((unsigned)cdiv(sh.Ns, 4 / WPR));
+template <typename T, int MODE>
+static void launch_gemv_m(const GemmShape& sh, const Epi& epi, hipStream_t stream) {
+    const dim3 grid((unsigned)cdiv(sh.Ns, 2));
     switch (sh.Mr) {
-        case 1: hipLaunchKernelGGL((gemv_kernel<T, 1, WPR>), grid, dim3(256), 0, stream, sh, epi); break;
-        case 2: hipLaunchKernelGGL((gemv_kernel<T, 2, WPR>), grid, dim3(256), 0, stream, sh, epi); break;
-        default: hipLaunchKernelGGL((gemv_kernel<T, 4, WPR>), grid, dim3(256), 0, stream, sh, epi); break;
+        case 1: hipLaunchKernelGGL((gemv_kernel<T, 1, MODE>), grid, dim3(256), 0, stream, sh, epi); break;
+        case 2: hipLaunchKernelGGL((gemv_kernel<T, 2, MODE>), grid, dim3(256), 0, stream, sh, epi); break;
+        default: hipLaunchKernelGGL((gemv_kernel<T, 4, MODE>), grid, dim3(256), 0, stream, sh, epi); break;
     }
-}
-
-// waves per operator row of the coarse-step products (PE_GEMV_WPR = 1, 2 or
-// 4; 2 measured fastest on MI355X at d = 2000)
-static int gemv_wpr() {
-    static int w = -1;
-    if (w < 0) {
-        const char* e = getenv("PE_GEMV_WPR");
-        w = e ? atoi(e) : 2;
-        if (w != 1 && w != 2 && w != 4) w = 2;
-    }
-    return w;
 }
 
 template <typename T>
 static hipError_t launch_gemv(const GemmShape& sh, const Epi& epi, hipStream_t stream) {
-    switch (gemv_wpr()) {
-        case 4: launch_gemv_w<T, 4>(sh, epi, stream); break;
-        case 2: launch_gemv_w<T, 2>(sh, epi, stream); break;
-        default: launch_gemv_w<T, 1>(sh, epi, stream); break;
+    switch (epi.mode) {
+        case EPI_STORE: launch_gemv_m<T, EPI_STORE>(sh, epi, stream); break;
+        case EPI_RESID: launch_gemv_m<T, EPI_RESID>(sh, epi, stream); break;
+        case EPI_FSTEP: launch_gemv_m<T, EPI_FSTEP>(sh, epi, stream); break;
+        case EPI_COARSE_INIT: launch_gemv_m<T, EPI_COARSE_INIT>(sh, epi, stream); break;
+        case EPI_COARSE_DELTA: launch_gemv_m<T, EPI_COARSE_DELTA>(sh, epi, stream); break;
+        case EPI_ADJ_STATE: launch_gemv_m<T, EPI_ADJ_STATE>(sh, epi, stream); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

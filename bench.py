@@ -37,7 +37,7 @@ PEAK_HBM_TBPS = 8.0      # MI355X HBM3E
 # copy reads for the same counters), keyed by workload and the kernel's tile
 # configuration (state-tile rows, operator-tile rows, K depth, split-K).
 # Reported only when the timed run used that kernel class and configuration.
-MEASURED_TRAFFIC = {("c1", "fine_step", (64, 32, 64, 8)): 2.0 * 18546.8 * 1024 + 1.0 * 4000.0 * 1024}
+MEASURED_TRAFFIC = {("c1", "fine_step", (64, 32, 64, 8)): 2.0 * 18546.6 * 1024 + 1.0 * 4000.0 * 1024}
 
 
 def time_solves(pr, x0, tol, steps, warmup, torch):

@@ -207,6 +207,41 @@ pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const
 pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH, double beta, double* J);
 
 /*
+ * pe_fine_wr - the fine propagator computed by the paper's waveform
+ * relaxation with the alpha-circulant diagonalisation in time (Sections 4.1
+ * and 4.2), FP64 in the caller's coordinates whatever the handle's precision.
+ * On every interval n of every sample b, from the start state x_n, K0
+ * iterations of:
+ *   (1) the V_H1 part at all P fine levels at once: the all-at-once system
+ *       of eq. (4.12) with the alpha-circulant matrix of eq. (4.4), whose
+ *       right-hand side (eq. (4.8)) uses the previous iterate's V_H2 part,
+ *       solved by the diagonalisation of eqs. (4.5)-(4.7): a scaled discrete
+ *       Fourier transform along time, one (d_k M11 + A11) solve per
+ *       frequency, the inverse transform;
+ *   (2) the V_H2 part sequentially in time (eq. (4.9)) with the new V_H1
+ *       levels.
+ * The history is reset at the interval start (as for the propagators of
+ * pe_solve) and the first iterate continues the start state in time. The
+ * iteration's fixed point is pe_fine_propagate's F (P steps of
+ * eqs. (2.5)-(2.6)); the error contracts by about gamma^2 per iteration
+ * (gamma of eq. (4.15)), and a smaller alpha converges faster but scales
+ * rounding errors by about 1/alpha.
+ *   B        samples (must equal the source's sample count when a source is set).
+ *   Xin      device, B x N x D: row b*N + n is the start state of interval n
+ *            of sample b (the layout of pe_fine_propagate).
+ *   alpha    in (0, 1).
+ *   K0       iterations, >= 0 (0 returns the start states).
+ *   Fout     device, B x N x D out: the end state of interval n after K0
+ *            iterations in row b*N + n.
+ * Operators (one complex-shifted inverse per frequency, P/2 + 1 of them,
+ * built by two Cholesky factorisations each) are built at the first call for
+ * an alpha and kept until the next alpha or source. Needs P <= 128.
+ * Errors: PE_ERR_ARG for bad arguments, PE_ERR_NOMEM, PE_ERR_NOT_SPD (only
+ * for a mass or stiffness block that is not positive definite), PE_ERR_HIP.
+ */
+pe_status pe_fine_wr(pe_problem p, int B, const double* Xin, double alpha, int K0, double* Fout);
+
+/*
  * Batches of different problems (different d1, d2, N, sources and sample
  * counts; same precision and step ratio P), solved together: every
  * product of a fine step runs as one grouped MFMA launch over all problems'
@@ -259,7 +294,13 @@ enum {
                                    environment at problem creation and the N*B
                                    interval columns fit one 64-row tile (by default
                                    each step is its own launch, replayed from a graph) */
-    PE_PROF_KINDS = 8
+    PE_PROF_WR_RHS = 8,         /* waveform relaxation: the right-hand-side products
+                                   of eqs. (4.8) and (4.9) over all fine levels  */
+    PE_PROF_WR_SOLVE = 9,       /* waveform relaxation: one complex-shifted solve
+                                   (d_k M11 + A11)^-1 per frequency, as a product
+                                   with its real 2 d1 x 2 d1 form                */
+    PE_PROF_WR_WSTEP = 10,      /* waveform relaxation: one sequential V_H2 step   */
+    PE_PROF_KINDS = 11
 };
 
 /*

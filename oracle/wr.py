@@ -65,11 +65,20 @@ def all_at_once_solve(M11, A11, R, alpha, h):
     gam = alpha ** (np.arange(P) / P)
     Rh = np.fft.fft(gam[:, None, None] * R, axis=0)                 # (a)
     d = circulant_eigs(P, alpha, h)
+    key = (id(M11), id(A11), M11.shape[0], float(alpha), float(h), P)
+    if _LU.get("key") != key:   # factorisations reused across iterations
+        _LU.clear()
+        _LU["key"] = key
+        _LU["refs"] = (M11, A11)  # held, so that the ids in the key stay unique
+        _LU["f"] = [sla.lu_factor(d[k] * M11 + A11) for k in range(P)]
     Uh = np.empty_like(Rh)
     for k in range(P):                                               # (b)
-        Uh[k] = sla.lu_solve(sla.lu_factor(d[k] * M11 + A11), Rh[k])
+        Uh[k] = sla.lu_solve(_LU["f"][k], Rh[k])
     U = np.fft.ifft(Uh, axis=0) / gam[:, None, None]                 # (c)
     return U.real
+
+
+_LU = {}
 
 
 def sequential_solve(M11, A11, R, h):

@@ -25,12 +25,12 @@ PE_NORM_M_REL = 1
 
 # every entry point declared in include/pe.h
 EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate",
-           "pe_coarse_propagate", "pe_mass_norms", "pe_adjoint", "pe_tracking", "pe_batch_create", "pe_batch_solve",
+           "pe_coarse_propagate", "pe_mass_norms", "pe_adjoint", "pe_tracking", "pe_fine_wr", "pe_batch_create", "pe_batch_solve",
            "pe_batch_destroy", "pe_batch_profile", "pe_batch_profile_read", "pe_profile", "pe_profile_read",
            "pe_autotune", "pe_last_tiles", "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
 PROFILE_KINDS = {"fine_step": 0, "fine_first": 1, "anchor": 2, "coarse": 3, "norm": 4, "splitk_reduce": 5,
-                 "adj_step": 6, "fine_sweep": 7}
+                 "adj_step": 6, "fine_sweep": 7, "wr_rhs": 8, "wr_solve": 9, "wr_wstep": 10}
 
 
 class PeError(RuntimeError):
@@ -62,6 +62,7 @@ def load():
     lib.pe_mass_norms.argtypes = [vp, ci, vp, vp]
     lib.pe_adjoint.argtypes = [vp, ci, vp, cd, vp, vp, cd, ci, vp, vp, vp, vp, vp]
     lib.pe_tracking.argtypes = [vp, ci, vp, vp, cd, vp]
+    lib.pe_fine_wr.argtypes = [vp, ci, vp, cd, ci, vp]
     lib.pe_batch_create.argtypes = [ctypes.POINTER(vp), ci, vp, vp]
     lib.pe_batch_solve.argtypes = [vp, vp, cd, ci, ci, vp, vp]
     lib.pe_batch_destroy.argtypes = [vp]

@@ -130,6 +130,17 @@ class Problem:
         L.check(self.lib.pe_fine_propagate(self.handle, B, _ptr(Xin), _ptr(Y)))
         return Y
 
+    def fine_wr(self, Xin, alpha, K0):
+        """The fine propagator by waveform relaxation with the alpha-circulant
+        diagonalisation (K0 iterations, FP64) applied to Xin (B, N, D) ->
+        (B, N, D); its fixed point is `fine`."""
+        Xin = _dev(Xin, self.device).reshape(-1, self.N, self.D)
+        B = Xin.shape[0]
+        Y = torch.empty_like(Xin)
+        self._order()
+        L.check(self.lib.pe_fine_wr(self.handle, B, _ptr(Xin), float(alpha), int(K0), _ptr(Y)))
+        return Y
+
     def coarse(self, Xin):
         """G applied to Xin (B, N, D) -> (B, N, D)."""
         Xin = _dev(Xin, self.device)

@@ -191,6 +191,17 @@ struct pe_problem_s {
     // captured HIP graphs of the sweeps, keyed by (kind, B, buffer parity)
     GraphCache gc;
 
+    // waveform-relaxation fine solver (pe_fine_wr, FP64): operators for one
+    // alpha and source version, workspace for a chunk of interval columns
+    int src_version = 0;
+    double wr_alpha = -1.0;
+    int wr_src_version = -1, wr_B = -1, wr_NBc = 0, wr_K = 0;
+    double *wrO = nullptr, *wrGu = nullptr, *wrZw = nullptr, *wrPhiW = nullptr, *wrM11h = nullptr;
+    double *wrGw = nullptr, *wrFintW = nullptr, *wrTw = nullptr;
+    double *wrUl = nullptr, *wrWl = nullptr, *wrR = nullptr, *wrRh = nullptr, *wrUh = nullptr;
+    double *wrWcat = nullptr, *wrUcat = nullptr, *wrV = nullptr, *wrY = nullptr;
+    std::vector<void*> wr_ops, wr_ws;
+
     std::vector<void*> op_allocs, ws_allocs;
 };
 
@@ -1797,6 +1808,215 @@ pe_status check_handle(pe_problem p) {
     return PE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// fine propagator by waveform relaxation (Sections 4.1-4.2), FP64, in the
+// caller's coordinates. Iteration j on every interval column at once:
+//   1. right-hand sides of eq. (4.8) at the levels s = 1..P,
+//        R_s = F1_s - (M12/h)(w_{s-1} - w_{s-2}) - A12 w_{s-1}   (w = w^{j-1})
+//      plus (M11/h)(u_0 - alpha u_P^{j-1}) at s = 1 (the periodic-like start);
+//   2. the all-at-once system (4.12) by the diagonalisation (4.5)-(4.7):
+//      scaled transform along time, one solve per frequency, inverse;
+//   3. eq. (4.9) sequentially in time with the new u levels:
+//        w_s = (I - h M22^-1 A22) w_{s-1} + V_s,
+//        V_s = h M22^-1 F2_s - M22^-1 M21 (u_{s-1} - u_{s-2}) - h M22^-1 A21 u_s
+//      (V for all s in one product before the sequential part).
+// The history at the interval start is reset (w_{-1} = w_0, u_{-1} = u_0) and
+// the first iterate continues the start state (w_s^0 = w_0, u_P^0 = u_0).
+// Operators (built once per alpha on the GPU):
+//   Gu = [M12/h | A12] (d1p x 2d2p), M11h = M11/h, Zw = [M22^-1 M21 | h M22^-1 A21]
+//   (d2p x 2d1p), PhiW = I - h M22^-1 A22, the source's w part h M22^-1 G2
+//   (or h M22^-1 F2 per interval for dense interval sources), and for each
+//   frequency k = 0..K-1 (K = P/2 + 1; the rest are conjugates) the real form
+//   O_k = [[Cr, -Ci], [Ci, Cr]] of (d_k M11 + A11)^-1 = Cr + i Ci, d_k = a_k + i b_k
+//   the eigenvalues of the alpha-circulant matrix (eq. (4.5)). With the SPD
+//   matrices Ar = A11 + a_k M11 (a_k > 0) and S = Ar + b_k^2 M11 Ar^-1 M11:
+//   Cr = S^-1, Ci = -b_k S^-1 M11 Ar^-1 (block elimination of the real 2x2
+//   form; two Cholesky factorisations, no complex arithmetic, and the
+//   condition number is not squared).
+// ---------------------------------------------------------------------------
+pe_status wr_build_ops(pe_problem p, int B, double alpha) {
+    const int d1 = p->d1, d2 = p->d2, d1p = p->d1p, d2p = p->d2p, Dp = p->Dp, P = p->P, N = p->N;
+    const double h = p->dtf;
+    const int K = P / 2 + 1;
+    const bool dense_src = p->src_set && p->src_kind == 2;
+    if (p->wr_alpha == alpha && p->wr_src_version == p->src_version && (!dense_src || p->wr_B == B)) return PE_OK;
+    PE_HIP(hipStreamSynchronize(p->st));
+    graphs_clear(p);
+    free_list(p->wr_ops);
+    p->wr_alpha = -1.0;
+    auto& OL = p->wr_ops;
+    const int nf1 = roundup(d1, 64), nf2 = roundup(std::max(d2, 1), 64);
+    const long l1 = 2L * d1p, l2 = 2L * std::max(d2p, 1);
+    PE_TRY(dalloc_t(p, OL, &p->wrO, (size_t)K * l1 * l1));
+    PE_TRY(dalloc_t(p, OL, &p->wrGu, (size_t)d1p * l2));
+    PE_TRY(dalloc_t(p, OL, &p->wrM11h, (size_t)d1p * d1p));
+    PE_TRY(dalloc_t(p, OL, &p->wrZw, (size_t)std::max(d2p, 1) * l1));
+    PE_TRY(dalloc_t(p, OL, &p->wrPhiW, (size_t)std::max(d2p, 1) * std::max(d2p, 1)));
+    PE_TRY(dalloc_t(p, OL, &p->wrTw, (size_t)4 * K * P));
+    const double* M11 = p->M64;
+    const double* A11 = p->A64;
+    const double* M12 = p->M64 + d1p;
+    const double* A12 = p->A64 + d1p;
+    const double* M22 = p->M64 + (long)d1p * Dp + d1p;
+    const double* A22 = p->A64 + (long)d1p * Dp + d1p;
+    PE_HIP(wr_twiddle(p->wrTw, P, K, alpha, p->st));
+    PE_HIP(hipMemsetAsync(p->wrM11h, 0, sizeof(double) * d1p * d1p, p->st));
+    PE_HIP(place(p->wrM11h, d1p, 0, 0, M11, Dp, d1, d1, 1.0 / h, 0, p->st));
+    PE_HIP(hipMemsetAsync(p->wrGu, 0, sizeof(double) * d1p * l2, p->st));
+    PE_HIP(hipMemsetAsync(p->wrZw, 0, sizeof(double) * std::max(d2p, 1) * l1, p->st));
+    PE_HIP(hipMemsetAsync(p->wrPhiW, 0, sizeof(double) * std::max(d2p, 1) * std::max(d2p, 1), p->st));
+    TmpList tmpl(p->st);
+    auto& tmp = tmpl.v;
+    if (d2 > 0) {
+        PE_HIP(place(p->wrGu, l2, 0, 0, M12, Dp, d1, d2, 1.0 / h, 0, p->st));
+        PE_HIP(place(p->wrGu, l2, 0, d2p, A12, Dp, d1, d2, 1.0, 0, p->st));
+        double *E2 = nullptr, *M22inv = nullptr;
+        PE_TRY(dalloc_t(p, tmp, &E2, (size_t)nf2 * nf2));
+        PE_TRY(dalloc_t(p, tmp, &M22inv, (size_t)nf2 * nf2));
+        PE_HIP(shifted_embed(E2, nf2, M22, nullptr, Dp, d2, 0.0, p->st));
+        PE_TRY(factor_inverse(p, E2, nf2, M22inv, "M22", d2));
+        // Zw = [M22^-1 M21 | h M22^-1 A21]: rows of M12 (A12) are the columns of M21 (A21)
+        PE_TRY(gemm<double>(p, shape(d2p, d1p, M22inv, nf2, M12, Dp, 0, d2p), store_epi(p->wrZw, l1)));
+        PE_TRY(gemm<double>(p, shape(d2p, d1p, M22inv, nf2, A12, Dp, 0, d2p), store_epi(p->wrZw + d1p, l1, h)));
+        // PhiW = I - h M22^-1 A22 (A22 symmetric)
+        Epi e = store_epi(p->wrPhiW, d2p, -h);
+        e.diag_add = 1.0;
+        PE_TRY(gemm<double>(p, shape(d2p, d2p, M22inv, nf2, A22, Dp, 0, d2p), e));
+        // the source's w part
+        if (p->src_set && p->src_kind == 1) {
+            PE_TRY(dalloc_t(p, OL, &p->wrGw, (size_t)d2p * p->Rp));
+            PE_TRY(gemm<double>(p, shape(d2p, p->Rp, M22inv, nf2, p->GT + d1p, Dp, 0, d2p),
+                                store_epi(p->wrGw, p->Rp, h)));
+        } else if (dense_src) {
+            PE_TRY(dalloc_t(p, OL, &p->wrFintW, (size_t)B * N * d2p));
+            PE_TRY(gemm<double>(p, shape(B * N, d2p, p->Fint + d1p, Dp, M22inv, nf2, 0, d2p),
+                                store_epi(p->wrFintW, d2p, h)));
+        }
+    }
+    // frequency operators
+    double *E = nullptr, *Ari = nullptr, *Si = nullptr, *T1 = nullptr, *T2 = nullptr, *Ci = nullptr;
+    PE_TRY(dalloc_t(p, tmp, &E, (size_t)nf1 * nf1));
+    PE_TRY(dalloc_t(p, tmp, &Ari, (size_t)nf1 * nf1));
+    PE_TRY(dalloc_t(p, tmp, &Si, (size_t)nf1 * nf1));
+    PE_TRY(dalloc_t(p, tmp, &T1, (size_t)d1p * d1p));
+    PE_TRY(dalloc_t(p, tmp, &T2, (size_t)d1p * d1p));
+    PE_TRY(dalloc_t(p, tmp, &Ci, (size_t)d1p * d1p));
+    PE_HIP(hipMemsetAsync(p->wrO, 0, sizeof(double) * K * l1 * l1, p->st));
+    const double g1 = std::pow(alpha, 1.0 / P);
+    for (int k = 0; k < K; ++k) {
+        const double th = 2.0 * M_PI * (double)k / (double)P;
+        const double a = (1.0 - g1 * std::cos(th)) / h, b = g1 * std::sin(th) / h;
+        char name[96];
+        snprintf(name, sizeof(name), "A11 + %.6e M11 (frequency %d)", a, k);
+        PE_HIP(shifted_embed(E, nf1, A11, M11, Dp, d1, a, p->st));
+        PE_TRY(factor_inverse(p, E, nf1, Ari, name, d1));
+        double* Ok = p->wrO + (long)k * l1 * l1;
+        if (b == 0.0) {
+            // real shift (k = 0 and k = P/2): Cr = Ar^-1, Ci = 0
+            PE_HIP(place(Ok, l1, 0, 0, Ari, nf1, d1, d1, 1.0, 0, p->st));
+            PE_HIP(place(Ok, l1, d1p, d1p, Ari, nf1, d1, d1, 1.0, 0, p->st));
+            continue;
+        }
+        // T1 = M11 Ar^-1, T2 = Ar^-1 M11 = T1^T (Ar^-1, M11 symmetric)
+        PE_TRY(gemm<double>(p, shape(d1p, d1p, M11, Dp, Ari, nf1, 0, d1p), store_epi(T1, d1p)));
+        PE_TRY(gemm<double>(p, shape(d1p, d1p, Ari, nf1, M11, Dp, 0, d1p), store_epi(T2, d1p)));
+        // S = Ar + b^2 M11 Ar^-1 M11, embedded; Cr = S^-1
+        PE_HIP(shifted_embed(E, nf1, A11, M11, Dp, d1, a, p->st));
+        PE_TRY(gemm<double>(p, shape(d1p, d1p, T1, d1p, M11, Dp, 0, d1p), store_epi(E, nf1, b * b, E, nf1, 1.0)));
+        snprintf(name, sizeof(name), "Schur complement of frequency %d", k);
+        PE_TRY(factor_inverse(p, E, nf1, Si, name, d1));
+        // Ci = -b S^-1 (M11 Ar^-1): row i of the second operand = column i of T1 = row i of T2
+        PE_TRY(gemm<double>(p, shape(d1p, d1p, Si, nf1, T2, d1p, 0, d1p), store_epi(Ci, d1p, -b)));
+        PE_HIP(place(Ok, l1, 0, 0, Si, nf1, d1, d1, 1.0, 0, p->st));
+        PE_HIP(place(Ok, l1, d1p, d1p, Si, nf1, d1, d1, 1.0, 0, p->st));
+        PE_HIP(place(Ok, l1, 0, d1p, Ci, d1p, d1, d1, -1.0, 0, p->st));
+        PE_HIP(place(Ok, l1, d1p, 0, Ci, d1p, d1, d1, 1.0, 0, p->st));
+    }
+    PE_HIP(hipStreamSynchronize(p->st));
+    p->wr_alpha = alpha;
+    p->wr_src_version = p->src_version;
+    p->wr_B = B;
+    p->wr_K = K;
+    return PE_OK;
+}
+
+pe_status wr_workspace(pe_problem p, int NBc) {
+    if (p->wr_NBc >= NBc) return PE_OK;
+    PE_HIP(hipStreamSynchronize(p->st));
+    graphs_clear(p);
+    free_list(p->wr_ws);
+    p->wr_NBc = 0;
+    const int P = p->P, K = P / 2 + 1;
+    const size_t E1 = (size_t)NBc * p->d1p, E2 = (size_t)NBc * std::max(p->d2p, 1);
+    auto& L = p->wr_ws;
+    PE_TRY(dalloc_t(p, L, &p->wrUl, (P + 1) * E1));
+    PE_TRY(dalloc_t(p, L, &p->wrWl, (P + 1) * E2));
+    PE_TRY(dalloc_t(p, L, &p->wrR, P * E1));
+    PE_TRY(dalloc_t(p, L, &p->wrRh, K * 2 * E1));
+    PE_TRY(dalloc_t(p, L, &p->wrUh, K * 2 * E1));
+    PE_TRY(dalloc_t(p, L, &p->wrWcat, P * 2 * E2));
+    PE_TRY(dalloc_t(p, L, &p->wrUcat, P * 2 * E1));
+    PE_TRY(dalloc_t(p, L, &p->wrV, P * E2));
+    PE_TRY(dalloc_t(p, L, &p->wrY, E1));
+    p->wr_NBc = NBc;
+    return PE_OK;
+}
+
+// one WR iteration on interval columns c0 .. c0+NBc-1
+pe_status wr_iteration(pe_problem p, int c0, int NBc, double alpha) {
+    const int d2 = p->d2, d1p = p->d1p, d2p = p->d2p, P = p->P, K = p->wr_K;
+    const long E1 = (long)NBc * d1p, E2 = (long)NBc * d2p, l1 = 2L * d1p, l2 = 2L * d2p;
+    // 1. right-hand sides of the u-system at s = 1..P (source at each row's level)
+    if (d2 > 0) PE_HIP(wr_cat(p->wrWl, p->wrWcat, P, NBc, d2p, 0, p->st));
+    {
+        Epi e;
+        e.mode = EPI_RESID;
+        e.R64 = p->wrR;
+        e.ldr = d1p;
+        source_fields(p, e);
+        e.cols_per_b = p->N;
+        e.rows_per_p = NBc;
+        e.col_off = c0;
+        e.p_step = 0;
+        PE_TRY(gemm<double>(p, shape(P * NBc, d1p, p->wrWcat, l2, p->wrGu, l2, 0, d2 > 0 ? (int)l2 : 0), e, 0,
+                            PE_PROF_WR_RHS));
+    }
+    // the periodic-like start at s = 1: + (M11/h)(u_0 - alpha u_P^{j-1})
+    PE_HIP(wr_axmy(p->wrY, p->wrUl, p->wrUl + (long)P * E1, alpha, E1, p->st));
+    PE_TRY(gemm<double>(p, shape(NBc, d1p, p->wrY, d1p, p->wrM11h, d1p, 0, d1p),
+                        store_epi(p->wrR, d1p, 1.0, p->wrR, d1p, 1.0)));
+    // 2. all-at-once solve: transform, one solve per frequency, inverse
+    PE_HIP(wr_dft(1, p->wrR, p->wrRh, p->wrTw, P, K, NBc, d1p, p->st));
+    for (int k = 0; k < K; ++k)
+        PE_TRY(gemm<double>(p, shape(NBc, (int)l1, p->wrRh + (long)k * NBc * l1, l1, p->wrO + (long)k * l1 * l1, l1,
+                                     0, (int)l1),
+                            store_epi(p->wrUh + (long)k * NBc * l1, l1), 0, PE_PROF_WR_SOLVE));
+    PE_HIP(wr_dft(-1, p->wrUh, p->wrUl, p->wrTw, P, K, NBc, d1p, p->st));
+    // 3. eq. (4.9) with the new u levels
+    if (d2 > 0) {
+        PE_HIP(wr_cat(p->wrUl, p->wrUcat, P, NBc, d1p, 1, p->st));
+        Epi e;
+        e.mode = EPI_RESID;
+        e.R64 = p->wrV;
+        e.ldr = d2p;
+        source_fields(p, e);
+        e.Gs = p->wrGw;
+        e.Fint = p->wrFintW;
+        e.ldf = d2p;
+        e.cols_per_b = p->N;
+        e.rows_per_p = NBc;
+        e.col_off = c0;
+        e.p_step = 0;
+        PE_TRY(gemm<double>(p, shape(P * NBc, d2p, p->wrUcat, l1, p->wrZw, l1, 0, (int)l1), e, 0, PE_PROF_WR_RHS));
+        for (int s = 1; s <= P; ++s)
+            PE_TRY(gemm<double>(p, shape(NBc, d2p, p->wrWl + (long)(s - 1) * E2, d2p, p->wrPhiW, d2p, 0, d2p),
+                                store_epi(p->wrWl + (long)s * E2, d2p, 1.0, p->wrV + (long)(s - 1) * E2, d2p, 1.0),
+                                0, PE_PROF_WR_WSTEP));
+    }
+    return PE_OK;
+}
+
+
 }  // namespace
 
 // ===========================================================================
@@ -1815,6 +2035,8 @@ pe_status pe_problem_destroy(pe_problem p) {
     free_list(p->ws_allocs);
     free_list(p->adj_allocs);
     free_list(p->op_allocs);
+    free_list(p->wr_ops);
+    free_list(p->wr_ws);
     if (p->gw.part) (void)hipFree(p->gw.part);
     if (p->own_stream) (void)hipStreamDestroy(p->st);
     delete p;
@@ -2111,6 +2333,7 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
     }
     p->Gs = p->Hs = p->Fint = p->Gs_w = p->Fint_w = p->CS = p->GT = p->GwT = p->ZGs = p->ZGT = p->ZFint = nullptr;
     p->src_set = 1;
+    p->src_version++;
     p->B_src = B;
     p->R = R;
     p->time_mode = time_mode;
@@ -2331,6 +2554,42 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
     PE_HIP(hipStreamSynchronize(p->st));
     PE_TRY(prof_collect(p));
     return n_active > 0 ? PE_WARN_NOT_CONVERGED : PE_OK;
+}
+
+
+pe_status pe_fine_wr(pe_problem p, int B, const double* Xin, double alpha, int K0, double* Fout) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1 || !Xin || !Fout) return fail(PE_ERR_ARG, "bad arguments");
+    if (!(alpha > 0.0 && alpha < 1.0)) return fail(PE_ERR_ARG, "need 0 < alpha < 1");
+    if (K0 < 0) return fail(PE_ERR_ARG, "need K0 >= 0");
+    if (p->P > 128) return fail(PE_ERR_ARG, "waveform relaxation supports P <= 128");
+    if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    const int N = p->N, D = p->D;
+    const long ldXb = (long)N * D;
+    const int NB = B * N;
+    if (K0 == 0) {
+        PE_HIP(hipMemcpyAsync(Fout, Xin, sizeof(double) * NB * D, hipMemcpyDeviceToDevice, p->st));
+        PE_HIP(hipStreamSynchronize(p->st));
+        return PE_OK;
+    }
+    PE_TRY(wr_build_ops(p, B, alpha));
+    // columns per chunk: the workspace holds about 12 P + 8 levels of a column
+    const double col_bytes = 8.0 * ((3.0 * p->P + 1.0 + 2.0 * (p->P / 2 + 1) * 2.0) * p->d1p +
+                                    (4.0 * p->P + 1.0) * std::max(p->d2p, 1));
+    const int max_cols = std::max(1, (int)std::min<double>(NB, (8.0 * (1 << 30)) / col_bytes));
+    const int NBc = std::min(NB, max_cols);
+    PE_TRY(wr_workspace(p, NBc));
+    for (int c0 = 0; c0 < NB; c0 += NBc) {
+        const int nc = std::min(NBc, NB - c0);
+        PE_HIP(wr_io(1, Xin, ldXb, nullptr, N, p->d1, p->d2, p->d1p, p->d2p, c0, nc, p->P, p->wrUl, p->wrWl, p->st));
+        for (int j = 0; j < K0; ++j)
+            PE_TRY(graph_run(p, {20, c0, nc, B}, [&]() -> pe_status { return wr_iteration(p, c0, nc, alpha); }));
+        PE_HIP(wr_io(-1, nullptr, 0, Fout, N, p->d1, p->d2, p->d1p, p->d2p, c0, nc, p->P, p->wrUl, p->wrWl, p->st));
+    }
+    PE_HIP(hipStreamSynchronize(p->st));
+    PE_TRY(prof_collect(p));
+    return PE_OK;
 }
 
 pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH, double beta, double* J) {

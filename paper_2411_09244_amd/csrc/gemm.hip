@@ -54,6 +54,10 @@ struct MfmaOp<double> {
 // ---------------------------------------------------------------------------
 __device__ inline double source_value_p(const Epi& e, int r, int s, int p_step) {
     if (e.src_kind == 0) return 0.0;
+    if (e.rows_per_p > 0) {
+        p_step += r / e.rows_per_p;
+        r = e.col_off + r % e.rows_per_p;
+    }
     int b, n;
     if (e.n_fixed >= 0) {
         b = r;

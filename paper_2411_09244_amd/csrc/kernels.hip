@@ -526,4 +526,198 @@ hipError_t chol_diag(double* Am, long ld, int j, double* Linv, int* info, hipStr
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// waveform relaxation in time (Sections 4.1-4.2): the transforms of the
+// alpha-circulant diagonalisation and the staging of the level differences.
+// Level-major layouts: level l of a (levels x NB x d) array is the NB x d
+// block at l * NB * d; E = NB * d elements per level.
+// ---------------------------------------------------------------------------
+// Tables for P levels and K = P/2 + 1 frequencies (real data, so the
+// frequencies P-K+1 .. P-1 are the conjugates of 1 .. K-2 for even P):
+//   fwd[k][q]       =  alpha^(q/P) cos(2 pi k q/P)   real part of frequency k
+//   fwd[K + k][q]   = -alpha^(q/P) sin(2 pi k q/P)   imaginary part
+//   inv[k][q]       =  w_k alpha^(-q/P) cos(2 pi k q/P) / P
+//   inv[K + k][q]   = -w_k alpha^(-q/P) sin(2 pi k q/P) / P
+// w_k = 1 for k = 0 and for k = P/2 (P even), 2 otherwise; level q + 1 of the
+// interval is time index q. fwd occupies [0, 2KP), inv [2KP, 4KP).
+__global__ void k_wr_twiddle(double* __restrict__ tw, int P, int K, double log_alpha) {
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < 4L * K * P; t += (long)gridDim.x * blockDim.x) {
+        const int which = (int)(t / ((long)K * P));
+        const int k = (int)((t / P) % K), q = (int)(t % P);
+        double sn, cs;
+        sincospi(2.0 * (double)(((long)k * q) % P) / (double)P, &sn, &cs);
+        const double g = exp(log_alpha * (double)q / (double)P);
+        const double wk = (k == 0 || 2 * k == P) ? 1.0 : 2.0;
+        double v;
+        switch (which) {
+            case 0: v = g * cs; break;
+            case 1: v = -g * sn; break;
+            case 2: v = wk * cs / (g * (double)P); break;
+            default: v = -wk * sn / (g * (double)P); break;
+        }
+        tw[t] = v;
+    }
+}
+
+hipError_t wr_twiddle(double* tw, int P, int K, double alpha, hipStream_t st) {
+    hipLaunchKernelGGL(k_wr_twiddle, grid1(4L * K * P), dim3(256), 0, st, tw, P, K, log(alpha));
+    return hipGetLastError();
+}
+
+// forward transform along time: R (P levels x NB x d1p) -> Rh (K x NB x
+// [re (d1p) | im (d1p)]). A work-group takes WR_TE consecutive elements,
+// stages their P levels in LDS and produces all 2K outputs of them.
+constexpr int WR_TE = 32;
+__global__ __launch_bounds__(256) void k_wr_dft_fwd(const double* __restrict__ R, double* __restrict__ Rh,
+                                                    const double* __restrict__ tw, int P, int K, long E,
+                                                    int d1p) {
+    extern __shared__ double sh[];
+    const long e0 = blockIdx.x * (long)WR_TE;
+    for (int t = threadIdx.x; t < P * WR_TE; t += blockDim.x) {
+        const int q = t / WR_TE, j = t % WR_TE;
+        const long e = e0 + j;
+        sh[t] = e < E ? R[(long)q * E + e] : 0.0;
+    }
+    __syncthreads();
+    const long NB = E / d1p;
+    for (int t = threadIdx.x; t < 2 * K * WR_TE; t += blockDim.x) {
+        const int j = t % WR_TE, kk = t / WR_TE;
+        const long e = e0 + j;
+        if (e >= E) continue;
+        const double* w = tw + (long)kk * P;
+        double acc = 0.0;
+        for (int q = 0; q < P; ++q) acc = fma(w[q], sh[q * WR_TE + j], acc);
+        const int part = kk / K, k = kk % K;
+        const long c = e / d1p;
+        const int i = (int)(e - c * d1p);
+        Rh[((long)k * NB + c) * 2 * d1p + (long)part * d1p + i] = acc;
+    }
+}
+
+// inverse transform: Uh (K x NB x [re | im]) -> levels 1..P of U (level
+// q + 1 = sum over the 2K table rows of inv[kk][q] times part kk of Uh)
+__global__ __launch_bounds__(256) void k_wr_dft_inv(const double* __restrict__ Uh, double* __restrict__ U,
+                                                    const double* __restrict__ tinv, int P, int K, long E,
+                                                    int d1p) {
+    extern __shared__ double sh[];
+    const long e0 = blockIdx.x * (long)WR_TE;
+    const long NB = E / d1p;
+    for (int t = threadIdx.x; t < 2 * K * WR_TE; t += blockDim.x) {
+        const int kk = t / WR_TE, j = t % WR_TE;
+        const long e = e0 + j;
+        double v = 0.0;
+        if (e < E) {
+            const int part = kk / K, k = kk % K;
+            const long c = e / d1p;
+            const int i = (int)(e - c * d1p);
+            v = Uh[((long)k * NB + c) * 2 * d1p + (long)part * d1p + i];
+        }
+        sh[t] = v;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < P * WR_TE; t += blockDim.x) {
+        const int q = t / WR_TE, j = t % WR_TE;
+        const long e = e0 + j;
+        if (e >= E) continue;
+        double acc = 0.0;
+        for (int kk = 0; kk < 2 * K; ++kk) acc = fma(tinv[(long)kk * P + q], sh[kk * WR_TE + j], acc);
+        U[(long)(q + 1) * E + e] = acc;
+    }
+}
+
+hipError_t wr_dft(int dir, const double* src, double* dst, const double* tw, int P, int K, long NB, int d1p,
+                  hipStream_t st) {
+    const long E = NB * d1p;
+    const dim3 g((unsigned)((E + WR_TE - 1) / WR_TE));
+    if (dir > 0) {
+        const size_t lds = sizeof(double) * (size_t)P * WR_TE;
+        hipLaunchKernelGGL(k_wr_dft_fwd, g, dim3(256), lds, st, src, dst, tw, P, K, E, d1p);
+    } else {
+        const size_t lds = sizeof(double) * (size_t)2 * K * WR_TE;
+        hipLaunchKernelGGL(k_wr_dft_inv, g, dim3(256), lds, st, src, dst, tw + 2L * K * P, P, K, E, d1p);
+    }
+    return hipGetLastError();
+}
+
+// staging for the two products of an iteration, s = 1..P (level s-1 of the
+// output): mode 0 (w): [w_{s-1} - w_{s-2} | w_{s-1}], w_{-1} = w_0;
+// mode 1 (u): [u_{s-1} - u_{s-2} | u_s], u_{-1} = u_0
+__global__ void k_wr_cat(const double* __restrict__ L, double* __restrict__ out, int P, long NB, int d, int mode) {
+    const long E = NB * d;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)P * E; t += (long)gridDim.x * blockDim.x) {
+        const int s1 = (int)(t / E);
+        const long rem = t - (long)s1 * E;
+        const double a = L[(long)s1 * E + rem];
+        const double b = s1 >= 1 ? L[(long)(s1 - 1) * E + rem] : a;
+        const double second = mode ? L[(long)(s1 + 1) * E + rem] : a;
+        const long c = rem / d;
+        const int i = (int)(rem - c * d);
+        double* o = out + ((long)s1 * NB + c) * 2 * d;
+        o[i] = a - b;
+        o[d + i] = second;
+    }
+}
+
+hipError_t wr_cat(const double* L, double* out, int P, long NB, int d, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_wr_cat, grid1((long)P * NB * d), dim3(256), 0, st, L, out, P, NB, d, mode);
+    return hipGetLastError();
+}
+
+// y = a - alpha b
+__global__ void k_wr_axmy(double* __restrict__ y, const double* __restrict__ a, const double* __restrict__ b,
+                          double alpha, long n) {
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        y[t] = a[t] - alpha * b[t];
+}
+
+hipError_t wr_axmy(double* y, const double* a, const double* b, double alpha, long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_wr_axmy, grid1(n), dim3(256), 0, st, y, a, b, alpha, n);
+    return hipGetLastError();
+}
+
+// Start of a WR run on columns c0 .. c0+NBc-1 (column c = b N + n, start
+// state row n of sample b in X, row stride D, sample stride ldXb): level 0
+// of U and W, the initial waveform w_s = w_0 (s = 1..P) and u_P = u_0.
+// dir < 0 writes the end states (level P) to Fout (B x N x D) instead.
+__global__ void k_wr_io(int dir, const double* __restrict__ X, long ldXb, double* __restrict__ Fout, int N,
+                        int d1, int d2, int d1p, int d2p, int c0, int NBc, int P, double* __restrict__ Ul,
+                        double* __restrict__ Wl) {
+    const int D = d1 + d2;
+    const long E1 = (long)NBc * d1p, E2 = (long)NBc * d2p;
+    if (dir > 0) {
+        const int Dp = d1p + d2p;
+        for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)NBc * Dp;
+             t += (long)gridDim.x * blockDim.x) {
+            const int c = (int)(t / Dp), s = (int)(t % Dp);
+            const int cg = c0 + c, b = cg / N, n = cg % N;
+            const double* x = X + (long)b * ldXb + (long)n * D;
+            if (s < d1p) {
+                const double v = s < d1 ? x[s] : 0.0;
+                Ul[(long)c * d1p + s] = v;
+                Ul[(long)P * E1 + (long)c * d1p + s] = v;
+            } else {
+                const int j = s - d1p;
+                const double v = j < d2 ? x[d1 + j] : 0.0;
+                for (int l = 0; l <= P; ++l) Wl[(long)l * E2 + (long)c * d2p + j] = v;
+            }
+        }
+    } else {
+        for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)NBc * D;
+             t += (long)gridDim.x * blockDim.x) {
+            const int c = (int)(t / D), s = (int)(t % D);
+            const double v = s < d1 ? Ul[(long)P * E1 + (long)c * d1p + s]
+                                    : Wl[(long)P * E2 + (long)c * d2p + (s - d1)];
+            Fout[(long)(c0 + c) * D + s] = v;
+        }
+    }
+}
+
+hipError_t wr_io(int dir, const double* X, long ldXb, double* Fout, int N, int d1, int d2, int d1p, int d2p,
+                 int c0, int NBc, int P, double* Ul, double* Wl, hipStream_t st) {
+    const long n = (long)NBc * (dir > 0 ? d1p + d2p : d1 + d2);
+    hipLaunchKernelGGL(k_wr_io, grid1(n), dim3(256), 0, st, dir, X, ldXb, Fout, N, d1, d2, d1p, d2p, c0, NBc, P,
+                       Ul, Wl);
+    return hipGetLastError();
+}
+
 }  // namespace pe

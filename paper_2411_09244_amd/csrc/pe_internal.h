@@ -59,6 +59,9 @@ struct Epi {
     int p_step = 0;              // fine step index inside the interval
     int cols_per_b = 1;          // column r -> sample r / cols_per_b, interval r % cols_per_b
     int n_fixed = -1;            // >= 0: every column belongs to this interval (r = sample)
+    int rows_per_p = 0;          // > 0: row r is fine step p_step + r / rows_per_p of
+                                 // column col_off + r % rows_per_p (rows ordered step-major)
+    int col_off = 0;
     int N = 1;
     const double* Fint = nullptr;  // (B*N) x Dp table of per-interval sources
     long ldf = 0;

@@ -38,4 +38,12 @@ hipError_t to_f32(const double* src, float* dst, long n, hipStream_t st);
 hipError_t asym(const double* X, const double* Y, long ldx, long ldy, int rows, int cols,
                 unsigned long long* out2, hipStream_t st);
 hipError_t chol_diag(double* Am, long ld, int j, double* Linv, int* info, hipStream_t st);
+// waveform relaxation in time
+hipError_t wr_twiddle(double* tw, int P, int K, double alpha, hipStream_t st);
+hipError_t wr_dft(int dir, const double* src, double* dst, const double* tw, int P, int K, long NB, int d1p,
+                  hipStream_t st);
+hipError_t wr_cat(const double* L, double* out, int P, long NB, int d, int mode, hipStream_t st);
+hipError_t wr_axmy(double* y, const double* a, const double* b, double alpha, long n, hipStream_t st);
+hipError_t wr_io(int dir, const double* X, long ldXb, double* Fout, int N, int d1, int d2, int d1p, int d2p,
+                 int c0, int NBc, int P, double* Ul, double* Wl, hipStream_t st);
 }  // namespace pe

@@ -350,6 +350,108 @@ def large_main(args, torch, pe):
     print(json.dumps(out), flush=True)
 
 
+WR_WORKLOAD = ("fine propagator by waveform relaxation with the alpha-circulant diagonalisation in time "
+               "(FP64), applied to the 64 interval start states of the first parareal iterate of the 200x200 "
+               "workload (d1=800, d2=1200, N=64 intervals x P=64 fine steps, f=sin(pi x)sin(pi y)e^-t)")
+
+
+def wr_main(args, torch, pe):
+    """The paper's fine solver (waveform relaxation, alpha-circulant
+    diagonalisation) on the 200x200 workload: a step is one WR fine sweep
+    (K0 iterations on all N intervals); the exact fine sweep (pe_fine_propagate,
+    FP64) is timed beside it, and the error after each iteration is recorded
+    for several alpha."""
+    import numpy as np
+    import oracle.wr as WR
+    import oracle.scheme as S
+    from problem import build_problem
+    p = build_problem("c1")
+    d1, d2, N, P = p["d1"], p["d2"], p["N"], p["P"]
+    D = d1 + d2
+    pr = pe.problem_from(p, "fp64")
+    x0 = torch.as_tensor(p["x0"], dtype=torch.float64, device="cuda")
+    X0, _, _, _ = pr.solve(x0, tol=0.0, k_max=0)          # coarse sweep: x_n^0
+    Xin = X0[:, :N].contiguous()
+    exact = pr.fine(Xin)
+    nrm = torch.linalg.norm(exact).item()
+    alpha, K0 = args.wr_alpha, args.wr_iters
+    curves = {}
+    for a in sorted({0.1, 0.05, alpha, 0.005}, reverse=True):
+        ts = time.perf_counter()
+        pr.fine_wr(Xin, a, 0)
+        torch.cuda.synchronize()
+        errs = []
+        for k in range(1, 13):
+            errs.append(float("%.3e" % (torch.linalg.norm(pr.fine_wr(Xin, a, k) - exact).item() / nrm)))
+        curves[str(a)] = errs
+        log(f"wr alpha {a}: rel err after 1..12 iterations {errs} ({time.perf_counter() - ts:.1f}s incl. set-up)")
+    for _ in range(args.warmup):
+        pr.fine_wr(Xin, alpha, K0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Y = pr.fine_wr(Xin, alpha, K0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err = torch.linalg.norm(Y - exact).item() / nrm
+    # the exact sequential fine sweep, same inputs
+    for _ in range(2):
+        pr.fine(Xin)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        pr.fine(Xin)
+    torch.cuda.synchronize()
+    dt_exact = time.perf_counter() - t1
+    pr.profile(True)
+    pr.fine_wr(Xin, alpha, K0)
+    torch.cuda.synchronize()
+    prof = pr.profile_read()
+    pr.profile(False)
+    log("wr launch timing: " + ", ".join(f"{k} {v[0]:.2f}ms/{v[1]}" for k, v in prof.items() if v[1]))
+    NB = N
+    flops = {"wr_rhs": 4.0 * P * NB * d1 * d2, "wr_solve": 8.0 * NB * d1 * d1 * (P // 2 + 1),
+             "wr_wstep": 2.0 * NB * d2 * d2}
+    names = {"wr_rhs": "gemm_nt_kernel<double> right-hand-side products of eqs. (4.8)/(4.9) over all fine levels",
+             "wr_solve": "gemm_grouped_kernel<double,64,64,16> the P/2+1 complex-shifted solves (real 2d1 x 2d1 "
+                         "forms), one grouped launch",
+             "wr_wstep": "gemm_nt_kernel<double> sequential V_H2 step"}
+    dom = max(flops, key=lambda k: prof[k][0])
+    ms, n = prof[dom]
+    avg = ms / n * 1e-3
+    classes = {k: dict(ms_per_sweep=round(prof[k][0], 3), launches=prof[k][1],
+                       tflops=round(flops[k] * prof[k][1] / (prof[k][0] * 1e-3) / 1e12, 3) if prof[k][1] else None)
+               for k in flops}
+    out = {"metric": "WR fine sweeps/s (all 64 intervals, K0 iterations)", "value": round(args.steps / dt, 4),
+           "unit": "sweeps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": WR_WORKLOAD, "name": "wr", "d1": d1, "d2": d2, "N": N, "P": P, "alpha": alpha,
+                      "K0": K0, "rel_err_vs_exact_F": float("%.3e" % err)},
+           "roofline": dict(kernel=names[dom], bound="mfma", achieved=round(flops[dom] / avg / 1e12, 3),
+                            peak=PEAK_FP64_MFMA, unit="TFLOP/s",
+                            frac=round(flops[dom] / avg / 1e12 / PEAK_FP64_MFMA, 5), traffic=None,
+                            avg_launch_us=round(avg * 1e6, 2), launches=n, flops_per_launch=flops[dom]),
+           "classes": classes,
+           "exact_fine_sweep": {"sweeps_per_s": round(args.steps / dt_exact, 4),
+                                "ms_per_sweep": round(1e3 * dt_exact / args.steps, 3)},
+           "convergence": {"rel_err_after_iterations_1_to_12": curves}}
+    if not args.no_cpu_baseline:
+        bl, src = S.Blocks.from_problem(p), S.Source.from_problem(p)
+        cols = Xin[0].cpu().numpy().T
+        ns, bs = list(range(N)), [0] * N
+        WR.wr_fine_cols(bl, src, cols, ns, bs, alpha, 1)      # factorisations (cached)
+        t2 = time.perf_counter()
+        WR.wr_fine_cols(bl, src, cols, ns, bs, alpha, 1)
+        t_it = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": round(1.0 / (t_it * K0), 5), "unit": "sweeps/s",
+                               "cores": os.cpu_count(), "kind": "oracle",
+                               "sample": f"one WR iteration on all {N} intervals ({t_it:.1f}s, shifted "
+                                         f"factorisations cached), scaled to K0 = {K0} iterations"}
+    print(json.dumps(out), flush=True)
+    pr.close()
+
+
 def cpu_baseline(p, tol):
     """The FP64 oracle's plain parareal on the same workload, one solve."""
     import numpy as np
@@ -374,9 +476,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c1")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c4"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c4", "wr"],
                     help="c1: one 200x200 problem (default line); c2: ragged batch of 256 solves; "
-                         "c4: 400x400, 32 samples, forward + adjoint")
+                         "c4: 400x400, 32 samples, forward + adjoint; wr: the waveform-relaxation "
+                         "fine solver on the 200x200 problem")
+    ap.add_argument("--wr-alpha", type=float, default=0.02)
+    ap.add_argument("--wr-iters", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint workload")
@@ -402,6 +507,8 @@ def main():
         return batch_main(args, torch, pe)
     if args.workload == "c4":
         return large_main(args, torch, pe)
+    if args.workload == "wr":
+        return wr_main(args, torch, pe)
     tol = 1e-7
     t0 = time.perf_counter()
     p = build_problem(args.config, verbose=False)

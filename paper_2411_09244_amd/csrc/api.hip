@@ -200,7 +200,13 @@ struct pe_problem_s {
     double *wrGw = nullptr, *wrFintW = nullptr, *wrTw = nullptr;
     double *wrUl = nullptr, *wrWl = nullptr, *wrR = nullptr, *wrRh = nullptr, *wrUh = nullptr;
     double *wrWcat = nullptr, *wrUcat = nullptr, *wrV = nullptr, *wrY = nullptr;
-    std::vector<void*> wr_ops, wr_ws;
+    // grouped launch of the per-frequency solves: items and work-group tables
+    // for chunks of wr_tab_nc columns (rebuilt with the operators or workspace)
+    GemmItem* wrItems = nullptr;
+    int *wrWgI = nullptr, *wrWgT = nullptr;
+    int wr_nwg = 0, wr_tab_nc = 0;
+    TileCfg wr_cfg;
+    std::vector<void*> wr_ops, wr_ws, wr_tab;
 
     std::vector<void*> op_allocs, ws_allocs;
 };
@@ -484,7 +490,9 @@ enum {
     SITE_ANCHOR = 2,
     SITE_NORM = 3,
     SITE_TRAJ = 6,
-    SITE_ADJ_STEP = 8
+    SITE_ADJ_STEP = 8,
+    SITE_WR_RHS = 9,
+    SITE_WR_WSTEP = 10
 };
 
 template <typename T>
@@ -1843,6 +1851,8 @@ pe_status wr_build_ops(pe_problem p, int B, double alpha) {
     PE_HIP(hipStreamSynchronize(p->st));
     graphs_clear(p);
     free_list(p->wr_ops);
+    free_list(p->wr_tab);
+    p->wr_tab_nc = 0;
     p->wr_alpha = -1.0;
     auto& OL = p->wr_ops;
     const int nf1 = roundup(d1, 64), nf2 = roundup(std::max(d2, 1), 64);
@@ -1945,6 +1955,8 @@ pe_status wr_workspace(pe_problem p, int NBc) {
     PE_HIP(hipStreamSynchronize(p->st));
     graphs_clear(p);
     free_list(p->wr_ws);
+    free_list(p->wr_tab);
+    p->wr_tab_nc = 0;
     p->wr_NBc = 0;
     const int P = p->P, K = P / 2 + 1;
     const size_t E1 = (size_t)NBc * p->d1p, E2 = (size_t)NBc * std::max(p->d2p, 1);
@@ -1959,6 +1971,46 @@ pe_status wr_workspace(pe_problem p, int NBc) {
     PE_TRY(dalloc_t(p, L, &p->wrV, P * E2));
     PE_TRY(dalloc_t(p, L, &p->wrY, E1));
     p->wr_NBc = NBc;
+    return PE_OK;
+}
+
+// the K per-frequency solves of a chunk of NBc columns as one grouped launch:
+// item k is Uh_k = Rh_k O_k^T (NBc x 2d1p), one work-group per output tile
+pe_status wr_tables(pe_problem p, int NBc) {
+    if (p->wr_tab_nc == NBc) return PE_OK;
+    PE_HIP(hipStreamSynchronize(p->st));
+    graphs_clear(p);  // captured iterations point at the old tables
+    free_list(p->wr_tab);
+    p->wr_tab_nc = 0;
+    const int K = p->wr_K;
+    const long l1 = 2L * p->d1p;
+    TileCfg c;
+    c.br = NBc >= 64 ? 64 : 32;
+    c.bs = 64;
+    c.bk2 = 0;
+    c.splitk = 1;
+    std::vector<GemmItem> items(K);
+    std::vector<int> wi, wt;
+    const int tr = (NBc + c.br - 1) / c.br, ts = (int)((l1 + c.bs - 1) / c.bs);
+    for (int k = 0; k < K; ++k) {
+        items[k].sh = shape(NBc, (int)l1, p->wrRh + (long)k * NBc * l1, l1, p->wrO + (long)k * l1 * l1, l1, 0, (int)l1);
+        items[k].epi = store_epi(p->wrUh + (long)k * NBc * l1, l1);
+        items[k].tiles_r = tr;
+        if (!gemm_shape_ok(items[k].sh, sizeof(double))) return fail(PE_ERR_ARG, "frequency solve shape");
+        for (int t = 0; t < tr * ts; ++t) {
+            wi.push_back(k);
+            wt.push_back(t);
+        }
+    }
+    PE_TRY(dalloc_t(p, p->wr_tab, &p->wrItems, items.size()));
+    PE_TRY(dalloc_t(p, p->wr_tab, &p->wrWgI, wi.size()));
+    PE_TRY(dalloc_t(p, p->wr_tab, &p->wrWgT, wt.size()));
+    PE_HIP(hipMemcpy(p->wrItems, items.data(), sizeof(GemmItem) * items.size(), hipMemcpyHostToDevice));
+    PE_HIP(hipMemcpy(p->wrWgI, wi.data(), sizeof(int) * wi.size(), hipMemcpyHostToDevice));
+    PE_HIP(hipMemcpy(p->wrWgT, wt.data(), sizeof(int) * wt.size(), hipMemcpyHostToDevice));
+    p->wr_nwg = (int)wi.size();
+    p->wr_cfg = c;
+    p->wr_tab_nc = NBc;
     return PE_OK;
 }
 
@@ -1979,7 +2031,7 @@ pe_status wr_iteration(pe_problem p, int c0, int NBc, double alpha) {
         e.col_off = c0;
         e.p_step = 0;
         PE_TRY(gemm<double>(p, shape(P * NBc, d1p, p->wrWcat, l2, p->wrGu, l2, 0, d2 > 0 ? (int)l2 : 0), e, 0,
-                            PE_PROF_WR_RHS));
+                            PE_PROF_WR_RHS, d2 > 0 ? SITE_WR_RHS : SITE_NONE));
     }
     // the periodic-like start at s = 1: + (M11/h)(u_0 - alpha u_P^{j-1})
     PE_HIP(wr_axmy(p->wrY, p->wrUl, p->wrUl + (long)P * E1, alpha, E1, p->st));
@@ -1987,10 +2039,13 @@ pe_status wr_iteration(pe_problem p, int c0, int NBc, double alpha) {
                         store_epi(p->wrR, d1p, 1.0, p->wrR, d1p, 1.0)));
     // 2. all-at-once solve: transform, one solve per frequency, inverse
     PE_HIP(wr_dft(1, p->wrR, p->wrRh, p->wrTw, P, K, NBc, d1p, p->st));
-    for (int k = 0; k < K; ++k)
-        PE_TRY(gemm<double>(p, shape(NBc, (int)l1, p->wrRh + (long)k * NBc * l1, l1, p->wrO + (long)k * l1 * l1, l1,
-                                     0, (int)l1),
-                            store_epi(p->wrUh + (long)k * NBc * l1, l1), 0, PE_PROF_WR_SOLVE));
+    {
+        size_t slot;
+        PE_TRY(prof_begin(p, PE_PROF_WR_SOLVE, &slot));
+        const hipError_t e = gemm_grouped_launch<double>(p->wrItems, p->wrWgI, p->wrWgT, p->wr_nwg, p->wr_cfg, p->st);
+        if (e != hipSuccess) return fail(PE_ERR_HIP, std::string("frequency solves: ") + hipGetErrorString(e));
+        PE_TRY(prof_end(p, slot));
+    }
     PE_HIP(wr_dft(-1, p->wrUh, p->wrUl, p->wrTw, P, K, NBc, d1p, p->st));
     // 3. eq. (4.9) with the new u levels
     if (d2 > 0) {
@@ -2007,11 +2062,12 @@ pe_status wr_iteration(pe_problem p, int c0, int NBc, double alpha) {
         e.rows_per_p = NBc;
         e.col_off = c0;
         e.p_step = 0;
-        PE_TRY(gemm<double>(p, shape(P * NBc, d2p, p->wrUcat, l1, p->wrZw, l1, 0, (int)l1), e, 0, PE_PROF_WR_RHS));
+        PE_TRY(gemm<double>(p, shape(P * NBc, d2p, p->wrUcat, l1, p->wrZw, l1, 0, (int)l1), e, 0, PE_PROF_WR_RHS,
+                            SITE_WR_RHS));
         for (int s = 1; s <= P; ++s)
             PE_TRY(gemm<double>(p, shape(NBc, d2p, p->wrWl + (long)(s - 1) * E2, d2p, p->wrPhiW, d2p, 0, d2p),
                                 store_epi(p->wrWl + (long)s * E2, d2p, 1.0, p->wrV + (long)(s - 1) * E2, d2p, 1.0),
-                                0, PE_PROF_WR_WSTEP));
+                                0, PE_PROF_WR_WSTEP, SITE_WR_WSTEP));
     }
     return PE_OK;
 }
@@ -2037,6 +2093,7 @@ pe_status pe_problem_destroy(pe_problem p) {
     free_list(p->op_allocs);
     free_list(p->wr_ops);
     free_list(p->wr_ws);
+    free_list(p->wr_tab);
     if (p->gw.part) (void)hipFree(p->gw.part);
     if (p->own_stream) (void)hipStreamDestroy(p->st);
     delete p;
@@ -2582,6 +2639,7 @@ pe_status pe_fine_wr(pe_problem p, int B, const double* Xin, double alpha, int K
     PE_TRY(wr_workspace(p, NBc));
     for (int c0 = 0; c0 < NB; c0 += NBc) {
         const int nc = std::min(NBc, NB - c0);
+        PE_TRY(wr_tables(p, nc));
         PE_HIP(wr_io(1, Xin, ldXb, nullptr, N, p->d1, p->d2, p->d1p, p->d2p, c0, nc, p->P, p->wrUl, p->wrWl, p->st));
         for (int j = 0; j < K0; ++j)
             PE_TRY(graph_run(p, {20, c0, nc, B}, [&]() -> pe_status { return wr_iteration(p, c0, nc, alpha); }));

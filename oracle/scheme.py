@@ -162,11 +162,13 @@ def m_norm(bl, e):
     return float(np.sqrt(max(e @ (bl.M @ e), 0.0)))
 
 
-def parareal(bl, src, x0, tol, k_max=None, b=0, columns=True, rel=False):
+def parareal(bl, src, x0, tol, k_max=None, b=0, columns=True, rel=False, fine_cols=None):
     """Plain parareal (Algorithm 1 with the update of eq. (2.7) and the stop
     test of eq. (2.8)). Returns dict with all iterates X[k] (k = 0..K, each
     (N+1, D)), the jump history J[k] (k = 1..K) and K.
-    With rel=True the tolerance is scaled by max_n |x_n^0|_M."""
+    With rel=True the tolerance is scaled by max_n |x_n^0|_M.
+    fine_cols (optional) replaces the fine propagator: called as
+    fine_cols(X, ns, bs) with the start states as columns of X (D, N)."""
     N = bl.N
     k_max = N if k_max is None else min(int(k_max), N)
     X = np.zeros((N + 1, bl.D))
@@ -183,7 +185,9 @@ def parareal(bl, src, x0, tol, k_max=None, b=0, columns=True, rel=False):
     k = 0
     while k < k_max:
         k += 1
-        if columns:
+        if fine_cols is not None:
+            f = fine_cols(X[:N].T.copy(), list(range(N)), [b] * N).T
+        elif columns:
             f = fine_propagator_cols(bl, src, X[:N].T.copy(), list(range(N)), [b] * N).T
         else:
             f = np.stack([fine_propagator(bl, src, X[n], n, b) for n in range(N)])

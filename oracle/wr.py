@@ -154,6 +154,25 @@ def wr_fine(bl, src, x, n, alpha, K0, b=0, history=False):
     return r[:, 0]
 
 
+def parareal_wr(bl, src, x0, tol, alpha, K0, k_max=None, b=0, rel=False):
+    """Algorithm 1 with the paper's fine solver: the parareal update of
+    eq. (2.7) where F is K0 iterations of WR on every interval (Section 4.3
+    uses WR as the fine propagator inside parareal)."""
+    from .scheme import parareal
+    return parareal(bl, src, x0, tol, k_max=k_max, b=b, rel=rel,
+                    fine_cols=lambda X, ns, bs: wr_fine_cols(bl, src, X, ns, bs, alpha, K0))
+
+
+def wr_composition(bl, src, x0, alpha, K0, b=0):
+    """X_{n+1} = F_WR(X_n), X_0 = x0: the limit of parareal with the WR fine
+    solver (the sequential composition of the fine solver it uses)."""
+    X = np.zeros((bl.N + 1, bl.D))
+    X[0] = x0
+    for n in range(bl.N):
+        X[n + 1] = wr_fine(bl, src, X[n], n, alpha, K0, b)
+    return X
+
+
 def gamma_sq(bl):
     """gamma^2 of eq. (4.15) for the discrete spaces: the largest generalised
     eigenvalue of (M21 M11^-1 M12, M22) (the squared cosine of the largest

@@ -3,7 +3,9 @@ alpha-circulant eigenvalues against a general eigensolver, the diagonalised
 all-at-once solve against the dense Kronecker system, the fixed point against
 the sequential fine propagator, finite termination of the alpha = 0
 iteration, the d2 = 0 closed-form recursion, the convergence factor of the
-theorem of Section 4.2, and affinity."""
+theorem of Section 4.2, affinity, and parareal with the WR fine solver
+(finite termination at the WR composition; the plain parareal iterates once
+WR has converged)."""
 import numpy as np
 import pytest
 
@@ -121,3 +123,27 @@ def test_affine_in_the_start_state(c0):
 
     lhs = f(x + y) - f(x) - f(y) + f(np.zeros(bl.D))
     assert np.linalg.norm(lhs) <= 1e-10 * np.linalg.norm(f(x))
+
+
+def test_parareal_with_wr_terminates_at_the_wr_composition(c0):
+    # parareal reproduces the sequential composition of the fine solver it
+    # uses after N iterations (the first k intervals are exact after k
+    # iterations), here with F = K0 WR iterations
+    bl, src = c0
+    x0 = np.random.default_rng(7).standard_normal(bl.D)
+    r = WR.parareal_wr(bl, src, x0, 0.0, 0.05, 2, k_max=bl.N)
+    ref = WR.wr_composition(bl, src, x0, 0.05, 2)
+    assert r["K"] == bl.N
+    assert np.linalg.norm(r["X"][-1] - ref) <= 1e-11 * np.linalg.norm(ref)
+    # and after k iterations the first k+1 boundary states are exact
+    k = 3
+    assert np.linalg.norm(r["X"][k][:k + 1] - ref[:k + 1]) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_parareal_with_converged_wr_is_plain_parareal(c0):
+    bl, src = c0
+    x0 = np.random.default_rng(8).standard_normal(bl.D)
+    a = WR.parareal_wr(bl, src, x0, 0.0, 0.01, 40, k_max=3)
+    b = S.parareal(bl, src, x0, 0.0, k_max=3)
+    for Xa, Xb in zip(a["X"], b["X"]):
+        assert np.linalg.norm(Xa - Xb) <= 1e-10 * np.linalg.norm(Xb)

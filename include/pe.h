@@ -242,6 +242,20 @@ pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH,
 pe_status pe_fine_wr(pe_problem p, int B, const double* Xin, double alpha, int K0, double* Fout);
 
 /*
+ * pe_set_fine_solver - the fine propagator F that pe_solve uses in the
+ * parareal update (eq. (2.7)):
+ *   PE_FINE_STEP (default): P steps of eqs. (2.5)-(2.6);
+ *   PE_FINE_WR: K0 >= 1 iterations of waveform relaxation with alpha in
+ *     (0, 1), exactly as pe_fine_wr (Algorithm 1 with the paper's fine
+ *     solver, Section 4.3). PE_FP64 handles only; parareal then converges
+ *     to the sequential composition of this F.
+ * pe_fine_propagate, pe_adjoint and pe_tracking always use P steps of the
+ * scheme. Errors: PE_ERR_ARG.
+ */
+enum { PE_FINE_STEP = 0, PE_FINE_WR = 1 };
+pe_status pe_set_fine_solver(pe_problem p, int kind, double alpha, int K0);
+
+/*
  * Batches of different problems (different d1, d2, N, sources and sample
  * counts; same precision and step ratio P), solved together: every
  * product of a fine step runs as one grouped MFMA launch over all problems'

@@ -130,6 +130,12 @@ class Problem:
         L.check(self.lib.pe_fine_propagate(self.handle, B, _ptr(Xin), _ptr(Y)))
         return Y
 
+    def set_fine_solver(self, kind="step", alpha=0.05, K0=1):
+        """The fine propagator used by solve(): "step" (P steps of the scheme)
+        or "wr" (K0 waveform-relaxation iterations with alpha, FP64 handles)."""
+        k = {"step": 0, "wr": 1}[kind]
+        L.check(self.lib.pe_set_fine_solver(self.handle, k, float(alpha), int(K0)))
+
     def fine_wr(self, Xin, alpha, K0):
         """The fine propagator by waveform relaxation with the alpha-circulant
         diagonalisation (K0 iterations, FP64) applied to Xin (B, N, D) ->

@@ -207,6 +207,10 @@ struct pe_problem_s {
     int wr_nwg = 0, wr_tab_nc = 0;
     TileCfg wr_cfg;
     std::vector<void*> wr_ops, wr_ws, wr_tab;
+    // fine propagator used by pe_solve (pe_set_fine_solver)
+    int fine_kind = PE_FINE_STEP;
+    double fine_alpha = 0.0;
+    int fine_K0 = 0;
 
     std::vector<void*> op_allocs, ws_allocs;
 };
@@ -2073,6 +2077,32 @@ pe_status wr_iteration(pe_problem p, int c0, int NBc, double alpha) {
 }
 
 
+// K0 WR iterations on the B*N interval columns: start states X (sample
+// stride ldXb; in_dir 1: caller layout rows of D, 2: padded rows of Dp),
+// end states to Y (row b*N + n; out_dir -1: caller layout, -2: padded)
+pe_status wr_sweep(pe_problem p, int B, const double* X, long ldXb, int in_dir, double* Y, int out_dir,
+                   double alpha, int K0) {
+    const int N = p->N, NB = B * N;
+    PE_TRY(wr_build_ops(p, B, alpha));
+    // columns per chunk: the workspace holds about 12 P + 8 levels of a column
+    const double col_bytes = 8.0 * ((3.0 * p->P + 1.0 + 2.0 * (p->P / 2 + 1) * 2.0) * p->d1p +
+                                    (4.0 * p->P + 1.0) * std::max(p->d2p, 1));
+    const int max_cols = std::max(1, (int)std::min<double>(NB, (8.0 * (1 << 30)) / col_bytes));
+    const int NBc = std::min(NB, max_cols);
+    PE_TRY(wr_workspace(p, NBc));
+    for (int c0 = 0; c0 < NB; c0 += NBc) {
+        const int nc = std::min(NBc, NB - c0);
+        PE_TRY(wr_tables(p, nc));
+        PE_HIP(wr_io(in_dir, X, ldXb, nullptr, N, p->d1, p->d2, p->d1p, p->d2p, c0, nc, p->P, p->wrUl, p->wrWl,
+                     p->st));
+        for (int j = 0; j < K0; ++j)
+            PE_TRY(graph_run(p, {20, c0, nc, B}, [&]() -> pe_status { return wr_iteration(p, c0, nc, alpha); }));
+        PE_HIP(wr_io(out_dir, nullptr, 0, Y, N, p->d1, p->d2, p->d1p, p->d2p, c0, nc, p->P, p->wrUl, p->wrWl,
+                     p->st));
+    }
+    return PE_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2570,7 +2600,10 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
     int n_active = B;
     for (int k = 1; k <= k_max && n_active > 0; ++k) {
         const int nxt = 1 - cur;
-        if (p->prec == PE_MIXED && k >= 2) {
+        if (p->fine_kind == PE_FINE_WR) {
+            // the paper's fine solver: K0 WR iterations on every interval
+            PE_TRY(wr_sweep(p, B, p->Xk[cur], ldX, 2, p->Fbuf, -2, p->fine_alpha, p->fine_K0));
+        } else if (p->prec == PE_MIXED && k >= 2) {
             // F is affine: F(x^{k-1}) = F(x^{k-2}) + F_hom(x^{k-1} - x^{k-2}). The
             // change (left in E by the previous jump test, rows n = 1..N) is
             // propagated without source and added to the stored F values, so
@@ -2614,6 +2647,24 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
 }
 
 
+pe_status pe_set_fine_solver(pe_problem p, int kind, double alpha, int K0) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (kind == PE_FINE_STEP) {
+        p->fine_kind = PE_FINE_STEP;
+        return PE_OK;
+    }
+    if (kind != PE_FINE_WR) return fail(PE_ERR_ARG, "unknown fine solver");
+    if (p->prec != PE_FP64) return fail(PE_ERR_ARG, "the waveform-relaxation fine solver needs a PE_FP64 handle");
+    if (!(alpha > 0.0 && alpha < 1.0)) return fail(PE_ERR_ARG, "need 0 < alpha < 1");
+    if (K0 < 1) return fail(PE_ERR_ARG, "need K0 >= 1");
+    if (p->P > 128) return fail(PE_ERR_ARG, "waveform relaxation supports P <= 128");
+    p->fine_kind = PE_FINE_WR;
+    p->fine_alpha = alpha;
+    p->fine_K0 = K0;
+    return PE_OK;
+}
+
 pe_status pe_fine_wr(pe_problem p, int B, const double* Xin, double alpha, int K0, double* Fout) {
     g_err.clear();
     PE_TRY(check_handle(p));
@@ -2630,21 +2681,7 @@ pe_status pe_fine_wr(pe_problem p, int B, const double* Xin, double alpha, int K
         PE_HIP(hipStreamSynchronize(p->st));
         return PE_OK;
     }
-    PE_TRY(wr_build_ops(p, B, alpha));
-    // columns per chunk: the workspace holds about 12 P + 8 levels of a column
-    const double col_bytes = 8.0 * ((3.0 * p->P + 1.0 + 2.0 * (p->P / 2 + 1) * 2.0) * p->d1p +
-                                    (4.0 * p->P + 1.0) * std::max(p->d2p, 1));
-    const int max_cols = std::max(1, (int)std::min<double>(NB, (8.0 * (1 << 30)) / col_bytes));
-    const int NBc = std::min(NB, max_cols);
-    PE_TRY(wr_workspace(p, NBc));
-    for (int c0 = 0; c0 < NB; c0 += NBc) {
-        const int nc = std::min(NBc, NB - c0);
-        PE_TRY(wr_tables(p, nc));
-        PE_HIP(wr_io(1, Xin, ldXb, nullptr, N, p->d1, p->d2, p->d1p, p->d2p, c0, nc, p->P, p->wrUl, p->wrWl, p->st));
-        for (int j = 0; j < K0; ++j)
-            PE_TRY(graph_run(p, {20, c0, nc, B}, [&]() -> pe_status { return wr_iteration(p, c0, nc, alpha); }));
-        PE_HIP(wr_io(-1, nullptr, 0, Fout, N, p->d1, p->d2, p->d1p, p->d2p, c0, nc, p->P, p->wrUl, p->wrWl, p->st));
-    }
+    PE_TRY(wr_sweep(p, B, Xin, ldXb, 1, Fout, -1, alpha, K0));
     PE_HIP(hipStreamSynchronize(p->st));
     PE_TRY(prof_collect(p));
     return PE_OK;

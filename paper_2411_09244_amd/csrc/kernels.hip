@@ -676,45 +676,49 @@ hipError_t wr_axmy(double* y, const double* a, const double* b, double alpha, lo
 }
 
 // Start of a WR run on columns c0 .. c0+NBc-1 (column c = b N + n, start
-// state row n of sample b in X, row stride D, sample stride ldXb): level 0
-// of U and W, the initial waveform w_s = w_0 (s = 1..P) and u_P = u_0.
-// dir < 0 writes the end states (level P) to Fout (B x N x D) instead.
+// state row n of sample b in X, sample stride ldXb): level 0 of U and W, the
+// initial waveform w_s = w_0 (s = 1..P) and u_P = u_0. dir < 0 writes the end
+// states (level P) to Fout (row c0 + c) instead. |dir| = 1: rows in the
+// caller's layout [u (d1) | w (d2)]; |dir| = 2: padded rows [u (d1p) | w (d2p)].
 __global__ void k_wr_io(int dir, const double* __restrict__ X, long ldXb, double* __restrict__ Fout, int N,
                         int d1, int d2, int d1p, int d2p, int c0, int NBc, int P, double* __restrict__ Ul,
                         double* __restrict__ Wl) {
-    const int D = d1 + d2;
+    const bool padded = dir == 2 || dir == -2;
+    const int D = d1 + d2, Dp = d1p + d2p;
+    const int ld = padded ? Dp : D, wo = padded ? d1p : d1;  // row length, offset of the w part
+    const int du = padded ? d1p : d1, dw = padded ? d2p : d2;  // stored lengths
     const long E1 = (long)NBc * d1p, E2 = (long)NBc * d2p;
     if (dir > 0) {
-        const int Dp = d1p + d2p;
         for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)NBc * Dp;
              t += (long)gridDim.x * blockDim.x) {
             const int c = (int)(t / Dp), s = (int)(t % Dp);
             const int cg = c0 + c, b = cg / N, n = cg % N;
-            const double* x = X + (long)b * ldXb + (long)n * D;
+            const double* x = X + (long)b * ldXb + (long)n * ld;
             if (s < d1p) {
-                const double v = s < d1 ? x[s] : 0.0;
+                const double v = s < du ? x[s] : 0.0;
                 Ul[(long)c * d1p + s] = v;
                 Ul[(long)P * E1 + (long)c * d1p + s] = v;
             } else {
                 const int j = s - d1p;
-                const double v = j < d2 ? x[d1 + j] : 0.0;
+                const double v = j < dw ? x[wo + j] : 0.0;
                 for (int l = 0; l <= P; ++l) Wl[(long)l * E2 + (long)c * d2p + j] = v;
             }
         }
     } else {
-        for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)NBc * D;
+        for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)NBc * ld;
              t += (long)gridDim.x * blockDim.x) {
-            const int c = (int)(t / D), s = (int)(t % D);
-            const double v = s < d1 ? Ul[(long)P * E1 + (long)c * d1p + s]
-                                    : Wl[(long)P * E2 + (long)c * d2p + (s - d1)];
-            Fout[(long)(c0 + c) * D + s] = v;
+            const int c = (int)(t / ld), s = (int)(t % ld);
+            const double v = s < wo ? (s < d1p ? Ul[(long)P * E1 + (long)c * d1p + s] : 0.0)
+                                    : Wl[(long)P * E2 + (long)c * d2p + (s - wo)];
+            Fout[(long)(c0 + c) * ld + s] = v;
         }
     }
 }
 
 hipError_t wr_io(int dir, const double* X, long ldXb, double* Fout, int N, int d1, int d2, int d1p, int d2p,
                  int c0, int NBc, int P, double* Ul, double* Wl, hipStream_t st) {
-    const long n = (long)NBc * (dir > 0 ? d1p + d2p : d1 + d2);
+    const bool padded = dir == 2 || dir == -2;
+    const long n = (long)NBc * (dir > 0 || padded ? d1p + d2p : d1 + d2);
     hipLaunchKernelGGL(k_wr_io, grid1(n), dim3(256), 0, st, dir, X, ldXb, Fout, N, d1, d2, d1p, d2p, c0, NBc, P,
                        Ul, Wl);
     return hipGetLastError();

@@ -183,3 +183,41 @@ def test_wr_full_size_sampled():
         print(f"c1 interval {n}: rel err vs oracle WR {err:.3e}")
         assert err < TOL
     pr.close()
+
+
+def test_parareal_with_wr_fine_solver():
+    # Algorithm 1 with the paper's fine solver: iterates against the oracle's
+    # parareal with F = K0 WR iterations, the limit at k = N against the
+    # sequential WR composition, then back to the scheme's F
+    pe = _pe()
+    p = build_problem("t1")
+    bl, src = S.Blocks.from_problem(p), S.Source.from_problem(p)
+    x0 = p["x0"][0]
+    pr = pe.problem_from(p, "fp64", device="cuda:0")
+    pr.set_fine_solver("wr", 0.05, 3)
+    X, iters, hist, st = pr.solve(p["x0"], tol=0.0, k_max=3)
+    ref = WR.parareal_wr(bl, src, x0, 0.0, 0.05, 3, k_max=3)
+    e3 = S.rel_l2_M(bl, X[0].cpu().numpy(), ref["X"][3])
+    ej = np.max(np.abs(hist[0, :3] - ref["J"][:3]) / np.abs(ref["J"][:3]))
+    X, iters, hist, st = pr.solve(p["x0"], tol=0.0, k_max=bl.N)
+    eN = S.rel_l2_M(bl, X[0].cpu().numpy(), WR.wr_composition(bl, src, x0, 0.05, 3))
+    pr.set_fine_solver("step")
+    X, iters, hist, st = pr.solve(p["x0"], tol=0.0, k_max=3)
+    es = S.rel_l2_M(bl, X[0].cpu().numpy(), S.parareal(bl, src, x0, 0.0, k_max=3)["X"][3])
+    print(f"parareal with WR: k=3 {e3:.3e} (jumps {ej:.3e}), k=N vs WR composition {eN:.3e}; scheme F {es:.3e}")
+    assert e3 < TOL and ej < 1e-8 and eN < TOL and es < 1e-10
+    pr.close()
+
+
+def test_set_fine_solver_errors():
+    pe = _pe()
+    p = build_problem("t1")
+    pm = pe.problem_from(p, "mixed", device="cuda:0")
+    with pytest.raises(Exception):
+        pm.set_fine_solver("wr", 0.05, 2)          # FP64 handles only
+    pm.close()
+    pr = pe.problem_from(p, "fp64", device="cuda:0")
+    for alpha, K0 in ((0.0, 2), (1.5, 2), (0.1, 0)):
+        with pytest.raises(Exception):
+            pr.set_fine_solver("wr", alpha, K0)
+    pr.close()

@@ -18,7 +18,7 @@ import time
 import numpy as np
 import scipy.linalg as sla
 
-from . import media
+from . import media, nlmc
 from .cem import CoarseGrid, cem_basis, local_spectral, split_spaces
 from .fem import FineGrid
 
@@ -40,11 +40,21 @@ CONFIGS = {
     "c4": dict(n=400, n_c=40, layers=2, J1=2, J2=3, medium="channels", n_h=10, n_v=10,
                contrast=1e6, seed=4, source="fourier8_interval", u0="zero", N=256, P=128,
                T=None, B=32, src_seed=4),
+    # the 200x200 medium with the NLMC split of Section 3.2 (fracture / matrix functions)
+    "c1n": dict(n=200, n_c=20, layers=2, J1=2, J2=3, medium="lognormal", sigma=1.0,
+                corr=0.05, n_h=5, n_v=5, contrast=1e6, incl=0.2, seed=1, split="nlmc_fm",
+                source="sine_exp", u0="zero", N=64, P=64, T=None, B=1),
     # small workloads for tests
     "t0": dict(n=20, n_c=2, layers=1, J1=2, J2=3, medium="channels", n_h=1, n_v=1,
                contrast=1e4, seed=10, source="one", u0="zero", N=6, P=4, T=None, B=1),
     "t1": dict(n=40, n_c=4, layers=2, J1=2, J2=3, medium="channels", n_h=2, n_v=2,
                contrast=1e6, seed=11, source="sine_exp", u0="sine2", N=8, P=8, T=None, B=1),
+    "t1n": dict(n=40, n_c=4, layers=2, J1=2, J2=3, medium="channels", n_h=2, n_v=2,
+                contrast=1e6, seed=11, split="nlmc_fm", source="sine_exp", u0="sine2", N=8, P=8,
+                T=None, B=1),
+    "t1p": dict(n=40, n_c=4, layers=2, J1=2, J2=3, medium="channels", n_h=2, n_v=2,
+                contrast=1e6, seed=11, split="nlmc", source="sine_exp", u0="sine2", N=8, P=8,
+                T=None, B=1),
     "t2": dict(n=60, n_c=6, layers=2, J1=2, J2=3, medium="lognormal", sigma=1.0,
                corr=0.05, n_h=2, n_v=2, contrast=1e6, incl=0.2, seed=12,
                source="fourier8_interval", u0="zero", N=12, P=8, T=None, B=3, src_seed=12),
@@ -65,11 +75,24 @@ def make_medium(cfg):
 
 
 def build_spaces(cfg, kappa=None, checks=False):
-    """Fine grid, coarse grid, and (Psi1, Psi2) for a configuration."""
+    """Fine grid, coarse grid, and (Psi1, Psi2) for a configuration. The split
+    is CEM-GMsFEM's eigen-index split (Section 3.1) by default; cfg["split"]
+    = "nlmc" / "nlmc_fm" builds the NLMC spaces of Section 3.2 (fractures =
+    cells with kappa >= cfg["frac_threshold"], default sqrt(contrast))."""
     if kappa is None:
         kappa = make_medium(cfg)
     fine = FineGrid(kappa)
     cg = CoarseGrid(fine, cfg["n_c"])
+    split = cfg.get("split", "cem")
+    if split in ("nlmc", "nlmc_fm"):
+        thr = cfg.get("frac_threshold") or float(np.sqrt(cfg["contrast"]))
+        regions = nlmc.fracture_regions(cg, thr)
+        res = nlmc.nlmc_basis(cg, regions, cfg["layers"], return_checks=checks)
+        psis, cres = res if checks else (res, None)
+        Psi1, Psi2 = nlmc.nlmc_split(cg, psis, "paper" if split == "nlmc" else "fm")
+        info = dict(constraint_residual=(max(cres) if cres else None),
+                    fractures=int(sum(len(r[1]) for r in regions)))
+        return fine, cg, Psi1, Psi2, info
     J = cfg["J1"] + cfg["J2"]
     lam, psi, spsi = local_spectral(cg, J)
     res = cem_basis(cg, J, cfg["layers"], spsi, return_checks=checks)
@@ -198,7 +221,7 @@ def cfg_key(cfg):
 # fields that fix the medium and the multiscale spaces (workloads that differ
 # only in source, initial state or time grid share them)
 _SPACE_FIELDS = ("n", "n_c", "layers", "J1", "J2", "medium", "sigma", "corr", "n_h", "n_v", "contrast",
-                 "incl", "seed")
+                 "incl", "seed", "split", "frac_threshold")
 _last_spaces = {}
 
 

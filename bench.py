@@ -351,8 +351,9 @@ def large_main(args, torch, pe):
 
 
 WR_WORKLOAD = ("fine propagator by waveform relaxation with the alpha-circulant diagonalisation in time "
-               "(FP64), applied to the 64 interval start states of the first parareal iterate of the 200x200 "
-               "workload (d1=800, d2=1200, N=64 intervals x P=64 fine steps, f=sin(pi x)sin(pi y)e^-t)")
+               "(FP64), applied to the interval start states of the first parareal iterate of the 200x200 "
+               "workload ({split}, d1={d1}, d2={d2}, N={N} intervals x P={P} fine steps, "
+               "f=sin(pi x)sin(pi y)e^-t)")
 
 
 def wr_main(args, torch, pe):
@@ -365,9 +366,11 @@ def wr_main(args, torch, pe):
     import oracle.wr as WR
     import oracle.scheme as S
     from problem import build_problem
-    p = build_problem("c1")
+    p = build_problem(args.config)
     d1, d2, N, P = p["d1"], p["d2"], p["N"], p["P"]
     D = d1 + d2
+    split = {"nlmc_fm": "NLMC fracture/matrix split", "nlmc": "NLMC split as printed"}.get(
+        p["cfg"].get("split", "cem"), "CEM-GMsFEM split")
     pr = pe.problem_from(p, "fp64")
     x0 = torch.as_tensor(p["x0"], dtype=torch.float64, device="cuda")
     X0, _, _, _ = pr.solve(x0, tol=0.0, k_max=0)          # coarse sweep: x_n^0
@@ -426,7 +429,8 @@ def wr_main(args, torch, pe):
            "unit": "sweeps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": WR_WORKLOAD, "name": "wr", "d1": d1, "d2": d2, "N": N, "P": P, "alpha": alpha,
+           "config": {"workload": WR_WORKLOAD.format(split=split, d1=d1, d2=d2, N=N, P=P),
+                      "name": "wr-" + args.config, "d1": d1, "d2": d2, "N": N, "P": P, "alpha": alpha,
                       "K0": K0, "rel_err_vs_exact_F": float("%.3e" % err)},
            "roofline": dict(kernel=names[dom], bound="mfma", achieved=round(flops[dom] / avg / 1e12, 3),
                             peak=PEAK_FP64_MFMA, unit="TFLOP/s",
@@ -595,7 +599,11 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "name": args.config, "d1": d1, "d2": d2, "N": N, "P": P,
+        "config": {"workload": WORKLOAD if args.config == "c1" else
+                   ("200x200 workload of the default line with the NLMC fracture/matrix split of Section 3.2 "
+                    f"(d1={d1} fracture functions, d2={d2} matrix functions), N={N} x P={P}, "
+                    f"dt={p['dt']:.3e}, rel tol 1e-7" if args.config == "c1n" else args.config),
+                   "name": args.config, "d1": d1, "d2": d2, "N": N, "P": P,
                    "samples": 1, "precision": "FP32 MFMA fine-step products in mass-whitened "
                    "coordinates; FP64 anchors, state, coarse sweep, jump norms and factorisations",
                    "iterations": mixed["iters"], "setup_s": round(mixed["setup"], 3)},

@@ -71,7 +71,7 @@ def test_coarse_propagator(name):
             assert _colwise_rel(bl, Y[b], ref) < 1e-12, (name, prec, b)
 
 
-@pytest.mark.parametrize("name", ["t0", "t1", "c0", "t2", "ragged"])
+@pytest.mark.parametrize("name", ["t0", "t1", "c0", "t2", "ragged", "t1n", "t1p"])
 @pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX)])
 def test_fine_propagator(name, prec, tol):
     pe = _pe()
@@ -92,7 +92,7 @@ def _oracle_parareal(p, k_max, tol=0.0, rel=False):
     return bl, [S.parareal(bl, src, p["x0"][b], tol, k_max=k_max, b=b, rel=rel) for b in range(p["B"])]
 
 
-@pytest.mark.parametrize("name", ["t0", "t1", "c0", "t2", "ragged"])
+@pytest.mark.parametrize("name", ["t0", "t1", "c0", "t2", "ragged", "t1n", "t1p"])
 @pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX)])
 def test_solve_equal_iteration(name, prec, tol):
     """GPU iterate k vs oracle iterate k (fixed k, no early stop)."""
@@ -113,7 +113,7 @@ def test_solve_equal_iteration(name, prec, tol):
         assert np.abs(hist[b] - r["J"]).max() <= tol * scale, (hist[b], r["J"])
 
 
-@pytest.mark.parametrize("name", ["t1", "c0"])
+@pytest.mark.parametrize("name", ["t1", "c0", "t1n"])
 def test_solve_exact_after_n_iterations(name):
     """k = N reproduces the sequential fine solution (finite termination)."""
     pe = _pe()

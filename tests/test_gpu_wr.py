@@ -221,3 +221,20 @@ def test_set_fine_solver_errors():
         with pytest.raises(Exception):
             pr.set_fine_solver("wr", alpha, K0)
     pr.close()
+
+
+def test_wr_converges_fast_on_nlmc_spaces():
+    # with the NLMC fracture/matrix split gamma^2 = 0.23 (Section 3.2): WR
+    # reaches the sequential F to rounding within 25 iterations, and its error
+    # after 1..6 iterations contracts at about gamma^2 or faster
+    pe = _pe()
+    p, bl, src, B, X = _setup("t1n", seed=9)
+    pr = pe.problem_from(p, "fp64", device="cuda:0")
+    exact = pr.fine(torch.tensor(X, device="cuda:0")).cpu().numpy()
+    errs = [_rel(pr.fine_wr(X, 0.05, k).cpu().numpy(), exact) for k in range(1, 7)]
+    final = _rel(pr.fine_wr(X, 0.05, 25).cpu().numpy(), exact)
+    print("t1n WR errors", " ".join(f"{e:.2e}" for e in errs), f"K0=25: {final:.2e}")
+    assert final < TOL
+    g2 = WR.gamma_sq(bl)
+    assert errs[-1] <= errs[0] * (1.5 * g2) ** 5
+    pr.close()

@@ -620,6 +620,14 @@ def main():
             a64 = flops_per_launch / ((ms64 / n64) * 1e-3) / 1e12
             out["fp64"]["roofline"] = dict(bound="mfma", achieved=round(a64, 3), peak=PEAK_FP64_MFMA,
                                            unit="TFLOP/s", frac=round(a64 / PEAK_FP64_MFMA, 5))
+    # peaks measured on this part (matrix-core loops, device copy) beside the
+    # datasheet values the roofline fractions use
+    pk = pe.probe_peaks()
+    out["measured_peaks"] = {k: round(v, 2) for k, v in pk.items()}
+    roofline["frac_of_measured_peak"] = round(achieved / pk["fp32_mfma_tflops"], 5)
+    if "hbm_achieved_TBps" in roofline:
+        roofline["hbm_frac_of_measured_copy"] = round(roofline["hbm_achieved_TBps"] / pk["hbm_copy_tbps"], 5)
+    log(f"measured peaks: {pk}")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args, torch, pe, build_problem, ["mixed"] if args.no_fp64 else ["mixed", "fp64"])
     if not args.no_cpu_baseline:

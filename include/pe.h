@@ -256,6 +256,18 @@ enum { PE_FINE_STEP = 0, PE_FINE_WR = 1 };
 pe_status pe_set_fine_solver(pe_problem p, int kind, double alpha, int K0);
 
 /*
+ * pe_probe_peaks - measured peaks of the part the library runs on, for the
+ * rooflines the benchmark reports: out3[0] FP32 and out3[1] FP64 matrix-core
+ * throughput (TFLOP/s; 2048 work-groups of 4 waves, each wave 16 independent
+ * chains of 16x16x4 products with register operands, 2000 rounds) and
+ * out3[2] HBM bandwidth (TB/s; read + write bytes of a 512 MiB device copy
+ * with 16-byte vectors). Best of three timed runs after a warm-up, HIP events
+ * on hip_stream (NULL: the default stream). Allocates ~1 GiB of device memory
+ * for the call. Errors: PE_ERR_ARG, PE_ERR_NOMEM, PE_ERR_HIP.
+ */
+pe_status pe_probe_peaks(void* hip_stream, double* out3);
+
+/*
  * Batches of different problems (different d1, d2, N, sources and sample
  * counts; same precision and step ratio P), solved together: every
  * product of a fine step runs as one grouped MFMA launch over all problems'

@@ -262,6 +262,16 @@ class Batch:
             pass
 
 
+def probe_peaks(device="cuda"):
+    """Measured peaks of the GPU: {"fp32_mfma_tflops", "fp64_mfma_tflops",
+    "hbm_copy_tbps"} (pe_probe_peaks on the device's current stream)."""
+    lib = L.load()
+    with torch.cuda.device(torch.device(device)):
+        out = (ctypes.c_double * 3)()
+        L.check(lib.pe_probe_peaks(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), out))
+    return {"fp32_mfma_tflops": out[0], "fp64_mfma_tflops": out[1], "hbm_copy_tbps": out[2]}
+
+
 def problem_from(prob, precision="fp64", device="cuda"):
     """Problem + source from a workload dict (blocks, G, H, time_mode)."""
     blocks = {k: prob[k] for k in ("M11", "M12", "M22", "A11", "A12", "A22")}

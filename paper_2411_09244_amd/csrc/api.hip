@@ -488,6 +488,8 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
     return PE_OK;
 }
 
+constexpr int PROBE_ACC_PER_ROUND = 16;  // independent products per wave per round (k_probe_mfma*)
+
 enum {
     SITE_NONE = -1,
     SITE_FINE_STEP = 7,
@@ -2646,6 +2648,52 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
     return n_active > 0 ? PE_WARN_NOT_CONVERGED : PE_OK;
 }
 
+
+pe_status pe_probe_peaks(void* hip_stream, double* out3) {
+    g_err.clear();
+    if (!out3) return fail(PE_ERR_ARG, "bad arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int blocks = 2048, iters = 2000;
+    const long ncopy = (512L << 20) / 16;  // 512 MiB of float4
+    void *o = nullptr, *src = nullptr, *dst = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](pe_status s) {
+        if (st) (void)hipStreamSynchronize(st); else (void)hipDeviceSynchronize();
+        for (void* v : {o, src, dst})
+            if (v) (void)hipFree(v);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return s;
+    };
+    if (hipMalloc(&o, sizeof(double) * blocks * 256) != hipSuccess || hipMalloc(&src, ncopy * 16) != hipSuccess ||
+        hipMalloc(&dst, ncopy * 16) != hipSuccess) {
+        (void)hipGetLastError();
+        return done(fail(PE_ERR_NOMEM, "peak probe buffers"));
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+        hipMemsetAsync(src, 0, ncopy * 16, st) != hipSuccess)
+        return done(fail(PE_ERR_HIP, "peak probe set-up"));
+    const double mfma_flops = 2.0 * 16 * 16 * 4;  // one 16x16x4 product
+    for (int kind = 0; kind < 3; ++kind) {
+        double best = 0.0;
+        for (int rep = 0; rep < 4; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) return done(fail(PE_ERR_HIP, "event"));
+            hipError_t e = kind < 2 ? probe_launch(kind, blocks, iters, o, nullptr, 0, st)
+                                    : probe_launch(2, 4096, 0, dst, src, ncopy, st);
+            if (e != hipSuccess) return done(fail(PE_ERR_HIP, std::string("peak probe: ") + hipGetErrorString(e)));
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return done(fail(PE_ERR_HIP, "event"));
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep == 0 || ms <= 0.f) continue;  // first run warms up
+            const double work = kind < 2 ? (double)blocks * 4 * iters * PROBE_ACC_PER_ROUND * mfma_flops
+                                         : 2.0 * ncopy * 16;
+            best = std::max(best, work / (ms * 1e-3) / 1e12);
+        }
+        out3[kind] = best;
+    }
+    return done(PE_OK);
+}
 
 pe_status pe_set_fine_solver(pe_problem p, int kind, double alpha, int K0) {
     g_err.clear();

@@ -46,4 +46,7 @@ hipError_t wr_cat(const double* L, double* out, int P, long NB, int d, int mode,
 hipError_t wr_axmy(double* y, const double* a, const double* b, double alpha, long n, hipStream_t st);
 hipError_t wr_io(int dir, const double* X, long ldXb, double* Fout, int N, int d1, int d2, int d1p, int d2p,
                  int c0, int NBc, int P, double* Ul, double* Wl, hipStream_t st);
+// peak probes: kind 0 FP32 MFMA, 1 FP64 MFMA (blocks x 256 threads, iters
+// rounds of 16 independent 16x16x4 products per wave), 2 copy of n float4
+hipError_t probe_launch(int kind, int blocks, int iters, void* out, const void* src, long n, hipStream_t st);
 }  // namespace pe

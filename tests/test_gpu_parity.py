@@ -258,3 +258,14 @@ def test_persistent_fine_sweep(prec, bar, monkeypatch):
         e = _colwise_rel(bl, Y[0].cpu().numpy(), ref)
         print(f"{name} {prec}: persistent F vs oracle {e:.3e}")
         assert e <= bar
+
+
+def test_probe_peaks_sane():
+    # measured matrix-core and HBM peaks: positive and not above the
+    # datasheet values (157.3 / 78.6 TFLOP/s, 8 TB/s) by more than 10 %
+    pe = _pe()
+    pk = pe.probe_peaks()
+    print(pk)
+    assert 0 < pk["fp32_mfma_tflops"] < 1.1 * 157.3
+    assert 0 < pk["fp64_mfma_tflops"] < 1.1 * 78.6
+    assert 0 < pk["hbm_copy_tbps"] < 1.1 * 8.0

@@ -212,3 +212,101 @@ def rel_l2_M(bl, X, Xref):
     num = sum(m_norm(bl, X[n] - Xref[n]) ** 2 for n in range(X.shape[0]))
     den = sum(m_norm(bl, Xref[n]) ** 2 for n in range(Xref.shape[0]))
     return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
+
+
+# ---------------------------------------------------------------------------
+# History carried across intervals (the alternative reading of the two-step
+# scheme at interval starts). The scheme (2.5)-(2.6) couples the two spaces
+# through the difference quotients (u_n - u_{n-1})/h and (w_n - w_{n-1})/h of
+# the previous step. Instead of restarting that history at every interval
+# start, the state carries it: y = [x; delta] with delta = x - x_prev the
+# change over the last step of size dt_fine (the rate times dt_fine). A fine
+# step starts from x_prev = x - delta; the coarse step of size Delta t = P
+# dt_fine uses the same rate, x_prev = x - P delta, and hands back the rate of
+# its own step, delta' = (x' - x)/P. The fine composition of this propagator
+# is one uninterrupted run of N*P steps of size dt_fine.
+# ---------------------------------------------------------------------------
+def fine_propagator_carry(bl, src, y, n, b=0):
+    """F with carried history: P steps of size dt_fine over interval n from
+    y = [x; delta] (shape (2D,)). Returns [x_P; x_P - x_{P-1}]."""
+    d1, D = bl.d1, bl.D
+    u, w = y[:d1].copy(), y[d1:D].copy()
+    u_prev, w_prev = u - y[D:D + d1], w - y[D + d1:]
+    for p in range(bl.P):
+        u_new, w_new = step(bl, bl.dt_fine, u, w, u_prev, w_prev, src.at_fine(b, n, p))
+        u_prev, w_prev, u, w = u, w, u_new, w_new
+    return np.concatenate([u, w, u - u_prev, w - w_prev])
+
+
+def coarse_propagator_carry(bl, src, y, n, b=0):
+    """G with carried history: one step of size dt over interval n whose
+    previous state is x - P delta (the carried rate over one coarse step);
+    returns [x'; (x' - x)/P]."""
+    d1, D, P = bl.d1, bl.D, bl.P
+    u, w = y[:d1], y[d1:D]
+    u_new, w_new = step(bl, bl.dt, u, w, u - P * y[D:D + d1], w - P * y[D + d1:], src.at_coarse(b, n))
+    return np.concatenate([u_new, w_new, (u_new - u) / P, (w_new - w) / P])
+
+
+def fine_composition_carry(bl, src, x0, b=0):
+    """Y*_{n+1} = F(Y*_n) with carried history from Y*_0 = [x0; 0] (no
+    history before t = 0). Returns (N+1, 2D)."""
+    Y = np.zeros((bl.N + 1, 2 * bl.D))
+    Y[0, :bl.D] = x0
+    for n in range(bl.N):
+        Y[n + 1] = fine_propagator_carry(bl, src, Y[n], n, b)
+    return Y
+
+
+def sequential_run(bl, src, x0, b=0):
+    """N*P steps of the scheme of size dt_fine without any restart (x_{-1} =
+    x_0), the history always taken from the previous step. Returns the states
+    at the coarse boundaries with their last change, (N+1, 2D)."""
+    d1, D, P = bl.d1, bl.D, bl.P
+    u, w = np.array(x0[:d1], dtype=np.float64), np.array(x0[d1:], dtype=np.float64)
+    u_prev, w_prev = u.copy(), w.copy()
+    out = np.zeros((bl.N + 1, 2 * D))
+    out[0, :D] = x0
+    for n in range(bl.N):
+        for p in range(P):
+            u_new, w_new = step(bl, bl.dt_fine, u, w, u_prev, w_prev, src.at_fine(b, n, p))
+            u_prev, w_prev, u, w = u, w, u_new, w_new
+        out[n + 1] = np.concatenate([u, w, u - u_prev, w - w_prev])
+    return out
+
+
+def parareal_carry(bl, src, x0, tol, k_max=None, b=0, rel=False):
+    """Parareal (update (2.7), stop test (2.8)) on the history-carrying states
+    y = [x; delta]; y_0^k = [x0; 0]. The stopping test measures the change of
+    x only, |x_n^k - x_n^{k-1}|_M, as (2.8) does. Returns the iterates
+    (each (N+1, 2D)), the jumps and K, as parareal()."""
+    N, D = bl.N, bl.D
+    k_max = N if k_max is None else min(int(k_max), N)
+    Y = np.zeros((N + 1, 2 * D))
+    Y[0, :D] = x0
+    g_old = np.zeros((N, 2 * D))
+    for n in range(N):
+        g_old[n] = coarse_propagator_carry(bl, src, Y[n], n, b)
+        Y[n + 1] = g_old[n]
+    iterates = [Y.copy()]
+    jumps = []
+    thr = tol
+    if rel:
+        thr = tol * max(m_norm(bl, Y[n, :D]) for n in range(N + 1))
+    k = 0
+    while k < k_max:
+        k += 1
+        f = np.stack([fine_propagator_carry(bl, src, Y[n], n, b) for n in range(N)])
+        Yn = np.zeros_like(Y)
+        Yn[0] = Y[0]
+        for n in range(N):
+            g = coarse_propagator_carry(bl, src, Yn[n], n, b)
+            Yn[n + 1] = g + f[n] - g_old[n]
+            g_old[n] = g
+        J = max(m_norm(bl, Yn[n, :D] - Y[n, :D]) for n in range(1, N + 1))
+        Y = Yn
+        iterates.append(Y.copy())
+        jumps.append(J)
+        if J <= thr:
+            break
+    return dict(X=iterates, J=np.array(jumps), K=k, threshold=thr)

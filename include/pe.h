@@ -256,6 +256,36 @@ enum { PE_FINE_STEP = 0, PE_FINE_WR = 1 };
 pe_status pe_set_fine_solver(pe_problem p, int kind, double alpha, int K0);
 
 /*
+ * pe_set_history - what the two-step scheme (2.5)-(2.6) uses as the previous
+ * level at the start of each propagator call (the paper passes only the
+ * state between the intervals of Algorithm 1 and leaves this open):
+ *   PE_HIST_RESTART (default): a fresh history, u_{-1} = u_0, w_{-1} = w_0 at
+ *     every interval start (the coupling differences vanish on the first
+ *     step); states are x = [u; w] of D entries.
+ *   PE_HIST_CARRY: the history travels with the state. Every state of the
+ *     iteration is [x; delta] (2D entries), delta = x - x_prev the change
+ *     over the last fine step of size dt_fine. F starts its first step from
+ *     x_prev = x - delta and returns [x_P; x_P - x_{P-1}]; the coarse step G
+ *     stays the one-step propagator with a fresh history (it reads x only)
+ *     and returns [x'; (x' - x)/P], its change at the fine-step rate. The
+ *     parareal limit is then one uninterrupted run of N*P fine steps from x0
+ *     (delta = 0 at t = 0). The carried change couples the intervals through
+ *     a slowly decaying mode of the two-step scheme that G cannot represent:
+ *     parareal contracts more slowly than with PE_HIST_RESTART (finite
+ *     termination at k = N still holds).
+ * With PE_HIST_CARRY: pe_solve takes x0 as B x D and writes X as
+ * B x (N+1) x 2D ([x_n; delta_n] per row; its stopping test measures the
+ * change of x only, as eq. (2.8)); pe_fine_propagate and pe_coarse_propagate
+ * take and return B x N x 2D. pe_adjoint, pe_tracking, pe_fine_wr, the
+ * waveform-relaxation fine solver and batches return PE_ERR_STATE.
+ * Changing the mode releases the iteration workspace (regrown at the next
+ * call). Errors: PE_ERR_ARG (unknown mode), PE_ERR_STATE (waveform-relaxation
+ * fine solver selected).
+ */
+enum { PE_HIST_RESTART = 0, PE_HIST_CARRY = 1 };
+pe_status pe_set_history(pe_problem p, int mode);
+
+/*
  * pe_probe_peaks - measured peaks of the part the library runs on, for the
  * rooflines the benchmark reports: out3[0] FP32 and out3[1] FP64 matrix-core
  * throughput (TFLOP/s; 2048 work-groups of 4 waves, each wave 16 independent

@@ -221,10 +221,12 @@ def rel_l2_M(bl, X, Xref):
 # the previous step. Instead of restarting that history at every interval
 # start, the state carries it: y = [x; delta] with delta = x - x_prev the
 # change over the last step of size dt_fine (the rate times dt_fine). A fine
-# step starts from x_prev = x - delta; the coarse step of size Delta t = P
-# dt_fine uses the same rate, x_prev = x - P delta, and hands back the rate of
-# its own step, delta' = (x' - x)/P. The fine composition of this propagator
-# is one uninterrupted run of N*P steps of size dt_fine.
+# step starts from x_prev = x - delta. The coarse step (one step of size
+# Delta t = P dt_fine, as in Algorithm 1) starts with a fresh history as
+# before and hands back the rate of its own step, delta' = (x' - x)/P. The
+# fine composition of this propagator is one uninterrupted run of N*P steps
+# of size dt_fine; the parareal limit depends on F only, so the choice of G
+# changes the convergence, not the limit.
 # ---------------------------------------------------------------------------
 def fine_propagator_carry(bl, src, y, n, b=0):
     """F with carried history: P steps of size dt_fine over interval n from
@@ -239,12 +241,12 @@ def fine_propagator_carry(bl, src, y, n, b=0):
 
 
 def coarse_propagator_carry(bl, src, y, n, b=0):
-    """G with carried history: one step of size dt over interval n whose
-    previous state is x - P delta (the carried rate over one coarse step);
-    returns [x'; (x' - x)/P]."""
+    """G on carried states: one step of size dt over interval n from x with a
+    fresh history (the carried change is not used); returns [x'; (x' - x)/P],
+    the change of one fine step at the coarse step's rate."""
     d1, D, P = bl.d1, bl.D, bl.P
     u, w = y[:d1], y[d1:D]
-    u_new, w_new = step(bl, bl.dt, u, w, u - P * y[D:D + d1], w - P * y[D + d1:], src.at_coarse(b, n))
+    u_new, w_new = step(bl, bl.dt, u, w, u, w, src.at_coarse(b, n))
     return np.concatenate([u_new, w_new, (u_new - u) / P, (w_new - w) / P])
 
 

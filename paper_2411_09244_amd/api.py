@@ -50,6 +50,7 @@ class Problem:
         self.lib.pe_problem_info(h, None, None, None, ctypes.byref(P))
         self.P = P.value
         self.B = None
+        self.carry = False
 
     def _order(self):
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
@@ -70,13 +71,27 @@ class Problem:
         self.T_len = self.N * self.P if mode == L.PE_T_FINE else self.N
         self._src_keep = (G, H)
 
+    @property
+    def S(self):
+        """Entries per state: D, or 2D ([x; delta]) with carried history."""
+        return 2 * self.D if self.carry else self.D
+
+    def set_history(self, mode):
+        """"restart" (fresh history at every interval start) or "carry" (the
+        state carries its change over the last fine step: states [x; delta]
+        of 2D entries in solve, fine and coarse)."""
+        m = {"restart": 0, "carry": 1}[mode]
+        L.check(self.lib.pe_set_history(self.handle, m))
+        self.carry = m == 1
+
     def solve(self, x0, tol, norm="abs", k_max=None, out=None):
-        """Parareal to the stopping test. Returns (X (B, N+1, D) tensor,
-        iters (B,) numpy, jump history (B, k_max) numpy, status)."""
+        """Parareal to the stopping test. Returns (X (B, N+1, S) tensor,
+        iters (B,) numpy, jump history (B, k_max) numpy, status); S = D, or
+        2D with carried history."""
         x0 = _dev(x0, self.device).reshape(-1, self.D)
         B = x0.shape[0]
         k_max = self.N if k_max is None else int(k_max)
-        X = out if out is not None else torch.empty((B, self.N + 1, self.D), dtype=torch.float64,
+        X = out if out is not None else torch.empty((B, self.N + 1, self.S), dtype=torch.float64,
                                                    device=self.device)
         iters = np.zeros(B, dtype=np.int32)
         hist = np.zeros((B, max(k_max, 1)), dtype=np.float64)
@@ -122,7 +137,7 @@ class Problem:
         return J
 
     def fine(self, Xin):
-        """F applied to Xin (B, N, D) -> (B, N, D)."""
+        """F applied to Xin (B, N, S) -> (B, N, S)."""
         Xin = _dev(Xin, self.device)
         B = Xin.shape[0]
         Y = torch.empty_like(Xin)
@@ -148,7 +163,7 @@ class Problem:
         return Y
 
     def coarse(self, Xin):
-        """G applied to Xin (B, N, D) -> (B, N, D)."""
+        """G applied to Xin (B, N, S) -> (B, N, S)."""
         Xin = _dev(Xin, self.device)
         B = Xin.shape[0]
         Y = torch.empty_like(Xin)

@@ -212,6 +212,17 @@ struct pe_problem_s {
     double fine_alpha = 0.0;
     int fine_K0 = 0;
 
+    // history carried across intervals (pe_set_history): the states of the
+    // iteration are [x | delta] (delta = change over the last fine step), of
+    // stride Sx = 2Dp (Sx = Dp with the restarting history); the coarse step
+    // on them (2Dp x 2Dp) and its source term (B*N x 2Dp)
+    int hist = PE_HIST_RESTART, Sx = 0;
+    double* PhiA64 = nullptr;
+    float* PhiA32 = nullptr;
+    double* CSa = nullptr;
+    int csa_version = -1;
+    std::vector<void*> hist_ops, hist_src;
+
     std::vector<void*> op_allocs, ws_allocs;
 };
 
@@ -828,14 +839,14 @@ pe_status ensure_workspace(pe_problem p, int B) {
     PE_HIP(hipStreamSynchronize(p->st));
     graphs_clear(p);
     free_list(p->ws_allocs);
-    const size_t N = p->N, Dp = p->Dp, Bs = B;
+    const size_t N = p->N, Dp = p->Dp, Sx = p->Sx, Bs = B;
     auto& L = p->ws_allocs;
-    PE_TRY(dalloc_t(p, L, &p->Xk[0], Bs * (N + 1) * Dp));
-    PE_TRY(dalloc_t(p, L, &p->Xk[1], Bs * (N + 1) * Dp));
-    PE_TRY(dalloc_t(p, L, &p->Fbuf, Bs * N * Dp));
+    PE_TRY(dalloc_t(p, L, &p->Xk[0], Bs * (N + 1) * Sx));
+    PE_TRY(dalloc_t(p, L, &p->Xk[1], Bs * (N + 1) * Sx));
+    PE_TRY(dalloc_t(p, L, &p->Fbuf, Bs * N * Sx));
     for (int i = 0; i < 2; ++i) {
-        PE_TRY(dalloc_t(p, L, &p->Dl64[i], Bs * Dp));
-        PE_TRY(dalloc_t(p, L, &p->Dl32[i], Bs * Dp));
+        PE_TRY(dalloc_t(p, L, &p->Dl64[i], Bs * Sx));
+        PE_TRY(dalloc_t(p, L, &p->Dl32[i], Bs * Sx));
     }
     PE_TRY(dalloc_t(p, L, &p->Xa, Bs * N * Dp));
     PE_TRY(dalloc_t(p, L, &p->Ya, Bs * N * Dp));
@@ -846,9 +857,9 @@ pe_status ensure_workspace(pe_problem p, int B) {
         PE_TRY(dalloc_t(p, L, &p->dev32[0], Bs * N * 2 * Dp));
         PE_TRY(dalloc_t(p, L, &p->dev32[1], Bs * N * 2 * Dp));
     }
-    PE_TRY(dalloc_t(p, L, &p->E, Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->E, Bs * (N + 1) * Sx));
     PE_TRY(dalloc_t(p, L, &p->Yn, Bs * (N + 1) * Dp));
-    PE_TRY(dalloc_t(p, L, &p->io, Bs * (N + 1) * Dp));
+    PE_TRY(dalloc_t(p, L, &p->io, Bs * (N + 1) * Sx));
     PE_TRY(dalloc_t(p, L, &p->Jd, Bs * (N + 1)));
     PE_TRY(dalloc_t(p, L, &p->nrm, Bs * (N + 1)));
     PE_TRY(dalloc_t(p, L, &p->x0p, Bs * Dp));
@@ -928,19 +939,31 @@ void source_fields(pe_problem p, Epi& e, bool whitened = false) {
 pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double* Y, bool with_source = true,
                      int n_shift = 0, bool accumulate = false, const SrcView* sv = nullptr,
                      double* traj = nullptr) {
-    const int Dp = p->Dp, d1p = p->d1p, d2p = p->d2p;
+    const int Dp = p->Dp, d1p = p->d1p, d2p = p->d2p, Sx = p->Sx;
     const int rows = B * p->N;
     const bool mixed = p->prec == PE_MIXED;
-    if (!mixed) {
-        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->Xa, p->dev64[0], nullptr, B, p->N, Dp, p->st));
-    } else {
-        // anchors into whitened coordinates: Xa = Tin x (block diagonal)
-        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->R64, p->dev64[0], p->dev32[0], B, p->N, Dp, p->st));
-        GemmShape gt = shape(rows, Dp, p->R64, Dp, p->Tin64, Dp, 0, d1p);
+    const bool hist = p->hist == PE_HIST_CARRY;
+    // whitening x~ = Tin x (block diagonal) of rows x Dp: in -> out
+    auto whiten_rows = [&](const double* in, double* out, const double* T) -> pe_status {
+        GemmShape gt = shape(rows, Dp, in, Dp, T, Dp, 0, d1p);
         gt.s_split = d1p;
         gt.k0b = d1p;
         gt.k1b = Dp;
-        PE_TRY(gemm<double>(p, gt, store_epi(p->Xa, Dp), 0, PE_PROF_ANCHOR, SITE_ANCHOR));
+        return gemm<double>(p, gt, store_epi(out, Dp), 0, PE_PROF_ANCHOR, SITE_ANCHOR);
+    };
+    if (!mixed) {
+        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->Xa, p->dev64[0], nullptr, B, p->N, Dp, p->st, Sx));
+    } else {
+        // anchors into whitened coordinates: Xa = Tin x
+        PE_HIP(fine_init(Xsrc, ldXb, -n_shift, p->N, p->R64, p->dev64[0], p->dev32[0], B, p->N, Dp, p->st, Sx));
+        PE_TRY(whiten_rows(p->R64, p->Xa, p->Tin64));
+    }
+    if (hist) {
+        // the carried change over the last fine step starts the step state's
+        // history (whitened like the state in PE_MIXED)
+        PE_HIP(gather_rows(Xsrc, ldXb, Sx, Dp, -n_shift, p->N, p->R64, B, p->N, Dp, p->st));
+        if (mixed) PE_TRY(whiten_rows(p->R64, p->Ya, p->Tin64));
+        PE_HIP(hist_put(mixed ? p->Ya : p->R64, p->dev64[0], mixed ? p->dev32[0] : nullptr, rows, Dp, d1p, p->st));
     }
     // anchor term Z_h A x_a (FP64, once per sweep)
     PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->ZA64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
@@ -974,7 +997,7 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     gs.k0b = 0;
     gs.k1b = 2 * Dp;
     bool done = false;
-    if (p->persistent && rows <= 64) {
+    if (p->persistent && rows <= 64 && !hist) {
         int& grid = p->pers_grid[mixed ? 1 : 0];
         if (grid < 0) {
             grid = mixed ? fine_sweep_persistent_grid<float>() : fine_sweep_persistent_grid<double>();
@@ -1027,7 +1050,7 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         const int c = step & 1;
         GemmShape g = gs;
         g.A = mixed ? (const void*)p->dev32[c] : (const void*)p->dev64[c];
-        if (step == 0) {  // zero deviation: empty K ranges
+        if (step == 0 && !hist) {  // zero deviation: empty K ranges
             g.k0a = g.k1a = g.k0b = g.k1b = 0;
         }
         Epi e = eb;
@@ -1044,16 +1067,25 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     }
     const double* dfin = p->dev64[p->P & 1];
     if (!mixed) {
-        PE_HIP(fine_final(p->Xa, dfin, Y, rows, Dp, d1p, accumulate ? 1 : 0, p->st));
+        PE_HIP(fine_final(p->Xa, dfin, Y, rows, Dp, d1p, accumulate ? 1 : 0, p->st, Sx));
+        // the last step's change: the history handed on
+        if (hist) PE_HIP(hist_get(dfin, Y + Dp, Sx, rows, Dp, d1p, accumulate ? 1 : 0, p->st));
     } else {
         // back to the caller's coordinates: Y (+)= Tout (Xa + dev)
+        auto unwhiten = [&](double* out) -> pe_status {
+            GemmShape gt = shape(rows, Dp, p->R64, Dp, p->Tout64, Dp, 0, d1p);
+            gt.s_split = d1p;
+            gt.k0b = d1p;
+            gt.k1b = Dp;
+            return gemm<double>(p, gt, store_epi(out, Sx, 1.0, accumulate ? out : nullptr, Sx, accumulate ? 1.0 : 0.0),
+                                0, PE_PROF_ANCHOR, SITE_ANCHOR);
+        };
         PE_HIP(fine_final(p->Xa, dfin, p->R64, rows, Dp, d1p, 0, p->st));
-        GemmShape gt = shape(rows, Dp, p->R64, Dp, p->Tout64, Dp, 0, d1p);
-        gt.s_split = d1p;
-        gt.k0b = d1p;
-        gt.k1b = Dp;
-        PE_TRY(gemm<double>(p, gt, store_epi(Y, Dp, 1.0, accumulate ? Y : nullptr, Dp, accumulate ? 1.0 : 0.0),
-                            0, PE_PROF_ANCHOR, SITE_ANCHOR));
+        PE_TRY(unwhiten(Y));
+        if (hist) {
+            PE_HIP(hist_get(dfin, p->R64, Dp, rows, Dp, d1p, 0, p->st));
+            PE_TRY(unwhiten(Y + Dp));
+        }
     }
     return PE_OK;
 }
@@ -1064,55 +1096,66 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
 // is x_{n+1}^k = F(x_n^{k-1}) + Phi_G (x_n^k - x_n^{k-1}): one product per
 // coarse step, on the iterate change (FP32 in PE_MIXED: its rounding then
 // scales with the change). The initial sweep is x_{n+1}^0 = Phi_G x_n^0 + c_n.
+// With carried history the states are [x | delta] (stride Sx = 2Dp), the step
+// matrix is [Phi_G; (Phi_G - I)/P] (2Dp x Dp, on x) and c_n = [Z_dt F; Z_dt F / P].
 pe_status coarse_sweep_initial(pe_problem p, int B, double* Xk) {
-    const int Dp = p->Dp, N = p->N;
-    const long ldX = (long)(N + 1) * Dp;
+    const int Sx = p->Sx, N = p->N;
+    const long ldX = (long)(N + 1) * Sx;
+    const bool hist = p->hist == PE_HIST_CARRY;
+    const double* cs = hist ? p->CSa : p->CS;
     for (int n = 0; n < N; ++n) {
         Epi e;
         e.mode = EPI_COARSE_INIT;
-        e.xout = Xk + (long)(n + 1) * Dp;
+        e.xout = Xk + (long)(n + 1) * Sx;
         e.ldxo = ldX;
-        e.cs = p->CS ? p->CS + (long)n * Dp : nullptr;
-        e.ldcs = (long)N * Dp;
-        PE_TRY(gemm<double>(p, shape(B, Dp, Xk + (long)n * Dp, ldX, p->PhiG64, Dp, 0, Dp), e, 0, PE_PROF_COARSE));
+        e.cs = cs ? cs + (long)n * Sx : nullptr;
+        e.ldcs = (long)N * Sx;
+        PE_TRY(gemm<double>(p, shape(B, Sx, Xk + (long)n * Sx, ldX, hist ? p->PhiA64 : p->PhiG64, p->Dp, 0, p->Dp),
+                            e, 0, PE_PROF_COARSE));
     }
     return PE_OK;
 }
 
 pe_status coarse_sweep_correct(pe_problem p, int B, double* Xk, const double* Xprev, const int* active) {
-    const int Dp = p->Dp, N = p->N;
-    const long ldX = (long)(N + 1) * Dp;
+    const int Sx = p->Sx, N = p->N;
+    const long ldX = (long)(N + 1) * Sx;
     const bool mixed = p->prec == PE_MIXED;
+    const bool hist = p->hist == PE_HIST_CARRY;
     int c = 0;
-    PE_HIP(zero_fill(mixed ? nullptr : p->Dl64[0], mixed ? p->Dl32[0] : nullptr, (long)B * Dp, p->st));
+    PE_HIP(zero_fill(mixed ? nullptr : p->Dl64[0], mixed ? p->Dl32[0] : nullptr, (long)B * Sx, p->st));
     for (int n = 0; n < N; ++n) {
         Epi e;
         e.mode = EPI_COARSE_DELTA;
-        e.xout = Xk + (long)(n + 1) * Dp;
+        e.xout = Xk + (long)(n + 1) * Sx;
         e.ldxo = ldX;
-        e.xprev = Xprev + (long)(n + 1) * Dp;
-        e.fbuf = p->Fbuf + (long)n * Dp;
-        e.ldfb = (long)N * Dp;
+        e.xprev = Xprev + (long)(n + 1) * Sx;
+        e.fbuf = p->Fbuf + (long)n * Sx;
+        e.ldfb = (long)N * Sx;
         e.dl64 = mixed ? nullptr : p->Dl64[1 - c];
         e.dl32 = mixed ? p->Dl32[1 - c] : nullptr;
-        e.ldl = Dp;
+        e.ldl = Sx;
         e.active = active;
+        const int Dp = p->Dp;
         if (mixed)
-            PE_TRY(gemm<float>(p, shape(B, Dp, p->Dl32[c], Dp, p->PhiG32, Dp, 0, Dp), e, 0, PE_PROF_COARSE));
+            PE_TRY(gemm<float>(p, shape(B, Sx, p->Dl32[c], Sx, hist ? p->PhiA32 : p->PhiG32, Dp, 0, Dp), e, 0,
+                               PE_PROF_COARSE));
         else
-            PE_TRY(gemm<double>(p, shape(B, Dp, p->Dl64[c], Dp, p->PhiG64, Dp, 0, Dp), e, 0, PE_PROF_COARSE));
+            PE_TRY(gemm<double>(p, shape(B, Sx, p->Dl64[c], Sx, hist ? p->PhiA64 : p->PhiG64, Dp, 0, Dp), e, 0,
+                                PE_PROF_COARSE));
         c = 1 - c;
     }
     return PE_OK;
 }
 
 // J_b = max_{j < nr} |Xk[b][n0+j] - Xp[b][n0+j]|_M  (Xp null: plain norms)
+// (states of stride Sx: E keeps the whole change, the norm is that of x,
+// eq. (2.8))
 pe_status jumps_launch(pe_problem p, int B, const double* Xk, const double* Xp, long ldXb, int n0, int nr) {
-    const int Dp = p->Dp;
-    PE_HIP(jump_diff(Xk, Xp, ldXb, n0, nr, B, Dp, p->E, p->st));
-    PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp), 0,
+    const int Dp = p->Dp, Sx = p->Sx;
+    PE_HIP(jump_diff(Xk, Xp, ldXb, n0, nr, B, Dp, p->E, p->st, Sx));
+    PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Sx, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp), 0,
                         PE_PROF_NORM, SITE_NORM));
-    PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, p->nrm, p->st));
+    PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, p->nrm, p->st, Sx));
     return PE_OK;
 }
 
@@ -1125,11 +1168,11 @@ pe_status jumps_read(pe_problem p, int B, double* Jhost) {
 
 pe_status jumps(pe_problem p, int B, const double* Xk, const double* Xp, long ldXb, int n0, int nr,
                 double* Jhost, double* norms_dev) {
-    const int Dp = p->Dp;
-    PE_HIP(jump_diff(Xk, Xp, ldXb, n0, nr, B, Dp, p->E, p->st));
-    PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Dp, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp), 0,
+    const int Dp = p->Dp, Sx = p->Sx;
+    PE_HIP(jump_diff(Xk, Xp, ldXb, n0, nr, B, Dp, p->E, p->st, Sx));
+    PE_TRY(gemm<double>(p, shape(B * nr, Dp, p->E, Sx, p->M64, Dp, 0, Dp), store_epi(p->Yn, Dp), 0,
                         PE_PROF_NORM, SITE_NORM));
-    PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, norms_dev ? norms_dev : p->nrm, p->st));
+    PE_HIP(jump_reduce(p->E, p->Yn, B, nr, Dp, p->Jd, norms_dev ? norms_dev : p->nrm, p->st, Sx));
     if (Jhost) {
         PE_HIP(hipMemcpyAsync(Jhost, p->Jd, sizeof(double) * B, hipMemcpyDeviceToHost, p->st));
         PE_HIP(hipStreamSynchronize(p->st));
@@ -1822,6 +1865,57 @@ pe_status check_handle(pe_problem p) {
     return PE_OK;
 }
 
+// Coarse step on the history-carrying states [x | delta] (built at the first
+// use). G is the one-step coarse propagator with a fresh history, as without
+// carried history; it reads x only and hands on its own step's change at the
+// fine-step rate:
+//   G([x; delta]) = [x + d; d / P],  d = Zc (F - A x),
+// i.e. the 2Dp x Dp matrix [Phi_G; (Phi_G - I)/P] on x and the source term
+// [Zc F; Zc F / P]. (The parareal limit is fixed by F alone.)
+pe_status ensure_hist_ops(pe_problem p) {
+    if (p->PhiA64) return PE_OK;
+    const int Dp = p->Dp;
+    std::vector<void*> L;
+    double* phi = nullptr;
+    float* phi32 = nullptr;
+    pe_status s = dalloc_t(p, L, &phi, (size_t)2 * Dp * Dp);
+    if (s == PE_OK && p->prec == PE_MIXED) s = dalloc_t(p, L, &phi32, (size_t)2 * Dp * Dp);
+    if (s == PE_OK && hist_phi(p->PhiG64, phi, Dp, p->P, p->st) != hipSuccess) s = fail(PE_ERR_HIP, "hist_phi");
+    if (s == PE_OK && phi32 && to_f32(phi, phi32, 2L * Dp * Dp, p->st) != hipSuccess) s = fail(PE_ERR_HIP, "to_f32");
+    if (s != PE_OK) {
+        (void)hipStreamSynchronize(p->st);
+        free_list(L);
+        return s;
+    }
+    p->PhiA64 = phi;
+    p->PhiA32 = phi32;
+    p->hist_ops = L;
+    return PE_OK;
+}
+
+// the coarse source term on [x | delta] for the current source
+pe_status ensure_hist_src(pe_problem p) {
+    if (!p->CS) {
+        p->CSa = nullptr;
+        return PE_OK;
+    }
+    if (p->CSa && p->csa_version == p->src_version) return PE_OK;
+    PE_HIP(hipStreamSynchronize(p->st));
+    free_list(p->hist_src);
+    p->CSa = nullptr;
+    const long rows = (long)p->B_src * p->N;
+    PE_TRY(dalloc_t(p, p->hist_src, &p->CSa, (size_t)rows * 2 * p->Dp));
+    PE_HIP(aug_cs(p->CS, p->CSa, rows, p->Dp, p->P, p->st));
+    p->csa_version = p->src_version;
+    return PE_OK;
+}
+
+pe_status hist_unsupported(pe_problem p, const char* what) {
+    if (p->hist == PE_HIST_CARRY)
+        return fail(PE_ERR_STATE, std::string(what) + " is not available with carried history (pe_set_history)");
+    return PE_OK;
+}
+
 // ---------------------------------------------------------------------------
 // fine propagator by waveform relaxation (Sections 4.1-4.2), FP64, in the
 // caller's coordinates. Iteration j on every interval column at once:
@@ -2126,6 +2220,8 @@ pe_status pe_problem_destroy(pe_problem p) {
     free_list(p->wr_ops);
     free_list(p->wr_ws);
     free_list(p->wr_tab);
+    free_list(p->hist_ops);
+    free_list(p->hist_src);
     if (p->gw.part) (void)hipFree(p->gw.part);
     if (p->own_stream) (void)hipStreamDestroy(p->st);
     delete p;
@@ -2161,9 +2257,9 @@ pe_status pe_autotune(pe_problem p, int B) {
     const int save = p->autotune;
     p->autotune = 1;
     // one fine sweep and one stopping-test product on zero states visit every tuned site
-    PE_HIP(zero_fill(p->Xk[0], nullptr, (long)B * (p->N + 1) * p->Dp, p->st));
-    pe_status s = fine_sweep(p, B, p->Xk[0], (long)(p->N + 1) * p->Dp, p->Fbuf);
-    if (s == PE_OK) s = jumps(p, B, p->Xk[0], nullptr, (long)(p->N + 1) * p->Dp, 1, p->N, nullptr, nullptr);
+    PE_HIP(zero_fill(p->Xk[0], nullptr, (long)B * (p->N + 1) * p->Sx, p->st));
+    pe_status s = fine_sweep(p, B, p->Xk[0], (long)(p->N + 1) * p->Sx, p->Fbuf);
+    if (s == PE_OK) s = jumps(p, B, p->Xk[0], nullptr, (long)(p->N + 1) * p->Sx, 1, p->N, nullptr, nullptr);
     p->autotune = save;
     PE_HIP(hipStreamSynchronize(p->st));
     p->prof.pending.clear();
@@ -2213,6 +2309,7 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
     p->d1p = roundup(d1, 8);
     p->d2p = roundup(d2, 8);
     p->Dp = p->d1p + p->d2p;
+    p->Sx = p->Dp;
     p->N = N;
     p->P = (int)Pr;
     p->dt = dt_coarse;
@@ -2514,9 +2611,10 @@ pe_status pe_fine_propagate(pe_problem p, int B, const double* Xin, double* Y) {
     if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
     PE_TRY(ensure_workspace(p, B));
     const long rows = (long)B * p->N;
-    PE_HIP(pack_states(Xin, p->io, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
-    PE_TRY(fine_sweep(p, B, p->io, (long)p->N * p->Dp, p->Fbuf));
-    PE_HIP(unpack_states(p->Fbuf, Y, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    const long w = p->Sx / p->Dp;  // states [x | delta] with carried history
+    PE_HIP(pack_states(Xin, p->io, rows * w, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_TRY(fine_sweep(p, B, p->io, (long)p->N * p->Sx, p->Fbuf));
+    PE_HIP(unpack_states(p->Fbuf, Y, rows * w, p->d1, p->d2, p->d1p, p->d2p, p->st));
     PE_HIP(hipStreamSynchronize(p->st));
     PE_TRY(prof_collect(p));
     return PE_OK;
@@ -2530,6 +2628,23 @@ pe_status pe_coarse_propagate(pe_problem p, int B, const double* Xin, double* Y)
     PE_TRY(ensure_workspace(p, B));
     const int Dp = p->Dp;
     const long rows = (long)B * p->N;
+    if (p->hist == PE_HIST_CARRY) {
+        // one product with the coarse step on [x | delta] for all columns
+        const int Sx = p->Sx;
+        PE_TRY(ensure_hist_ops(p));
+        PE_TRY(ensure_hist_src(p));
+        PE_HIP(pack_states(Xin, p->io, rows * 2, p->d1, p->d2, p->d1p, p->d2p, p->st));
+        Epi e;
+        e.mode = EPI_COARSE_INIT;
+        e.xout = p->Fbuf;
+        e.ldxo = Sx;
+        e.cs = p->CSa;
+        e.ldcs = Sx;
+        PE_TRY(gemm<double>(p, shape((int)rows, Sx, p->io, Sx, p->PhiA64, Dp, 0, Dp), e));
+        PE_HIP(unpack_states(p->Fbuf, Y, rows * 2, p->d1, p->d2, p->d1p, p->d2p, p->st));
+        PE_HIP(hipStreamSynchronize(p->st));
+        return PE_OK;
+    }
     PE_HIP(pack_states(Xin, p->Xa, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
     Epi e1;
     e1.mode = EPI_RESID;
@@ -2574,9 +2689,16 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
     if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
     if (!(tol >= 0) || k_max < 0 || k_max > p->N) return fail(PE_ERR_ARG, "need tol >= 0 and 0 <= k_max <= N");
     if (norm_mode != PE_NORM_M_ABS && norm_mode != PE_NORM_M_REL) return fail(PE_ERR_ARG, "unknown norm_mode");
+    if (p->hist == PE_HIST_CARRY && p->fine_kind == PE_FINE_WR)
+        return fail(PE_ERR_STATE, "the waveform-relaxation fine solver restarts the history; use PE_HIST_RESTART");
     PE_TRY(ensure_workspace(p, B));
-    const int N = p->N, Dp = p->Dp;
-    const long ldX = (long)(N + 1) * Dp;
+    const int N = p->N, Dp = p->Dp, Sx = p->Sx;
+    const long ldX = (long)(N + 1) * Sx;
+    const long w = Sx / Dp;  // 2: states [x | delta] with carried history
+    if (p->hist == PE_HIST_CARRY) {
+        PE_TRY(ensure_hist_ops(p));
+        PE_TRY(ensure_hist_src(p));
+    }
 
     std::vector<int> active(B, 1);
     std::vector<double> thr(B, tol), J(B, 0.0);
@@ -2590,7 +2712,7 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
     PE_HIP(pack_states(x0, p->x0p, B, p->d1, p->d2, p->d1p, p->d2p, p->st));
     const long rel = norm_mode == PE_NORM_M_REL ? 1 : 0;
     PE_TRY(graph_run(p, {0, B, rel}, [&]() -> pe_status {
-        PE_HIP(set_x0(p->x0p, p->Xk[0], ldX, B, Dp, p->st));
+        PE_HIP(set_x0(p->x0p, p->Xk[0], ldX, B, Dp, p->st, Sx));
         PE_TRY(coarse_sweep_initial(p, B, p->Xk[0]));
         if (rel) PE_TRY(jumps_launch(p, B, p->Xk[0], nullptr, ldX, 0, N + 1));
         return PE_OK;
@@ -2611,13 +2733,13 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
             // propagated without source and added to the stored F values, so
             // FP32 rounding scales with the change, not with the state.
             PE_TRY(graph_run(p, {1, B, 2},
-                             [&]() { return fine_sweep(p, B, p->E, (long)N * Dp, p->Fbuf, false, 1, true); }));
+                             [&]() { return fine_sweep(p, B, p->E, (long)N * Sx, p->Fbuf, false, 1, true); }));
         } else {
             PE_TRY(graph_run(p, {1, B, cur}, [&]() { return fine_sweep(p, B, p->Xk[cur], ldX, p->Fbuf); }));
         }
         if (n_active < B) PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, ldX, B, p->st));
         PE_TRY(graph_run(p, {2, B, cur}, [&]() -> pe_status {
-            PE_HIP(set_x0(p->x0p, p->Xk[nxt], ldX, B, Dp, p->st));
+            PE_HIP(set_x0(p->x0p, p->Xk[nxt], ldX, B, Dp, p->st, Sx));
             PE_TRY(coarse_sweep_correct(p, B, p->Xk[nxt], p->Xk[cur], p->active_d));
             PE_TRY(jumps_launch(p, B, p->Xk[nxt], p->Xk[cur], ldX, 1, N));
             return PE_OK;
@@ -2627,7 +2749,7 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
         for (int b = 0; b < B; ++b) {
             if (!active[b]) continue;
             if (!std::isfinite(J[b])) {
-                PE_HIP(unpack_states(p->Xk[cur], X, (long)B * (N + 1), p->d1, p->d2, p->d1p, p->d2p, p->st));
+                PE_HIP(unpack_states(p->Xk[cur], X, (long)B * (N + 1) * w, p->d1, p->d2, p->d1p, p->d2p, p->st));
                 PE_HIP(hipStreamSynchronize(p->st));
                 return fail(PE_ERR_NONFINITE, "non-finite parareal jump for sample " + std::to_string(b) +
                                                   " at iteration " + std::to_string(k));
@@ -2642,7 +2764,7 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
         if (n_active > 0 && n_active < B)
             PE_HIP(hipMemcpyAsync(p->active_d, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, p->st));
     }
-    PE_HIP(unpack_states(p->Xk[cur], X, (long)B * (N + 1), p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_HIP(unpack_states(p->Xk[cur], X, (long)B * (N + 1) * w, p->d1, p->d2, p->d1p, p->d2p, p->st));
     PE_HIP(hipStreamSynchronize(p->st));
     PE_TRY(prof_collect(p));
     return n_active > 0 ? PE_WARN_NOT_CONVERGED : PE_OK;
@@ -2695,9 +2817,27 @@ pe_status pe_probe_peaks(void* hip_stream, double* out3) {
     return done(PE_OK);
 }
 
+pe_status pe_set_history(pe_problem p, int mode) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (mode != PE_HIST_RESTART && mode != PE_HIST_CARRY) return fail(PE_ERR_ARG, "unknown history mode");
+    if (mode == p->hist) return PE_OK;
+    if (mode == PE_HIST_CARRY && p->fine_kind == PE_FINE_WR)
+        return fail(PE_ERR_STATE, "the waveform-relaxation fine solver restarts the history");
+    // the iteration workspace changes its state stride: released and regrown
+    PE_HIP(hipStreamSynchronize(p->st));
+    graphs_clear(p);
+    free_list(p->ws_allocs);
+    p->B_cap = 0;
+    p->hist = mode;
+    p->Sx = mode == PE_HIST_CARRY ? 2 * p->Dp : p->Dp;
+    return PE_OK;
+}
+
 pe_status pe_set_fine_solver(pe_problem p, int kind, double alpha, int K0) {
     g_err.clear();
     PE_TRY(check_handle(p));
+    if (kind == PE_FINE_WR) PE_TRY(hist_unsupported(p, "the waveform-relaxation fine solver"));
     if (kind == PE_FINE_STEP) {
         p->fine_kind = PE_FINE_STEP;
         return PE_OK;
@@ -2721,6 +2861,7 @@ pe_status pe_fine_wr(pe_problem p, int B, const double* Xin, double alpha, int K
     if (K0 < 0) return fail(PE_ERR_ARG, "need K0 >= 0");
     if (p->P > 128) return fail(PE_ERR_ARG, "waveform relaxation supports P <= 128");
     if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    PE_TRY(hist_unsupported(p, "pe_fine_wr"));
     const int N = p->N, D = p->D;
     const long ldXb = (long)N * D;
     const int NB = B * N;
@@ -2740,6 +2881,7 @@ pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH,
     PE_TRY(check_handle(p));
     if (B < 1 || !Ybnd || !J) return fail(PE_ERR_ARG, "bad arguments");
     if (!(beta >= 0)) return fail(PE_ERR_ARG, "need beta >= 0");
+    PE_TRY(hist_unsupported(p, "pe_tracking"));
     if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
     const bool fdh = dH && p->src_set && p->src_kind == 2;
     PE_TRY(ensure_workspace(p, B));
@@ -2764,6 +2906,7 @@ pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const
     if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
     if (!(tol >= 0) || k_max < 0 || k_max > p->N) return fail(PE_ERR_ARG, "need tol >= 0 and 0 <= k_max <= N");
     if (!(beta >= 0)) return fail(PE_ERR_ARG, "need beta >= 0");
+    PE_TRY(hist_unsupported(p, "pe_adjoint"));
     if (beta > 0 && !Ybnd) return fail(PE_ERR_ARG, "beta > 0 needs the tracked trajectory Ybnd");
     const bool track = beta > 0;
     const bool want_h = Hbar && p->src_set && p->R > 0;
@@ -2881,8 +3024,10 @@ pe_status pe_batch_create(pe_batch* out, int count, const pe_problem* problems, 
     g_err.clear();
     if (!out || count < 1 || !problems) return fail(PE_ERR_ARG, "bad arguments");
     *out = nullptr;
-    for (int i = 0; i < count; ++i)
+    for (int i = 0; i < count; ++i) {
         if (!problems[i]) return fail(PE_ERR_ARG, "null problem handle in the batch");
+        PE_TRY(hist_unsupported(problems[i], "a batch"));
+    }
     const int prec = problems[0]->prec, P = problems[0]->P;
     for (int i = 1; i < count; ++i) {
         if (problems[i]->prec != prec) return fail(PE_ERR_ARG, "all problems of a batch need the same precision");
@@ -2958,8 +3103,10 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
     if (!(tol >= 0) || k_max < 0) return fail(PE_ERR_ARG, "need tol >= 0 and k_max >= 0");
     if (norm_mode != PE_NORM_M_ABS && norm_mode != PE_NORM_M_REL) return fail(PE_ERR_ARG, "unknown norm_mode");
     const int G = bt->count;
-    for (int g = 0; g < G; ++g)
+    for (int g = 0; g < G; ++g) {
         if (!x0[g] || !X[g]) return fail(PE_ERR_ARG, "null state pointer for problem " + std::to_string(g));
+        PE_TRY(hist_unsupported(bt->pr[g], "a batch"));
+    }
     // samples per problem: the B of its source (1 without a source)
     bt->Bs.assign(G, 1);
     for (int g = 0; g < G; ++g) {

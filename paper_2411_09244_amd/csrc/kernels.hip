@@ -62,7 +62,7 @@ hipError_t unpack_states(const double* src, double* dst, long rows, int d1, int 
 // 0 <= n + row_off < nvalid) into Xa[b*N + n], zero the deviation state;
 // afterwards Y (+)= Xa + deviation.
 // ---------------------------------------------------------------------------
-__global__ void k_fine_init(const double* __restrict__ X, long ldXb, int row_off, int nvalid,
+__global__ void k_fine_init(const double* __restrict__ X, long ldXb, int sx, int row_off, int nvalid,
                             double* __restrict__ Xa, double* __restrict__ dev64, float* __restrict__ dev32,
                             int B, int N, int Dp) {
     const long rows = (long)B * N;
@@ -72,7 +72,7 @@ __global__ void k_fine_init(const double* __restrict__ X, long ldXb, int row_off
         const int s = (int)(i - r * Dp);
         const long b = r / N, n = r - b * N;
         const long j = n + row_off;
-        Xa[i] = (j >= 0 && j < nvalid) ? X[b * ldXb + j * Dp + s] : 0.0;
+        Xa[i] = (j >= 0 && j < nvalid) ? X[b * ldXb + j * sx + s] : 0.0;
         dev64[r * 2 * Dp + s] = 0.0;
         dev64[r * 2 * Dp + Dp + s] = 0.0;
         if (dev32) {
@@ -83,28 +83,29 @@ __global__ void k_fine_init(const double* __restrict__ X, long ldXb, int row_off
 }
 
 hipError_t fine_init(const double* X, long ldXb, int row_off, int nvalid, double* Xa, double* dev64,
-                     float* dev32, int B, int N, int Dp, hipStream_t st) {
-    hipLaunchKernelGGL(k_fine_init, grid1((long)B * N * Dp), dim3(256), 0, st, X, ldXb, row_off, nvalid, Xa,
-                       dev64, dev32, B, N, Dp);
+                     float* dev32, int B, int N, int Dp, hipStream_t st, int sx) {
+    hipLaunchKernelGGL(k_fine_init, grid1((long)B * N * Dp), dim3(256), 0, st, X, ldXb, sx > 0 ? sx : Dp,
+                       row_off, nvalid, Xa, dev64, dev32, B, N, Dp);
     return hipGetLastError();
 }
 
 // Y[r][s] (+)= Xa[r][s] + dev[r][d1p + s]  (u and w deviations sit at d1p + s)
 __global__ void k_fine_final(const double* __restrict__ Xa, const double* __restrict__ dev64,
-                             double* __restrict__ Y, long rows, int Dp, int d1p, int accumulate) {
+                             double* __restrict__ Y, long ldy, long rows, int Dp, int d1p, int accumulate) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
          i += (long)gridDim.x * blockDim.x) {
         const long r = i / Dp;
         const int s = (int)(i - r * Dp);
         const double v = Xa[i] + dev64[r * 2 * Dp + d1p + s];
-        Y[i] = accumulate ? Y[i] + v : v;
+        double* y = Y + r * ldy + s;
+        *y = accumulate ? *y + v : v;
     }
 }
 
 hipError_t fine_final(const double* Xa, const double* dev64, double* Y, long rows, int Dp, int d1p,
-                      int accumulate, hipStream_t st) {
-    hipLaunchKernelGGL(k_fine_final, grid1(rows * Dp), dim3(256), 0, st, Xa, dev64, Y, rows, Dp, d1p,
-                       accumulate);
+                      int accumulate, hipStream_t st, long ldy) {
+    hipLaunchKernelGGL(k_fine_final, grid1(rows * Dp), dim3(256), 0, st, Xa, dev64, Y, ldy > 0 ? ldy : Dp, rows,
+                       Dp, d1p, accumulate);
     return hipGetLastError();
 }
 
@@ -112,33 +113,36 @@ hipError_t fine_final(const double* Xa, const double* dev64, double* Y, long row
 // jump norms of eq. (2.8): E[b*nr + j] = Xk[b][n0 + j] - Xp[b][n0 + j]
 // (Xp may be null: plain norms), then J_b = max_j sqrt(E_j . (M E_j)).
 // ---------------------------------------------------------------------------
+// (states of stride sx, copied whole: with carried history E holds the
+// change of [x | delta], the norm below reads its first Dp entries)
 __global__ void k_jump_diff(const double* __restrict__ Xk, const double* __restrict__ Xp, long ldXb,
-                            int n0, int nr, int B, int Dp, double* __restrict__ E) {
+                            int n0, int nr, int B, int sx, double* __restrict__ E) {
     const long rows = (long)B * nr;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * sx;
          i += (long)gridDim.x * blockDim.x) {
-        const long r = i / Dp;
-        const int s = (int)(i - r * Dp);
+        const long r = i / sx;
+        const int s = (int)(i - r * sx);
         const long b = r / nr, j = r - b * nr;
-        const long o = b * ldXb + (n0 + j) * Dp + s;
+        const long o = b * ldXb + (n0 + j) * sx + s;
         E[i] = Xp ? (Xk[o] - Xp[o]) : Xk[o];
     }
 }
 
 hipError_t jump_diff(const double* Xk, const double* Xp, long ldXb, int n0, int nr, int B, int Dp,
-                     double* E, hipStream_t st) {
-    hipLaunchKernelGGL(k_jump_diff, grid1((long)B * nr * Dp), dim3(256), 0, st, Xk, Xp, ldXb, n0, nr, B,
-                       Dp, E);
+                     double* E, hipStream_t st, int sx) {
+    if (sx <= 0) sx = Dp;
+    hipLaunchKernelGGL(k_jump_diff, grid1((long)B * nr * sx), dim3(256), 0, st, Xk, Xp, ldXb, n0, nr, B,
+                       sx, E);
     return hipGetLastError();
 }
 
 // one work-group per state row: norms[r] = sqrt(E_r . Y_r) (fixed order)
-__global__ __launch_bounds__(256) void k_row_norms(const double* __restrict__ E, const double* __restrict__ Y,
-                                                   int Dp, double* __restrict__ norms) {
+__global__ __launch_bounds__(256) void k_row_norms(const double* __restrict__ E, long lde,
+                                                   const double* __restrict__ Y, int Dp, double* __restrict__ norms) {
     __shared__ double red[4];
     const long r = blockIdx.x;
     double acc = 0.0;
-    for (int s = threadIdx.x; s < Dp; s += 256) acc += E[r * Dp + s] * Y[r * Dp + s];
+    for (int s = threadIdx.x; s < Dp; s += 256) acc += E[r * lde + s] * Y[r * Dp + s];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -163,8 +167,9 @@ __global__ void k_sample_max(const double* __restrict__ norms, int B, int nr, do
 }
 
 hipError_t jump_reduce(const double* E, const double* Y, int B, int nr, int Dp, double* J, double* norms,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_row_norms, dim3((unsigned)((long)B * nr)), dim3(256), 0, st, E, Y, Dp, norms);
+                       hipStream_t st, long lde) {
+    hipLaunchKernelGGL(k_row_norms, dim3((unsigned)((long)B * nr)), dim3(256), 0, st, E, lde > 0 ? lde : Dp, Y, Dp,
+                       norms);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sample_max, dim3((B + 63) / 64), dim3(64), 0, st, norms, B, nr, J);
@@ -338,18 +343,21 @@ hipError_t freeze_inactive(const double* Xsrc, double* Xdst, const int* active, 
 }
 
 // x0 into row 0 of every sample of X (x_0^k = x_0)
+// (states of stride sx >= Dp: the entries past Dp, the carried history, are
+// zero at t = 0)
 __global__ void k_set_x0(const double* __restrict__ x0p, double* __restrict__ X, long ldXb, int B,
-                         int Dp) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)B * Dp;
+                         int Dp, int sx) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)B * sx;
          i += (long)gridDim.x * blockDim.x) {
-        const long b = i / Dp;
-        const int s = (int)(i - b * Dp);
-        X[b * ldXb + s] = x0p[i];
+        const long b = i / sx;
+        const int s = (int)(i - b * sx);
+        X[b * ldXb + s] = s < Dp ? x0p[b * Dp + s] : 0.0;
     }
 }
 
-hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st) {
-    hipLaunchKernelGGL(k_set_x0, grid1((long)B * Dp), dim3(256), 0, st, x0p, X, ldXb, B, Dp);
+hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st, int sx) {
+    if (sx <= 0) sx = Dp;
+    hipLaunchKernelGGL(k_set_x0, grid1((long)B * sx), dim3(256), 0, st, x0p, X, ldXb, B, Dp, sx);
     return hipGetLastError();
 }
 
@@ -721,6 +729,102 @@ hipError_t wr_io(int dir, const double* X, long ldXb, double* Fout, int N, int d
     const long n = (long)NBc * (dir > 0 || padded ? d1p + d2p : d1 + d2);
     hipLaunchKernelGGL(k_wr_io, grid1(n), dim3(256), 0, st, dir, X, ldXb, Fout, N, d1, d2, d1p, d2p, c0, NBc, P,
                        Ul, Wl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// carried history (states [x | delta] of 2Dp, delta = the change over the last
+// fine step): gather, placement into the fine-step state and back, the
+// coarse step's augmented source and operator
+// ---------------------------------------------------------------------------
+// out[b*N + n][s] = X[b][n + row_off][off + s] (zero unless 0 <= n + row_off < nvalid)
+__global__ void k_gather_rows(const double* __restrict__ X, long ldXb, int sx, int off, int row_off, int nvalid,
+                              double* __restrict__ out, int B, int N, int Dp) {
+    const long rows = (long)B * N;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const long b = r / N, n = r - b * N;
+        const long j = n + row_off;
+        out[i] = (j >= 0 && j < nvalid) ? X[b * ldXb + j * sx + off + s] : 0.0;
+    }
+}
+
+hipError_t gather_rows(const double* X, long ldXb, int sx, int off, int row_off, int nvalid, double* out, int B,
+                       int N, int Dp, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_rows, grid1((long)B * N * Dp), dim3(256), 0, st, X, ldXb, sx, off, row_off, nvalid,
+                       out, B, N, Dp);
+    return hipGetLastError();
+}
+
+// history rows H (rows x Dp, [du | dw]) into the fine-step state
+// [du_prev | u - u_a | w - w_a | dw_prev] (2Dp per row), both precisions
+__global__ void k_hist_put(const double* __restrict__ H, double* __restrict__ dev64, float* __restrict__ dev32,
+                           long rows, int Dp, int d1p) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const long o = r * 2 * Dp + (s < d1p ? s : Dp + s);
+        const double v = H[i];
+        dev64[o] = v;
+        if (dev32) dev32[o] = (float)v;
+    }
+}
+
+hipError_t hist_put(const double* H, double* dev64, float* dev32, long rows, int Dp, int d1p, hipStream_t st) {
+    hipLaunchKernelGGL(k_hist_put, grid1(rows * Dp), dim3(256), 0, st, H, dev64, dev32, rows, Dp, d1p);
+    return hipGetLastError();
+}
+
+// out[r][s] (+)= history of the fine-step state (the last step's change)
+__global__ void k_hist_get(const double* __restrict__ dev64, double* __restrict__ out, long ldo, long rows,
+                           int Dp, int d1p, int accumulate) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const double v = dev64[r * 2 * Dp + (s < d1p ? s : Dp + s)];
+        double* y = out + r * ldo + s;
+        *y = accumulate ? *y + v : v;
+    }
+}
+
+hipError_t hist_get(const double* dev64, double* out, long ldo, long rows, int Dp, int d1p, int accumulate,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_hist_get, grid1(rows * Dp), dim3(256), 0, st, dev64, out, ldo, rows, Dp, d1p, accumulate);
+    return hipGetLastError();
+}
+
+// CSa[r] = [CS[r]; CS[r] / P]: the coarse step's source term on [x | delta]
+__global__ void k_aug_cs(const double* __restrict__ CS, double* __restrict__ CSa, long rows, int Dp, double invP) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < rows * 2 * Dp;
+         i += (long)gridDim.x * blockDim.x) {
+        const long r = i / (2 * Dp);
+        const int s = (int)(i - r * 2 * Dp);
+        CSa[i] = s < Dp ? CS[r * Dp + s] : invP * CS[r * Dp + s - Dp];
+    }
+}
+
+hipError_t aug_cs(const double* CS, double* CSa, long rows, int Dp, int P, hipStream_t st) {
+    hipLaunchKernelGGL(k_aug_cs, grid1(rows * 2 * Dp), dim3(256), 0, st, CS, CSa, rows, Dp, 1.0 / P);
+    return hipGetLastError();
+}
+
+// the coarse step on [x | delta] (2Dp x Dp: it reads x only):
+//   [Phi_G; (Phi_G - I)/P]
+__global__ void k_hist_phi(const double* __restrict__ Phi, double* __restrict__ out, int Dp, double invP) {
+    const long n = (long)Dp * Dp;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < 2 * n; t += (long)gridDim.x * blockDim.x) {
+        const long u = t < n ? t : t - n;
+        const int i = (int)(u / Dp), j = (int)(u - (long)i * Dp);
+        out[t] = t < n ? Phi[u] : invP * (Phi[u] - (i == j ? 1.0 : 0.0));
+    }
+}
+
+hipError_t hist_phi(const double* Phi, double* out, int Dp, int P, hipStream_t st) {
+    hipLaunchKernelGGL(k_hist_phi, grid1(2L * Dp * Dp), dim3(256), 0, st, Phi, out, Dp, 1.0 / P);
     return hipGetLastError();
 }
 

@@ -7,8 +7,9 @@ hipError_t pack_states(const double* src, double* dst, long rows, int d1, int d2
                        hipStream_t st);
 hipError_t unpack_states(const double* src, double* dst, long rows, int d1, int d2, int d1p, int d2p,
                          hipStream_t st);
+// states of X have stride sx (0: Dp)
 hipError_t fine_init(const double* X, long ldXb, int row_off, int nvalid, double* Xa, double* dev64,
-                     float* dev32, int B, int N, int Dp, hipStream_t st);
+                     float* dev32, int B, int N, int Dp, hipStream_t st, int sx = 0);
 hipError_t adj_init(const double* src, const double* add, long ld_add, double* S, float* nu32, double* nu_set,
                     long ld_set, long rows, int Dp, hipStream_t st);
 hipError_t axpy(double* y, const double* x, double a, long n, hipStream_t st);
@@ -19,15 +20,23 @@ hipError_t take_a(const double* S, double* Y, long rows, int Dp, int accumulate,
 hipError_t add_rows(double* Y, const double* X, int B, int N, int Dp, hipStream_t st);
 hipError_t copy_row(const double* src, double* dst, long ldb, int B, int Dp, hipStream_t st);
 hipError_t fine_final(const double* Xa, const double* dev64, double* Y, long rows, int Dp, int d1p,
-                      int accumulate, hipStream_t st);
+                      int accumulate, hipStream_t st, long ldy = 0);
 hipError_t jump_diff(const double* Xk, const double* Xp, long ldXb, int n0, int nr, int B, int Dp,
-                     double* E, hipStream_t st);
+                     double* E, hipStream_t st, int sx = 0);
 hipError_t jump_reduce(const double* E, const double* Y, int B, int nr, int Dp, double* J, double* norms,
-                       hipStream_t st);
+                       hipStream_t st, long lde = 0);
 hipError_t freeze_inactive(const double* Xsrc, double* Xdst, const int* active, long ldXb, int B,
                            hipStream_t st);
 hipError_t zero_fill(double* a, float* b, long n, hipStream_t st);
-hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st);
+hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st, int sx = 0);
+// carried history
+hipError_t gather_rows(const double* X, long ldXb, int sx, int off, int row_off, int nvalid, double* out, int B,
+                       int N, int Dp, hipStream_t st);
+hipError_t hist_put(const double* H, double* dev64, float* dev32, long rows, int Dp, int d1p, hipStream_t st);
+hipError_t hist_get(const double* dev64, double* out, long ldo, long rows, int Dp, int d1p, int accumulate,
+                    hipStream_t st);
+hipError_t aug_cs(const double* CS, double* CSa, long rows, int Dp, int P, hipStream_t st);
+hipError_t hist_phi(const double* Phi, double* out, int Dp, int P, hipStream_t st);
 hipError_t place(double* dst, long ldd, int ro, int co, const double* src, long lds, int rows, int cols,
                  double scale, int trans, hipStream_t st, int accumulate = 0);
 hipError_t shifted_embed(double* dst, int n, const double* A, const double* Bm, long lds, int d,

@@ -7,10 +7,8 @@ What fixes them independently of their own code:
     same equations over all N*P levels (a sparse all-at-once system), and
     the fine composition with carried history equals that run;
   * with no history (delta = 0) the carrying propagators reduce to the
-    restarting ones;
-  * the coarse step depends on the carried change only through the rate
-    delta / dt_fine (same result for (delta, P) and (delta / 2, 2P));
-  * P = 1: fine and coarse propagator are the same step;
+    restarting ones, and the coarse step never reads the carried change;
+  * P = 1 and delta = 0: fine and coarse propagator are the same step;
   * parareal with carried history is exact at n <= k and ends at the fine
     composition, i.e. at the uninterrupted run, which the restarting
     parareal does not reach when M12 != 0;
@@ -71,23 +69,21 @@ def test_zero_history_reduces_to_restart():
         np.testing.assert_allclose(g[bl.D:], (g0 - y[:bl.D]) / bl.P, rtol=1e-13, atol=1e-14)
 
 
-def test_coarse_step_depends_on_the_rate_only():
+def test_coarse_step_ignores_the_carried_change():
+    """G starts with a fresh history: its x part is the restarting G for any
+    carried change, its delta part that step's change at the fine-step
+    rate."""
     p, bl, src = _prob("t1")
-    bl2 = S.Blocks(p["M11"], p["M12"], p["M22"], p["A11"], p["A12"], p["A22"], p["dt"], p["dt"] / (2 * bl.P),
-                   bl.N)
-    assert bl2.P == 2 * bl.P
-    zero = S.Source(None, None, S.TIME_FINE, bl.N, bl.P)
-    zero2 = S.Source(None, None, S.TIME_FINE, bl.N, bl2.P)
     y = _rand_state(bl, 8)
-    y2 = y.copy()
-    y2[bl.D:] *= 0.5
-    g = S.coarse_propagator_carry(bl, zero, y, 0)
-    g2 = S.coarse_propagator_carry(bl2, zero2, y2, 0)
-    np.testing.assert_allclose(g2[:bl.D], g[:bl.D], rtol=1e-12, atol=1e-13)
-    np.testing.assert_allclose(2.0 * g2[bl.D:], g[bl.D:], rtol=1e-12, atol=1e-13)
-    # and the history is used at all (M12 != 0 in this space)
-    g0 = S.coarse_propagator_carry(bl, zero, np.concatenate([y[:bl.D], 0 * y[bl.D:]]), 0)
-    assert np.abs(g0[:bl.D] - g[:bl.D]).max() > 1e-6 * np.abs(g[:bl.D]).max()
+    for n in (1, 6):
+        g = S.coarse_propagator_carry(bl, src, y, n)
+        g0 = S.coarse_propagator(bl, src, y[:bl.D], n)
+        np.testing.assert_allclose(g[:bl.D], g0, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(g[bl.D:], (g0 - y[:bl.D]) / bl.P, rtol=1e-13, atol=1e-14)
+    # the fine propagator does read it (M12 != 0 in this space)
+    z = np.concatenate([y[:bl.D], np.zeros(bl.D)])
+    f, f0 = S.fine_propagator_carry(bl, src, y, 2), S.fine_propagator_carry(bl, src, z, 2)
+    assert np.abs(f[:bl.D] - f0[:bl.D]).max() > 1e-6 * np.abs(f[:bl.D]).max()
 
 
 def test_p1_fine_equals_coarse():
@@ -96,6 +92,7 @@ def test_p1_fine_equals_coarse():
     src = S.Source(p["G"], p["H"][:, :, ::bl.P] if p["time_mode"] == S.TIME_FINE else p["H"],
                    p["time_mode"], bl.N, 1)
     y = _rand_state(bl1, 9)
+    y[bl1.D:] = 0.0
     for n in (0, 5):
         np.testing.assert_allclose(S.fine_propagator_carry(bl1, src, y, n), S.coarse_propagator_carry(bl1, src, y, n),
                                    rtol=1e-13, atol=1e-14)

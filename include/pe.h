@@ -393,7 +393,9 @@ pe_status pe_autotune(pe_problem p, int B);
  * pe_last_tiles - tile configuration of the last product launched in class
  * `kind` (PE_PROF_*): tiles4 = {rows of the state tile, rows of the operator
  * tile, K depth per LDS stage, split-K count}; all 0 for the GEMV kernel or
- * if the class has not run. tiles4: host, 4 ints.
+ * if the class has not run. For the wave-split-K kernel (every wave of a
+ * work-group takes its own slice of K, no LDS staging) tiles4[2] is minus
+ * the number of waves per work-group. tiles4: host, 4 ints.
  */
 pe_status pe_last_tiles(pe_problem p, int kind, int* tiles4);
 

@@ -187,6 +187,9 @@ struct pe_problem_s {
     // autotuned tile configurations per product site and shape
     int autotune = 1;
     std::map<std::vector<int>, pe::TileCfg> tuned;
+    // PE_FORCE_WSK="bs,waves,splitk": every product whose state columns fit
+    // one 64-row tile runs the wave-split-K kernel with this configuration
+    pe::TileCfg force_wsk;
 
     // captured HIP graphs of the sweeps, keyed by (kind, B, buffer parity)
     GraphCache gc;
@@ -389,7 +392,8 @@ pe_status graph_run(pe_problem p, const std::vector<long>& key, Fn&& fn) {
 // operands (output to a scratch buffer, so no side effects) and keep the
 // fastest. Choices are looked up first in the read-only database named by
 // PE_TUNE_DB and the cache named by PE_TUNE_CACHE (one line per site: key
-// fields then br bs bk2 splitk); new choices are appended to the cache.
+// fields then br bs bk2 splitk [wsk], wsk > 0 naming the wave-split-K kernel
+// with that many waves); new choices are appended to the cache.
 // Runs that share these files use identical configurations (identical
 // rounding).
 // ---------------------------------------------------------------------------
@@ -409,12 +413,13 @@ void tune_file_load(pe_problem p, const char* path) {
             v.push_back(atoi(tok));
             tok = strtok(nullptr, " \t\n");
         }
-        if (v.size() != 13) continue;
+        if (v.size() != 13 && v.size() != 14) continue;
         TileCfg c;
         c.br = v[9];
         c.bs = v[10];
         c.bk2 = v[11];
         c.splitk = v[12];
+        c.wsk = v.size() == 14 ? v[13] : 0;
         v.resize(9);
         p->tuned[v] = c;
     }
@@ -434,7 +439,7 @@ void tune_cache_store(const std::vector<int>& key, const TileCfg& c) {
     FILE* f = fopen(path, "a");
     if (!f) return;
     for (int x : key) fprintf(f, "%d ", x);
-    fprintf(f, "%d %d %d %d\n", c.br, c.bs, c.bk2, c.splitk);
+    fprintf(f, "%d %d %d %d %d\n", c.br, c.bs, c.bk2, c.splitk, c.wsk);
     fclose(f);
 }
 
@@ -489,13 +494,44 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
             }
         }
     }
+    // wave-split-K kernel for products whose state columns fit one 64-row tile
+    if (sh.Mr <= 64) {
+        const int nst = (kext + 15) / 16;
+        const int ws_shapes[4][2] = {{32, 4}, {32, 8}, {16, 4}, {16, 8}};
+        for (auto& wc : ws_shapes) {
+            const long tiles = (sh.Ns + wc[0] - 1) / wc[0];
+            for (int sk = 1; sk <= 32; sk *= 2) {
+                if (sk > 1 && (nst / (sk * wc[1]) < 2 || tiles * sk > 4096)) break;
+                TileCfg c;
+                c.br = 64;
+                c.bs = wc[0];
+                c.wsk = wc[1];
+                c.splitk = sk;
+                const size_t need = gemm_part_bytes(sh, c, sizeof(T));
+                if (need > ((size_t)512 << 20)) continue;
+                PE_TRY(ensure_gemm_work(p, need));
+                if (gemm_launch<T>(sh, epi, c, p->gw, p->st) != hipSuccess) continue;
+                const int reps = 3;
+                PE_HIP(hipEventRecord(e0, p->st));
+                for (int i = 0; i < reps; ++i) PE_HIP(gemm_launch<T>(sh, epi, c, p->gw, p->st));
+                PE_HIP(hipEventRecord(e1, p->st));
+                PE_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                PE_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms / reps < best) {
+                    best = ms / reps;
+                    *best_out = c;
+                }
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(scratch);
     if (getenv("PE_VERBOSE"))
-        fprintf(stderr, "[libpe] tuned %s Mr=%d Ns=%d K=%d: tile %dx%d bk2=%d splitk=%d (%.2f us)\n",
+        fprintf(stderr, "[libpe] tuned %s Mr=%d Ns=%d K=%d: tile %dx%d bk2=%d splitk=%d wsk=%d (%.2f us)\n",
                 fp32 ? "f32" : "f64", sh.Mr, sh.Ns, kext, best_out->br, best_out->bs, best_out->bk2,
-                best_out->splitk, best * 1e3);
+                best_out->splitk, best_out->wsk, best * 1e3);
     return PE_OK;
 }
 
@@ -519,6 +555,8 @@ pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_spli
     TileCfg cfg = choose_tiles(sh, sizeof(T) == 4, p->n_cu);
     if (force_splitk > 0) {
         cfg.splitk = force_splitk;
+    } else if (p->force_wsk.wsk > 0 && sh.Mr > 4 && sh.Mr <= 64) {
+        cfg = p->force_wsk;
     } else if (site != SITE_NONE && p->autotune && sh.Mr > 4) {
         const std::vector<int> key = tune_key(site, sizeof(T) == 4, sh);
         auto it = p->tuned.find(key);
@@ -537,7 +575,7 @@ pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_spli
         const bool gemv = sh.Mr <= 4;
         p->last_cfg[kind][0] = gemv ? 0 : cfg.br;
         p->last_cfg[kind][1] = gemv ? 0 : cfg.bs;
-        p->last_cfg[kind][2] = gemv ? 0 : (sizeof(T) == 4 ? 32 : 16) << cfg.bk2;
+        p->last_cfg[kind][2] = gemv ? 0 : cfg.wsk > 0 ? -cfg.wsk : (sizeof(T) == 4 ? 32 : 16) << cfg.bk2;
         p->last_cfg[kind][3] = gemv ? 0 : cfg.splitk;
     }
     size_t slot;
@@ -2333,6 +2371,16 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         // replayed from graphs on MI355X: each grid-wide barrier costs tens of µs)
         const char* pz = getenv("PE_PERSISTENT");
         p->persistent = (pz && pz[0] == '1') ? 1 : 0;
+        if (const char* fw = getenv("PE_FORCE_WSK")) {
+            int bs = 0, w = 0, sk = 0;
+            if (sscanf(fw, "%d,%d,%d", &bs, &w, &sk) == 3 && (bs == 16 || bs == 32) && (w == 4 || w == 8) &&
+                sk >= 1 && sk <= 64) {
+                p->force_wsk.br = 64;
+                p->force_wsk.bs = bs;
+                p->force_wsk.wsk = w;
+                p->force_wsk.splitk = sk;
+            }
+        }
         tune_cache_load(p);
     }
     int dev = 0;

@@ -431,6 +431,188 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmShape sh, const 
     gemm_tile<T, BR, BS, BK>(sh, epi, tiles_r, blockIdx.x, blockIdx.y, splitk, part);
 }
 
+// ---------------------------------------------------------------------------
+// Wave-split-K product for skinny outputs (all state columns of a product in
+// one 64-row tile, as in the fine steps of one sample): each of the W waves
+// of a work-group computes the whole 64 x BS output tile over its own slice
+// of K. A wave reads its MFMA operands straight from global memory into
+// registers in the MFMA lane layout (lane l holds rows l % 16 + 16 i and the
+// four consecutive k values 4 (l / 16) .. +3 of each 16-deep step), keeping
+// PF steps in flight: there is no LDS staging and no barrier in the K loop,
+// so each wave streams its slice at its own pace. At the end the W partial
+// tiles are added through LDS in wave order (bitwise reproducible) and the
+// sum goes to the epilogue (one split) or to the split's plane, which the
+// split-K reduction kernel adds in split order.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Quad4 {
+    T v[4];
+};
+
+// elements k .. k+3 of a row, read at min(k, k1 - 4) so that the address
+// stays inside the row's K range [.., k1) (k1 a multiple of 16 / sizeof(T));
+// the caller zeroes a quad with k >= k1 when it uses it. Loads are never
+// skipped or post-processed here, so that the compiler can keep them in
+// flight across loop iterations.
+template <typename T>
+__device__ __forceinline__ Quad4<T> load_quad(const T* row, int k, int k1);
+
+template <>
+__device__ __forceinline__ Quad4<float> load_quad<float>(const float* row, int k, int k1) {
+    const float4 x = *(const float4*)(row + min(k, k1 - 4));
+    return Quad4<float>{{x.x, x.y, x.z, x.w}};
+}
+
+template <>
+__device__ __forceinline__ Quad4<double> load_quad<double>(const double* row, int k, int k1) {
+    const double2 a = *(const double2*)(row + min(k, k1 - 2));
+    const double2 b = *(const double2*)(row + min(k + 2, k1 - 2));
+    return Quad4<double>{{a.x, a.y, b.x, b.y}};
+}
+
+template <typename T, int BS, int W, int PF>
+__global__ __launch_bounds__(W * 64) void gemm_wsk_kernel(const GemmShape sh, const Epi epi, const int tiles_r,
+                                                          const int splitk, T* __restrict__ part) {
+    using Op = MfmaOp<T>;
+    using acc_t = typename Op::acc_t;
+    constexpr int BR = 64, MI = BR / 16, MJ = BS / 16;
+    constexpr int LDR = BS + 4;  // padded row of the LDS partial tiles
+    static_assert(BS % 16 == 0, "bad tile");
+    __shared__ __align__(16) T red[W][BR * LDR];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tile = blockIdx.x, split = blockIdx.y;
+    const int tr = tile % tiles_r, ts = tile / tiles_r;
+    const int r0 = tr * BR, s0 = ts * BS;
+    const int s1 = min(s0 + BS, sh.Ns);
+
+    int k0, k1;
+    if (s1 <= sh.s_split) {
+        k0 = sh.k0a;
+        k1 = sh.k1a;
+    } else if (s0 >= sh.s_split) {
+        k0 = sh.k0b;
+        k1 = sh.k1b;
+    } else {
+        k0 = min(sh.k0a, sh.k0b);
+        k1 = max(sh.k1a, sh.k1b);
+    }
+    // this wave's slice: steps [st0, st0 + n) of 16 K values, piece
+    // split * W + wave of splitk * W equal pieces
+    const int nst = (k1 > k0) ? (k1 - k0 + 15) / 16 : 0;
+    const int pieces = splitk * W;
+    const int per = (nst + pieces - 1) / pieces;
+    const int st0 = min(nst, (split * W + wave) * per);
+    const int n = min(nst, st0 + per) - st0;
+
+    const T* __restrict__ A = (const T*)sh.A;
+    const T* __restrict__ B = (const T*)sh.B;
+    const int kl = k0 + 4 * (lane >> 4);  // this lane's first k
+    // operand rows of this lane; a row out of range reads row 0 instead (its
+    // outputs are never stored, and no valid output depends on it)
+    const T* pa[MI];
+    const T* pb[MJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+        const int r = r0 + i * 16 + (lane & 15);
+        pa[i] = A + (long)(r < sh.Mr ? r : 0) * sh.lda;
+    }
+#pragma unroll
+    for (int j = 0; j < MJ; ++j) {
+        const int s = s0 + j * 16 + (lane & 15);
+        pb[j] = B + (long)(s < sh.Ns ? s : 0) * sh.ldb;
+    }
+
+    acc_t acc[MI][MJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < MJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    // ring of PF steps in registers; a step index past the slice repeats its
+    // last step (loaded, never used)
+    Quad4<T> qa[PF][MI], qb[PF][MJ];
+    auto load = [&](Quad4<T>(&xa)[MI], Quad4<T>(&xb)[MJ], int step) {
+        const int k = kl + (st0 + min(step, n - 1)) * 16;
+#pragma unroll
+        for (int i = 0; i < MI; ++i) xa[i] = load_quad<T>(pa[i], k, k1);
+#pragma unroll
+        for (int j = 0; j < MJ; ++j) xb[j] = load_quad<T>(pb[j], k, k1);
+    };
+    // step `step` of the slice: the operator quads past k1 (only in a last,
+    // partial step of the K range) are zeroed, which zeroes their products
+    auto mma_step = [&](const Quad4<T>(&xa)[MI], const Quad4<T>(&xb)[MJ], int step) {
+        const int k = kl + (st0 + step) * 16;
+        const bool z_lo = k >= k1, z_hi = k + 2 >= k1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool z = q < 2 ? z_lo : z_hi;
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+                for (int j = 0; j < MJ; ++j)
+                    acc[i][j] = Op::mma(xa[i].v[q], z ? T(0) : xb[j].v[q], acc[i][j]);
+        }
+    };
+    if (n > 0) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) load(qa[u], qb[u], u);
+        int t = 0;
+        // full rounds: step t + u is used, then its slot is refilled with
+        // step t + u + PF (same load sequence on every path)
+        for (; t + PF < n; t += PF) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                mma_step(qa[u], qb[u], t + u);
+                // keep the refill between this step's and the next step's
+                // products (the scheduler would otherwise sink every load
+                // of the round below the last product)
+                __builtin_amdgcn_sched_barrier(0);
+                load(qa[u], qb[u], t + u + PF);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // last round: no more loads
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+            if (t + u < n) mma_step(qa[u], qb[u], t + u);
+    }
+
+    // partial tiles through LDS, added in wave order
+    T* mine = red[wave];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < MJ; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                mine[(i * 16 + Op::row(lane, q)) * LDR + j * 16 + (lane & 15)] = acc[i][j][q];
+    __syncthreads();
+    auto tile_sum = [&](int o) {
+        const int idx = (o / BS) * LDR + (o % BS);
+        T v = red[0][idx];
+#pragma unroll
+        for (int w = 1; w < W; ++w) v += red[w][idx];
+        return v;
+    };
+    if (splitk == 1) {
+        epi_dispatch(epi.mode, [&](auto m) {
+            constexpr int MODE = decltype(m)::value;
+            for (int o = threadIdx.x; o < BR * BS; o += W * 64) {
+                const int r = r0 + o / BS, s = s0 + o % BS;
+                if (r < sh.Mr && s < sh.Ns) epi_apply<MODE>(epi, r, s, (double)tile_sum(o));
+            }
+        });
+        return;
+    }
+    T* plane = part + (long)split * sh.Mr * sh.Ns;
+    for (int o = threadIdx.x; o < BR * BS; o += W * 64) {
+        const int r = r0 + o / BS, s = s0 + o % BS;
+        if (r < sh.Mr && s < sh.Ns) plane[(long)r * sh.Ns + s] = tile_sum(o);
+    }
+}
+
 // Persistent fine sweep: every fused step of one sweep in one cooperative
 // launch, for products whose state columns fit one row tile (Mr <= BR).
 // Step p: the work-groups compute the split-K partial tiles of Z W dev into
@@ -636,19 +818,10 @@ static void launch_reduce(dim3 g, dim3 b, hipStream_t stream, const GemmShape& s
     }
 }
 
-template <typename T, int BR, int BS, int BK>
-static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, GemmWork& ws,
-                             hipStream_t stream) {
-    const int tr = cdiv(sh.Mr, BR), tsn = cdiv(sh.Ns, BS);
-    dim3 grid(tr * tsn, splitk);
-    if (splitk > 1) {
-        const size_t need = (size_t)splitk * sh.Mr * sh.Ns * sizeof(T);
-        if (need > ws.part_bytes) return hipErrorInvalidValue;
-    }
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BR, BS, BK>), grid, dim3(256), 0, stream, sh, epi, tr, splitk,
-                       (T*)ws.part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || splitk == 1) return e;
+// split-K reduction of the partial planes in ws.part and the epilogue
+template <typename T>
+static hipError_t launch_splitk_reduce(const GemmShape& sh, const Epi& epi, int splitk, GemmWork& ws,
+                                       hipStream_t stream) {
     if (ws.between) ws.between(ws.between_arg);
     const long total = (long)sh.Mr * sh.Ns;
     long blocks = (total + 255) / 256;
@@ -665,6 +838,39 @@ static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, Ge
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T, int BR, int BS, int BK>
+static hipError_t launch_cfg(const GemmShape& sh, const Epi& epi, int splitk, GemmWork& ws,
+                             hipStream_t stream) {
+    const int tr = cdiv(sh.Mr, BR), tsn = cdiv(sh.Ns, BS);
+    dim3 grid(tr * tsn, splitk);
+    if (splitk > 1) {
+        const size_t need = (size_t)splitk * sh.Mr * sh.Ns * sizeof(T);
+        if (need > ws.part_bytes) return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BR, BS, BK>), grid, dim3(256), 0, stream, sh, epi, tr, splitk,
+                       (T*)ws.part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || splitk == 1) return e;
+    return launch_splitk_reduce<T>(sh, epi, splitk, ws, stream);
+}
+
+// wave-split-K kernel: W waves per work-group, PF steps in flight per wave
+template <typename T, int BS, int W>
+static hipError_t launch_wsk(const GemmShape& sh, const Epi& epi, int splitk, GemmWork& ws, hipStream_t stream) {
+    constexpr int PF = sizeof(T) == 4 ? 4 : 2;
+    const int tr = cdiv(sh.Mr, 64), tsn = cdiv(sh.Ns, BS);
+    dim3 grid(tr * tsn, splitk);
+    if (splitk > 1) {
+        const size_t need = (size_t)splitk * sh.Mr * sh.Ns * sizeof(T);
+        if (need > ws.part_bytes) return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((gemm_wsk_kernel<T, BS, W, PF>), grid, dim3(W * 64), 0, stream, sh, epi, tr, splitk,
+                       (T*)ws.part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || splitk == 1) return e;
+    return launch_splitk_reduce<T>(sh, epi, splitk, ws, stream);
 }
 
 template <typename T, int MODE>
@@ -705,6 +911,13 @@ hipError_t gemm_launch(const GemmShape& sh, const Epi& epi, const TileCfg& cfg, 
     if (sh.Mr <= 4) return launch_gemv<T>(sh, epi, stream);
     const int sk = cfg.splitk < 1 ? 1 : cfg.splitk;
     constexpr int B0 = MfmaOp<T>::BK;  // base K depth: 32 (FP32), 16 (FP64)
+    if (cfg.wsk > 0) {
+        if (cfg.bs == 32 && cfg.wsk == 4) return launch_wsk<T, 32, 4>(sh, epi, sk, ws, stream);
+        if (cfg.bs == 32 && cfg.wsk == 8) return launch_wsk<T, 32, 8>(sh, epi, sk, ws, stream);
+        if (cfg.bs == 16 && cfg.wsk == 4) return launch_wsk<T, 16, 4>(sh, epi, sk, ws, stream);
+        if (cfg.bs == 16 && cfg.wsk == 8) return launch_wsk<T, 16, 8>(sh, epi, sk, ws, stream);
+        return hipErrorInvalidValue;
+    }
     const bool deep = cfg.bk2 != 0;
 #define PE_CFG(R, S)                                                                 \
     if (cfg.br == R && cfg.bs == S)                                                  \

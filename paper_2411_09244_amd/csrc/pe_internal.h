@@ -104,6 +104,7 @@ struct Epi {
 struct TileCfg {
     int br = 64, bs = 64, splitk = 1;
     int bk2 = 0;  // 1: twice the base K depth per LDS stage
+    int wsk = 0;  // > 0: wave-split-K kernel with this many waves per work-group (64-row tiles)
 };
 
 // Workspace for split-K partial planes.

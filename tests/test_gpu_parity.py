@@ -269,3 +269,40 @@ def test_probe_peaks_sane():
     assert 0 < pk["fp32_mfma_tflops"] < 1.1 * 157.3
     assert 0 < pk["fp64_mfma_tflops"] < 1.1 * 78.6
     assert 0 < pk["hbm_copy_tbps"] < 1.1 * 8.0
+
+
+WSK_CFGS = ["32,4,1", "32,8,2", "16,4,4", "16,8,1"]
+
+
+@pytest.mark.parametrize("cfg", WSK_CFGS)
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX)])
+def test_wave_split_k_kernel(cfg, prec, tol, monkeypatch):
+    """Every product whose state columns fit one 64-row tile forced onto the
+    wave-split-K kernel (cfg = operator rows per tile, waves per work-group,
+    K splits): the fine propagator against the oracle on ragged and tiled
+    sizes (including the 200x200 workload), and parareal at equal k."""
+    pe = _pe()
+    monkeypatch.setenv("PE_FORCE_WSK", cfg)
+    for name in ("t1", "ragged", "c0", "c1"):
+        p = _prob(name)
+        bl, src = S.Blocks.from_problem(p), S.Source.from_problem(p)
+        B, N = p["B"], p["N"]
+        print(f"[wsk] {cfg} {prec} {name}", flush=True)
+        Xin = _random_states(p, 3, B, N)
+        pr = pe.problem_from(p, prec)
+        Y = pr.fine(Xin).cpu().numpy()
+        tiles = pr.last_tiles("fine_step")
+        assert tiles[2] == -int(cfg.split(",")[1]) and tiles[1] == int(cfg.split(",")[0]), tiles
+        for b in range(B):
+            ref = S.fine_propagator_cols(bl, src, Xin[b].T.copy(), list(range(N)), [b] * N).T
+            err = _colwise_rel(bl, Y[b], ref)
+            print(f"  F vs oracle b={b}: {err:.3e}")
+            assert err < tol, (name, cfg, prec, b, err)
+        if name in ("t1", "ragged"):
+            X, iters, hist, st = pr.solve(p["x0"], tol=0.0, k_max=3)
+            _, refs = _oracle_parareal(p, 3)
+            for b in range(B):
+                err = S.rel_l2_M(bl, X[b].cpu().numpy(), refs[b]["X"][3])
+                print(f"  parareal k=3 vs oracle b={b}: {err:.3e}")
+                assert err < tol, (name, cfg, prec, b, err)
+        pr.close()

@@ -298,6 +298,41 @@ pe_status pe_set_history(pe_problem p, int mode);
 pe_status pe_probe_peaks(void* hip_stream, double* out3);
 
 /*
+ * pe_cem_spaces - the set-up pipeline on the GPU: CEM-GMsFEM basis
+ * functions (Section 3.1, eq. (3.2)) and the Galerkin blocks of eq. (3.8).
+ * Medium: Q1 elements on the unit square with n x n cells of side 1/n,
+ * zero boundary values, kappa one value per cell (row-major, cell (cy, cx)
+ * at cy*n + cx). Coarse grid: n_c x n_c elements of m = n/n_c cells per
+ * side; the oversampled patch of element i is the element plus `layers`
+ * coarse layers, clipped to the domain. For every element i and j < J the
+ * basis function phi_j^(i) minimises a(phi, phi) over functions vanishing
+ * outside the patch's interior nodes, subject to s(phi, psi_l^(k)) =
+ * delta_{(k,l),(i,j)} for the J auxiliary functions of every element k of
+ * the patch (eq. (3.2)); the constraint data are spsi = S_k psi_l^(k), the
+ * local spectral eigenvectors of eq. (3.1) multiplied by the element's
+ * kappa H^-2-weighted mass, given per element on its (m+1)^2 local nodes
+ * (row-major) as n_c^2 x (m+1)^2 x J. Functions j < J1 of every element
+ * span V_H1 (d1 = n_c^2 J1, ordered element-major), j >= J1 span V_H2
+ * (d2 = n_c^2 (J - J1)); each is scaled to unit L2 norm.
+ * Outputs (caller-allocated, row-major): M11 (d1 x d1), M12 (d1 x d2),
+ * M22, A11, A12, A22 (the mass and kappa-weighted stiffness Gram blocks,
+ * the diagonal blocks symmetrised); with R > 0 the source factors
+ * G = [Psi1^T b; Psi2^T b] (D x R) of the fine-grid load vectors loads
+ * (R x (n-1)^2, one per interior node, row-major); Psi (nullable) the
+ * normalised basis, D x (n-1)^2 (one function per row, V_H1 first).
+ * All pointers are device memory; inputs are borrowed for the call. Work is
+ * ordered on hip_stream and the call returns after it finished. Allocates
+ * its workspace for the call (about 3 D (n-1)^2 + patches x 200 K doubles).
+ * Limits: J <= 8, at most 128 constraints per patch, at most 62 interior
+ * nodes along a patch row. Errors: PE_ERR_ARG, PE_ERR_NOT_SPD (a patch
+ * stiffness or constraint Gram matrix without a positive pivot, the patch
+ * named in the message), PE_ERR_NOMEM, PE_ERR_HIP.
+ */
+pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, const double* kappa, const double* spsi,
+                        int R, const double* loads, double* M11, double* M12, double* M22, double* A11,
+                        double* A12, double* A22, double* G, double* Psi, void* hip_stream);
+
+/*
  * Batches of different problems (different d1, d2, N, sources and sample
  * counts; same precision and step ratio P), solved together: every
  * product of a fine step runs as one grouped MFMA launch over all problems'

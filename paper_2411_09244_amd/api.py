@@ -287,6 +287,40 @@ def probe_peaks(device="cuda"):
     return {"fp32_mfma_tflops": out[0], "fp64_mfma_tflops": out[1], "hbm_copy_tbps": out[2]}
 
 
+def cem_spaces(kappa, spsi, n_c, layers, J1, loads=None, want_basis=False, device="cuda"):
+    """Multiscale spaces and Galerkin blocks on the GPU (pe_cem_spaces).
+    kappa: (n, n) cell values; spsi: (n_c^2, (m+1)^2, J) constraint data of
+    the local spectral problems; loads: (R, (n-1)^2) fine-grid load vectors
+    or None. Returns a dict of device tensors M11, M12, M22, A11, A12, A22,
+    G (D x R, if loads) and Psi (D x (n-1)^2, if want_basis)."""
+    lib = L.load()
+    dev = torch.device(device)
+    kappa = _dev(np.ascontiguousarray(kappa, dtype=np.float64), dev)
+    spsi = _dev(np.ascontiguousarray(spsi, dtype=np.float64), dev)
+    n = kappa.shape[0]
+    n_el, _, J = spsi.shape
+    d1, d2 = n_el * J1, n_el * (J - J1)
+    D = d1 + d2
+    z = lambda r, c: torch.zeros((r, c), dtype=torch.float64, device=dev)
+    out = {"M11": z(d1, d1), "M12": z(d1, d2), "M22": z(d2, d2), "A11": z(d1, d1), "A12": z(d1, d2),
+           "A22": z(d2, d2)}
+    R = 0
+    ld = None
+    if loads is not None:
+        ld = _dev(np.ascontiguousarray(np.atleast_2d(loads), dtype=np.float64), dev)
+        R = ld.shape[0]
+        out["G"] = z(D, R)
+    if want_basis:
+        out["Psi"] = z(D, (n - 1) ** 2)
+    p = lambda k: _ptr(out[k]) if k in out else None
+    with torch.cuda.device(dev):
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        L.check(lib.pe_cem_spaces(n, n_c, layers, J, J1, _ptr(kappa), _ptr(spsi), R,
+                                  _ptr(ld) if ld is not None else None, p("M11"), p("M12"), p("M22"),
+                                  p("A11"), p("A12"), p("A22"), p("G"), p("Psi"), st))
+    return out
+
+
 def problem_from(prob, precision="fp64", device="cuda"):
     """Problem + source from a workload dict (blocks, G, H, time_mode)."""
     blocks = {k: prob[k] for k in ("M11", "M12", "M22", "A11", "A12", "A22")}

@@ -63,6 +63,12 @@ inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
 }  // namespace
 
+namespace pe {
+// error status and message of the calling thread, for the other sources of
+// the library
+pe_status set_error(pe_status code, const std::string& msg) { return fail(code, msg); }
+}  // namespace pe
+
 // captured HIP graphs of repeated launch sequences, keyed by what fixes
 // their pointers (first visit eager, second captured, later replayed)
 struct GraphCache {
@@ -487,6 +493,9 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
                 PE_HIP(hipEventSynchronize(e1));
                 float ms = 0.f;
                 PE_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (getenv("PE_VERBOSE") && atoi(getenv("PE_VERBOSE")) > 1)
+                    fprintf(stderr, "[libpe]   candidate %dx%d bk2=%d splitk=%d wsk=%d: %.2f us\n", c.br, c.bs,
+                            c.bk2, c.splitk, c.wsk, ms / reps * 1e3);
                 if (ms / reps < best) {
                     best = ms / reps;
                     *best_out = c;
@@ -518,6 +527,9 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
                 PE_HIP(hipEventSynchronize(e1));
                 float ms = 0.f;
                 PE_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (getenv("PE_VERBOSE") && atoi(getenv("PE_VERBOSE")) > 1)
+                    fprintf(stderr, "[libpe]   candidate %dx%d bk2=%d splitk=%d wsk=%d: %.2f us\n", c.br, c.bs,
+                            c.bk2, c.splitk, c.wsk, ms / reps * 1e3);
                 if (ms / reps < best) {
                     best = ms / reps;
                     *best_out = c;

@@ -1,0 +1,635 @@
+// Set-up pipeline on the GPU: the CEM-GMsFEM basis functions of Section 3.1
+// (eq. (3.2)) on every oversampled patch, and the Galerkin blocks of eq. (3.8)
+// with the source factors.
+//
+// Basis. For coarse element i with oversampled patch K_i^+ (K_i plus `layers`
+// coarse layers, clipped to the domain) the basis functions phi_j^(i),
+// j < J, minimise the energy a(phi, phi) over H^1_0(K_i^+) subject to
+// s(phi, psi_l^(k)) = delta_{(k,l),(i,j)} for every auxiliary function of
+// every element k of the patch. With A the kappa-weighted Q1 stiffness on
+// the patch's interior nodes and C the constraint matrix (row (k, l) =
+// (S_k psi_l^(k))^T on the patch nodes), the saddle-point system
+//     [A C^T; C 0] [phi; mu] = [0; e_(i,j)]
+// gives phi = A^-1 C^T S^-1 e_(i,j) with S = C A^-1 C^T. Numbering the
+// patch's interior nodes row by row makes A banded with half-bandwidth
+// nx + 1 (nx nodes per row), so per patch:
+//   1. banded Cholesky A = L L^T (one work-group; the active (bw+1)^2
+//      window lives in LDS, stiffness entries are formed from kappa as rows
+//      enter the window);
+//   2. Y = L^-1 C^T by a forward sweep over the rows, one thread per
+//      constraint column;
+//   3. S = Y^T Y;
+//   4. Cholesky of S in LDS, z = S^-1 e_(i,j) for the J functions of
+//      element i, w = Y z, and phi = L^-T w by a backward sweep.
+// Projection. Every basis function is scattered into a dense row of
+// Psi^T (one row per function, fine-grid interior nodes as columns); the
+// fine mass and stiffness are applied by their 9-point stencils, the Gram
+// matrices Psi^T M Psi and Psi^T K Psi and the source factors Psi^T b come
+// from the FP64 MFMA product kernel, and a last kernel normalises every
+// function to unit L2 norm, symmetrises the diagonal blocks and writes the
+// blocks of the V_H1 / V_H2 split (the J1 lowest eigen-indices of every
+// element span V_H1, the next J2 span V_H2).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/pe.h"
+#include "pe_internal.h"
+
+namespace pe {
+
+pe_status set_error(pe_status code, const std::string& msg);
+
+namespace {
+
+constexpr int CEM_WN = 64;     // largest band window (half-bandwidth + 1)
+constexpr int CEM_NAUX = 128;  // largest number of constraints per patch
+constexpr int CEM_LDS_S = CEM_NAUX * CEM_NAUX;  // doubles of the step-4 LDS area
+
+struct CemGeom {
+    int n, n_c, m, layers, J;
+    long lb_stride;  // doubles of band storage per patch
+    long y_stride;   // doubles of Y per patch (rows x CEM_NAUX)
+    long ldp;        // row length of Psi^T (fine interior nodes, padded)
+    int n_dof1;      // interior nodes per side, n - 1
+};
+
+struct Patch {
+    int ex0, ey0, nex, ney;  // first coarse element and element counts
+    int gx0, gy0;            // global node of patch node 0
+    int nx, ny, nf;          // interior nodes per row, rows, total
+    int bw, wn;              // half-bandwidth nx + 1, window bw + 1
+    int naux;                // constraints nex * ney * J
+    int ai;                  // position of the patch's own element
+};
+
+__device__ inline Patch patch_of(const CemGeom& g, int i) {
+    Patch p;
+    const int ey = i / g.n_c, ex = i % g.n_c;
+    const int ey0 = max(ey - g.layers, 0), ey1 = min(ey + g.layers, g.n_c - 1);
+    const int ex0 = max(ex - g.layers, 0), ex1 = min(ex + g.layers, g.n_c - 1);
+    p.ex0 = ex0;
+    p.ey0 = ey0;
+    p.nex = ex1 - ex0 + 1;
+    p.ney = ey1 - ey0 + 1;
+    p.gx0 = ex0 * g.m + 1;
+    p.gy0 = ey0 * g.m + 1;
+    p.nx = p.nex * g.m - 1;
+    p.ny = p.ney * g.m - 1;
+    p.nf = p.nx * p.ny;
+    p.bw = p.nx + 1;
+    p.wn = p.bw + 1;
+    p.naux = p.nex * p.ney * g.J;
+    p.ai = (ey - ey0) * p.nex + (ex - ex0);
+    return p;
+}
+
+// Q1 stiffness between interior fine nodes (gy, gx) and (hy, hx): the
+// element matrix kappa/6 [[4,-1,-2,-1],...] summed over the cells that
+// contain both nodes (node (y, x) is a corner of cells (y-1|y, x-1|x)).
+__device__ inline double q1_stiff(const double* __restrict__ kappa, int n, int gy, int gx, int hy, int hx) {
+    const int dy = hy - gy, dx = hx - gx;
+    if (dy < -1 || dy > 1 || dx < -1 || dx > 1) return 0.0;
+    auto k = [&](int cy, int cx) { return kappa[(long)cy * n + cx]; };
+    if (dy == 0 && dx == 0) return (4.0 / 6.0) * (k(gy - 1, gx - 1) + k(gy - 1, gx) + k(gy, gx - 1) + k(gy, gx));
+    if (dy == 0) {
+        const int cx = min(gx, hx);
+        return (-1.0 / 6.0) * (k(gy - 1, cx) + k(gy, cx));
+    }
+    if (dx == 0) {
+        const int cy = min(gy, hy);
+        return (-1.0 / 6.0) * (k(cy, gx - 1) + k(cy, gx));
+    }
+    return (-2.0 / 6.0) * k(min(gy, hy), min(gx, hx));
+}
+
+// stiffness between patch nodes r and c
+__device__ inline double patch_stiff(const double* __restrict__ kappa, const CemGeom& g, const Patch& p, int r,
+                                     int c) {
+    const int ry = r / p.nx, rx = r - ry * p.nx;
+    const int cy = c / p.nx, cx = c - cy * p.nx;
+    return q1_stiff(kappa, g.n, p.gy0 + ry, p.gx0 + rx, p.gy0 + cy, p.gx0 + cx);
+}
+
+// constraint q = (patch element a, eigen-index l) at patch node r:
+// (S_k psi_l^(k)) at the node if it belongs to element k, else 0
+__device__ inline double constraint(const double* __restrict__ spsi, const CemGeom& g, const Patch& p, int q,
+                                    int r) {
+    const int a = q / g.J, l = q - a * g.J;
+    const int ky = p.ey0 + a / p.nex, kx = p.ex0 + a % p.nex;
+    const int ry = r / p.nx, rx = r - ry * p.nx;
+    const int ly = p.gy0 + ry - ky * g.m, lx = p.gx0 + rx - kx * g.m;
+    if (ly < 0 || ly > g.m || lx < 0 || lx > g.m) return 0.0;
+    const int k = ky * g.n_c + kx;
+    return spsi[((long)k * (g.m + 1) * (g.m + 1) + ly * (g.m + 1) + lx) * g.J + l];
+}
+
+// 1. banded Cholesky of the patch stiffness. Lb row r holds L[r][r - d] at
+// d = 0..bw. info[i] = 0, or the 1-based row of a non-positive pivot.
+__global__ __launch_bounds__(256) void k_cem_band_chol(const CemGeom g, const double* __restrict__ kappa,
+                                                       double* __restrict__ Lb, int* __restrict__ info) {
+    __shared__ double win[CEM_WN * CEM_WN];
+    __shared__ double col[CEM_WN];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const Patch p = patch_of(g, i);
+    const int nf = p.nf, bw = p.bw, wn = p.wn;
+    double* L = Lb + (long)i * g.lb_stride;
+    // rows 0..bw of the window: entries (r, c), max(0, r - bw) <= c <= r
+    for (int idx = tid; idx < wn * wn; idx += 256) {
+        const int r = idx / wn, d = idx - r * wn;
+        if (r < nf && d <= r) win[(r % wn) * wn + (r - d) % wn] = patch_stiff(kappa, g, p, r, r - d);
+    }
+    __syncthreads();
+    for (int j = 0; j < nf; ++j) {
+        // entry of the row entering the window at the end of this step
+        // (row j + wn, column j + 1 + tid), loaded early
+        const int rn = j + wn;
+        const double anew = (tid < wn && rn < nf) ? patch_stiff(kappa, g, p, rn, j + 1 + tid) : 0.0;
+        const double piv = win[(j % wn) * wn + j % wn];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (tid == 0) info[i] = j + 1;
+            return;  // uniform: every thread read the same pivot
+        }
+        const double s = sqrt(piv);
+        if (tid < wn) {
+            const int r = j + tid;
+            double l = 0.0;
+            if (r < nf) {
+                l = tid == 0 ? s : win[(r % wn) * wn + j % wn] / s;
+                L[(long)r * wn + tid] = l;
+            }
+            col[tid] = l;
+        }
+        __syncthreads();
+        // trailing update of rows j+1..j+bw (row j's slots are not touched)
+        for (int idx = tid; idx < bw * bw; idx += 256) {
+            const int a = idx / bw + 1, b = idx - (a - 1) * bw + 1;
+            if (b <= a && j + a < nf) win[((j + a) % wn) * wn + (j + b) % wn] -= col[a] * col[b];
+        }
+        // the new row takes the retired row j's slots
+        if (tid < wn && rn < nf) win[(rn % wn) * wn + (j + 1 + tid) % wn] = anew;
+        __syncthreads();
+    }
+    if (tid == 0) info[i] = 0;
+}
+
+// 2. Y = L^-1 C^T, one thread per constraint column; the last wn rows of Y
+// are kept in LDS for the band products. Y row r at Y + r * CEM_NAUX.
+__global__ __launch_bounds__(CEM_NAUX) void k_cem_forward(const CemGeom g, const double* __restrict__ Lb,
+                                                          const double* __restrict__ spsi, double* __restrict__ Yg) {
+    __shared__ double yw[CEM_WN][CEM_NAUX];
+    __shared__ double lrow[2][CEM_WN];
+    const int i = blockIdx.x, q = threadIdx.x;
+    const Patch p = patch_of(g, i);
+    const int nf = p.nf, wn = p.wn;
+    const double* L = Lb + (long)i * g.lb_stride;
+    double* Y = Yg + (long)i * g.y_stride;
+    const bool act = q < p.naux;
+    // row 0 operands
+    if (q < wn) lrow[0][q] = q == 0 ? L[0] : 0.0;
+    double c = act ? constraint(spsi, g, p, q, 0) : 0.0;
+    __syncthreads();
+    for (int r = 0; r < nf; ++r) {
+        const int cur = r & 1;
+        // next row's operands, loaded before this row's arithmetic
+        const int rn = r + 1;
+        const double ln = (q < wn && rn < nf && q <= rn) ? L[(long)rn * wn + q] : 0.0;
+        const double cn = (act && rn < nf) ? constraint(spsi, g, p, q, rn) : 0.0;
+        if (act) {
+            double s = c;
+            const int dmax = min(p.bw, r);
+            for (int d = 1; d <= dmax; ++d) s -= lrow[cur][d] * yw[(r - d) % wn][q];
+            const double y = s / lrow[cur][0];
+            yw[r % wn][q] = y;
+            Y[(long)r * CEM_NAUX + q] = y;
+        }
+        if (q < wn) lrow[cur ^ 1][q] = ln;
+        c = cn;
+        __syncthreads();
+    }
+}
+
+// 3. S = Y^T Y (naux x naux, stored CEM_NAUX x CEM_NAUX): 256 threads, each
+// an 8 x 8 block; Y staged through LDS 16 rows at a time.
+__global__ __launch_bounds__(256) void k_cem_gram(const CemGeom g, const double* __restrict__ Yg,
+                                                  double* __restrict__ Sg) {
+    constexpr int RB = 16;
+    __shared__ double ys[RB][CEM_NAUX];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const Patch p = patch_of(g, i);
+    const double* Y = Yg + (long)i * g.y_stride;
+    const int ty = tid / 16, tx = tid % 16;
+    double acc[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    for (int r0 = 0; r0 < p.nf; r0 += RB) {
+        for (int idx = tid; idx < RB * CEM_NAUX; idx += 256) {
+            const int rr = idx / CEM_NAUX, qq = idx % CEM_NAUX;
+            ys[rr][qq] = (r0 + rr < p.nf && qq < p.naux) ? Y[(long)(r0 + rr) * CEM_NAUX + qq] : 0.0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < RB; ++rr) {
+            double va[8], vb[8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) va[a] = ys[rr][ty * 8 + a];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) vb[b] = ys[rr][tx * 8 + b];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) acc[a][b] += va[a] * vb[b];
+        }
+        __syncthreads();
+    }
+    double* S = Sg + (long)i * CEM_NAUX * CEM_NAUX;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) S[(long)(ty * 8 + a) * CEM_NAUX + tx * 8 + b] = acc[a][b];
+}
+
+// 4. Cholesky of S in LDS, z = S^-1 e_(ai, l) for l < J, w = Y z,
+// phi = L^-T w; phi_l goes to row i * J + l of Psi^T at the fine interior
+// node of every patch node. info[i] = -(1-based pivot) if S is not positive.
+__global__ __launch_bounds__(256) void k_cem_finish(const CemGeom g, const double* __restrict__ Lb,
+                                                    const double* __restrict__ Yg, const double* __restrict__ Sg,
+                                                    double* __restrict__ PsiT, int* __restrict__ info) {
+    __shared__ double sh[CEM_LDS_S];  // S, then w (nf x J)
+    __shared__ double z[CEM_NAUX][8];
+    __shared__ double phw[CEM_WN][8];
+    __shared__ int bad;
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const Patch p = patch_of(g, i);
+    const int na = p.naux, J = g.J, nf = p.nf, wn = p.wn;
+    const double* Sgl = Sg + (long)i * CEM_NAUX * CEM_NAUX;
+    for (int idx = tid; idx < na * na; idx += 256) sh[idx] = Sgl[(long)(idx / na) * CEM_NAUX + idx % na];
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    // right-looking Cholesky, lower triangle of sh (na x na)
+    for (int k = 0; k < na; ++k) {
+        const double piv = sh[k * na + k];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (tid == 0) bad = k + 1;
+            break;  // uniform
+        }
+        const double s = sqrt(piv);
+        __syncthreads();
+        for (int r = k + 1 + tid; r < na; r += 256) sh[r * na + k] /= s;
+        if (tid == 0) sh[k * na + k] = s;
+        __syncthreads();
+        const int m = na - k - 1;
+        for (int idx = tid; idx < m * m; idx += 256) {
+            const int r = k + 1 + idx / m, c = k + 1 + idx % m;
+            if (c <= r) sh[r * na + c] -= sh[r * na + k] * sh[c * na + k];
+        }
+        __syncthreads();
+    }
+    __syncthreads();  // bad is written by thread 0 inside the loop
+    if (bad) {
+        if (tid == 0) info[i] = -bad;
+        return;  // uniform
+    }
+    // z = S^-1 e_(ai*J + l): forward and backward substitution, thread l
+    if (tid < J) {
+        const int l = tid, e = p.ai * J + l;
+        for (int r = 0; r < na; ++r) {
+            double v = r == e ? 1.0 : 0.0;
+            for (int c = 0; c < r; ++c) v -= sh[r * na + c] * z[c][l];
+            z[r][l] = v / sh[r * na + r];
+        }
+        for (int r = na - 1; r >= 0; --r) {
+            double v = z[r][l];
+            for (int c = r + 1; c < na; ++c) v -= sh[c * na + r] * z[c][l];
+            z[r][l] = v / sh[r * na + r];
+        }
+    }
+    __syncthreads();
+    // w = Y z into sh (nf x J), one thread per row
+    const double* Y = Yg + (long)i * g.y_stride;
+    for (int r = tid; r < nf; r += 256) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int q = 0; q < na; ++q) {
+            const double y = Y[(long)r * CEM_NAUX + q];
+#pragma unroll
+            for (int l = 0; l < 8; ++l) acc[l] += y * z[q][l];
+        }
+#pragma unroll
+        for (int l = 0; l < 8; ++l)
+            if (l < J) sh[r * J + l] = acc[l];
+    }
+    __syncthreads();
+    // phi = L^-T w by a backward sweep on wave 0 alone (in-order LDS
+    // traffic of one wave, no work-group barrier below): lane d - 1 holds
+    // L[r + d][r] for d = 1..bw; the last wn rows of phi stay in phw
+    if (tid >= 64) return;
+    const int lane = tid, d = lane + 1;
+    const double* L = Lb + (long)i * g.lb_stride;
+    const int n1 = g.n_dof1;
+    auto lval = [&](int r) { return (d <= p.bw && r + d < nf) ? L[(long)(r + d) * wn + d] : 0.0; };
+    auto ldiag = [&](int r) { return L[(long)r * wn]; };
+    double lc = lval(nf - 1), dg = ldiag(nf - 1);
+    for (int r = nf - 1; r >= 0; --r) {
+        const double ln = r > 0 ? lval(r - 1) : 0.0;
+        const double dn = r > 0 ? ldiag(r - 1) : 1.0;
+        const bool in = d <= p.bw && r + d < nf;
+        double part[8];
+#pragma unroll
+        for (int l = 0; l < 8; ++l) part[l] = (in && l < J) ? lc * phw[(r + d) % wn][l] : 0.0;
+#pragma unroll
+        for (int l = 0; l < 8; ++l) {
+            double v = part[l];
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+            part[l] = v;
+        }
+        // every lane holds the sums; lane l < J finishes column l
+        double mine = part[0];
+#pragma unroll
+        for (int l = 1; l < 8; ++l)
+            if (lane == l) mine = part[l];
+        if (lane < J) {
+            const double ph = (sh[r * J + lane] - mine) / dg;
+            phw[r % wn][lane] = ph;
+            const int ry = r / p.nx, rx = r - ry * p.nx;
+            const long dof = (long)(p.gy0 + ry - 1) * n1 + (p.gx0 + rx - 1);
+            PsiT[(long)(i * J + lane) * g.ldp + dof] = ph;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        lc = ln;
+        dg = dn;
+    }
+    if (lane == 0) info[i] = 0;
+}
+
+// M and K applied to rows of Psi^T by the Q1 stencils on the interior nodes
+__global__ __launch_bounds__(256) void k_cem_stencil(const double* __restrict__ kappa, int n, long ldp,
+                                                     const double* __restrict__ X, double* __restrict__ MX,
+                                                     double* __restrict__ KX) {
+    const int n1 = n - 1;
+    const long nd = (long)n1 * n1;
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    const long row = blockIdx.y;
+    if (t >= ldp) return;
+    if (t >= nd) {  // padding columns stay zero
+        MX[row * ldp + t] = 0.0;
+        KX[row * ldp + t] = 0.0;
+        return;
+    }
+    const int gy = (int)(t / n1) + 1, gx = (int)(t % n1) + 1;
+    const double h = 1.0 / n, h2 = h * h;
+    const double* x = X + row * ldp;
+    double m = 0.0, k = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int hy = gy + dy;
+        if (hy < 1 || hy > n1) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int hx = gx + dx;
+            if (hx < 1 || hx > n1) continue;
+            const double v = x[(long)(hy - 1) * n1 + (hx - 1)];
+            const int ad = (dy != 0) + (dx != 0);
+            // mass: 16/36 h^2 (same node), 2 cells x 2/36 h^2 (edge), 1/36 h^2 (diagonal)
+            const double mc = ad == 0 ? 16.0 / 36.0 : ad == 1 ? 4.0 / 36.0 : 1.0 / 36.0;
+            m += mc * h2 * v;
+            k += q1_stiff(kappa, n, gy, gx, hy, hx) * v;
+        }
+    }
+    MX[row * ldp + t] = m;
+    KX[row * ldp + t] = k;
+}
+
+// loads (R x n_dof) into a zero-padded copy (R x ldp)
+__global__ void k_cem_pad(const double* __restrict__ src, long nd, long ldp, long rows, double* __restrict__ dst) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= rows * ldp) return;
+    const long r = t / ldp, c = t % ldp;
+    dst[t] = c < nd ? src[r * nd + c] : 0.0;
+}
+
+// space index -> full index (element-major, J per element) of the V_H1 /
+// V_H2 split
+__device__ inline int cem_full(int s, int d1, int J, int J1) {
+    if (s < d1) return (s / J1) * J + s % J1;
+    const int J2 = J - J1, t = s - d1;
+    return (t / J2) * J + J1 + t % J2;
+}
+
+// blocks of eq. (3.8) from the Gram matrices of the unnormalised functions
+__global__ void k_cem_blocks(const double* __restrict__ Gm, const double* __restrict__ Gk, int Dall, int d1,
+                             int d2, int J, int J1, double* __restrict__ M11, double* __restrict__ M12,
+                             double* __restrict__ M22, double* __restrict__ A11, double* __restrict__ A12,
+                             double* __restrict__ A22) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    const int D = d1 + d2;
+    if (t >= (long)D * D) return;
+    const int a = (int)(t / D), b = (int)(t % D);
+    const int fa = cem_full(a, d1, J, J1), fb = cem_full(b, d1, J, J1);
+    const double s = 1.0 / (sqrt(Gm[(long)fa * Dall + fa]) * sqrt(Gm[(long)fb * Dall + fb]));
+    const double mab = Gm[(long)fa * Dall + fb] * s, mba = Gm[(long)fb * Dall + fa] * s;
+    const double kab = Gk[(long)fa * Dall + fb] * s, kba = Gk[(long)fb * Dall + fa] * s;
+    if (a < d1 && b < d1) {
+        M11[(long)a * d1 + b] = 0.5 * (mab + mba);
+        A11[(long)a * d1 + b] = 0.5 * (kab + kba);
+    } else if (a < d1) {
+        M12[(long)a * d2 + (b - d1)] = mab;
+        A12[(long)a * d2 + (b - d1)] = kab;
+    } else if (b >= d1) {
+        M22[(long)(a - d1) * d2 + (b - d1)] = 0.5 * (mab + mba);
+        A22[(long)(a - d1) * d2 + (b - d1)] = 0.5 * (kab + kba);
+    }
+}
+
+// source factors G (D x R) and, optionally, the normalised basis (D x n_dof)
+__global__ void k_cem_sources(const double* __restrict__ Gm, const double* __restrict__ GL, int Dall, int d1, int D,
+                              int J, int J1, int R, double* __restrict__ G) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)D * R) return;
+    const int a = (int)(t / R), c = (int)(t % R);
+    const int fa = cem_full(a, d1, J, J1);
+    G[t] = GL[(long)fa * R + c] / sqrt(Gm[(long)fa * Dall + fa]);
+}
+
+__global__ void k_cem_basis_out(const double* __restrict__ Gm, const double* __restrict__ PsiT, int Dall, int d1,
+                                int D, int J, int J1, long nd, long ldp, double* __restrict__ out) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)D * nd) return;
+    const int a = (int)(t / nd);
+    const long c = t % nd;
+    const int fa = cem_full(a, d1, J, J1);
+    out[t] = PsiT[(long)fa * ldp + c] / sqrt(Gm[(long)fa * Dall + fa]);
+}
+
+}  // namespace
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, const double* kappa,
+                                   const double* spsi, int R, const double* loads, double* M11, double* M12,
+                                   double* M22, double* A11, double* A12, double* A22, double* G, double* Psi,
+                                   void* hip_stream) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (n <= 0 || n_c <= 0 || n % n_c != 0 || layers < 0 || J <= 0 || J > 8 || J1 <= 0 || J1 > J || !kappa ||
+        !spsi || R < 0 || (R > 0 && (!loads || !G)) || !M11 || !M22 || !A11 || !A22 ||
+        (J1 < J && (!M12 || !A12)))
+        return set_error(PE_ERR_ARG, "pe_cem_spaces: bad arguments");
+    const int m = n / n_c;
+    if (m < 2) return set_error(PE_ERR_ARG, "pe_cem_spaces: a coarse element needs at least 2 fine cells per side");
+    const int span = std::min(2 * layers + 1, n_c);  // coarse elements per patch side, at most
+    const int nx_max = span * m - 1, nf_max = nx_max * nx_max;
+    if (nx_max + 2 > CEM_WN)
+        return set_error(PE_ERR_ARG, "pe_cem_spaces: patch rows of " + std::to_string(nx_max) +
+                                         " nodes exceed the band window (at most " + std::to_string(CEM_WN - 2) +
+                                         ")");
+    if (span * span * J > CEM_NAUX)
+        return set_error(PE_ERR_ARG, "pe_cem_spaces: more than " + std::to_string(CEM_NAUX) +
+                                         " constraints per patch");
+    if ((long)nf_max * J > CEM_LDS_S)
+        return set_error(PE_ERR_ARG, "pe_cem_spaces: patch too large for the final sweep");
+    const int n_elem = n_c * n_c, Dall = n_elem * J;
+    const int d1 = n_elem * J1, d2 = n_elem * (J - J1), D = d1 + d2;
+    const long nd = (long)(n - 1) * (n - 1);
+    const long ldp = (nd + 7) / 8 * 8;
+
+    CemGeom g;
+    g.n = n;
+    g.n_c = n_c;
+    g.m = m;
+    g.layers = layers;
+    g.J = J;
+    g.lb_stride = (long)nf_max * (nx_max + 2);
+    g.y_stride = (long)nf_max * CEM_NAUX;
+    g.ldp = ldp;
+    g.n_dof1 = n - 1;
+
+    std::vector<void*> bufs;
+    auto alloc = [&](void** ptr, size_t bytes) {
+        if (hipMalloc(ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *ptr = nullptr;
+            return false;
+        }
+        bufs.push_back(*ptr);
+        return true;
+    };
+    auto done = [&](pe_status s) {
+        (void)hipStreamSynchronize(st);
+        for (void* b : bufs) (void)hipFree(b);
+        return s;
+    };
+    double *Lb, *Yb, *Sb, *PsiT, *MX, *KX, *Gm, *Gk, *Ld = nullptr, *GL = nullptr;
+    int* info;
+    if (!alloc((void**)&Lb, sizeof(double) * g.lb_stride * n_elem) ||
+        !alloc((void**)&Yb, sizeof(double) * g.y_stride * n_elem) ||
+        !alloc((void**)&Sb, sizeof(double) * CEM_NAUX * CEM_NAUX * n_elem) ||
+        !alloc((void**)&PsiT, sizeof(double) * ldp * Dall) || !alloc((void**)&MX, sizeof(double) * ldp * Dall) ||
+        !alloc((void**)&KX, sizeof(double) * ldp * Dall) || !alloc((void**)&Gm, sizeof(double) * Dall * Dall) ||
+        !alloc((void**)&Gk, sizeof(double) * Dall * Dall) || !alloc((void**)&info, sizeof(int) * n_elem) ||
+        (R > 0 && (!alloc((void**)&Ld, sizeof(double) * ldp * R) || !alloc((void**)&GL, sizeof(double) * Dall * R))))
+        return done(set_error(PE_ERR_NOMEM, "pe_cem_spaces: device memory"));
+    auto hip_ok = [&](hipError_t e, const char* what) -> pe_status {
+        if (e == hipSuccess) return PE_OK;
+        return set_error(PE_ERR_HIP, std::string("pe_cem_spaces: ") + what + ": " + hipGetErrorString(e));
+    };
+    pe_status s;
+    if ((s = hip_ok(hipMemsetAsync(PsiT, 0, sizeof(double) * ldp * Dall, st), "clear")) != PE_OK) return done(s);
+    if ((s = hip_ok(hipMemsetAsync(info, 0, sizeof(int) * n_elem, st), "clear")) != PE_OK) return done(s);
+    hipLaunchKernelGGL(k_cem_band_chol, dim3(n_elem), dim3(256), 0, st, g, kappa, Lb, info);
+    hipLaunchKernelGGL(k_cem_forward, dim3(n_elem), dim3(CEM_NAUX), 0, st, g, Lb, spsi, Yb);
+    hipLaunchKernelGGL(k_cem_gram, dim3(n_elem), dim3(256), 0, st, g, Yb, Sb);
+    if ((s = hip_ok(hipGetLastError(), "patch kernels")) != PE_OK) return done(s);
+    // a failed band factorisation leaves its patch's later stages reading
+    // finite garbage only; its status is reported below
+    std::vector<int> hinfo(n_elem);
+    if ((s = hip_ok(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * n_elem, hipMemcpyDeviceToHost, st),
+                    "status")) != PE_OK)
+        return done(s);
+    if ((s = hip_ok(hipStreamSynchronize(st), "patch factorisations")) != PE_OK) return done(s);
+    for (int i = 0; i < n_elem; ++i)
+        if (hinfo[i] != 0)
+            return done(set_error(PE_ERR_NOT_SPD, "pe_cem_spaces: patch " + std::to_string(i) +
+                                                      " stiffness not positive definite at row " +
+                                                      std::to_string(hinfo[i])));
+    hipLaunchKernelGGL(k_cem_finish, dim3(n_elem), dim3(256), 0, st, g, Lb, Yb, Sb, PsiT, info);
+    if ((s = hip_ok(hipGetLastError(), "basis kernel")) != PE_OK) return done(s);
+    if ((s = hip_ok(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * n_elem, hipMemcpyDeviceToHost, st),
+                    "status")) != PE_OK)
+        return done(s);
+    if ((s = hip_ok(hipStreamSynchronize(st), "basis functions")) != PE_OK) return done(s);
+    for (int i = 0; i < n_elem; ++i)
+        if (hinfo[i] != 0)
+            return done(set_error(PE_ERR_NOT_SPD, "pe_cem_spaces: constraint Gram matrix of patch " +
+                                                      std::to_string(i) + " not positive definite at row " +
+                                                      std::to_string(-hinfo[i])));
+    // projections
+    const unsigned gx = (unsigned)((ldp + 255) / 256);
+    hipLaunchKernelGGL(k_cem_stencil, dim3(gx, Dall), dim3(256), 0, st, kappa, n, ldp, PsiT, MX, KX);
+    if (R > 0) {
+        const long tot = (long)R * ldp;
+        hipLaunchKernelGGL(k_cem_pad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, loads, nd, ldp,
+                           (long)R, Ld);
+    }
+    if ((s = hip_ok(hipGetLastError(), "stencil")) != PE_OK) return done(s);
+    GemmWork ws;
+    auto product = [&](const double* Bop, int Ns, double* C) -> pe_status {
+        GemmShape sh;
+        sh.Mr = Dall;
+        sh.Ns = Ns;
+        sh.A = PsiT;
+        sh.lda = ldp;
+        sh.B = Bop;
+        sh.ldb = ldp;
+        sh.s_split = Ns;
+        sh.k0a = 0;
+        sh.k1a = (int)ldp;
+        sh.k0b = 0;
+        sh.k1b = 0;
+        Epi epi;
+        epi.mode = EPI_STORE;
+        epi.C = C;
+        epi.ldc = Ns;
+        TileCfg cfg = choose_tiles(sh, false, 256);
+        const size_t need = gemm_part_bytes(sh, cfg, sizeof(double));
+        if (need > ws.part_bytes) {
+            if (ws.part) (void)hipFree(ws.part);
+            ws.part = nullptr;
+            ws.part_bytes = 0;
+            if (hipMalloc(&ws.part, need) != hipSuccess) {
+                (void)hipGetLastError();
+                return set_error(PE_ERR_NOMEM, "pe_cem_spaces: product workspace");
+            }
+            ws.part_bytes = need;
+        }
+        return hip_ok(gemm_launch<double>(sh, epi, cfg, ws, st), "Gram product");
+    };
+    s = product(MX, Dall, Gm);
+    if (s == PE_OK) s = product(KX, Dall, Gk);
+    if (s == PE_OK && R > 0) s = product(Ld, R, GL);
+    if (s != PE_OK) {
+        pe_status r = done(s);
+        if (ws.part) (void)hipFree(ws.part);
+        return r;
+    }
+    {
+        const long tot = (long)D * D;
+        hipLaunchKernelGGL(k_cem_blocks, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Gm, Gk, Dall, d1,
+                           d2, J, J1, M11, M12, M22, A11, A12, A22);
+    }
+    if (R > 0) {
+        const long tot = (long)D * R;
+        hipLaunchKernelGGL(k_cem_sources, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Gm, GL, Dall, d1,
+                           D, J, J1, R, G);
+    }
+    if (Psi) {
+        const long tot = (long)D * nd;
+        hipLaunchKernelGGL(k_cem_basis_out, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Gm, PsiT, Dall,
+                           d1, D, J, J1, nd, ldp, Psi);
+    }
+    s = hip_ok(hipGetLastError(), "block kernels");
+    pe_status r = done(s);
+    if (ws.part) (void)hipFree(ws.part);
+    return r;
+}

@@ -1,0 +1,144 @@
+"""GPU set-up pipeline (pe_cem_spaces) against the CPU generator: CEM-GMsFEM
+basis functions of eq. (3.2) on every oversampled patch (banded Cholesky and
+constraint Schur complement on the GPU; sparse LU of the saddle-point system
+on the CPU) and the Galerkin blocks of eq. (3.8) with the source factors.
+
+Both sides compute in FP64 by different factorisations of the same
+saddle-point system (the CPU's sparse LU pivots within the saddle-point
+matrix; the GPU factors the patch stiffness, then the constraint Schur
+complement). The bar is the FP64 path's parity bar, 1e-10 relative
+(Frobenius), for the basis, every block and the source factors: the blocks
+feed the FP64 solve, whose own bar is 1e-10. The properties that fix the
+basis (unit norm, support, constraints) are checked on the GPU basis alone."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from problem.build import CONFIGS, build_problem, make_medium, project_blocks
+from problem.cem import CoarseGrid, cem_basis, local_spectral, split_spaces
+from problem.fem import FineGrid
+
+pytestmark = pytest.mark.gpu
+
+BAR = 1e-10
+BLOCKS = ("M11", "M12", "M22", "A11", "A12", "A22")
+
+
+def _pe():
+    import paper_2411_09244_amd as pe
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return pe
+
+
+def _cpu_spaces(cfg):
+    kappa = make_medium(cfg)
+    fine = FineGrid(kappa)
+    cg = CoarseGrid(fine, cfg["n_c"])
+    J = cfg["J1"] + cfg["J2"]
+    lam, psi, spsi = local_spectral(cg, J)
+    phis = cem_basis(cg, J, cfg["layers"], spsi)
+    Psi1, Psi2 = split_spaces(cg, phis, cfg["J1"], cfg["J2"])
+    return kappa, fine, cg, spsi, Psi1, Psi2
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("name", ["t0", "t1", "c0", "t2"])
+def test_cem_spaces_match_cpu(name):
+    pe = _pe()
+    cfg = dict(CONFIGS[name])
+    print(f"[cem] {name}", flush=True)
+    kappa, fine, cg, spsi, Psi1, Psi2 = _cpu_spaces(cfg)
+    bl = project_blocks(fine, Psi1, Psi2)
+    loads = np.stack([fine.load_smooth(lambda x, y: np.sin(np.pi * x) * np.sin(np.pi * y)),
+                      fine.load_smooth(lambda x, y: np.ones_like(x))])
+    Gref = np.concatenate([Psi1.T @ loads.T, Psi2.T @ loads.T])
+    out = pe.cem_spaces(kappa, spsi, cfg["n_c"], cfg["layers"], cfg["J1"], loads=loads, want_basis=True)
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    ref_psi = np.vstack([Psi1.T.toarray(), Psi2.T.toarray()])
+    e = _rel(out["Psi"], ref_psi)
+    print(f"  basis rel {e:.3e}")
+    assert e < BAR
+    for k in BLOCKS:
+        e = _rel(out[k], bl[k])
+        print(f"  {k} rel {e:.3e}")
+        assert e < BAR, k
+    e = _rel(out["G"], Gref)
+    print(f"  G rel {e:.3e}")
+    assert e < BAR
+    # properties of the GPU basis alone: unit L2 norm, support inside the
+    # patch, and the constraints s(phi_j^(i), psi_l^(k)) = delta (eq. (3.2))
+    # up to the normalisation factor of each function
+    Psi = out["Psi"]
+    Mf = fine.M
+    nrm = np.sqrt(np.einsum("ij,ij->i", Psi, (Mf @ Psi.T).T))
+    assert np.abs(nrm - 1).max() < 1e-12
+    n, m, J, J1 = fine.n, cg.m, cfg["J1"] + cfg["J2"], cfg["J1"]
+    n_el = cg.n_elem
+    for i in (0, n_el // 2, n_el - 1):
+        for j in range(J):
+            row = i * J1 + j if j < J1 else n_el * J1 + i * (J - J1) + (j - J1)
+            elems, free_ids = cg.patch(i, cfg["layers"])
+            outside = np.ones(fine.n_dof, dtype=bool)
+            outside[fine.node2dof[free_ids]] = False
+            assert not outside.any() or np.abs(Psi[row][outside]).max() == 0.0
+            # constraint values against every auxiliary function of the patch
+            vals = []
+            for k in elems:
+                nodes = cg.element_nodes(k)
+                dofs = fine.node2dof[nodes]
+                keep = dofs >= 0
+                vals.append(spsi[k][keep].T @ Psi[row][dofs[keep]])
+            vals = np.concatenate(vals)
+            a_i = int(np.flatnonzero(elems == i)[0])
+            target = np.zeros_like(vals)
+            target[a_i * J + j] = 1.0
+            scale = np.abs(vals).max()
+            assert np.abs(vals / scale - target).max() < 1e-9, (i, j)
+
+
+def test_cem_spaces_full_size():
+    """The 200 x 200 workload (20 x 20 coarse elements, 400 patches of up to
+    49 x 49 nodes): GPU blocks and source factor against the CPU generator's,
+    with the GPU pipeline's time beside the CPU build time."""
+    pe = _pe()
+    cfg = dict(CONFIGS["c1"])
+    p = build_problem("c1")
+    kappa = make_medium(cfg)
+    fine = FineGrid(kappa)
+    cg = CoarseGrid(fine, cfg["n_c"])
+    t0 = time.perf_counter()
+    _, _, spsi = local_spectral(cg, cfg["J1"] + cfg["J2"])
+    t_spec = time.perf_counter() - t0
+    loads = fine.load_smooth(lambda x, y: np.sin(np.pi * x) * np.sin(np.pi * y))[None]
+    pe.cem_spaces(kappa, spsi, cfg["n_c"], cfg["layers"], cfg["J1"], loads=loads)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = pe.cem_spaces(kappa, spsi, cfg["n_c"], cfg["layers"], cfg["J1"], loads=loads)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    print(f"c1 set-up: GPU pipeline {t_gpu:.3f} s (local spectral problems on the host {t_spec:.2f} s)")
+    for k in BLOCKS:
+        e = _rel(out[k].cpu().numpy(), p[k])
+        print(f"  {k} rel {e:.3e}")
+        assert e < BAR, k
+    e = _rel(out["G"].cpu().numpy(), p["G"])
+    print(f"  G rel {e:.3e}")
+    assert e < BAR
+
+
+def test_cem_spaces_errors():
+    pe = _pe()
+    kappa = np.ones((20, 20))
+    spsi = np.zeros((4, 121, 5))
+    with pytest.raises(pe.PeError):  # n not a multiple of n_c
+        pe.cem_spaces(np.ones((21, 21)), spsi, 2, 1, 2)
+    with pytest.raises(pe.PeError):  # more than 8 functions per element
+        pe.cem_spaces(kappa, np.zeros((4, 121, 9)), 2, 1, 2)
+    with pytest.raises(pe.PeError) as ei:  # zero constraints: singular constraint Gram matrix
+        pe.cem_spaces(kappa, spsi, 2, 1, 2)
+    assert ei.value.status == -2

@@ -322,7 +322,8 @@ pe_status pe_probe_peaks(void* hip_stream, double* out3);
  * normalised basis, D x (n-1)^2 (one function per row, V_H1 first).
  * All pointers are device memory; inputs are borrowed for the call. Work is
  * ordered on hip_stream and the call returns after it finished. Allocates
- * its workspace for the call (about 3 D (n-1)^2 + patches x 200 K doubles).
+ * its workspace for the call (about 3 D (n-1)^2 doubles, plus about 450 K
+ * doubles per patch at 49 x 49 patch nodes).
  * Limits: J <= 8, at most 128 constraints per patch, at most 62 interior
  * nodes along a patch row. Errors: PE_ERR_ARG, PE_ERR_NOT_SPD (a patch
  * stiffness or constraint Gram matrix without a positive pivot, the patch

@@ -298,6 +298,30 @@ pe_status pe_set_history(pe_problem p, int mode);
 pe_status pe_probe_peaks(void* hip_stream, double* out3);
 
 /*
+ * pe_local_spectral - the local spectral problems of eq. (3.1) on the GPU:
+ * on every coarse element A_e psi = lambda S_e psi over the element's nodes
+ * not on the domain boundary (natural conditions on interior coarse edges),
+ * A_e the kappa-weighted Q1 stiffness and S_e the (kappa H^-2)-weighted Q1
+ * mass over the element's cells (same medium and grids as pe_cem_spaces,
+ * m = n/n_c cells per element side, (m+1)^2 <= 128). Outputs, per element
+ * e, its J smallest eigenvalues lam (n_c^2 x J, ascending), the
+ * S_e-orthonormal eigenvectors psi (nullable; n_c^2 x (m+1)^2 x J on the
+ * local nodes, row-major, zero on the domain boundary) and spsi = S_e psi
+ * over all local nodes (the constraint data pe_cem_spaces takes). An
+ * eigenvector is fixed up to sign: each is signed so that sum_f (f+1) psi_f
+ * > 0 over the free nodes f in local order; within an eigenvalue of
+ * multiplicity > 1 the vectors are one orthonormal basis of the eigenspace
+ * (the one the rotations reach). Dense per element: Cholesky of S_e, cyclic
+ * Jacobi on L^-1 A_e L^-T (sweeps until the off-diagonal Frobenius norm is
+ * below 1e-16 of the diagonal's, at most 30). All pointers are device
+ * memory; work on hip_stream, returns when done. Allocates 256 KiB per
+ * element for the call. Errors: PE_ERR_ARG, PE_ERR_NOT_SPD (an element's
+ * weighted mass), PE_ERR_NOMEM, PE_ERR_HIP.
+ */
+pe_status pe_local_spectral(int n, int n_c, int J, const double* kappa, double* lam, double* psi, double* spsi,
+                            void* hip_stream);
+
+/*
  * pe_cem_spaces - the set-up pipeline on the GPU: CEM-GMsFEM basis
  * functions (Section 3.1, eq. (3.2)) and the Galerkin blocks of eq. (3.8).
  * Medium: Q1 elements on the unit square with n x n cells of side 1/n,

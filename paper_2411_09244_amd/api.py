@@ -287,16 +287,43 @@ def probe_peaks(device="cuda"):
     return {"fp32_mfma_tflops": out[0], "fp64_mfma_tflops": out[1], "hbm_copy_tbps": out[2]}
 
 
-def cem_spaces(kappa, spsi, n_c, layers, J1, loads=None, want_basis=False, device="cuda"):
+def local_spectral(kappa, n_c, J, device="cuda"):
+    """Local spectral problems of eq. (3.1) on the GPU (pe_local_spectral).
+    kappa: (n, n) cell values. Returns device tensors lam (n_c^2, J),
+    psi and spsi (n_c^2, (m+1)^2, J)."""
+    lib = L.load()
+    dev = torch.device(device)
+    if torch.is_tensor(kappa):
+        kappa = kappa.to(device=dev, dtype=torch.float64).contiguous()
+    else:
+        kappa = _dev(np.ascontiguousarray(kappa, dtype=np.float64), dev)
+    n = kappa.shape[0]
+    m = n // n_c
+    lam = torch.zeros((n_c * n_c, J), dtype=torch.float64, device=dev)
+    psi = torch.zeros((n_c * n_c, (m + 1) ** 2, J), dtype=torch.float64, device=dev)
+    spsi = torch.zeros_like(psi)
+    with torch.cuda.device(dev):
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        L.check(lib.pe_local_spectral(n, n_c, J, _ptr(kappa), _ptr(lam), _ptr(psi), _ptr(spsi), st))
+    return lam, psi, spsi
+
+
+def cem_spaces(kappa, spsi, n_c, layers, J1, loads=None, want_basis=False, device="cuda", J=None):
     """Multiscale spaces and Galerkin blocks on the GPU (pe_cem_spaces).
     kappa: (n, n) cell values; spsi: (n_c^2, (m+1)^2, J) constraint data of
-    the local spectral problems; loads: (R, (n-1)^2) fine-grid load vectors
-    or None. Returns a dict of device tensors M11, M12, M22, A11, A12, A22,
+    the local spectral problems, or None to solve them on the GPU as well
+    (pe_local_spectral, J functions per element); loads: (R, (n-1)^2)
+    fine-grid load vectors or None. Returns a dict of device tensors M11, M12, M22, A11, A12, A22,
     G (D x R, if loads) and Psi (D x (n-1)^2, if want_basis)."""
     lib = L.load()
     dev = torch.device(device)
     kappa = _dev(np.ascontiguousarray(kappa, dtype=np.float64), dev)
-    spsi = _dev(np.ascontiguousarray(spsi, dtype=np.float64), dev)
+    if spsi is None:
+        if J is None:
+            raise ValueError("cem_spaces: J (functions per element) is needed when spsi is None")
+        _, _, spsi = local_spectral(kappa, n_c, J, device=device)
+    else:
+        spsi = _dev(np.ascontiguousarray(spsi, dtype=np.float64), dev)
     n = kappa.shape[0]
     n_el, _, J = spsi.shape
     d1, d2 = n_el * J1, n_el * (J - J1)

@@ -462,6 +462,303 @@ __global__ void k_cem_basis_out(const double* __restrict__ Gm, const double* __r
     out[t] = PsiT[(long)fa * ldp + c] / sqrt(Gm[(long)fa * Dall + fa]);
 }
 
+// ---------------------------------------------------------------------------
+// Local spectral problems of eq. (3.1): on every coarse element
+// A_e psi = lambda S_e psi over the element's nodes not on the boundary of
+// the domain (natural conditions on interior coarse edges), A_e the
+// kappa-weighted Q1 stiffness and S_e the (kappa H^-2)-weighted Q1 mass over
+// the element's cells. One work-group per element: S_e = L L^T (Cholesky in
+// LDS), C = L^-1 A_e L^-T, cyclic Jacobi on C in LDS with the round-robin
+// pair order (n/2 disjoint rotations per round, C <- R^T C R; the
+// accumulated rotations V in global memory), the J smallest eigenvalues,
+// psi = L^-T V[:, j] (S_e-orthonormal). Each psi is signed so that
+// sum_f (f + 1) psi[f] > 0 over the free nodes f in local order (an
+// eigenvector is fixed only up to sign).
+// ---------------------------------------------------------------------------
+constexpr int SPEC_N = 128;  // largest number of element nodes
+
+// element matrix entry between nodes (gy, gx), (hy, hx) of element (ey, ex):
+// sum over the element's cells containing both of kappa_c * (stiffness
+// reference entry) or kappa_c * (mass reference entry)
+__device__ inline void elem_pair(const double* __restrict__ kappa, int n, int m, int ey, int ex, int gy, int gx,
+                                 int hy, int hx, double& a, double& s) {
+    a = 0.0;
+    s = 0.0;
+    const int dy = hy - gy, dx = hx - gx;
+    if (dy < -1 || dy > 1 || dx < -1 || dx > 1) return;
+    const int ad = (dy != 0) + (dx != 0);
+    const double ke = ad == 0 ? 4.0 / 6.0 : ad == 1 ? -1.0 / 6.0 : -2.0 / 6.0;
+    const double me = ad == 0 ? 4.0 / 36.0 : ad == 1 ? 2.0 / 36.0 : 1.0 / 36.0;
+    for (int cy = max(gy, hy) - 1; cy <= min(gy, hy); ++cy) {
+        if (cy < ey * m || cy >= (ey + 1) * m) continue;
+        for (int cx = max(gx, hx) - 1; cx <= min(gx, hx); ++cx) {
+            if (cx < ex * m || cx >= (ex + 1) * m) continue;
+            const double k = kappa[(long)cy * n + cx];
+            a += k * ke;
+            s += k * me;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, const double* __restrict__ kappa,
+                                                      double* __restrict__ Lg, double* __restrict__ Vg,
+                                                      double* __restrict__ lam, double* __restrict__ psi,
+                                                      double* __restrict__ spsi, int* __restrict__ info) {
+    __shared__ double C[SPEC_N * SPEC_N];
+    __shared__ double cs[SPEC_N / 2], sn[SPEC_N / 2];
+    __shared__ int pp[SPEC_N / 2], qq[SPEC_N / 2];
+    __shared__ int node_of[SPEC_N];  // free index -> local node
+    __shared__ int free_of[SPEC_N];  // local node -> free index or -1
+    __shared__ double red[256];
+    __shared__ int sel[8];
+    __shared__ int nfree, bad;
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const int m = n / n_c, ml = m + 1, nl = ml * ml;
+    const int ey = e / n_c, ex = e % n_c;
+    const double H = 1.0 / n_c, h = 1.0 / n, sw = h * h / (H * H);  // mass weight h^2 / H^2
+    double* L = Lg + (long)e * SPEC_N * SPEC_N;
+    double* V = Vg + (long)e * SPEC_N * SPEC_N;
+    if (tid == 0) {
+        int c = 0;
+        for (int ln = 0; ln < nl; ++ln) {
+            const int gy = ey * m + ln / ml, gx = ex * m + ln % ml;
+            const bool fr = gy >= 1 && gy <= n - 1 && gx >= 1 && gx <= n - 1;
+            free_of[ln] = fr ? c : -1;
+            if (fr) node_of[c++] = ln;
+        }
+        nfree = c;
+        bad = 0;
+    }
+    __syncthreads();
+    const int nf = nfree;
+    const int n2 = nf + (nf & 1);  // even size for the round-robin pairs
+    auto gnode = [&](int f, int& gy, int& gx) {
+        const int ln = node_of[f];
+        gy = ey * m + ln / ml;
+        gx = ex * m + ln % ml;
+    };
+    // S_e (free x free) in LDS, Cholesky in place (lower)
+    for (int idx = tid; idx < nf * nf; idx += 256) {
+        const int r = idx / nf, c = idx % nf;
+        int gy, gx, hy, hx;
+        gnode(r, gy, gx);
+        gnode(c, hy, hx);
+        double a, s;
+        elem_pair(kappa, n, m, ey, ex, gy, gx, hy, hx, a, s);
+        C[r * nf + c] = s * sw;
+    }
+    __syncthreads();
+    for (int k = 0; k < nf; ++k) {
+        const double piv = C[k * nf + k];
+        if (!(piv > 0.0)) {
+            if (tid == 0) bad = 1;
+            break;  // uniform
+        }
+        const double sq = sqrt(piv);
+        __syncthreads();
+        for (int r = k + 1 + tid; r < nf; r += 256) C[r * nf + k] /= sq;
+        if (tid == 0) C[k * nf + k] = sq;
+        __syncthreads();
+        const int w = nf - k - 1;
+        for (int idx = tid; idx < w * w; idx += 256) {
+            const int r = k + 1 + idx / w, c = k + 1 + idx % w;
+            if (c <= r) C[r * nf + c] -= C[r * nf + k] * C[c * nf + k];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) info[e] = 1;
+        return;  // uniform
+    }
+    for (int idx = tid; idx < nf * nf; idx += 256) {
+        const int r = idx / nf, c = idx % nf;
+        L[r * SPEC_N + c] = c <= r ? C[r * nf + c] : 0.0;
+    }
+    __syncthreads();
+    // A_e into LDS (stride n2), then X = L^-1 A (thread per column) and
+    // C = X L^-T (thread per row); pad row/column nf (odd nf) decoupled with
+    // a diagonal above every eigenvalue
+    for (int idx = tid; idx < n2 * n2; idx += 256) {
+        const int r = idx / n2, c = idx % n2;
+        double a = 0.0, s;
+        if (r < nf && c < nf) {
+            int gy, gx, hy, hx;
+            gnode(r, gy, gx);
+            gnode(c, hy, hx);
+            elem_pair(kappa, n, m, ey, ex, gy, gx, hy, hx, a, s);
+        }
+        C[r * n2 + c] = a;
+    }
+    __syncthreads();
+    if (tid < nf) {
+        const int j = tid;
+        for (int r = 0; r < nf; ++r) {
+            double v = C[r * n2 + j];
+            for (int c = 0; c < r; ++c) v -= L[r * SPEC_N + c] * C[c * n2 + j];
+            C[r * n2 + j] = v / L[r * SPEC_N + r];
+        }
+    }
+    __syncthreads();
+    if (tid < nf) {
+        const int i = tid;
+        for (int c = 0; c < nf; ++c) {
+            double v = C[i * n2 + c];
+            for (int k = 0; k < c; ++k) v -= L[c * SPEC_N + k] * C[i * n2 + k];
+            C[i * n2 + c] = v / L[c * SPEC_N + c];
+        }
+    }
+    __syncthreads();
+    // symmetrise, trace bound for the pad entry
+    double part = 0.0;
+    for (int idx = tid; idx < nf * nf; idx += 256) {
+        const int r = idx / nf, c = idx % nf;
+        if (c > r) {
+            const double v = 0.5 * (C[r * n2 + c] + C[c * n2 + r]);
+            C[r * n2 + c] = v;
+            C[c * n2 + r] = v;
+        }
+        if (r == c) part += fabs(C[r * n2 + r]);
+    }
+    red[tid] = part;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    // for a symmetric positive semi-definite C the trace bounds every
+    // eigenvalue
+    if (n2 > nf && tid == 0) C[nf * n2 + nf] = 2.0 * red[0] + 1.0;
+    for (int idx = tid; idx < n2 * n2; idx += 256) V[(idx / n2) * SPEC_N + idx % n2] = (idx / n2 == idx % n2);
+    __syncthreads();
+    // cyclic Jacobi sweeps
+    const int half = n2 / 2;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, dg = 0.0;
+        for (int idx = tid; idx < n2 * n2; idx += 256) {
+            const int r = idx / n2, c = idx % n2;
+            const double v = C[idx];
+            if (r == c)
+                dg += v * v;
+            else
+                off += v * v;
+        }
+        red[tid] = off;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        const double offs = red[0];
+        __syncthreads();
+        red[tid] = dg;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        const double dgs = red[0];
+        __syncthreads();
+        if (!(offs > 1e-32 * dgs)) break;  // uniform (NaN stops too)
+        for (int rd = 0; rd < n2 - 1; ++rd) {
+            if (tid < half) {
+                const int k = tid;
+                const int a = k == 0 ? 0 : (k - 1 + rd) % (n2 - 1) + 1;
+                const int b = (n2 - 2 - k + rd) % (n2 - 1) + 1;
+                const int p = min(a, b), q = max(a, b);
+                const double apq = C[p * n2 + q];
+                double c = 1.0, s = 0.0;
+                if (apq != 0.0) {
+                    const double th = (C[q * n2 + q] - C[p * n2 + p]) / (2.0 * apq);
+                    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                    c = 1.0 / sqrt(t * t + 1.0);
+                    s = t * c;
+                }
+                cs[k] = c;
+                sn[k] = s;
+                pp[k] = p;
+                qq[k] = q;
+            }
+            __syncthreads();
+            // columns p, q of C and V
+            for (int idx = tid; idx < half * n2; idx += 256) {
+                const int k = idx / n2, r = idx % n2;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                const double x = C[r * n2 + p], y = C[r * n2 + q];
+                C[r * n2 + p] = c * x - s * y;
+                C[r * n2 + q] = s * x + c * y;
+                const double vx = V[r * SPEC_N + p], vy = V[r * SPEC_N + q];
+                V[r * SPEC_N + p] = c * vx - s * vy;
+                V[r * SPEC_N + q] = s * vx + c * vy;
+            }
+            __syncthreads();
+            // rows p, q of C
+            for (int idx = tid; idx < half * n2; idx += 256) {
+                const int k = idx / n2, j = idx % n2;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                const double x = C[p * n2 + j], y = C[q * n2 + j];
+                C[p * n2 + j] = c * x - s * y;
+                C[q * n2 + j] = s * x + c * y;
+            }
+            __syncthreads();
+        }
+    }
+    // the J smallest eigenvalues (ascending, ties by index)
+    if (tid == 0) {
+        for (int j = 0; j < J; ++j) {
+            int best = -1;
+            for (int i = 0; i < nf; ++i) {
+                bool used = false;
+                for (int u = 0; u < j; ++u) used |= sel[u] == i;
+                if (used) continue;
+                if (best < 0 || C[i * n2 + i] < C[best * n2 + best]) best = i;
+            }
+            sel[j] = best;
+            lam[(long)e * J + j] = C[best * n2 + best];
+        }
+    }
+    __syncthreads();
+    // psi = L^-T u for the selected columns u of V, in LDS rows [f][j]
+    // (the area of C is free now)
+    double* W = C;
+    if (tid < J) {
+        const int j = tid, col = sel[j];
+        for (int r = nf - 1; r >= 0; --r) {
+            double v = V[r * SPEC_N + col];
+            for (int c = r + 1; c < nf; ++c) v -= L[c * SPEC_N + r] * W[c * 8 + j];
+            W[r * 8 + j] = v / L[r * SPEC_N + r];
+        }
+        double sg = 0.0;
+        for (int r = 0; r < nf; ++r) sg += (r + 1) * W[r * 8 + j];
+        if (sg < 0.0)
+            for (int r = 0; r < nf; ++r) W[r * 8 + j] = -W[r * 8 + j];
+    }
+    __syncthreads();
+    // psi on the element's local nodes (zero on the domain boundary) and
+    // spsi = S_e psi over all local nodes (the element's full weighted mass)
+    for (int idx = tid; idx < nl * J; idx += 256) {
+        const int ln = idx / J, j = idx % J;
+        const int f = free_of[ln];
+        if (psi) psi[((long)e * nl + ln) * J + j] = f >= 0 ? W[f * 8 + j] : 0.0;
+        const int gy = ey * m + ln / ml, gx = ex * m + ln % ml;
+        double acc = 0.0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int ly = ln / ml + dy, lx = ln % ml + dx;
+                if (ly < 0 || ly > m || lx < 0 || lx > m) continue;
+                const int f2 = free_of[ly * ml + lx];
+                if (f2 < 0) continue;
+                double a, s;
+                elem_pair(kappa, n, m, ey, ex, gy, gx, gy + dy, gx + dx, a, s);
+                acc += s * sw * W[f2 * 8 + j];
+            }
+        spsi[((long)e * nl + ln) * J + j] = acc;
+    }
+    if (tid == 0) info[e] = 0;
+}
+
 }  // namespace
 }  // namespace pe
 
@@ -632,4 +929,46 @@ extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, co
     pe_status r = done(s);
     if (ws.part) (void)hipFree(ws.part);
     return r;
+}
+
+extern "C" pe_status pe_local_spectral(int n, int n_c, int J, const double* kappa, double* lam, double* psi,
+                                       double* spsi, void* hip_stream) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (n <= 0 || n_c <= 0 || n % n_c != 0 || J <= 0 || J > 8 || !kappa || !lam || !spsi)
+        return set_error(PE_ERR_ARG, "pe_local_spectral: bad arguments");
+    const int m = n / n_c;
+    if ((m + 1) * (m + 1) > SPEC_N)
+        return set_error(PE_ERR_ARG, "pe_local_spectral: more than " + std::to_string(SPEC_N) +
+                                         " nodes per coarse element");
+    // every element keeps at least (m - 1)^2 nodes off the boundary
+    if (m < 2 || J > (m - 1) * (m - 1)) return set_error(PE_ERR_ARG, "pe_local_spectral: J exceeds the element's nodes");
+    const int n_elem = n_c * n_c;
+    double *Lg = nullptr, *Vg = nullptr;
+    int* info = nullptr;
+    auto done = [&](pe_status s) {
+        (void)hipStreamSynchronize(st);
+        for (void* b : {(void*)Lg, (void*)Vg, (void*)info})
+            if (b) (void)hipFree(b);
+        return s;
+    };
+    const size_t mat = sizeof(double) * SPEC_N * SPEC_N * n_elem;
+    if (hipMalloc((void**)&Lg, mat) != hipSuccess || hipMalloc((void**)&Vg, mat) != hipSuccess ||
+        hipMalloc((void**)&info, sizeof(int) * n_elem) != hipSuccess) {
+        (void)hipGetLastError();
+        return done(set_error(PE_ERR_NOMEM, "pe_local_spectral: device memory"));
+    }
+    hipLaunchKernelGGL(k_spec_element, dim3(n_elem), dim3(256), 0, st, n, n_c, J, kappa, Lg, Vg, lam, psi, spsi,
+                       info);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return done(set_error(PE_ERR_HIP, std::string("pe_local_spectral: ") + hipGetErrorString(e)));
+    std::vector<int> hinfo(n_elem);
+    if (hipMemcpyAsync(hinfo.data(), info, sizeof(int) * n_elem, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return done(set_error(PE_ERR_HIP, "pe_local_spectral: status read-back"));
+    for (int i = 0; i < n_elem; ++i)
+        if (hinfo[i] != 0)
+            return done(set_error(PE_ERR_NOT_SPD, "pe_local_spectral: weighted mass of element " +
+                                                      std::to_string(i) + " not positive definite"));
+    return done(PE_OK);
 }

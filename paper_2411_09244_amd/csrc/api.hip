@@ -126,6 +126,16 @@ struct pe_problem_s {
     double* Zc64 = nullptr;  // Dp x Dp   coarse increment operator
     double* PhiG64 = nullptr;  // Dp x Dp   coarse step matrix I - Z_dt A
     float* PhiG32 = nullptr;
+    // coarse sweep as a doubling scan (one sample, fresh history): powers
+    // Phi_G^(2^l), l < scan_L (l = 0 is PhiG), and two (Z + N) x Dp
+    // ping-pong buffers whose first Z = 2^(scan_L - 1) rows stay zero
+    int coarse_scan = 1;
+    int scan_L = 0;
+    std::vector<double*> pow64;
+    std::vector<float*> pow32;
+    double* scan64[2] = {nullptr, nullptr};
+    float* scan32[2] = {nullptr, nullptr};
+    std::vector<void*> scan_allocs;
     // PE_MIXED: the fine sweep works in mass-whitened coordinates
     // x~ = Tin x, Tin = blkdiag(L1^T, L2^T) with M11 = L1 L1^T, M22 = L2 L2^T
     // (there M~11 = M~22 = I); x = Tout x~, Tout = Tin^-1; Linv = Tout^T
@@ -557,7 +567,8 @@ enum {
     SITE_TRAJ = 6,
     SITE_ADJ_STEP = 8,
     SITE_WR_RHS = 9,
-    SITE_WR_WSTEP = 10
+    SITE_WR_WSTEP = 10,
+    SITE_COARSE_SCAN = 11
 };
 
 template <typename T>
@@ -1194,6 +1205,94 @@ pe_status coarse_sweep_correct(pe_problem p, int B, double* Xk, const double* Xp
                                 PE_PROF_COARSE));
         c = 1 - c;
     }
+    return PE_OK;
+}
+
+// Coarse sweep of one sample as a doubling scan. In change form, with
+// d_n = x_n^k - x_n^{k-1} (d_0 = 0), the correction above is the linear
+// recurrence
+//     d_{n+1} = Phi_G d_n + e_n,    e_n = F(x_n^{k-1}) - x_{n+1}^{k-1},
+// so d_n = sum_{j<n} Phi_G^(n-1-j) e_j. Starting from t_n = e_{n-1}, level l
+// adds Phi_G^(2^l) t_{n-2^l} to every t_n (rows n <= 2^l read zero rows kept
+// in front of the buffer); after ceil(log2 N) levels t_n = d_n, and
+// x_n^k = x_n^{k-1} + d_n. One product per level over all N rows replaces N
+// dependent coarse steps; the products run in the path's precision on the
+// change, as the sequential sweep's do. The powers are formed once per
+// problem in FP64 (squarings, with the transposes for the NT products).
+pe_status scan_prepare(pe_problem p) {
+    if (p->scan_L > 0) return PE_OK;
+    const int N = p->N, Dp = p->Dp;
+    const bool mixed = p->prec == PE_MIXED;
+    int L = 0;
+    while ((1 << L) < N) ++L;
+    const int Z = 1 << (L - 1);
+    std::vector<void*>& OL = p->scan_allocs;
+    TmpList tmpl(p->st);
+    std::vector<void*>& tmp = tmpl.v;
+    auto done = [&](pe_status r) {
+        (void)hipStreamSynchronize(p->st);
+        free_list(tmp);
+        return r;
+    };
+    pe_status s;
+    p->pow64.assign(L, nullptr);
+    p->pow32.assign(L, nullptr);
+    p->pow64[0] = p->PhiG64;
+    p->pow32[0] = p->PhiG32;
+    double *T0 = nullptr, *T1 = nullptr;
+    if ((s = dalloc_t(p, tmp, &T0, (size_t)Dp * Dp)) < 0 || (s = dalloc_t(p, tmp, &T1, (size_t)Dp * Dp)) < 0)
+        return done(s);
+    PE_HIP(place(T0, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
+    double* PT = T0;  // transpose of the last power
+    for (int l = 1; l < L; ++l) {
+        if ((s = dalloc_t(p, OL, &p->pow64[l], (size_t)Dp * Dp)) < 0) return done(s);
+        const double* P = p->pow64[l - 1];
+        // P^2 is the NT product of P with P^T, its transpose that of P^T
+        // with P
+        if ((s = gemm<double>(p, shape(Dp, Dp, P, Dp, PT, Dp, 0, Dp), store_epi(p->pow64[l], Dp))) < 0)
+            return done(s);
+        if (l + 1 < L) {
+            double* PT2 = PT == T0 ? T1 : T0;
+            if ((s = gemm<double>(p, shape(Dp, Dp, PT, Dp, P, Dp, 0, Dp), store_epi(PT2, Dp))) < 0) return done(s);
+            PT = PT2;
+        }
+        if (mixed) {
+            if ((s = dalloc_t(p, OL, &p->pow32[l], (size_t)Dp * Dp)) < 0) return done(s);
+            PE_HIP(to_f32(p->pow64[l], p->pow32[l], (long)Dp * Dp, p->st));
+        }
+    }
+    for (int c = 0; c < 2; ++c) {
+        if ((s = dalloc_t(p, OL, &p->scan64[c], (size_t)(Z + N) * Dp)) < 0) return done(s);
+        PE_HIP(zero_fill(p->scan64[c], nullptr, (long)(Z + N) * Dp, p->st));
+        if (mixed) {
+            if ((s = dalloc_t(p, OL, &p->scan32[c], (size_t)(Z + N) * Dp)) < 0) return done(s);
+            PE_HIP(zero_fill(nullptr, p->scan32[c], (long)(Z + N) * Dp, p->st));
+        }
+    }
+    p->scan_L = L;
+    return done(PE_OK);
+}
+
+pe_status coarse_sweep_scan(pe_problem p, double* Xk, const double* Xprev, const int* active) {
+    const int N = p->N, Dp = p->Dp, L = p->scan_L;
+    const int Z = 1 << (L - 1);
+    const bool mixed = p->prec == PE_MIXED;
+    const long zoff = (long)Z * Dp;
+    PE_HIP(scan_init(p->Fbuf, Xprev, p->scan64[0] + zoff, mixed ? p->scan32[0] + zoff : nullptr, N, Dp, p->st));
+    for (int l = 0; l < L; ++l) {
+        const int c = l & 1;
+        const long shift = (long)(Z - (1 << l)) * Dp;
+        Epi e = store_epi(p->scan64[1 - c] + zoff, Dp, 1.0, p->scan64[c] + zoff, Dp, 1.0);
+        if (mixed) {
+            e.C32 = p->scan32[1 - c] + zoff;
+            PE_TRY(gemm<float>(p, shape(N, Dp, p->scan32[c] + shift, Dp, p->pow32[l], Dp, 0, Dp), e, 0,
+                               PE_PROF_COARSE, SITE_COARSE_SCAN));
+        } else {
+            PE_TRY(gemm<double>(p, shape(N, Dp, p->scan64[c] + shift, Dp, p->pow64[l], Dp, 0, Dp), e, 0,
+                                PE_PROF_COARSE, SITE_COARSE_SCAN));
+        }
+    }
+    PE_HIP(scan_final(Xprev, p->scan64[L & 1] + zoff, Xk, N, Dp, active, p->st));
     return PE_OK;
 }
 
@@ -2272,6 +2371,7 @@ pe_status pe_problem_destroy(pe_problem p) {
     free_list(p->wr_tab);
     free_list(p->hist_ops);
     free_list(p->hist_src);
+    free_list(p->scan_allocs);
     if (p->gw.part) (void)hipFree(p->gw.part);
     if (p->own_stream) (void)hipStreamDestroy(p->st);
     delete p;
@@ -2381,6 +2481,8 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         p->gc.use_graphs = (gr && gr[0] == '0') ? 0 : 1;
         // persistent fine sweep: opt-in (measured slower than per-step launches
         // replayed from graphs on MI355X: each grid-wide barrier costs tens of µs)
+        const char* cs = getenv("PE_COARSE_SCAN");
+        p->coarse_scan = (cs && cs[0] == '0') ? 0 : 1;
         const char* pz = getenv("PE_PERSISTENT");
         p->persistent = (pz && pz[0] == '1') ? 1 : 0;
         if (const char* fw = getenv("PE_FORCE_WSK")) {
@@ -2798,9 +2900,14 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
             PE_TRY(graph_run(p, {1, B, cur}, [&]() { return fine_sweep(p, B, p->Xk[cur], ldX, p->Fbuf); }));
         }
         if (n_active < B) PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, ldX, B, p->st));
+        const bool scan = B == 1 && p->hist != PE_HIST_CARRY && p->coarse_scan && N >= 4;
+        if (scan) PE_TRY(scan_prepare(p));
         PE_TRY(graph_run(p, {2, B, cur}, [&]() -> pe_status {
             PE_HIP(set_x0(p->x0p, p->Xk[nxt], ldX, B, Dp, p->st, Sx));
-            PE_TRY(coarse_sweep_correct(p, B, p->Xk[nxt], p->Xk[cur], p->active_d));
+            if (scan)
+                PE_TRY(coarse_sweep_scan(p, p->Xk[nxt], p->Xk[cur], p->active_d));
+            else
+                PE_TRY(coarse_sweep_correct(p, B, p->Xk[nxt], p->Xk[cur], p->active_d));
             PE_TRY(jumps_launch(p, B, p->Xk[nxt], p->Xk[cur], ldX, 1, N));
             return PE_OK;
         }));

@@ -172,6 +172,7 @@ __device__ inline void epi_finish(const Epi& e, int r, int s, double acc, const 
         if (e.beta != 0.0) v += e.beta * in.a;
         if (e.diag_add != 0.0 && r == s + e.diag_off) v += e.diag_add;
         e.C[(long)r * e.ldc + s] = v;
+        if (e.C32) e.C32[(long)r * e.ldc + s] = (float)v;
     } else if constexpr (MODE == EPI_RESID) {
         double v = in.a - acc;
         if (e.base) v -= in.b;

@@ -183,6 +183,37 @@ __global__ void k_zero(double* __restrict__ a, float* __restrict__ b, long n) {
     }
 }
 
+__global__ void k_scan_init(const double* __restrict__ F, const double* __restrict__ Xp, double* __restrict__ t64,
+                            float* __restrict__ t32, long n_el, int Dp) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_el) return;
+    const double v = F[i] - Xp[i + Dp];
+    t64[i] = v;
+    if (t32) t32[i] = (float)v;
+}
+
+hipError_t scan_init(const double* F, const double* Xp, double* t64, float* t32, int N, int Dp, hipStream_t st) {
+    const long n_el = (long)N * Dp;
+    hipLaunchKernelGGL(k_scan_init, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, F, Xp, t64, t32, n_el,
+                       Dp);
+    return hipGetLastError();
+}
+
+__global__ void k_scan_final(const double* __restrict__ Xp, const double* __restrict__ t, double* __restrict__ X,
+                             long n_el, int Dp, const int* __restrict__ active) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_el || (active && !active[0])) return;
+    X[i + Dp] = Xp[i + Dp] + t[i];
+}
+
+hipError_t scan_final(const double* Xp, const double* t, double* X, int N, int Dp, const int* active,
+                      hipStream_t st) {
+    const long n_el = (long)N * Dp;
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, Xp, t, X, n_el, Dp,
+                       active);
+    return hipGetLastError();
+}
+
 hipError_t zero_fill(double* a, float* b, long n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero, grid1(n), dim3(256), 0, st, a, b, n);

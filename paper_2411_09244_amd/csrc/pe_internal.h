@@ -41,6 +41,7 @@ struct Epi {
     double diag_add = 0.0;
     int diag_off = 0;
     double* C = nullptr;
+    float* C32 = nullptr;  // EPI_STORE: nullable FP32 copy of C (same ldc)
     const double* C0 = nullptr;
     long ldc = 0, ldc0 = 0;
     // EPI_RESID

@@ -126,11 +126,13 @@ struct pe_problem_s {
     double* Zc64 = nullptr;  // Dp x Dp   coarse increment operator
     double* PhiG64 = nullptr;  // Dp x Dp   coarse step matrix I - Z_dt A
     float* PhiG32 = nullptr;
-    // coarse sweep as a doubling scan (one sample, fresh history): powers
-    // Phi_G^(2^l), l < scan_L (l = 0 is PhiG), and two (Z + N) x Dp
-    // ping-pong buffers whose first Z = 2^(scan_L - 1) rows stay zero
+    // coarse sweeps as doubling scans (one sample, fresh history): powers
+    // Phi_G^(2^l), l < scan_L0 (l = 0 is PhiG), and two (Z + N + 1) x Dp
+    // ping-pong buffers whose first Z = 2^(scan_L0 - 1) rows stay zero;
+    // scan_L levels for the correction (N terms), scan_L0 for the initial
+    // sweep (N + 1 terms)
     int coarse_scan = 1;
-    int scan_L = 0;
+    int scan_L = 0, scan_L0 = 0;
     std::vector<double*> pow64;
     std::vector<float*> pow32;
     double* scan64[2] = {nullptr, nullptr};
@@ -1223,9 +1225,10 @@ pe_status scan_prepare(pe_problem p) {
     if (p->scan_L > 0) return PE_OK;
     const int N = p->N, Dp = p->Dp;
     const bool mixed = p->prec == PE_MIXED;
-    int L = 0;
+    int L = 0, L0 = 0;
     while ((1 << L) < N) ++L;
-    const int Z = 1 << (L - 1);
+    while ((1 << L0) < N + 1) ++L0;
+    const int Z = 1 << (L0 - 1);
     std::vector<void*>& OL = p->scan_allocs;
     TmpList tmpl(p->st);
     std::vector<void*>& tmp = tmpl.v;
@@ -1235,8 +1238,8 @@ pe_status scan_prepare(pe_problem p) {
         return r;
     };
     pe_status s;
-    p->pow64.assign(L, nullptr);
-    p->pow32.assign(L, nullptr);
+    p->pow64.assign(L0, nullptr);
+    p->pow32.assign(L0, nullptr);
     p->pow64[0] = p->PhiG64;
     p->pow32[0] = p->PhiG32;
     double *T0 = nullptr, *T1 = nullptr;
@@ -1244,38 +1247,40 @@ pe_status scan_prepare(pe_problem p) {
         return done(s);
     PE_HIP(place(T0, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
     double* PT = T0;  // transpose of the last power
-    for (int l = 1; l < L; ++l) {
+    for (int l = 1; l < L0; ++l) {
         if ((s = dalloc_t(p, OL, &p->pow64[l], (size_t)Dp * Dp)) < 0) return done(s);
         const double* P = p->pow64[l - 1];
         // P^2 is the NT product of P with P^T, its transpose that of P^T
         // with P
         if ((s = gemm<double>(p, shape(Dp, Dp, P, Dp, PT, Dp, 0, Dp), store_epi(p->pow64[l], Dp))) < 0)
             return done(s);
-        if (l + 1 < L) {
+        if (l + 1 < L0) {
             double* PT2 = PT == T0 ? T1 : T0;
             if ((s = gemm<double>(p, shape(Dp, Dp, PT, Dp, P, Dp, 0, Dp), store_epi(PT2, Dp))) < 0) return done(s);
             PT = PT2;
         }
-        if (mixed) {
+        if (mixed && l < L) {
             if ((s = dalloc_t(p, OL, &p->pow32[l], (size_t)Dp * Dp)) < 0) return done(s);
             PE_HIP(to_f32(p->pow64[l], p->pow32[l], (long)Dp * Dp, p->st));
         }
     }
+    const long rows = (long)Z + N + 1;
     for (int c = 0; c < 2; ++c) {
-        if ((s = dalloc_t(p, OL, &p->scan64[c], (size_t)(Z + N) * Dp)) < 0) return done(s);
-        PE_HIP(zero_fill(p->scan64[c], nullptr, (long)(Z + N) * Dp, p->st));
+        if ((s = dalloc_t(p, OL, &p->scan64[c], (size_t)rows * Dp)) < 0) return done(s);
+        PE_HIP(zero_fill(p->scan64[c], nullptr, rows * Dp, p->st));
         if (mixed) {
-            if ((s = dalloc_t(p, OL, &p->scan32[c], (size_t)(Z + N) * Dp)) < 0) return done(s);
-            PE_HIP(zero_fill(nullptr, p->scan32[c], (long)(Z + N) * Dp, p->st));
+            if ((s = dalloc_t(p, OL, &p->scan32[c], (size_t)rows * Dp)) < 0) return done(s);
+            PE_HIP(zero_fill(nullptr, p->scan32[c], rows * Dp, p->st));
         }
     }
     p->scan_L = L;
+    p->scan_L0 = L0;
     return done(PE_OK);
 }
 
 pe_status coarse_sweep_scan(pe_problem p, double* Xk, const double* Xprev, const int* active) {
     const int N = p->N, Dp = p->Dp, L = p->scan_L;
-    const int Z = 1 << (L - 1);
+    const int Z = 1 << (p->scan_L0 - 1);
     const bool mixed = p->prec == PE_MIXED;
     const long zoff = (long)Z * Dp;
     PE_HIP(scan_init(p->Fbuf, Xprev, p->scan64[0] + zoff, mixed ? p->scan32[0] + zoff : nullptr, N, Dp, p->st));
@@ -1293,6 +1298,25 @@ pe_status coarse_sweep_scan(pe_problem p, double* Xk, const double* Xprev, const
         }
     }
     PE_HIP(scan_final(Xprev, p->scan64[L & 1] + zoff, Xk, N, Dp, active, p->st));
+    return PE_OK;
+}
+
+// Initial sweep x_{n+1} = Phi_G x_n + c_n of one sample as the same scan
+// over the N + 1 terms t_0 = x0, t_n = c_{n-1}: after ceil(log2(N + 1))
+// levels t_n = x_n (FP64 products on the states, as the sequential initial
+// sweep's).
+pe_status coarse_sweep_initial_scan(pe_problem p, double* Xk) {
+    const int N = p->N, Dp = p->Dp, L0 = p->scan_L0;
+    const long zoff = (long)(1 << (L0 - 1)) * Dp;
+    PE_HIP(scan_init0(Xk, p->CS, p->scan64[0] + zoff, N, Dp, p->st));
+    for (int l = 0; l < L0; ++l) {
+        const int c = l & 1;
+        const long shift = zoff - (long)(1 << l) * Dp;
+        Epi e = store_epi(p->scan64[1 - c] + zoff, Dp, 1.0, p->scan64[c] + zoff, Dp, 1.0);
+        PE_TRY(gemm<double>(p, shape(N + 1, Dp, p->scan64[c] + shift, Dp, p->pow64[l], Dp, 0, Dp), e, 0,
+                            PE_PROF_COARSE, SITE_COARSE_SCAN));
+    }
+    PE_HIP(scan_final(nullptr, p->scan64[L0 & 1] + zoff + Dp, Xk, N, Dp, nullptr, p->st));
     return PE_OK;
 }
 
@@ -2873,9 +2897,14 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
     int cur = 0;
     PE_HIP(pack_states(x0, p->x0p, B, p->d1, p->d2, p->d1p, p->d2p, p->st));
     const long rel = norm_mode == PE_NORM_M_REL ? 1 : 0;
+    const bool scan = B == 1 && p->hist != PE_HIST_CARRY && p->coarse_scan && N >= 4;
+    if (scan) PE_TRY(scan_prepare(p));
     PE_TRY(graph_run(p, {0, B, rel}, [&]() -> pe_status {
         PE_HIP(set_x0(p->x0p, p->Xk[0], ldX, B, Dp, p->st, Sx));
-        PE_TRY(coarse_sweep_initial(p, B, p->Xk[0]));
+        if (scan)
+            PE_TRY(coarse_sweep_initial_scan(p, p->Xk[0]));
+        else
+            PE_TRY(coarse_sweep_initial(p, B, p->Xk[0]));
         if (rel) PE_TRY(jumps_launch(p, B, p->Xk[0], nullptr, ldX, 0, N + 1));
         return PE_OK;
     }));
@@ -2900,8 +2929,6 @@ pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_m
             PE_TRY(graph_run(p, {1, B, cur}, [&]() { return fine_sweep(p, B, p->Xk[cur], ldX, p->Fbuf); }));
         }
         if (n_active < B) PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, ldX, B, p->st));
-        const bool scan = B == 1 && p->hist != PE_HIST_CARRY && p->coarse_scan && N >= 4;
-        if (scan) PE_TRY(scan_prepare(p));
         PE_TRY(graph_run(p, {2, B, cur}, [&]() -> pe_status {
             PE_HIP(set_x0(p->x0p, p->Xk[nxt], ldX, B, Dp, p->st, Sx));
             if (scan)

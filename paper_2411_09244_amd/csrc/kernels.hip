@@ -203,7 +203,20 @@ __global__ void k_scan_final(const double* __restrict__ Xp, const double* __rest
                              long n_el, int Dp, const int* __restrict__ active) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n_el || (active && !active[0])) return;
-    X[i + Dp] = Xp[i + Dp] + t[i];
+    X[i + Dp] = (Xp ? Xp[i + Dp] : 0.0) + t[i];
+}
+
+__global__ void k_scan_init0(const double* __restrict__ x0, const double* __restrict__ cs, double* __restrict__ t,
+                             long n_el, int Dp) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_el) return;
+    t[i] = i < Dp ? x0[i] : (cs ? cs[i - Dp] : 0.0);
+}
+
+hipError_t scan_init0(const double* x0, const double* cs, double* t, int N, int Dp, hipStream_t st) {
+    const long n_el = (long)(N + 1) * Dp;
+    hipLaunchKernelGGL(k_scan_init0, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, x0, cs, t, n_el, Dp);
+    return hipGetLastError();
 }
 
 hipError_t scan_final(const double* Xp, const double* t, double* X, int N, int Dp, const int* active,

@@ -29,11 +29,14 @@ hipError_t freeze_inactive(const double* Xsrc, double* Xdst, const int* active, 
                            hipStream_t st);
 hipError_t zero_fill(double* a, float* b, long n, hipStream_t st);
 // coarse sweep as a scan (one sample): t[n] = F[n] - Xp[n+1] (n < N, rows of
-// Dp, FP32 copy nullable); X[n+1] = Xp[n+1] + t[n] unless the sample is
-// inactive
+// Dp, FP32 copy nullable); X[n+1] = Xp[n+1] + t[n] (Xp nullable: zero)
+// unless the sample is inactive
 hipError_t scan_init(const double* F, const double* Xp, double* t64, float* t32, int N, int Dp, hipStream_t st);
 hipError_t scan_final(const double* Xp, const double* t, double* X, int N, int Dp, const int* active,
                       hipStream_t st);
+// initial sweep as a scan: t[0] = x0, t[n] = cs[n-1] (n = 1..N; cs nullable:
+// zero source). scan_final with Xp = nullptr then copies t[1..N] to X[1..N].
+hipError_t scan_init0(const double* x0, const double* cs, double* t, int N, int Dp, hipStream_t st);
 hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st, int sx = 0);
 // carried history
 hipError_t gather_rows(const double* X, long ldXb, int sx, int off, int row_off, int nvalid, double* out, int B,

@@ -306,3 +306,29 @@ def test_wave_split_k_kernel(cfg, prec, tol, monkeypatch):
                 print(f"  parareal k=3 vs oracle b={b}: {err:.3e}")
                 assert err < tol, (name, cfg, prec, b, err)
         pr.close()
+
+
+@pytest.mark.parametrize("name", ["t0", "t1", "c0", "ragged"])
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX)])
+def test_coarse_scan_matches_sequential(name, prec, tol, monkeypatch):
+    """The one-sample coarse sweep as a doubling scan (default) against the
+    sequential sweep (PE_COARSE_SCAN=0) and the oracle at equal k, with N = 6,
+    8, 8, 5 intervals (3, 3, 3 and 3 scan levels; the rows before each
+    shift read the zero rows in front of the buffer)."""
+    pe = _pe()
+    p = _prob(name)
+    k = min(3, p["N"])
+    bl, refs = _oracle_parareal(p, k)
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("PE_COARSE_SCAN", mode)
+        pr = pe.problem_from(p, prec)
+        X, iters, hist, st = pr.solve(p["x0"], tol=0.0, k_max=k)
+        out[mode] = X.cpu().numpy()
+        pr.close()
+    for b, r in enumerate(refs):
+        e_scan = S.rel_l2_M(bl, out["1"][b], r["X"][k])
+        e_seq = S.rel_l2_M(bl, out["0"][b], r["X"][k])
+        e_ab = S.rel_l2_M(bl, out["1"][b], out["0"][b])
+        print(f"{name} {prec}: scan {e_scan:.3e}, sequential {e_seq:.3e}, scan vs sequential {e_ab:.3e}")
+        assert e_scan < tol and e_seq < tol and e_ab < tol

@@ -498,7 +498,7 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
                 if (need > ((size_t)512 << 20)) continue;
                 PE_TRY(ensure_gemm_work(p, need));
                 if (gemm_launch<T>(sh, epi, c, p->gw, p->st) != hipSuccess) continue;
-                const int reps = 3;
+                const int reps = 10;
                 PE_HIP(hipEventRecord(e0, p->st));
                 for (int i = 0; i < reps; ++i) PE_HIP(gemm_launch<T>(sh, epi, c, p->gw, p->st));
                 PE_HIP(hipEventRecord(e1, p->st));
@@ -532,7 +532,7 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
                 if (need > ((size_t)512 << 20)) continue;
                 PE_TRY(ensure_gemm_work(p, need));
                 if (gemm_launch<T>(sh, epi, c, p->gw, p->st) != hipSuccess) continue;
-                const int reps = 3;
+                const int reps = 10;
                 PE_HIP(hipEventRecord(e0, p->st));
                 for (int i = 0; i < reps; ++i) PE_HIP(gemm_launch<T>(sh, epi, c, p->gw, p->st));
                 PE_HIP(hipEventRecord(e1, p->st));

@@ -133,8 +133,12 @@ struct pe_problem_s {
     // sweep (N + 1 terms)
     int coarse_scan = 1;
     int scan_L = 0, scan_L0 = 0;
-    std::vector<double*> pow64;
-    std::vector<float*> pow32;
+    std::vector<double*> pow64, pow64T;  // powers and their transposes
+    std::vector<float*> pow32, pow32T;
+    // backward (adjoint) scans: (N + 1 + Z) x Dp ping-pong buffers whose
+    // rows after N + 1 stay zero
+    double* scanA64[2] = {nullptr, nullptr};
+    float* scanA32[2] = {nullptr, nullptr};
     double* scan64[2] = {nullptr, nullptr};
     float* scan32[2] = {nullptr, nullptr};
     std::vector<void*> scan_allocs;
@@ -1240,37 +1244,45 @@ pe_status scan_prepare(pe_problem p) {
     pe_status s;
     p->pow64.assign(L0, nullptr);
     p->pow32.assign(L0, nullptr);
+    p->pow64T.assign(L0, nullptr);
+    p->pow32T.assign(L0, nullptr);
     p->pow64[0] = p->PhiG64;
     p->pow32[0] = p->PhiG32;
-    double *T0 = nullptr, *T1 = nullptr;
-    if ((s = dalloc_t(p, tmp, &T0, (size_t)Dp * Dp)) < 0 || (s = dalloc_t(p, tmp, &T1, (size_t)Dp * Dp)) < 0)
-        return done(s);
-    PE_HIP(place(T0, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
-    double* PT = T0;  // transpose of the last power
+    if ((s = dalloc_t(p, OL, &p->pow64T[0], (size_t)Dp * Dp)) < 0) return done(s);
+    PE_HIP(place(p->pow64T[0], Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
     for (int l = 1; l < L0; ++l) {
-        if ((s = dalloc_t(p, OL, &p->pow64[l], (size_t)Dp * Dp)) < 0) return done(s);
-        const double* P = p->pow64[l - 1];
+        if ((s = dalloc_t(p, OL, &p->pow64[l], (size_t)Dp * Dp)) < 0 ||
+            (s = dalloc_t(p, OL, &p->pow64T[l], (size_t)Dp * Dp)) < 0)
+            return done(s);
+        const double *P = p->pow64[l - 1], *PT = p->pow64T[l - 1];
         // P^2 is the NT product of P with P^T, its transpose that of P^T
         // with P
-        if ((s = gemm<double>(p, shape(Dp, Dp, P, Dp, PT, Dp, 0, Dp), store_epi(p->pow64[l], Dp))) < 0)
+        if ((s = gemm<double>(p, shape(Dp, Dp, P, Dp, PT, Dp, 0, Dp), store_epi(p->pow64[l], Dp))) < 0 ||
+            (s = gemm<double>(p, shape(Dp, Dp, PT, Dp, P, Dp, 0, Dp), store_epi(p->pow64T[l], Dp))) < 0)
             return done(s);
-        if (l + 1 < L0) {
-            double* PT2 = PT == T0 ? T1 : T0;
-            if ((s = gemm<double>(p, shape(Dp, Dp, PT, Dp, P, Dp, 0, Dp), store_epi(PT2, Dp))) < 0) return done(s);
-            PT = PT2;
-        }
-        if (mixed && l < L) {
-            if ((s = dalloc_t(p, OL, &p->pow32[l], (size_t)Dp * Dp)) < 0) return done(s);
-            PE_HIP(to_f32(p->pow64[l], p->pow32[l], (long)Dp * Dp, p->st));
-        }
     }
+    if (mixed)
+        for (int l = 0; l < L; ++l) {
+            if (l > 0) {
+                if ((s = dalloc_t(p, OL, &p->pow32[l], (size_t)Dp * Dp)) < 0) return done(s);
+                PE_HIP(to_f32(p->pow64[l], p->pow32[l], (long)Dp * Dp, p->st));
+            }
+            if ((s = dalloc_t(p, OL, &p->pow32T[l], (size_t)Dp * Dp)) < 0) return done(s);
+            PE_HIP(to_f32(p->pow64T[l], p->pow32T[l], (long)Dp * Dp, p->st));
+        }
     const long rows = (long)Z + N + 1;
     for (int c = 0; c < 2; ++c) {
-        if ((s = dalloc_t(p, OL, &p->scan64[c], (size_t)rows * Dp)) < 0) return done(s);
+        if ((s = dalloc_t(p, OL, &p->scan64[c], (size_t)rows * Dp)) < 0 ||
+            (s = dalloc_t(p, OL, &p->scanA64[c], (size_t)rows * Dp)) < 0)
+            return done(s);
         PE_HIP(zero_fill(p->scan64[c], nullptr, rows * Dp, p->st));
+        PE_HIP(zero_fill(p->scanA64[c], nullptr, rows * Dp, p->st));
         if (mixed) {
-            if ((s = dalloc_t(p, OL, &p->scan32[c], (size_t)rows * Dp)) < 0) return done(s);
+            if ((s = dalloc_t(p, OL, &p->scan32[c], (size_t)rows * Dp)) < 0 ||
+                (s = dalloc_t(p, OL, &p->scanA32[c], (size_t)rows * Dp)) < 0)
+                return done(s);
             PE_HIP(zero_fill(nullptr, p->scan32[c], rows * Dp, p->st));
+            PE_HIP(zero_fill(nullptr, p->scanA32[c], rows * Dp, p->st));
         }
     }
     p->scan_L = L;
@@ -1283,7 +1295,7 @@ pe_status coarse_sweep_scan(pe_problem p, double* Xk, const double* Xprev, const
     const int Z = 1 << (p->scan_L0 - 1);
     const bool mixed = p->prec == PE_MIXED;
     const long zoff = (long)Z * Dp;
-    PE_HIP(scan_init(p->Fbuf, Xprev, p->scan64[0] + zoff, mixed ? p->scan32[0] + zoff : nullptr, N, Dp, p->st));
+    PE_HIP(scan_init(p->Fbuf, Xprev, 1, p->scan64[0] + zoff, mixed ? p->scan32[0] + zoff : nullptr, N, Dp, p->st));
     for (int l = 0; l < L; ++l) {
         const int c = l & 1;
         const long shift = (long)(Z - (1 << l)) * Dp;
@@ -1297,7 +1309,7 @@ pe_status coarse_sweep_scan(pe_problem p, double* Xk, const double* Xprev, const
                                 PE_PROF_COARSE, SITE_COARSE_SCAN));
         }
     }
-    PE_HIP(scan_final(Xprev, p->scan64[L & 1] + zoff, Xk, N, Dp, active, p->st));
+    PE_HIP(scan_final(Xprev, p->scan64[L & 1] + zoff, Xk, 1, N, Dp, active, p->st));
     return PE_OK;
 }
 
@@ -1316,7 +1328,51 @@ pe_status coarse_sweep_initial_scan(pe_problem p, double* Xk) {
         PE_TRY(gemm<double>(p, shape(N + 1, Dp, p->scan64[c] + shift, Dp, p->pow64[l], Dp, 0, Dp), e, 0,
                             PE_PROF_COARSE, SITE_COARSE_SCAN));
     }
-    PE_HIP(scan_final(nullptr, p->scan64[L0 & 1] + zoff + Dp, Xk, N, Dp, nullptr, p->st));
+    PE_HIP(scan_final(nullptr, p->scan64[L0 & 1] + zoff + Dp, Xk, 1, N, Dp, nullptr, p->st));
+    return PE_OK;
+}
+
+// The backward sweeps of the adjoint (one sample) as the same scan with the
+// transposed powers, running from n = N down: the correction in change form
+// is d_n = Phi_G^T d_{n+1} + e_n (e_n = Fbuf_n - lam_n^{k-1}, d_N = 0), the
+// initial sweep lam_n = cs_n + Phi_G^T lam_{n+1} (lam_N = cs_N). Level l adds
+// (Phi_G^T)^(2^l) t_{n+2^l}; rows past the data read the zero rows kept
+// after it (row N is cleared for the correction's N terms).
+pe_status coarse_adj_scan_correct(pe_problem p, double* Lk, const double* Lprev, const int* active) {
+    const int N = p->N, Dp = p->Dp, L = p->scan_L;
+    const bool mixed = p->prec == PE_MIXED;
+    PE_HIP(place(Lk + (long)N * Dp, Dp, 0, 0, Lprev + (long)N * Dp, Dp, 1, Dp, 1.0, 0, p->st));
+    for (int c = 0; c < 2; ++c)
+        PE_HIP(zero_fill(p->scanA64[c] + (long)N * Dp, mixed ? p->scanA32[c] + (long)N * Dp : nullptr, Dp, p->st));
+    PE_HIP(scan_init(p->Fbuf, Lprev, 0, p->scanA64[0], mixed ? p->scanA32[0] : nullptr, N, Dp, p->st));
+    for (int l = 0; l < L; ++l) {
+        const int c = l & 1;
+        const long shift = (long)(1 << l) * Dp;
+        Epi e = store_epi(p->scanA64[1 - c], Dp, 1.0, p->scanA64[c], Dp, 1.0);
+        if (mixed) {
+            e.C32 = p->scanA32[1 - c];
+            PE_TRY(gemm<float>(p, shape(N, Dp, p->scanA32[c] + shift, Dp, p->pow32T[l], Dp, 0, Dp), e, 0,
+                               PE_PROF_COARSE, SITE_COARSE_SCAN));
+        } else {
+            PE_TRY(gemm<double>(p, shape(N, Dp, p->scanA64[c] + shift, Dp, p->pow64T[l], Dp, 0, Dp), e, 0,
+                                PE_PROF_COARSE, SITE_COARSE_SCAN));
+        }
+    }
+    PE_HIP(scan_final(Lprev, p->scanA64[L & 1], Lk, 0, N, Dp, active, p->st));
+    return PE_OK;
+}
+
+pe_status coarse_adj_scan_initial(pe_problem p, double* Lk, const double* cs) {
+    const int N = p->N, Dp = p->Dp, L0 = p->scan_L0;
+    PE_HIP(scan_final(nullptr, cs, p->scanA64[0], 0, N + 1, Dp, nullptr, p->st));
+    for (int l = 0; l < L0; ++l) {
+        const int c = l & 1;
+        const long shift = (long)(1 << l) * Dp;
+        Epi e = store_epi(p->scanA64[1 - c], Dp, 1.0, p->scanA64[c], Dp, 1.0);
+        PE_TRY(gemm<double>(p, shape(N + 1, Dp, p->scanA64[c] + shift, Dp, p->pow64T[l], Dp, 0, Dp), e, 0,
+                            PE_PROF_COARSE, SITE_COARSE_SCAN));
+    }
+    PE_HIP(scan_final(nullptr, p->scanA64[L0 & 1], Lk, 0, N + 1, Dp, nullptr, p->st));
     return PE_OK;
 }
 
@@ -3144,7 +3200,13 @@ pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const
     int cur = 0;
     PE_HIP(hipMemcpyAsync(p->io, p->Xb, sizeof(double) * rowsX * Dp, hipMemcpyDeviceToDevice, p->st));
     PE_HIP(axpy(p->io, p->Qb, 1.0, rowsX * Dp, p->st));
-    PE_TRY(coarse_adj_initial(p, B, p->Xk[0], p->io));
+    const bool scan = B == 1 && p->coarse_scan && N >= 4;
+    if (scan) {
+        PE_TRY(scan_prepare(p));
+        PE_TRY(coarse_adj_scan_initial(p, p->Xk[0], p->io));
+    } else {
+        PE_TRY(coarse_adj_initial(p, B, p->Xk[0], p->io));
+    }
     PE_HIP(axpy(p->Xk[0], p->Qb, -1.0, rowsX * Dp, p->st));
     PE_TRY(adj_jumps_launch(p, B, p->Xk[0], nullptr, 0, N + 1));
     PE_TRY(jumps_read(p, B, thr.data()));
@@ -3168,7 +3230,10 @@ pe_status pe_adjoint(pe_problem p, int B, const double* Xbar, double beta, const
         }
         if (n_active < B) PE_HIP(freeze_inactive(p->Xk[cur], p->Xk[nxt], p->active_d, ldX, B, p->st));
         PE_TRY(graph_run(p, {11, B, cur}, [&]() -> pe_status {
-            PE_TRY(coarse_adj_correct(p, B, p->Xk[nxt], p->Xk[cur], p->active_d));
+            if (scan)
+                PE_TRY(coarse_adj_scan_correct(p, p->Xk[nxt], p->Xk[cur], p->active_d));
+            else
+                PE_TRY(coarse_adj_correct(p, B, p->Xk[nxt], p->Xk[cur], p->active_d));
             PE_TRY(adj_jumps_launch(p, B, p->Xk[nxt], p->Xk[cur], 0, N));
             return PE_OK;
         }));

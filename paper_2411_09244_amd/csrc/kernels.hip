@@ -183,27 +183,28 @@ __global__ void k_zero(double* __restrict__ a, float* __restrict__ b, long n) {
     }
 }
 
-__global__ void k_scan_init(const double* __restrict__ F, const double* __restrict__ Xp, double* __restrict__ t64,
-                            float* __restrict__ t32, long n_el, int Dp) {
+__global__ void k_scan_init(const double* __restrict__ F, const double* __restrict__ Xp, long xoff,
+                            double* __restrict__ t64, float* __restrict__ t32, long n_el) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n_el) return;
-    const double v = F[i] - Xp[i + Dp];
+    const double v = F[i] - Xp[i + xoff];
     t64[i] = v;
     if (t32) t32[i] = (float)v;
 }
 
-hipError_t scan_init(const double* F, const double* Xp, double* t64, float* t32, int N, int Dp, hipStream_t st) {
+hipError_t scan_init(const double* F, const double* Xp, int xrow, double* t64, float* t32, int N, int Dp,
+                     hipStream_t st) {
     const long n_el = (long)N * Dp;
-    hipLaunchKernelGGL(k_scan_init, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, F, Xp, t64, t32, n_el,
-                       Dp);
+    hipLaunchKernelGGL(k_scan_init, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, F, Xp, (long)xrow * Dp,
+                       t64, t32, n_el);
     return hipGetLastError();
 }
 
 __global__ void k_scan_final(const double* __restrict__ Xp, const double* __restrict__ t, double* __restrict__ X,
-                             long n_el, int Dp, const int* __restrict__ active) {
+                             long n_el, long xoff, const int* __restrict__ active) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n_el || (active && !active[0])) return;
-    X[i + Dp] = (Xp ? Xp[i + Dp] : 0.0) + t[i];
+    X[i + xoff] = (Xp ? Xp[i + xoff] : 0.0) + t[i];
 }
 
 __global__ void k_scan_init0(const double* __restrict__ x0, const double* __restrict__ cs, double* __restrict__ t,
@@ -219,11 +220,11 @@ hipError_t scan_init0(const double* x0, const double* cs, double* t, int N, int 
     return hipGetLastError();
 }
 
-hipError_t scan_final(const double* Xp, const double* t, double* X, int N, int Dp, const int* active,
+hipError_t scan_final(const double* Xp, const double* t, double* X, int xrow, int N, int Dp, const int* active,
                       hipStream_t st) {
     const long n_el = (long)N * Dp;
-    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, Xp, t, X, n_el, Dp,
-                       active);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, Xp, t, X, n_el,
+                       (long)xrow * Dp, active);
     return hipGetLastError();
 }
 

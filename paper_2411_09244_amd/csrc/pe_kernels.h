@@ -28,11 +28,12 @@ hipError_t jump_reduce(const double* E, const double* Y, int B, int nr, int Dp, 
 hipError_t freeze_inactive(const double* Xsrc, double* Xdst, const int* active, long ldXb, int B,
                            hipStream_t st);
 hipError_t zero_fill(double* a, float* b, long n, hipStream_t st);
-// coarse sweep as a scan (one sample): t[n] = F[n] - Xp[n+1] (n < N, rows of
-// Dp, FP32 copy nullable); X[n+1] = Xp[n+1] + t[n] (Xp nullable: zero)
-// unless the sample is inactive
-hipError_t scan_init(const double* F, const double* Xp, double* t64, float* t32, int N, int Dp, hipStream_t st);
-hipError_t scan_final(const double* Xp, const double* t, double* X, int N, int Dp, const int* active,
+// coarse sweep as a scan (one sample): t[n] = F[n] - Xp[n + xrow] (n < N,
+// rows of Dp, FP32 copy nullable); X[n + xrow] = Xp[n + xrow] + t[n] (Xp
+// nullable: zero) unless the sample is inactive
+hipError_t scan_init(const double* F, const double* Xp, int xrow, double* t64, float* t32, int N, int Dp,
+                     hipStream_t st);
+hipError_t scan_final(const double* Xp, const double* t, double* X, int xrow, int N, int Dp, const int* active,
                       hipStream_t st);
 // initial sweep as a scan: t[0] = x0, t[n] = cs[n-1] (n = 1..N; cs nullable:
 // zero source). scan_final with Xp = nullptr then copies t[1..N] to X[1..N].

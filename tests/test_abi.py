@@ -49,3 +49,29 @@ def test_binding_has_no_cpu_fallback():
         if f.endswith(".py"):
             src = open(os.path.join(pkg, f)).read()
             assert not re.search(r"^\s*(from|import)\s+(oracle|problem)\b", src, re.M), f
+
+
+def test_setup_pipeline_argument_errors_without_device():
+    """pe_cem_spaces and pe_local_spectral validate sizes before any device
+    work: a fine grid that is not a multiple of the coarse one, more than 8
+    functions per element, patches beyond the band window or the constraint
+    limit, elements with more than 128 nodes."""
+    from paper_2411_09244_amd import _lib
+    lib = _lib.load()
+    p = ctypes.c_void_p(16)
+    blocks = [p] * 6
+
+    def cem(n, n_c, layers, J, J1):
+        return lib.pe_cem_spaces(n, n_c, layers, J, J1, p, p, 0, None, *blocks, None, None, None)
+
+    assert cem(21, 2, 1, 5, 2) == _lib.PE_ERR_ARG            # n % n_c != 0
+    assert cem(20, 2, 1, 9, 2) == _lib.PE_ERR_ARG            # J > 8
+    assert cem(20, 2, 1, 5, 6) == _lib.PE_ERR_ARG            # J1 > J
+    assert cem(400, 20, 3, 5, 2) == _lib.PE_ERR_ARG          # 7 x 20 cells per patch row: band too wide
+    assert b"band window" in lib.pe_last_error()
+    assert cem(100, 20, 2, 8, 2) == _lib.PE_ERR_ARG          # 25 elements x 8 constraints > 128
+    assert b"constraints" in lib.pe_last_error()
+    assert lib.pe_local_spectral(240, 20, 5, p, p, None, p, None) == _lib.PE_ERR_ARG  # 13^2 nodes > 128
+    assert b"nodes per coarse element" in lib.pe_last_error()
+    assert lib.pe_local_spectral(20, 3, 5, p, p, None, p, None) == _lib.PE_ERR_ARG    # 20 % 3 != 0
+    assert lib.pe_local_spectral(20, 2, 0, p, p, None, p, None) == _lib.PE_ERR_ARG    # J = 0

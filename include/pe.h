@@ -312,8 +312,9 @@ pe_status pe_probe_peaks(void* hip_stream, double* out3);
  * > 0 over the free nodes f in local order; within an eigenvalue of
  * multiplicity > 1 the vectors are one orthonormal basis of the eigenspace
  * (the one the rotations reach). Dense per element: Cholesky of S_e, cyclic
- * Jacobi on L^-1 A_e L^-T (sweeps until the off-diagonal Frobenius norm is
- * below 1e-16 of the diagonal's, at most 30). All pointers are device
+ * Jacobi on L^-1 A_e L^-T (sweeps down to the rounding floor: once the
+ * off-diagonal Frobenius norm is below 1e-10 of the diagonal's, until a sweep
+ * no longer halves it; at most 30). All pointers are device
  * memory; work on hip_stream, returns when done. Allocates 256 KiB per
  * element for the call. Errors: PE_ERR_ARG, PE_ERR_NOT_SPD (an element's
  * weighted mass), PE_ERR_NOMEM, PE_ERR_HIP.

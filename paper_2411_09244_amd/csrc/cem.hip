@@ -631,8 +631,12 @@ __global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, con
     if (n2 > nf && tid == 0) C[nf * n2 + nf] = 2.0 * red[0] + 1.0;
     for (int idx = tid; idx < n2 * n2; idx += 256) V[(idx / n2) * SPEC_N + idx % n2] = (idx / n2 == idx % n2);
     __syncthreads();
-    // cyclic Jacobi sweeps
+    // cyclic Jacobi sweeps down to the rounding floor: once the off-diagonal
+    // Frobenius norm is below 1e-10 of the diagonal's, stop at the first
+    // sweep that no longer halves the off-diagonal mass (early sweeps may
+    // reduce it by less; the eigenvectors need the floor, not a threshold)
     const int half = n2 / 2;
+    double off_prev = -1.0;
     for (int sweep = 0; sweep < 30; ++sweep) {
         double off = 0.0, dg = 0.0;
         for (int idx = tid; idx < n2 * n2; idx += 256) {
@@ -659,7 +663,9 @@ __global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, con
         }
         const double dgs = red[0];
         __syncthreads();
-        if (!(offs > 1e-32 * dgs)) break;  // uniform (NaN stops too)
+        if (!(offs > 0.0) || (offs < 1e-20 * dgs && off_prev >= 0.0 && offs > 0.5 * off_prev))
+            break;  // uniform (NaN stops too)
+        off_prev = offs;
         for (int rd = 0; rd < n2 - 1; ++rd) {
             if (tid < half) {
                 const int k = tid;
@@ -680,17 +686,32 @@ __global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, con
                 qq[k] = q;
             }
             __syncthreads();
-            // columns p, q of C and V
-            for (int idx = tid; idx < half * n2; idx += 256) {
-                const int k = idx / n2, r = idx % n2;
-                const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                const double x = C[r * n2 + p], y = C[r * n2 + q];
-                C[r * n2 + p] = c * x - s * y;
-                C[r * n2 + q] = s * x + c * y;
-                const double vx = V[r * SPEC_N + p], vy = V[r * SPEC_N + q];
-                V[r * SPEC_N + p] = c * vx - s * vy;
-                V[r * SPEC_N + q] = s * vx + c * vy;
+            // columns p, q of C and V, four entries per thread at a time so
+            // that their global loads of V are in flight together
+            for (int base = tid; base < half * n2; base += 4 * 256) {
+                int rr[4], pc[4], qc[4], kc[4];
+                double x[4], y[4], vx[4], vy[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int idx = min(base + u * 256, half * n2 - 1);
+                    kc[u] = idx / n2;
+                    rr[u] = idx % n2;
+                    pc[u] = pp[kc[u]];
+                    qc[u] = qq[kc[u]];
+                    vx[u] = V[rr[u] * SPEC_N + pc[u]];
+                    vy[u] = V[rr[u] * SPEC_N + qc[u]];
+                    x[u] = C[rr[u] * n2 + pc[u]];
+                    y[u] = C[rr[u] * n2 + qc[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (base + u * 256 >= half * n2) break;
+                    const double c = cs[kc[u]], s = sn[kc[u]];
+                    C[rr[u] * n2 + pc[u]] = c * x[u] - s * y[u];
+                    C[rr[u] * n2 + qc[u]] = s * x[u] + c * y[u];
+                    V[rr[u] * SPEC_N + pc[u]] = c * vx[u] - s * vy[u];
+                    V[rr[u] * SPEC_N + qc[u]] = s * vx[u] + c * vy[u];
+                }
             }
             __syncthreads();
             // rows p, q of C

@@ -129,7 +129,12 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
  * Blocks until done; one scalar read-back per iteration. After the first
  * call for a given B, each sweep (fine sweep, coarse sweep + stopping-test
  * products) is replayed from a captured HIP graph (PE_GRAPHS=0 in the
- * environment at problem creation keeps every launch eager).
+ * environment at problem creation keeps every launch eager). With B = 1, a
+ * fresh history and N >= 4 the coarse sweeps run as doubling scans over the
+ * intervals (ceil(log2 N) products with powers of the coarse step matrix,
+ * formed at the first such call; PE_COARSE_SCAN=0 at problem creation keeps
+ * the sequential sweeps); the results agree with the sequential sweeps up
+ * to rounding order.
  * Returns PE_WARN_NOT_CONVERGED if some sample did not meet the test.
  */
 pe_status pe_solve(pe_problem p, int B, const double* x0, double tol, int norm_mode,
@@ -445,7 +450,10 @@ pe_status pe_profile_read(pe_problem p, int kind, double* total_ms, long long* l
  * environment variable PE_TUNE_CACHE, which later handles read back). The
  * same happens lazily at the first use of a shape unless PE_AUTOTUNE=0.
  * Shapes listed in the read-only file named by PE_TUNE_DB (a database of
- * configurations measured on MI355X) are not re-tuned.
+ * configurations measured on MI355X) are not re-tuned. PE_FORCE_WSK=
+ * "bs,waves,splitk" at problem creation runs every product of at most 64
+ * state columns on the wave-split-K kernel with that configuration (for
+ * tests; operator tiles of 16 or 32 rows, 4 or 8 waves).
  * Results are bitwise reproducible for fixed configurations.
  */
 pe_status pe_autotune(pe_problem p, int B);

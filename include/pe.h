@@ -4,7 +4,7 @@
  *
  * Method (Wang, Yang, Leung, "Parallel in time partially explicit splitting
  * scheme for high contrast linear multiscale diffusion problems"):
- *   - the splitting scheme of eqs. (2.5)-(2.6): u in V_H1 implicit, w in
+ *   - the splitting scheme of eqs. (2.4)-(2.5): u in V_H1 implicit, w in
  *     V_H2 explicit, step h, with mass-coupling differences of the previous
  *     step;
  *   - the coarse propagator G = one step of size dt_coarse, the fine
@@ -164,7 +164,7 @@ pe_status pe_mass_norms(pe_problem p, int count, const double* X, double* out);
 /*
  * pe_adjoint - gradients of a loss L of the sequential fine solution (the
  * limit of parareal, eq. (2.7)) with respect to the initial states and the
- * source amplitudes. The transposed splitting scheme of eqs. (2.5)-(2.6) is
+ * source amplitudes. The transposed splitting scheme of eqs. (2.4)-(2.5) is
  * run backward in time, itself parallel across the intervals by parareal:
  *     lambda_N = Xbar_N,
  *     lambda_n^k = Xbar_n + F_n^T lambda_{n+1}^{k-1}
@@ -228,7 +228,7 @@ pe_status pe_tracking(pe_problem p, int B, const double* Ybnd, const double* dH,
  * The history is reset at the interval start (as for the propagators of
  * pe_solve) and the first iterate continues the start state in time. The
  * iteration's fixed point is pe_fine_propagate's F (P steps of
- * eqs. (2.5)-(2.6)); the error contracts by about gamma^2 per iteration
+ * eqs. (2.4)-(2.5)); the error contracts by about gamma^2 per iteration
  * (gamma of eq. (4.15)), and a smaller alpha converges faster but scales
  * rounding errors by about 1/alpha.
  *   B        samples (must equal the source's sample count when a source is set).
@@ -249,7 +249,7 @@ pe_status pe_fine_wr(pe_problem p, int B, const double* Xin, double alpha, int K
 /*
  * pe_set_fine_solver - the fine propagator F that pe_solve uses in the
  * parareal update (eq. (2.7)):
- *   PE_FINE_STEP (default): P steps of eqs. (2.5)-(2.6);
+ *   PE_FINE_STEP (default): P steps of eqs. (2.4)-(2.5);
  *   PE_FINE_WR: K0 >= 1 iterations of waveform relaxation with alpha in
  *     (0, 1), exactly as pe_fine_wr (Algorithm 1 with the paper's fine
  *     solver, Section 4.3). PE_FP64 handles only; parareal then converges
@@ -261,7 +261,7 @@ enum { PE_FINE_STEP = 0, PE_FINE_WR = 1 };
 pe_status pe_set_fine_solver(pe_problem p, int kind, double alpha, int K0);
 
 /*
- * pe_set_history - what the two-step scheme (2.5)-(2.6) uses as the previous
+ * pe_set_history - what the two-step scheme (2.4)-(2.5) uses as the previous
  * level at the start of each propagator call (the paper passes only the
  * state between the intervals of Algorithm 1 and leaves this open):
  *   PE_HIST_RESTART (default): a fresh history, u_{-1} = u_0, w_{-1} = w_0 at

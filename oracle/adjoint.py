@@ -7,7 +7,7 @@ limit of parareal, eq. (2.7)), is linear in (x0, H) jointly, and so is the
 map to every fine time level of that solution. Given the cotangents
 Xbar_n = dL/dX*_n at the coarse boundaries and, optionally, cotangents at
 the fine levels (a tracking term), the adjoint returns dL/dx0 and dL/dH by
-running the transpose of every fine step of eqs. (2.5)-(2.6) backward in
+running the transpose of every fine step of eqs. (2.4)-(2.5) backward in
 time: the transposed implicit solve with M11/h + A11, the transposed
 explicit solve with M22, the history copies, and the fresh history at every
 interval start (whose transpose adds the history adjoint to the state

@@ -1,4 +1,4 @@
-"""Brute-force fine-grid backward Euler, paper eq. (2.4) with V_H replaced by
+"""Brute-force fine-grid backward Euler, paper eq. (2.3) with V_H replaced by
 the full Q1 space: (M_f/dt + A_f) u' = M_f u/dt + b(t'), solved by a sparse
 LU factorisation. TEST INFRASTRUCTURE ONLY."""
 import numpy as np

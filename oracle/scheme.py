@@ -6,14 +6,14 @@ import this package; only the tests, the smoke check and the CPU-baseline leg
 of the benchmark use it. It is written directly from the paper and shares no
 code with the GPU path.
 
-Scheme (paper eqs. (2.5)-(2.6)) in matrix form, step size h, state (u, w) at
+Scheme (paper eqs. (2.4)-(2.5)) in matrix form, step size h, state (u, w) at
 level n and history (u_prev, w_prev) at level n-1:
     M11 (u' - u)/h + M12 (w - w_prev)/h + A11 u' + A12 w = F1
     M22 (w' - w)/h + M21 (u - u_prev)/h + A21 u' + A22 w = F2
 with M21 = M12^T, A21 = A12^T (symmetric forms a(.,.) and (.,.)).
 Readings:
   * the source is taken at the new time level t_{n+1}, as in eqs. (4.8)-(4.9)
-    and in backward Euler (2.4);
+    and in backward Euler (2.3);
   * every propagator call starts a fresh history: u_prev = u, w_prev = w at
     the first step of an interval (the coupling differences vanish there);
     the coarse propagator G is then one step of size Delta t;
@@ -97,7 +97,7 @@ class Source:
 
 
 def step(bl, h, u, w, u_prev, w_prev, F):
-    """One step of eqs. (2.5)-(2.6) with step size h. u, w (and the history)
+    """One step of eqs. (2.4)-(2.5) with step size h. u, w (and the history)
     are vectors or (d, ncol) arrays of independent columns; F is 0 or has
     the shape of the stacked state [u; w]."""
     d1 = bl.d1
@@ -216,7 +216,7 @@ def rel_l2_M(bl, X, Xref):
 
 # ---------------------------------------------------------------------------
 # History carried across intervals (the alternative reading of the two-step
-# scheme at interval starts). The scheme (2.5)-(2.6) couples the two spaces
+# scheme at interval starts). The scheme (2.4)-(2.5) couples the two spaces
 # through the difference quotients (u_n - u_{n-1})/h and (w_n - w_{n-1})/h of
 # the previous step. Instead of restarting that history at every interval
 # start, the state carries it: y = [x; delta] with delta = x - x_prev the

@@ -32,7 +32,7 @@ Readings (beyond those of the scheme oracle):
   * initial waveform: w_s^0 = w_0 at every level and u_P^0 = u_0 (the start
     state continued as a constant);
   * the fixed point of the iteration is the sequential fine propagator F
-    (P steps of eqs. (2.5)-(2.6)); the theorem of Section 4.2 bounds the
+    (P steps of eqs. (2.4)-(2.5)); the theorem of Section 4.2 bounds the
     error after j iterations by a factor gamma^(2(j-1)), gamma the cosine of
     eq. (4.15) (continuous time, alpha -> 0).
 """

@@ -2,7 +2,7 @@
 // the GPU), the fine and coarse propagators, and the parareal iteration of
 // Algorithm 1 (update (2.7), stopping test (2.8)).
 //
-// Step of the splitting scheme, eqs. (2.5)-(2.6), written with residuals and
+// Step of the splitting scheme, eqs. (2.4)-(2.5), written with residuals and
 // increments. Per state column keep [du_prev | u | w | dw_prev], where
 // du_prev = u_n - u_{n-1}, dw_prev = w_n - w_{n-1} (zero at an interval
 // start: every propagator call begins with a fresh history). With
@@ -116,7 +116,7 @@ struct pe_problem_s {
     // operators (padded, row-major)
     double* A64 = nullptr;   // Dp x Dp   full stiffness
     double* M64 = nullptr;   // Dp x Dp   full mass
-    // fine step (eqs. (2.5)-(2.6) at dt_fine): increment Z_h R with the
+    // fine step (eqs. (2.4)-(2.5) at dt_fine): increment Z_h R with the
     // residual R = F - A x_a - W_h dev, fused into one product per step:
     // Z_h R = Z_h F - (Z_h A) x_a - (Z_h W_h) dev
     double* Zf64 = nullptr;  // Dp x Dp   Z_h (FP64; whitened coordinates in PE_MIXED)
@@ -795,7 +795,7 @@ pe_status build_step_ops(pe_problem p, double h, const double* M11, const double
 
 // Second operator of the transposed fine step, Yop = [A; A + Mh] (2Dp x Dp):
 // A the full stiffness (Dp x Dp, symmetric) and Mh = [[0, M12/h], [M21/h, 0]]
-// the mass coupling of the history terms of eqs. (2.5)-(2.6). M12 is d1 x d2
+// the mass coupling of the history terms of eqs. (2.4)-(2.5). M12 is d1 x d2
 // with leading dimension ld12.
 pe_status build_adj_state_op(pe_problem p, const double* A, const double* M12, long ld12, double h, double* Y) {
     const int d1 = p->d1, d2 = p->d2, d1p = p->d1p, Dp = p->Dp;

@@ -1,5 +1,5 @@
 """Pins for the oracle's history-carrying propagators (the reading in which
-the two-step scheme (2.5)-(2.6) keeps its previous-step differences across
+the two-step scheme (2.4)-(2.5) keeps its previous-step differences across
 interval starts instead of restarting them).
 
 What fixes them independently of their own code:

@@ -138,7 +138,7 @@ def test_first_order_convergence_to_semidiscrete_ode():
 
 
 def _all_at_once(bl, x0, F_of_m, h, steps):
-    """Space-time solve of eqs. (2.5)-(2.6) for `steps` steps: one sparse
+    """Space-time solve of eqs. (2.4)-(2.5) for `steps` steps: one sparse
     linear system for all levels 1..steps, history at level -1 equal to
     level 0. Unknown ordering [u_1, w_1, u_2, w_2, ...]."""
     d1, d2, D = bl.d1, bl.d2, bl.D
@@ -149,8 +149,8 @@ def _all_at_once(bl, x0, F_of_m, h, steps):
     u0, w0 = x0[:d1], x0[d1:]
     for m in range(steps):     # equations producing level m+1
         Fm = F_of_m(m)
-        # eq. (2.5): M11 (u_{m+1}-u_m)/h + M12 (w_m - w_{m-1})/h + A11 u_{m+1} + A12 w_m = F1
-        # eq. (2.6): M22 (w_{m+1}-w_m)/h + M21 (u_m - u_{m-1})/h + A21 u_{m+1} + A22 w_m = F2
+        # eq. (2.4): M11 (u_{m+1}-u_m)/h + M12 (w_m - w_{m-1})/h + A11 u_{m+1} + A12 w_m = F1
+        # eq. (2.5): M22 (w_{m+1}-w_m)/h + M21 (u_m - u_{m-1})/h + A21 u_{m+1} + A22 w_m = F2
         diag = np.block([[M11 / h + A11, np.zeros((d1, d2))], [A12.T, M22 / h]])
         blocks[m][m] = sp.csr_matrix(diag)
         cur = np.block([[-M11 / h, M12 / h + A12], [M12.T / h, -M22 / h + A22]])   # level m

@@ -52,7 +52,7 @@ def test_all_at_once_solve_matches_kronecker(c0, alpha):
 @pytest.mark.parametrize("alpha", [0.0, 1e-3, 1e-2])
 def test_fixed_point_is_the_fine_propagator(c0, alpha):
     # the WR fixed point solves eqs. (4.8)-(4.9) with equal iterates, i.e. the
-    # sequential scheme (2.5)-(2.6): F
+    # sequential scheme (2.4)-(2.5): F
     bl, src = c0
     X = np.random.default_rng(2).standard_normal((bl.D, 4))
     ns, bs = [0, 3, 5, 7], [0] * 4

@@ -46,16 +46,31 @@ enum {
     PE_ERR_NONFINITE = -3,     /* NaN or Inf in a parareal jump */
     PE_ERR_STATE = -4,         /* call order violated (e.g. solve before source) */
     PE_ERR_HIP = -5,           /* HIP runtime error */
-    PE_ERR_NOMEM = -6          /* device allocation failed */
+    PE_ERR_NOMEM = -6,         /* device allocation failed */
+    PE_ERR_NUMERIC = -7        /* an iteration of the set-up pipeline did not converge */
 };
 
 /* precision of the fine propagator */
 enum {
     PE_FP64 = 0,  /* every product in FP64 on FP64 MFMA */
-    PE_MIXED = 1  /* fine-step products in FP32 on MFMA with FP32 accumulation,
+    PE_MIXED = 1, /* fine-step products in FP32 on MFMA with FP32 accumulation,
                      applied to the deviation from an FP64 anchor state taken at
                      each interval start; FP64 state accumulation, FP64
                      factorisations, coarse propagator and jump norms */
+    PE_MIXED_REFINE = 2 /* PE_MIXED plus one refinement of the implicit V_H1 solve
+                     of every fine step (eq. (2.4)): the residual
+                     r = F1 - A11 u' - A12 w - M12 (w - w_prev)/dt_fine - M11 (u' - u)/dt_fine
+                     of the FP32 step's u' is formed in FP64 from the FP64
+                     state, and the FP32 correction Z[:, u] r (Z the step's
+                     solve operator, formed in FP64) is added to the
+                     increments of u and w. Applied in the fine sweeps taken
+                     at the state's scale (the first parareal iteration's
+                     sweep, pe_fine_propagate, the adjoint's trajectory
+                     recomputation); the later sweeps, which propagate only
+                     the iterate change, run unrefined (their FP32 rounding
+                     scales with that change) unless PE_REFINE_ALL=1 is in
+                     the environment at creation. The transposed (adjoint)
+                     sweeps are not refined. */
 };
 
 /* time layout of the source amplitudes */
@@ -84,7 +99,7 @@ enum {
  *   dt_fine     fine step delta t; P = dt_coarse/dt_fine must be an integer
  *               within 1e-9 relative, else PE_ERR_ARG.
  *   N           number of coarse intervals (>= 1).
- *   precision   PE_FP64 or PE_MIXED.
+ *   precision   PE_FP64, PE_MIXED or PE_MIXED_REFINE.
  *   hip_stream  hipStream_t for all work of this handle. NULL: the handle
  *               creates and owns a non-blocking stream (the caller then
  *               orders its own producers/consumers by the blocking calls).
@@ -319,10 +334,13 @@ pe_status pe_probe_peaks(void* hip_stream, double* out3);
  * (the one the rotations reach). Dense per element: Cholesky of S_e, cyclic
  * Jacobi on L^-1 A_e L^-T (sweeps down to the rounding floor: once the
  * off-diagonal Frobenius norm is below 1e-10 of the diagonal's, until a sweep
- * no longer halves it; at most 30). All pointers are device
+ * no longer halves it; at most 30, or PE_SPECTRAL_SWEEPS from the
+ * environment). All pointers are device
  * memory; work on hip_stream, returns when done. Allocates 256 KiB per
  * element for the call. Errors: PE_ERR_ARG, PE_ERR_NOT_SPD (an element's
- * weighted mass), PE_ERR_NOMEM, PE_ERR_HIP.
+ * weighted mass), PE_ERR_NUMERIC (an element's sweeps stopped at the cap with
+ * the off-diagonal norm above 1e-10 of the diagonal's; the message names the
+ * element), PE_ERR_NOMEM, PE_ERR_HIP.
  */
 pe_status pe_local_spectral(int n, int n_c, int J, const double* kappa, double* lam, double* psi, double* spsi,
                             void* hip_stream);
@@ -422,7 +440,9 @@ enum {
                                    (d_k M11 + A11)^-1 per frequency, as a product
                                    with its real 2 d1 x 2 d1 form                */
     PE_PROF_WR_WSTEP = 10,      /* waveform relaxation: one sequential V_H2 step   */
-    PE_PROF_KINDS = 11
+    PE_PROF_REFINE = 11,        /* PE_MIXED_REFINE: the FP64 residual product and the
+                                   FP32 correction product of a fine step        */
+    PE_PROF_KINDS = 12
 };
 
 /*

@@ -16,8 +16,10 @@ PE_ERR_NONFINITE = -3
 PE_ERR_STATE = -4
 PE_ERR_HIP = -5
 PE_ERR_NOMEM = -6
+PE_ERR_NUMERIC = -7
 PE_FP64 = 0
 PE_MIXED = 1
+PE_MIXED_REFINE = 2
 PE_T_FINE = 0
 PE_T_INTERVAL = 1
 PE_NORM_M_ABS = 0
@@ -30,7 +32,7 @@ EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate"
            "pe_autotune", "pe_last_tiles", "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
 PROFILE_KINDS = {"fine_step": 0, "fine_first": 1, "anchor": 2, "coarse": 3, "norm": 4, "splitk_reduce": 5,
-                 "adj_step": 6, "fine_sweep": 7, "wr_rhs": 8, "wr_solve": 9, "wr_wstep": 10}
+                 "adj_step": 6, "fine_sweep": 7, "wr_rhs": 8, "wr_solve": 9, "wr_wstep": 10, "refine": 11}
 
 
 class PeError(RuntimeError):

@@ -22,7 +22,7 @@ class Problem:
     """One multiscale problem: blocks of eq. (3.8) + step sizes + N.
 
     blocks: dict with M11, M22, A11, A12, A22 and optionally M12, A21 (numpy
-    arrays or tensors, FP64). precision: "fp64" or "mixed"."""
+    arrays or tensors, FP64). precision: "fp64", "mixed" or "mixed_refine"."""
 
     def __init__(self, blocks, dt, dt_fine, N, precision="fp64", device="cuda", stream=None):
         self.lib = L.load()
@@ -33,7 +33,7 @@ class Problem:
         self.N = int(N)
         self.dt, self.dt_fine = float(dt), float(dt_fine)
         self.precision = precision
-        prec = {"fp64": L.PE_FP64, "mixed": L.PE_MIXED}[precision]
+        prec = {"fp64": L.PE_FP64, "mixed": L.PE_MIXED, "mixed_refine": L.PE_MIXED_REFINE}[precision]
         # a stream of the problem's own (default priority), ordered after the
         # caller's current stream at every call; every library call blocks
         # until its work is done, so results are ready when it returns

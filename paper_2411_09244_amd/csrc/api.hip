@@ -142,6 +142,16 @@ struct pe_problem_s {
     double* scan64[2] = {nullptr, nullptr};
     float* scan32[2] = {nullptr, nullptr};
     std::vector<void*> scan_allocs;
+    // the coarse correction of a batch (PE_MIXED) as the same scan, for B
+    // samples: FP32 powers Phi_G^(2^l), l = 1..bscan_L-1 (l = 0 is PhiG32),
+    // formed by FP64 squaring, and two B x (Z + N) x Dp ping-pong buffers
+    // (FP64 sums, FP32 copies) whose first Z = 2^(bscan_L - 1) rows per
+    // sample stay zero
+    int bscan_L = -1, bscan_Z = 0, bscan_B = 0;
+    std::vector<float*> bpow32;
+    double* bscan64[2] = {nullptr, nullptr};
+    float* bscan32[2] = {nullptr, nullptr};
+    std::vector<void*> bscan_allocs;
     // PE_MIXED: the fine sweep works in mass-whitened coordinates
     // x~ = Tin x, Tin = blkdiag(L1^T, L2^T) with M11 = L1 L1^T, M22 = L2 L2^T
     // (there M~11 = M~22 = I); x = Tout x~, Tout = Tin^-1; Linv = Tout^T
@@ -160,6 +170,14 @@ struct pe_problem_s {
     double* Mw64 = nullptr;
     int adj_ops = 0;           // adjoint operators built (on first use)
     double* M12k = nullptr;    // d1p x d2p (ld d2p): M12 in the fine sweep's coordinates
+    // PE_MIXED_REFINE (refine = 1; 2: also the sweeps on iterate changes):
+    // the implicit V_H1 equation of a fine step in whitened coordinates,
+    // Wr = [K~ | A~11 | A~12 | M~12/dt_fine] (d1p x 2Dp, FP64, K~ = I/dt_fine + A~11),
+    // applied to [du_new | u - u_a | w - w_a | dw_prev], and the correction
+    // operator Zc = Z_h[:, u] (Dp x d1p, FP32)
+    int refine = 0;
+    double* Wr64 = nullptr;
+    float* Zc32 = nullptr;
 
     // source
     int src_set = 0, B_src = 0, R = 0, Rp = 0, time_mode = 0, src_kind = 0;
@@ -184,6 +202,11 @@ struct pe_problem_s {
     float* Dl32[2] = {nullptr, nullptr};
     double* dev64[2] = {nullptr, nullptr};  // fine-step state, ping-pong (N*B x 2Dp)
     float* dev32[2] = {nullptr, nullptr};
+    // refinement workspace (PE_MIXED_REFINE): operands of the implicit
+    // equation (N*B x 2Dp), the u rows of A x_a (N*B x d1p) and the residual
+    // (N*B x d1p, FP32)
+    double *Vr = nullptr, *AxU = nullptr;
+    float* res32 = nullptr;
     double *E = nullptr, *Yn = nullptr, *Jd = nullptr, *x0p = nullptr, *io = nullptr, *nrm = nullptr;
     int* active_d = nullptr;
     GemmWork gw;
@@ -259,6 +282,7 @@ pe_status dalloc(pe_problem p, std::vector<void*>& list, void** out, size_t byte
     hipError_t e = hipMalloc(out, bytes);
     if (e != hipSuccess) {
         *out = nullptr;
+        (void)hipGetLastError();  // later launches must not report this failure
         return fail(PE_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
                                       hipGetErrorString(e));
     }
@@ -308,7 +332,10 @@ pe_status ensure_gemm_work(pe_problem p, size_t part_bytes) {
     w.part_bytes = 0;
     const size_t nb = std::max(part_bytes, (size_t)1 << 20);
     hipError_t e = hipMalloc(&w.part, nb);
-    if (e != hipSuccess) return fail(PE_ERR_NOMEM, "split-K workspace allocation failed");
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PE_ERR_NOMEM, "split-K workspace allocation failed");
+    }
     w.part_bytes = nb;
     return PE_OK;
 }
@@ -472,7 +499,10 @@ pe_status tune(pe_problem p, const GemmShape& sh, TileCfg* best_out) {
     const bool fp32 = sizeof(T) == 4;
     *best_out = choose_tiles(sh, fp32, p->n_cu);
     double* scratch = nullptr;
-    if (hipMalloc((void**)&scratch, sizeof(double) * sh.Mr * sh.Ns) != hipSuccess) return PE_OK;
+    if (hipMalloc((void**)&scratch, sizeof(double) * sh.Mr * sh.Ns) != hipSuccess) {
+        (void)hipGetLastError();  // no room to time candidates: keep the default tiles
+        return PE_OK;
+    }
     hipEvent_t e0, e1;
     PE_HIP(hipEventCreate(&e0));
     PE_HIP(hipEventCreate(&e1));
@@ -574,7 +604,9 @@ enum {
     SITE_ADJ_STEP = 8,
     SITE_WR_RHS = 9,
     SITE_WR_WSTEP = 10,
-    SITE_COARSE_SCAN = 11
+    SITE_COARSE_SCAN = 11,
+    SITE_REFINE_RES = 12,
+    SITE_REFINE_CORR = 13
 };
 
 template <typename T>
@@ -924,6 +956,11 @@ pe_status ensure_workspace(pe_problem p, int B) {
         PE_TRY(dalloc_t(p, L, &p->dev32[0], Bs * N * 2 * Dp));
         PE_TRY(dalloc_t(p, L, &p->dev32[1], Bs * N * 2 * Dp));
     }
+    if (p->refine) {
+        PE_TRY(dalloc_t(p, L, &p->Vr, Bs * N * 2 * Dp));
+        PE_TRY(dalloc_t(p, L, &p->AxU, Bs * N * (size_t)p->d1p));
+        PE_TRY(dalloc_t(p, L, &p->res32, Bs * N * (size_t)p->d1p));
+    }
     PE_TRY(dalloc_t(p, L, &p->E, Bs * (N + 1) * Sx));
     PE_TRY(dalloc_t(p, L, &p->Yn, Bs * (N + 1) * Dp));
     PE_TRY(dalloc_t(p, L, &p->io, Bs * (N + 1) * Sx));
@@ -965,6 +1002,7 @@ struct SrcView {
     int kind = 0;
     const double* Hs = nullptr;
     const double* ZFint = nullptr;
+    const double* Fint_w = nullptr;  // the table itself, whitened (refinement residual, PE_MIXED)
 };
 
 // source fields of the fused fine step: Z_h G (or the per-interval Z_h F)
@@ -1010,6 +1048,9 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     const int rows = B * p->N;
     const bool mixed = p->prec == PE_MIXED;
     const bool hist = p->hist == PE_HIST_CARRY;
+    // PE_MIXED_REFINE: the sweeps at the state's scale (with the source),
+    // and with refine = 2 also those on iterate changes
+    const bool refine = mixed && p->refine && (with_source || p->refine > 1);
     // whitening x~ = Tin x (block diagonal) of rows x Dp: in -> out
     auto whiten_rows = [&](const double* in, double* out, const double* T) -> pe_status {
         GemmShape gt = shape(rows, Dp, in, Dp, T, Dp, 0, d1p);
@@ -1035,6 +1076,11 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     // anchor term Z_h A x_a (FP64, once per sweep)
     PE_TRY(gemm<double>(p, shape(rows, Dp, p->Xa, Dp, p->ZA64, Dp, 0, Dp), store_epi(p->Ya, Dp), 0,
                         PE_PROF_ANCHOR, SITE_ANCHOR));
+    // refinement: the u rows of A x_a (FP64, once per sweep), the anchor
+    // part of the implicit equation's residual
+    if (refine)
+        PE_TRY(gemm<double>(p, shape(rows, d1p, p->Xa, Dp, p->Aw64, Dp, 0, Dp), store_epi(p->AxU, d1p), 0,
+                            PE_PROF_ANCHOR, SITE_ANCHOR));
     const long ldS = 2L * Dp;
     // the fused step's epilogue fields (step index and state buffers are per step)
     Epi eb;
@@ -1064,7 +1110,7 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
     gs.k0b = 0;
     gs.k1b = 2 * Dp;
     bool done = false;
-    if (p->persistent && rows <= 64 && !hist) {
+    if (p->persistent && rows <= 64 && !hist && !refine) {
         int& grid = p->pers_grid[mixed ? 1 : 0];
         if (grid < 0) {
             grid = mixed ? fine_sweep_persistent_grid<float>() : fine_sweep_persistent_grid<double>();
@@ -1127,10 +1173,48 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
         e.dev32 = mixed ? p->dev32[1 - c] : nullptr;
         e.traj = traj ? traj + (long)step * Dp : nullptr;
         const int kind = step > 0 ? PE_PROF_FINE_STEP : PE_PROF_FINE_FIRST;
+        // the first step of a fresh history has no FP32 product (zero
+        // deviation): nothing to refine
+        const bool ref_step = refine && (step > 0 || hist);
+        if (ref_step) e.vr = p->Vr;
         if (mixed)
             PE_TRY(gemm<float>(p, g, e, 0, kind, SITE_FINE_STEP));
         else
             PE_TRY(gemm<double>(p, g, e, 0, kind, SITE_FINE_STEP));
+        if (ref_step) {
+            // FP64 residual of the implicit V_H1 equation (eq. (2.4)) at the
+            // FP32 step's u': r = F~1(t) - (A~ x_a)_u - Wr [du | u - u_a | w - w_a | dw_prev]
+            Epi er;
+            er.mode = EPI_RESID;
+            er.R32 = p->res32;
+            er.ldr = d1p;
+            er.base = p->AxU;
+            er.ldb = d1p;
+            source_fields(p, er, true);
+            if (sv) {
+                er.src_kind = sv->kind;
+                er.Hs = sv->Hs;
+                er.Fint = sv->Fint_w;
+            }
+            if (!with_source) er.src_kind = 0;
+            er.cols_per_b = p->N;
+            er.n_fixed = -1;
+            er.p_step = step;
+            PE_TRY(gemm<double>(p, shape(rows, d1p, p->Vr, ldS, p->Wr64, ldS, 0, (int)ldS), er, 0, PE_PROF_REFINE,
+                                SITE_REFINE_RES));
+            // FP32 correction of both increments: Z_h[:, u] r
+            Epi ec;
+            ec.mode = EPI_FCORR;
+            ec.dev64 = p->dev64[1 - c];
+            ec.dev32 = p->dev32[1 - c];
+            ec.ldd = ldS;
+            ec.d1p = d1p;
+            ec.d2p = d2p;
+            ec.traj = e.traj;
+            ec.ldtraj = eb.ldtraj;
+            PE_TRY(gemm<float>(p, shape(rows, Dp, p->res32, d1p, p->Zc32, d1p, 0, d1p), ec, 0, PE_PROF_REFINE,
+                               SITE_REFINE_CORR));
+        }
     }
     const double* dfin = p->dev64[p->P & 1];
     if (!mixed) {
@@ -1288,6 +1372,53 @@ pe_status scan_prepare(pe_problem p) {
     p->scan_L = L;
     p->scan_L0 = L0;
     return done(PE_OK);
+}
+
+// scan operators and buffers of a batch's coarse correction (B samples)
+pe_status batch_scan_prepare(pe_problem p, int B) {
+    const int N = p->N, Dp = p->Dp;
+    int L = 0;
+    while ((1 << L) < N) ++L;
+    const int Z = L > 0 ? 1 << (L - 1) : 1;
+    if (p->bscan_L == L && p->bscan_B == B) return PE_OK;
+    PE_HIP(hipStreamSynchronize(p->st));
+    free_list(p->bscan_allocs);
+    p->bscan_L = -1;
+    std::vector<void*>& OL = p->bscan_allocs;
+    p->bpow32.assign(std::max(L, 1), nullptr);
+    p->bpow32[0] = p->PhiG32;
+    if (L > 1) {
+        TmpList tmpl(p->st);
+        std::vector<void*>& tmp = tmpl.v;
+        double *P, *PT, *Q, *QT;
+        PE_TRY(dalloc_t(p, tmp, &P, (size_t)Dp * Dp));
+        PE_TRY(dalloc_t(p, tmp, &PT, (size_t)Dp * Dp));
+        PE_TRY(dalloc_t(p, tmp, &Q, (size_t)Dp * Dp));
+        PE_TRY(dalloc_t(p, tmp, &QT, (size_t)Dp * Dp));
+        PE_HIP(hipMemcpyAsync(P, p->PhiG64, sizeof(double) * Dp * Dp, hipMemcpyDeviceToDevice, p->st));
+        PE_HIP(place(PT, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
+        for (int l = 1; l < L; ++l) {
+            // P^2 as the NT product of P with P^T (and its transpose, for the next level)
+            PE_TRY(gemm<double>(p, shape(Dp, Dp, P, Dp, PT, Dp, 0, Dp), store_epi(Q, Dp)));
+            if (l + 1 < L) PE_TRY(gemm<double>(p, shape(Dp, Dp, PT, Dp, P, Dp, 0, Dp), store_epi(QT, Dp)));
+            PE_TRY(dalloc_t(p, OL, &p->bpow32[l], (size_t)Dp * Dp));
+            PE_HIP(to_f32(Q, p->bpow32[l], (long)Dp * Dp, p->st));
+            std::swap(P, Q);
+            std::swap(PT, QT);
+        }
+        PE_HIP(hipStreamSynchronize(p->st));
+    }
+    const long rows = (long)B * (Z + N);
+    for (int c = 0; c < 2; ++c) {
+        PE_TRY(dalloc_t(p, OL, &p->bscan64[c], (size_t)rows * Dp));
+        PE_TRY(dalloc_t(p, OL, &p->bscan32[c], (size_t)rows * Dp));
+        PE_HIP(zero_fill(p->bscan64[c], p->bscan32[c], rows * Dp, p->st));
+    }
+    PE_HIP(hipStreamSynchronize(p->st));
+    p->bscan_L = L;
+    p->bscan_Z = Z;
+    p->bscan_B = B;
+    return PE_OK;
 }
 
 pe_status coarse_sweep_scan(pe_problem p, double* Xk, const double* Xprev, const int* active) {
@@ -1662,6 +1793,7 @@ pe_status tracking_levels(pe_problem p, int B, const double* dH, double beta) {
             double* dst = mixed ? p->Fdh : p->Fdh_w;
             PE_TRY(gemm<double>(p, shape(B * N, Dp, src, Dp, p->Zf64, Dp, 0, Dp), store_epi(dst, Dp)));
             sv.ZFint = dst;
+            if (mixed) sv.Fint_w = p->Fdh_w;
         }
     }
     PE_TRY(fine_sweep(p, B, p->Yb, (long)(N + 1) * Dp, p->Fbuf, true, 0, false, &sv, p->Ytraj));
@@ -1698,6 +1830,19 @@ struct pe_batch_s {
     std::vector<void*> allocs;
     GroupPlan anc1, anc2, fin[2], nrm_rel, nrm_k;
     std::vector<GroupPlan> resid[2];  // [with source][fine step]
+    // PE_MIXED_REFINE: the u rows of A x_a, the FP64 residual products
+    // [with source][fine step] and the FP32 corrections [fine step]
+    int refine = 0;
+    GroupPlan anc3;
+    std::vector<GroupPlan> rres[2], rcorr;
+    // PE_MIXED: the coarse correction as a doubling scan; level l is one
+    // grouped launch over the (problem, sample) items whose problem has
+    // more than 2^l intervals
+    int scan = 0, scan_L = 0;
+    std::vector<GroupPlan> scanp;                    // [level]
+    std::vector<std::vector<int>> scan_item_g;       // [level][item] -> problem
+    std::vector<std::vector<long>> scan_item_tiles;  // [level][item] -> tiles
+    std::vector<int*> scan_wi_d, scan_wt_d;          // [level] work-group tables
     CoarseItem* c_init = nullptr;
     CoarseItem* c_corr[2] = {nullptr, nullptr};
     int *c_wg_item = nullptr, *c_wg_row = nullptr;
@@ -1708,8 +1853,8 @@ struct pe_batch_s {
     Prof prof;
     // problems still iterating: finished ones leave the launch tables
     std::vector<int> pact, fin_buf;
-    std::vector<long> t_fine, t_nk;  // tiles per problem of the fine and jump product families
-    int *fi_d = nullptr, *ft_d = nullptr, *ki_d = nullptr, *kt_d = nullptr;
+    std::vector<long> t_fine, t_nk, t_u;  // tiles per problem of the fine, jump and V_H1-row product families
+    int *fi_d = nullptr, *ft_d = nullptr, *ki_d = nullptr, *kt_d = nullptr, *ui_d = nullptr, *ut_d = nullptr;
     int tables_all = 1;
     long act_hash = 0;
 };
@@ -1800,6 +1945,11 @@ pe_status batch_plan(pe_batch bt) {
     std::vector<std::vector<GemmShape>> r_sh(bt->P, std::vector<GemmShape>(G));
     std::vector<std::vector<Epi>> r_ep[2];
     for (int w = 0; w < 2; ++w) r_ep[w].assign(bt->P, std::vector<Epi>(G));
+    // refinement families (PE_MIXED_REFINE)
+    std::vector<GemmShape> a3(G), rr_sh(G), rc_sh(G);
+    std::vector<Epi> e_a3(G);
+    std::vector<std::vector<Epi>> rr_ep[2], rc_ep(bt->P, std::vector<Epi>(G));
+    for (int w = 0; w < 2; ++w) rr_ep[w].assign(bt->P, std::vector<Epi>(G));
     for (int g = 0; g < G; ++g) {
         pe_problem p = bt->pr[g];
         const int B = bt->Bs[g], N = p->N, Dp = p->Dp, d1p = p->d1p, d2p = p->d2p, rows = B * N;
@@ -1827,8 +1977,25 @@ pe_status batch_plan(pe_batch bt) {
             }
             r_sh[step][g] = g1;
             for (int w = 0; w < 2; ++w) {
+                // refined steps: the full sweep's (w = 1), or every sweep's with refine = 2
+                const bool ref_step = bt->refine && step > 0 && (w == 1 || bt->refine > 1);
+                if (ref_step) {
+                    Epi er;
+                    er.mode = EPI_RESID;
+                    er.R32 = p->res32;
+                    er.ldr = d1p;
+                    er.base = p->AxU;
+                    er.ldb = d1p;
+                    source_fields(p, er, true);
+                    if (!w) er.src_kind = 0;
+                    er.cols_per_b = N;
+                    er.n_fixed = -1;
+                    er.p_step = step;
+                    rr_ep[w][step][g] = er;
+                }
                 Epi e1;
                 e1.mode = EPI_FSTEP;
+                if (ref_step) e1.vr = p->Vr;
                 e1.base = p->Ya;
                 e1.ldb = Dp;
                 source_fields_step(p, e1);
@@ -1844,6 +2011,20 @@ pe_status batch_plan(pe_batch bt) {
                 e1.d2p = d2p;
                 r_ep[w][step][g] = e1;
             }
+            Epi ec;
+            ec.mode = EPI_FCORR;
+            ec.dev64 = p->dev64[1 - c];
+            ec.dev32 = p->dev32[1 - c];
+            ec.ldd = ldS;
+            ec.d1p = d1p;
+            ec.d2p = d2p;
+            rc_ep[step][g] = ec;
+        }
+        if (bt->refine) {
+            a3[g] = shape(rows, d1p, p->Xa, Dp, p->Aw64, Dp, 0, Dp);
+            e_a3[g] = store_epi(p->AxU, d1p);
+            rr_sh[g] = shape(rows, d1p, p->Vr, ldS, p->Wr64, ldS, 0, (int)ldS);
+            rc_sh[g] = shape(rows, Dp, p->res32, d1p, p->Zc32, d1p, 0, d1p);
         }
         // back to the caller's coordinates (mixed)
         fsh[g] = shape(rows, Dp, p->R64, Dp, p->Tout64, Dp, 0, d1p);
@@ -1877,15 +2058,105 @@ pe_status batch_plan(pe_batch bt) {
     }
     PE_TRY(group_plan(bt, nrel_sh, e_nrel, sizeof(double), ri, rt, rn, &bt->nrm_rel));
     PE_TRY(group_plan(bt, nk_sh, e_nk, sizeof(double), ki, kt, kn, &bt->nrm_k));
+    bt->ui_d = bt->ut_d = nullptr;
+    for (int w = 0; w < 2; ++w) bt->rres[w].clear();
+    bt->rcorr.clear();
+    if (bt->refine) {
+        const int *ui, *ut;
+        int un;
+        PE_TRY(group_tables(bt, a3, &ui, &ut, &un));
+        PE_TRY(group_plan(bt, a3, e_a3, sizeof(double), ui, ut, un, &bt->anc3));
+        for (int w = 0; w < 2; ++w) {
+            bt->rres[w].assign(bt->P, GroupPlan());
+            if (!w && bt->refine < 2) continue;
+            for (int step = 1; step < bt->P; ++step)
+                PE_TRY(group_plan(bt, rr_sh, rr_ep[w][step], sizeof(double), ui, ut, un, &bt->rres[w][step]));
+        }
+        bt->rcorr.assign(bt->P, GroupPlan());
+        for (int step = 1; step < bt->P; ++step)
+            PE_TRY(group_plan(bt, rc_sh, rc_ep[step], sizeof(float), fi, ft, fn, &bt->rcorr[step]));
+        bt->ui_d = (int*)ui;
+        bt->ut_d = (int*)ut;
+    }
+    // coarse correction as a scan (PE_MIXED; PE_BATCH_SCAN=0 keeps the sequential sweep)
+    bt->scan = 0;
+    bt->scan_L = 0;
+    bt->scanp.clear();
+    bt->scan_item_g.clear();
+    bt->scan_item_tiles.clear();
+    bt->scan_wi_d.clear();
+    bt->scan_wt_d.clear();
+    {
+        const char* sc = getenv("PE_BATCH_SCAN");
+        if (mixed && !(sc && sc[0] == '0')) bt->scan = 1;
+    }
+    if (bt->scan) {
+        for (int g = 0; g < G && bt->scan; ++g) {
+            const pe_status s = batch_scan_prepare(bt->pr[g], bt->Bs[g]);
+            if (s == PE_ERR_NOMEM) {
+                // not enough device memory for the powers: the batch keeps
+                // the sequential correction sweep
+                for (int h = 0; h <= g; ++h) {
+                    pe_problem q = bt->pr[h];
+                    (void)hipStreamSynchronize(q->st);
+                    free_list(q->bscan_allocs);
+                    q->bscan_L = -1;
+                }
+                g_err.clear();
+                bt->scan = 0;
+                bt->scan_L = 0;
+                break;
+            }
+            PE_TRY(s);
+            bt->scan_L = std::max(bt->scan_L, bt->pr[g]->bscan_L);
+        }
+    }
+    if (bt->scan) {
+        bt->scanp.assign(bt->scan_L, GroupPlan());
+        bt->scan_item_g.assign(bt->scan_L, {});
+        bt->scan_item_tiles.assign(bt->scan_L, {});
+        bt->scan_wi_d.assign(bt->scan_L, nullptr);
+        bt->scan_wt_d.assign(bt->scan_L, nullptr);
+        for (int l = 0; l < bt->scan_L; ++l) {
+            const int c = l & 1;
+            std::vector<GemmShape> sh;
+            std::vector<Epi> ep;
+            for (int g = 0; g < G; ++g) {
+                pe_problem p = bt->pr[g];
+                if (p->bscan_L <= l) continue;
+                const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
+                for (int b = 0; b < bt->Bs[g]; ++b) {
+                    const long o = ((long)b * (Z + N) + Z) * Dp;
+                    const long oa = o - (long)(1 << l) * Dp;
+                    sh.push_back(shape(N, Dp, p->bscan32[c] + oa, Dp, p->bpow32[l], Dp, 0, Dp));
+                    Epi e = store_epi(p->bscan64[1 - c] + o, Dp, 1.0, p->bscan64[c] + o, Dp, 1.0);
+                    e.C32 = p->bscan32[1 - c] + o;
+                    ep.push_back(e);
+                    bt->scan_item_g[l].push_back(g);
+                    bt->scan_item_tiles[l].push_back((long)((N + bt->cfg.br - 1) / bt->cfg.br) *
+                                                     ((Dp + bt->cfg.bs - 1) / bt->cfg.bs));
+                }
+            }
+            const int *wi, *wt;
+            int wn;
+            PE_TRY(group_tables(bt, sh, &wi, &wt, &wn));
+            PE_TRY(group_plan(bt, sh, ep, sizeof(float), wi, wt, wn, &bt->scanp[l]));
+            bt->scan_wi_d[l] = (int*)wi;
+            bt->scan_wt_d[l] = (int*)wt;
+        }
+    }
     bt->fi_d = (int*)fi;
     bt->ft_d = (int*)ft;
     bt->ki_d = (int*)ki;
     bt->kt_d = (int*)kt;
     bt->t_fine.assign(G, 0);
     bt->t_nk.assign(G, 0);
+    bt->t_u.assign(G, 0);
     for (int g = 0; g < G; ++g) {
         bt->t_fine[g] = (long)((fine_sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br) * ((fine_sh[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
         bt->t_nk[g] = (long)((nk_sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br) * ((nk_sh[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
+        if (bt->refine)
+            bt->t_u[g] = (long)((a3[g].Mr + bt->cfg.br - 1) / bt->cfg.br) * ((a3[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
     }
 
     // coarse steps: problems by decreasing N, so the problems still running
@@ -1966,12 +2237,16 @@ pe_status batch_plan(pe_batch bt) {
 // the problems still iterating (bt->pact); the stream must be idle.
 pe_status batch_tables(pe_batch bt) {
     const int G = bt->count;
-    std::vector<int> fi, ft, ki, kt, wi, wr;
+    std::vector<int> fi, ft, ki, kt, wi, wr, ui, ut;
     for (int g = 0; g < G; ++g) {
         if (!bt->pact[g]) continue;
         for (long t = 0; t < bt->t_fine[g]; ++t) {
             fi.push_back(g);
             ft.push_back((int)t);
+        }
+        for (long t = 0; bt->refine && t < bt->t_u[g]; ++t) {
+            ui.push_back(g);
+            ut.push_back((int)t);
         }
         for (long t = 0; t < bt->t_nk[g]; ++t) {
             ki.push_back(g);
@@ -2003,10 +2278,31 @@ pe_status batch_tables(pe_batch bt) {
     PE_TRY(put(bt->kt_d, kt));
     PE_TRY(put(bt->c_wg_item, wi));
     PE_TRY(put(bt->c_wg_row, wr));
-    const int fn = (int)fi.size(), kn = (int)ki.size();
+    if (bt->refine) {
+        PE_TRY(put(bt->ui_d, ui));
+        PE_TRY(put(bt->ut_d, ut));
+    }
+    const int fn = (int)fi.size(), kn = (int)ki.size(), un = (int)ui.size();
     for (GroupPlan* g : {&bt->anc1, &bt->anc2, &bt->fin[0], &bt->fin[1]}) g->n_wg = fn;
     for (int w = 0; w < 2; ++w)
         for (GroupPlan& g : bt->resid[w]) g.n_wg = fn;
+    bt->anc3.n_wg = un;
+    for (int w = 0; w < 2; ++w)
+        for (GroupPlan& g : bt->rres[w]) g.n_wg = un;
+    for (GroupPlan& g : bt->rcorr) g.n_wg = fn;
+    for (int l = 0; l < bt->scan_L; ++l) {
+        std::vector<int> si, st;
+        for (size_t i = 0; i < bt->scan_item_g[l].size(); ++i) {
+            if (!bt->pact[bt->scan_item_g[l][i]]) continue;
+            for (long t = 0; t < bt->scan_item_tiles[l][i]; ++t) {
+                si.push_back((int)i);
+                st.push_back((int)t);
+            }
+        }
+        PE_TRY(put(bt->scan_wi_d[l], si));
+        PE_TRY(put(bt->scan_wt_d[l], st));
+        bt->scanp[l].n_wg = (int)si.size();
+    }
     bt->nrm_k.n_wg = kn;
     bt->tables_all = std::count(bt->pact.begin(), bt->pact.end(), 1) == G;
     // graphs are keyed by the active set (the tables' content); repeated
@@ -2052,13 +2348,20 @@ pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
     }
     if (mixed) PE_TRY(grouped<double>(bt, bt->anc1, PE_PROF_ANCHOR));
     PE_TRY(grouped<double>(bt, bt->anc2, PE_PROF_ANCHOR));
+    const int w = incremental ? 0 : 1;
+    const bool refine = bt->refine && (w == 1 || bt->refine > 1);
+    if (refine) PE_TRY(grouped<double>(bt, bt->anc3, PE_PROF_ANCHOR));
     for (int step = 0; step < bt->P; ++step) {
-        const GroupPlan& r = bt->resid[incremental ? 0 : 1][step];
+        const GroupPlan& r = bt->resid[w][step];
         const int k1 = step > 0 ? PE_PROF_FINE_STEP : PE_PROF_FINE_FIRST;
         if (mixed)
             PE_TRY(grouped<float>(bt, r, k1));
         else
             PE_TRY(grouped<double>(bt, r, k1));
+        if (refine && step > 0) {
+            PE_TRY(grouped<double>(bt, bt->rres[w][step], PE_PROF_REFINE));
+            PE_TRY(grouped<float>(bt, bt->rcorr[step], PE_PROF_REFINE));
+        }
     }
     for (int g = 0; g < bt->count; ++g) {
         if (!bt->pact[g]) continue;
@@ -2452,6 +2755,7 @@ pe_status pe_problem_destroy(pe_problem p) {
     free_list(p->hist_ops);
     free_list(p->hist_src);
     free_list(p->scan_allocs);
+    free_list(p->bscan_allocs);
     if (p->gw.part) (void)hipFree(p->gw.part);
     if (p->own_stream) (void)hipStreamDestroy(p->st);
     delete p;
@@ -2530,7 +2834,15 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
     const double Pr = std::round(ratio);
     if (Pr < 1 || std::fabs(ratio - Pr) > 1e-9 * Pr || Pr > 1e7)
         return fail(PE_ERR_ARG, "dt_coarse / dt_fine must be a positive integer");
-    if (precision != PE_FP64 && precision != PE_MIXED) return fail(PE_ERR_ARG, "unknown precision");
+    if (precision != PE_FP64 && precision != PE_MIXED && precision != PE_MIXED_REFINE)
+        return fail(PE_ERR_ARG, "unknown precision");
+    // PE_MIXED_REFINE is the mixed path with the refinement operators
+    int refine = 0;
+    if (precision == PE_MIXED_REFINE) {
+        precision = PE_MIXED;
+        const char* ra = getenv("PE_REFINE_ALL");
+        refine = (ra && ra[0] == '1') ? 2 : 1;
+    }
 
     pe_problem p = new pe_problem_s();
     p->d1 = d1;
@@ -2545,6 +2857,7 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
     p->dt = dt_coarse;
     p->dtf = dt_fine;
     p->prec = precision;
+    p->refine = refine;
     p->st = (hipStream_t)hip_stream;
     if (!p->st) {
         // no stream given: the handle owns one (default priority, non-blocking)
@@ -2724,6 +3037,21 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
             CKH(hipMemcpyAsync(p->M12k, wM12, sizeof(double) * m12n, hipMemcpyDeviceToDevice, p->st));
             CK(dalloc_t(p, tmp, &ZW, (size_t)Dp * 2 * Dp));
             Aop = p->Aw64;
+            if (refine) {
+                // Wr = the u rows of W_h [0 | A~11 | A~12 | M~12/h] with the
+                // implicit operator K~ = I/h + A~11 in the first block
+                CK(dalloc_t(p, OL, &p->Wr64, (size_t)d1p * 2 * Dp));
+                CKH(hipMemcpyAsync(p->Wr64, W64, sizeof(double) * d1p * 2 * Dp, hipMemcpyDeviceToDevice, p->st));
+                CKH(place(p->Wr64, 2L * Dp, 0, 0, wA11, d1p, d1, d1, 1.0, 0, p->st, 1));
+                CKH(place(p->Wr64, 2L * Dp, 0, 0, I11, d1p, d1, d1, 1.0 / dt_fine, 0, p->st, 1));
+                // Zc = Z_h[:, u]: the solve of a V_H1 residual and its effect
+                // on the explicit V_H2 increment
+                double* Zc = nullptr;
+                CK(dalloc_t(p, tmp, &Zc, (size_t)Dp * d1p));
+                CKH(place(Zc, d1p, 0, 0, p->Zf64, Dp, Dp, d1p, 1.0, 0, p->st));
+                CK(dalloc_t(p, OL, &p->Zc32, (size_t)Dp * d1p));
+                CKH(to_f32(Zc, p->Zc32, (long)Dp * d1p, p->st));
+            }
         }
         // Z_h W_h = Z_h (W_h^T)^T: NT product with W_h^T as the operator rows
         CKH(place(WT, Dp, 0, 0, W64, 2L * Dp, 2 * Dp, Dp, 1.0, 1, p->st));
@@ -3291,10 +3619,13 @@ pe_status pe_batch_create(pe_batch* out, int count, const pe_problem* problems, 
     for (int i = 1; i < count; ++i) {
         if (problems[i]->prec != prec) return fail(PE_ERR_ARG, "all problems of a batch need the same precision");
         if (problems[i]->P != P) return fail(PE_ERR_ARG, "all problems of a batch need the same step ratio P");
+        if (problems[i]->refine != problems[0]->refine)
+            return fail(PE_ERR_ARG, "all problems of a batch need the same refinement (PE_MIXED_REFINE or not)");
     }
     pe_batch bt = new pe_batch_s();
     bt->count = count;
     bt->prec = prec;
+    bt->refine = problems[0]->refine;
     bt->P = P;
     bt->pr.assign(problems, problems + count);
     for (pe_problem p : bt->pr) bt->N_max = std::max(bt->N_max, p->N);
@@ -3452,11 +3783,37 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
                 PE_HIP(zero_fill(mixed ? nullptr : p->Dl64[0], mixed ? p->Dl32[0] : nullptr, (long)bt->Bs[g] * p->Dp,
                                  bt->st));
             }
-            for (int n = 0; n < bt->N_max; ++n) {
-                if (mixed)
-                    PE_TRY(coarse_grouped<float>(bt, bt->c_corr[cur], n, 1, n & 1));
-                else
-                    PE_TRY(coarse_grouped<double>(bt, bt->c_corr[cur], n, 1, n & 1));
+            if (bt->scan) {
+                // change form d_{n+1} = Phi_G d_n + e_n, e_n = F(x_n^{k-1}) - x_{n+1}^{k-1},
+                // summed by the doubling scan; then x_n^k = x_n^{k-1} + d_n
+                for (int g = 0; g < G; ++g) {
+                    if (!bt->pact[g]) continue;
+                    pe_problem p = bt->pr[g];
+                    const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
+                    for (int b = 0; b < bt->Bs[g]; ++b) {
+                        const long o = ((long)b * (Z + N) + Z) * Dp;
+                        PE_HIP(scan_init(p->Fbuf + (long)b * N * Dp, p->Xk[cur] + (long)b * (N + 1) * Dp, 1,
+                                         p->bscan64[0] + o, p->bscan32[0] + o, N, Dp, bt->st));
+                    }
+                }
+                for (int l = 0; l < bt->scan_L; ++l) PE_TRY(grouped<float>(bt, bt->scanp[l], PE_PROF_COARSE));
+                for (int g = 0; g < G; ++g) {
+                    if (!bt->pact[g]) continue;
+                    pe_problem p = bt->pr[g];
+                    const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
+                    for (int b = 0; b < bt->Bs[g]; ++b) {
+                        const long o = ((long)b * (Z + N) + Z) * Dp, ox = (long)b * (N + 1) * Dp;
+                        PE_HIP(scan_final(p->Xk[cur] + ox, p->bscan64[p->bscan_L & 1] + o, p->Xk[nxt] + ox, 1, N,
+                                          Dp, p->active_d + b, bt->st));
+                    }
+                }
+            } else {
+                for (int n = 0; n < bt->N_max; ++n) {
+                    if (mixed)
+                        PE_TRY(coarse_grouped<float>(bt, bt->c_corr[cur], n, 1, n & 1));
+                    else
+                        PE_TRY(coarse_grouped<double>(bt, bt->c_corr[cur], n, 1, n & 1));
+                }
             }
             PE_TRY(batch_jumps(bt, nxt, false));
             return PE_OK;

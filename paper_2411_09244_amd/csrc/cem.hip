@@ -500,10 +500,14 @@ __device__ inline void elem_pair(const double* __restrict__ kappa, int n, int m,
     }
 }
 
+// info[e]: 0, 1 (weighted mass not positive definite) or 2 (the Jacobi
+// sweeps hit max_sweeps with the off-diagonal norm still above 1e-10 of the
+// diagonal's)
 __global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, const double* __restrict__ kappa,
                                                       double* __restrict__ Lg, double* __restrict__ Vg,
                                                       double* __restrict__ lam, double* __restrict__ psi,
-                                                      double* __restrict__ spsi, int* __restrict__ info) {
+                                                      double* __restrict__ spsi, int* __restrict__ info,
+                                                      int max_sweeps) {
     __shared__ double C[SPEC_N * SPEC_N];
     __shared__ double cs[SPEC_N / 2], sn[SPEC_N / 2];
     __shared__ int pp[SPEC_N / 2], qq[SPEC_N / 2];
@@ -637,7 +641,9 @@ __global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, con
     // reduce it by less; the eigenvectors need the floor, not a threshold)
     const int half = n2 / 2;
     double off_prev = -1.0;
-    for (int sweep = 0; sweep < 30; ++sweep) {
+    bool converged = false;
+    double offs_last = 0.0, dgs_last = 0.0;
+    for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
         double off = 0.0, dg = 0.0;
         for (int idx = tid; idx < n2 * n2; idx += 256) {
             const int r = idx / n2, c = idx % n2;
@@ -663,8 +669,15 @@ __global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, con
         }
         const double dgs = red[0];
         __syncthreads();
-        if (!(offs > 0.0) || (offs < 1e-20 * dgs && off_prev >= 0.0 && offs > 0.5 * off_prev))
-            break;  // uniform (NaN stops too)
+        offs_last = offs;
+        dgs_last = dgs;
+        if (offs != offs || dgs != dgs) break;  // NaN: reported as not converged
+        if (!(offs > 0.0) || (offs < 1e-20 * dgs && off_prev >= 0.0 && offs > 0.5 * off_prev)) {
+            converged = true;
+            break;  // uniform
+        }
+        // the last pass only measures what max_sweeps sweeps left
+        if (sweep == max_sweeps) break;
         off_prev = offs;
         for (int rd = 0; rd < n2 - 1; ++rd) {
             if (tid < half) {
@@ -777,7 +790,7 @@ __global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, con
             }
         spsi[((long)e * nl + ln) * J + j] = acc;
     }
-    if (tid == 0) info[e] = 0;
+    if (tid == 0) info[e] = (converged || offs_last < 1e-20 * dgs_last) ? 0 : 2;
 }
 
 }  // namespace
@@ -978,8 +991,15 @@ extern "C" pe_status pe_local_spectral(int n, int n_c, int J, const double* kapp
         (void)hipGetLastError();
         return done(set_error(PE_ERR_NOMEM, "pe_local_spectral: device memory"));
     }
+    // sweep cap (PE_SPECTRAL_SWEEPS overrides the default 30, e.g. to test
+    // the non-convergence report)
+    int max_sweeps = 30;
+    if (const char* ms = getenv("PE_SPECTRAL_SWEEPS")) {
+        const int v = atoi(ms);
+        if (v >= 0 && v <= 1000) max_sweeps = v;
+    }
     hipLaunchKernelGGL(k_spec_element, dim3(n_elem), dim3(256), 0, st, n, n_c, J, kappa, Lg, Vg, lam, psi, spsi,
-                       info);
+                       info, max_sweeps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return done(set_error(PE_ERR_HIP, std::string("pe_local_spectral: ") + hipGetErrorString(e)));
@@ -987,9 +1007,14 @@ extern "C" pe_status pe_local_spectral(int n, int n_c, int J, const double* kapp
     if (hipMemcpyAsync(hinfo.data(), info, sizeof(int) * n_elem, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return done(set_error(PE_ERR_HIP, "pe_local_spectral: status read-back"));
-    for (int i = 0; i < n_elem; ++i)
+    for (int i = 0; i < n_elem; ++i) {
+        if (hinfo[i] == 2)
+            return done(set_error(PE_ERR_NUMERIC, "pe_local_spectral: the Jacobi sweeps of element " +
+                                                      std::to_string(i) + " did not converge in " +
+                                                      std::to_string(max_sweeps) + " sweeps"));
         if (hinfo[i] != 0)
             return done(set_error(PE_ERR_NOT_SPD, "pe_local_spectral: weighted mass of element " +
                                                       std::to_string(i) + " not positive definite"));
+    }
     return done(PE_OK);
 }

@@ -132,7 +132,7 @@ __device__ inline void fstep_apply(const Epi& e, int r, int s, double acc, int p
 // round trip instead of two. The arithmetic, and its order, is the same as
 // in a single-phase epilogue.
 struct EpiIn {
-    double a = 0.0, b = 0.0, c = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
     bool ok = true;
 };
 
@@ -147,8 +147,16 @@ __device__ inline EpiIn epi_load(const Epi& e, int r, int s) {
     } else if constexpr (MODE == EPI_FSTEP) {
         // branch-free load first, the source term (branches, waits) last
         in.c = e.din[(long)r * e.ldd + (s < e.d1p ? e.d1p + s : 2L * e.d1p + (s - e.d1p))];
+        if (e.vr && s >= e.d1p) in.d = e.din[(long)r * e.ldd + 2L * e.d1p + e.d2p + (s - e.d1p)];
         if (e.base) in.b = e.base[(long)r * e.ldb + s];
         in.a = source_value_p(e, r, s, e.p_step);
+    } else if constexpr (MODE == EPI_FCORR) {
+        const double* d = e.dev64 + (long)r * e.ldd;
+        const long o0 = s < e.d1p ? (long)s : 2L * e.d1p + (s - e.d1p);
+        const long o1 = s < e.d1p ? (long)e.d1p + s : 2L * e.d1p + e.d2p + (s - e.d1p);
+        in.a = d[o0];
+        in.b = d[o1];
+        if (e.traj) in.c = e.traj[(long)r * e.ldtraj + s];
     } else if constexpr (MODE == EPI_COARSE_INIT) {
         if (e.cs) in.a = e.cs[(long)r * e.ldcs + s];
     } else if constexpr (MODE == EPI_COARSE_DELTA) {
@@ -176,7 +184,7 @@ __device__ inline void epi_finish(const Epi& e, int r, int s, double acc, const 
     } else if constexpr (MODE == EPI_RESID) {
         double v = in.a - acc;
         if (e.base) v -= in.b;
-        e.R64[(long)r * e.ldr + s] = v;
+        if (e.R64) e.R64[(long)r * e.ldr + s] = v;
         if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
     } else if constexpr (MODE == EPI_FSTEP) {
         // increment d = Z F(t) - base - acc, then the state/history update
@@ -195,6 +203,11 @@ __device__ inline void epi_finish(const Epi& e, int r, int s, double acc, const 
                 d32[e.d1p + s] = (float)u;
             }
             full_dev = u;
+            if (e.vr) {
+                double* q = e.vr + (long)r * e.ldd;
+                q[s] = v;
+                q[e.d1p + s] = in.c;
+            }
         } else {
             const int j = s - e.d1p;
             const long ow = 2L * e.d1p + j, oh = 2L * e.d1p + e.d2p + j;
@@ -206,8 +219,29 @@ __device__ inline void epi_finish(const Epi& e, int r, int s, double acc, const 
                 d32[oh] = (float)v;
             }
             full_dev = w;
+            if (e.vr) {
+                double* q = e.vr + (long)r * e.ldd;
+                q[ow] = in.c;
+                q[oh] = in.d;
+            }
         }
         if (e.traj) e.traj[(long)r * e.ldtraj + s] = e.xa[(long)r * (e.d1p + e.d2p) + s] + full_dev;
+    } else if constexpr (MODE == EPI_FCORR) {
+        // the correction c = acc of the step's increment: du (or dw) and the
+        // state u - u_a (or w - w_a) both move by c
+        double* d = e.dev64 + (long)r * e.ldd;
+        float* d32 = e.dev32 ? e.dev32 + (long)r * e.ldd : nullptr;
+        const long o0 = s < e.d1p ? (long)s : 2L * e.d1p + (s - e.d1p);
+        const long o1 = s < e.d1p ? (long)e.d1p + s : 2L * e.d1p + e.d2p + (s - e.d1p);
+        // o0 holds du (u rows) or w - w_a (w rows); o1 holds u - u_a or dw
+        const double a = in.a + acc, b = in.b + acc;
+        d[o0] = a;
+        d[o1] = b;
+        if (d32) {
+            d32[o0] = (float)a;
+            d32[o1] = (float)b;
+        }
+        if (e.traj) e.traj[(long)r * e.ldtraj + s] = in.c + acc;
     } else if constexpr (MODE == EPI_COARSE_INIT) {
         double x = acc;
         if (e.cs) x += in.a;
@@ -251,6 +285,7 @@ __device__ inline void epi_dispatch(int mode, F&& f) {
         case EPI_COARSE_INIT: f(std::integral_constant<int, EPI_COARSE_INIT>{}); break;
         case EPI_COARSE_DELTA: f(std::integral_constant<int, EPI_COARSE_DELTA>{}); break;
         case EPI_ADJ_STATE: f(std::integral_constant<int, EPI_ADJ_STATE>{}); break;
+        case EPI_FCORR: f(std::integral_constant<int, EPI_FCORR>{}); break;
         default: break;
     }
 }
@@ -836,6 +871,7 @@ static hipError_t launch_splitk_reduce(const GemmShape& sh, const Epi& epi, int 
         case EPI_COARSE_INIT: launch_reduce<T, EPI_COARSE_INIT>(g, b, stream, sh, splitk, part, epi); break;
         case EPI_COARSE_DELTA: launch_reduce<T, EPI_COARSE_DELTA>(g, b, stream, sh, splitk, part, epi); break;
         case EPI_ADJ_STATE: launch_reduce<T, EPI_ADJ_STATE>(g, b, stream, sh, splitk, part, epi); break;
+        case EPI_FCORR: launch_reduce<T, EPI_FCORR>(g, b, stream, sh, splitk, part, epi); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -893,6 +929,7 @@ static hipError_t launch_gemv(const GemmShape& sh, const Epi& epi, hipStream_t s
         case EPI_COARSE_INIT: launch_gemv_m<T, EPI_COARSE_INIT>(sh, epi, stream); break;
         case EPI_COARSE_DELTA: launch_gemv_m<T, EPI_COARSE_DELTA>(sh, epi, stream); break;
         case EPI_ADJ_STATE: launch_gemv_m<T, EPI_ADJ_STATE>(sh, epi, stream); break;
+        case EPI_FCORR: launch_gemv_m<T, EPI_FCORR>(sh, epi, stream); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

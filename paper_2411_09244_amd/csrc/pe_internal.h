@@ -32,6 +32,7 @@ enum EpiMode : int {
     EPI_COARSE_INIT = 3,   // initial coarse sweep: x_{n+1} = Phi_G x_n + c_n
     EPI_COARSE_DELTA = 4,  // correction of eq. (2.7): x_{n+1}^k = F_n + Phi_G (x_n^k - x_n^{k-1})
     EPI_ADJ_STATE = 6,     // fused adjoint step: [a; nu] <- a - [A; A + Mh] Z^T nu (+ cotangent)
+    EPI_FCORR = 7,         // refinement of a fine step: state/history += acc (the correction Z_h[:, u] r)
 };
 
 struct Epi {
@@ -44,7 +45,7 @@ struct Epi {
     float* C32 = nullptr;  // EPI_STORE: nullable FP32 copy of C (same ldc)
     const double* C0 = nullptr;
     long ldc = 0, ldc0 = 0;
-    // EPI_RESID
+    // EPI_RESID (R64 and R32 nullable)
     double* R64 = nullptr;
     float* R32 = nullptr;
     long ldr = 0;
@@ -76,6 +77,11 @@ struct Epi {
     double* traj = nullptr;         // nullable: full new state xa + deviation at traj + r*ldtraj
     const double* xa = nullptr;     // anchors, ld d1p + d2p
     long ldtraj = 0;
+    // EPI_FSTEP with refinement (nullable): the implicit equation's operands
+    // [du_new | u - u_a | w - w_a | dw_prev] (the step's input state with its
+    // first block replaced by the new V_H1 increment), ld ldd
+    double* vr = nullptr;
+    // EPI_FCORR uses dev64 / dev32 (state updated in place), ldd, d1p, d2p, traj, ldtraj
     // EPI_COARSE_*  (column r is sample r)
     double* xout = nullptr;         // X^k[b][n+1] = xout + b*ldxo
     long ldxo = 0;

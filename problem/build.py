@@ -44,6 +44,15 @@ CONFIGS = {
     "c1n": dict(n=200, n_c=20, layers=2, J1=2, J2=3, medium="lognormal", sigma=1.0,
                 corr=0.05, n_h=5, n_v=5, contrast=1e6, incl=0.2, seed=1, split="nlmc_fm",
                 source="sine_exp", u0="zero", N=64, P=64, T=None, B=1),
+    # ill-conditioned implicit solves at a stable step: the NLMC split at
+    # fracture contrast 1e10 (fractures = cells above 1e3), where
+    # cond(M11/dt_fine + A11) reaches about 2e6 (200x200, P = 32)
+    "c1s": dict(n=200, n_c=20, layers=2, J1=2, J2=3, medium="lognormal", sigma=1.0,
+                corr=0.05, n_h=5, n_v=5, contrast=1e10, incl=0.2, seed=1, split="nlmc_fm",
+                frac_threshold=1e3, source="sine_exp", u0="zero", N=64, P=32, T=None, B=1),
+    "c4s": dict(n=400, n_c=40, layers=2, J1=2, J2=3, medium="lognormal", sigma=1.0,
+                corr=0.05, n_h=10, n_v=10, contrast=1e10, incl=0.2, seed=4, split="nlmc_fm",
+                frac_threshold=1e3, source="sine_exp", u0="zero", N=64, P=32, T=None, B=1),
     # small workloads for tests
     "t0": dict(n=20, n_c=2, layers=1, J1=2, J2=3, medium="channels", n_h=1, n_v=1,
                contrast=1e4, seed=10, source="one", u0="zero", N=6, P=4, T=None, B=1),
@@ -55,6 +64,9 @@ CONFIGS = {
     "t1p": dict(n=40, n_c=4, layers=2, J1=2, J2=3, medium="channels", n_h=2, n_v=2,
                 contrast=1e6, seed=11, split="nlmc", source="sine_exp", u0="sine2", N=8, P=8,
                 T=None, B=1),
+    "t1s": dict(n=40, n_c=4, layers=2, J1=2, J2=3, medium="lognormal", sigma=1.0, corr=0.05,
+                n_h=2, n_v=2, contrast=1e10, incl=0.5, seed=11, split="nlmc_fm", frac_threshold=1e3,
+                source="sine_exp", u0="sine2", N=8, P=8, T=None, B=1),
     "t2": dict(n=60, n_c=6, layers=2, J1=2, J2=3, medium="lognormal", sigma=1.0,
                corr=0.05, n_h=2, n_v=2, contrast=1e6, incl=0.2, seed=12,
                source="fourier8_interval", u0="zero", N=12, P=8, T=None, B=3, src_seed=12),

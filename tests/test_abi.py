@@ -38,6 +38,11 @@ def test_error_paths_without_device():
                                ctypes.c_void_p(16), ctypes.c_void_p(16), None, ctypes.c_void_p(16),
                                1.0, 0.3, 4, 0, None)
     assert st == _lib.PE_ERR_ARG and b"integer" in lib.pe_last_error()
+    # precisions: PE_FP64, PE_MIXED, PE_MIXED_REFINE; anything else is refused
+    st = lib.pe_problem_create(ctypes.byref(h), 4, 4, ctypes.c_void_p(16), None, ctypes.c_void_p(16),
+                               ctypes.c_void_p(16), ctypes.c_void_p(16), None, ctypes.c_void_p(16),
+                               1.0, 0.5, 4, _lib.PE_MIXED_REFINE + 1, None)
+    assert st == _lib.PE_ERR_ARG and b"precision" in lib.pe_last_error()
     assert lib.pe_solve(None, 1, None, 0.0, 0, 1, None, None, None) == _lib.PE_ERR_ARG
     assert lib.pe_problem_destroy(None) == 0
 

@@ -232,3 +232,21 @@ def test_gpu_pipeline_end_to_end(name):
         e = _rel(out[k].cpu().numpy(), da[:, None] * bl[k] * db[None, :])
         print(f"  {k} rel {e:.3e}")
         assert e < 1e-8, k
+
+
+def test_local_spectral_reports_unconverged_sweeps(monkeypatch):
+    """With the sweep cap forced down to one sweep (PE_SPECTRAL_SWEEPS=1),
+    the Jacobi iterations of the lognormal medium's elements stop far above
+    the rounding floor: pe_local_spectral reports PE_ERR_NUMERIC naming an
+    element, instead of passing the unconverged vectors on; with the default
+    cap the same call succeeds."""
+    pe = _pe()
+    from paper_2411_09244_amd import _lib
+    cfg = dict(CONFIGS["t2"])
+    kappa = make_medium(cfg)
+    monkeypatch.setenv("PE_SPECTRAL_SWEEPS", "1")
+    with pytest.raises(pe.PeError) as ei:
+        pe.local_spectral(kappa, cfg["n_c"], 5)
+    assert ei.value.status == _lib.PE_ERR_NUMERIC and "did not converge" in str(ei.value)
+    monkeypatch.delenv("PE_SPECTRAL_SWEEPS")
+    pe.local_spectral(kappa, cfg["n_c"], 5)

@@ -4,7 +4,8 @@ per-interval amplitudes), where the oracle cannot run the whole solve: it
 checks sampled outputs one by one.
 
 Forward: the converged parareal iterate satisfies X_{n+1} = F(X_n) up to
-the stopping tolerance; the oracle applies its fine propagator to sampled
+the stopping tolerance (rel 1e-9 on the mixed path, 1e-12 on the FP64
+path, against bars of 1e-6 and 1e-10); the oracle applies its fine propagator to sampled
 GPU states X_n and compares with the GPU's X_{n+1}. Adjoint (terminal plus
 coarse-boundary tracking loss): lam_n = Xbar_n + F_n^T lam_{n+1}, and the
 source gradient of interval n is G^T (sum of the transposed steps' source
@@ -35,8 +36,8 @@ def _rel_M(bl, a, b):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec,bar", [("mixed", 1e-6)])
-def test_large_forward_and_adjoint_sampled(prec, bar):
+@pytest.mark.parametrize("prec,bar,tol", [("mixed", 1e-6, 1e-9), ("fp64", 1e-10, 1e-12)])
+def test_large_forward_and_adjoint_sampled(prec, bar, tol):
     import paper_2411_09244_amd as pe
     assert torch.cuda.is_available()
     c = _setup()
@@ -44,7 +45,7 @@ def test_large_forward_and_adjoint_sampled(prec, bar):
     B, N = p["H"].shape[0], p["N"]
     pr = pe.problem_from(p, prec)
     x0 = torch.zeros((B, bl.D), dtype=torch.float64, device="cuda")
-    X, it, hist, st = pr.solve(x0, tol=1e-9, norm="rel")
+    X, it, hist, st = pr.solve(x0, tol=tol, norm="rel")
     print(f"forward: iterations {it.min()}..{it.max()}, status {st}", flush=True)
     assert st == 0
     # loss 1/2 |x_N|_M^2 + 1/2 sum_{n=1}^{N} dt |x_n|_M^2 (targets zero)
@@ -52,7 +53,7 @@ def test_large_forward_and_adjoint_sampled(prec, bar):
     Xbar = bl.dt * (X @ Mt)
     Xbar[:, 0] = 0.0
     Xbar[:, -1] += X[:, -1] @ Mt
-    r = pr.adjoint(Xbar=Xbar, tol=1e-9, lam=True)
+    r = pr.adjoint(Xbar=Xbar, tol=tol, lam=True)
     print(f"adjoint: iterations {r['iters'].min()}..{r['iters'].max()}, status {r['status']}", flush=True)
     assert r["status"] == 0
     Xh, lam, Hb = X.cpu().numpy(), r["lam"].cpu().numpy(), r["Hbar"].cpu().numpy()

@@ -382,6 +382,30 @@ pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, const double*
                         double* A12, double* A22, double* G, double* Psi, void* hip_stream);
 
 /*
+ * pe_nlmc_spaces - the set-up pipeline for the NLMC spaces of Section 3.2
+ * (eqs. (3.4)-(3.6)), split by continuum: every coarse element k has
+ * counts[k] regions, its matrix region (slot 0) and its fracture pieces
+ * (slots 1..counts[k]-1); the basis function of region (k, l) minimises
+ * a(psi, psi) over functions vanishing outside the oversampled patch's
+ * interior nodes subject to int_r psi = delta_{r,(k,l)} for every region r
+ * of every element of the patch (eq. (3.6)). The constraint data rdata
+ * (device, n_c^2 x (m+1)^2 x J, as pe_cem_spaces' spsi) hold, for region
+ * slot l of element k on its local node (row-major), the region's integral
+ * of the Q1 function of that node: h^2/4 for every region cell the node is
+ * a corner of; slots at or beyond counts[k] are not read. counts: host
+ * array of n_c^2 entries, 1 <= counts[k] <= J <= 8. V_H1 = the fracture
+ * functions (d1 = sum_k (counts[k] - 1), element-major), V_H2 = the matrix
+ * functions (d2 = n_c^2, element-major); each scaled to unit L2 norm. The
+ * medium, grids, outputs, workspace, limits and errors are those of
+ * pe_cem_spaces (the constraint limit counts regions); no fracture function
+ * at all is PE_ERR_ARG. The paper's own V_H2 (with the mean function psi_bar
+ * of eq. (3.7) and the s-orthogonalised fracture functions) is not built here.
+ */
+pe_status pe_nlmc_spaces(int n, int n_c, int layers, int J, const int* counts, const double* kappa,
+                         const double* rdata, int R, const double* loads, double* M11, double* M12, double* M22,
+                         double* A11, double* A12, double* A22, double* G, double* Psi, void* hip_stream);
+
+/*
  * Batches of different problems (different d1, d2, N, sources and sample
  * counts; same precision and step ratio P), solved together: every
  * product of a fine step runs as one grouped MFMA launch over all problems'

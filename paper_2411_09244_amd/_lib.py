@@ -27,7 +27,7 @@ PE_NORM_M_REL = 1
 
 # every entry point declared in include/pe.h
 EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate",
-           "pe_coarse_propagate", "pe_mass_norms", "pe_adjoint", "pe_tracking", "pe_fine_wr", "pe_set_fine_solver", "pe_set_history", "pe_probe_peaks", "pe_cem_spaces", "pe_local_spectral", "pe_batch_create", "pe_batch_solve",
+           "pe_coarse_propagate", "pe_mass_norms", "pe_adjoint", "pe_tracking", "pe_fine_wr", "pe_set_fine_solver", "pe_set_history", "pe_probe_peaks", "pe_cem_spaces", "pe_nlmc_spaces", "pe_local_spectral", "pe_batch_create", "pe_batch_solve",
            "pe_batch_destroy", "pe_batch_profile", "pe_batch_profile_read", "pe_profile", "pe_profile_read",
            "pe_autotune", "pe_last_tiles", "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
@@ -70,6 +70,7 @@ def load():
     lib.pe_probe_peaks.argtypes = [vp, vp]
     lib.pe_local_spectral.argtypes = [ci, ci, ci, vp, vp, vp, vp, vp]
     lib.pe_cem_spaces.argtypes = [ci, ci, ci, ci, ci, vp, vp, ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pe_nlmc_spaces.argtypes = [ci, ci, ci, ci, vp, vp, vp, ci, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pe_batch_create.argtypes = [ctypes.POINTER(vp), ci, vp, vp]
     lib.pe_batch_solve.argtypes = [vp, vp, cd, ci, ci, vp, vp]
     lib.pe_batch_destroy.argtypes = [vp]

@@ -348,6 +348,43 @@ def cem_spaces(kappa, spsi, n_c, layers, J1, loads=None, want_basis=False, devic
     return out
 
 
+def nlmc_spaces(kappa, counts, rdata, n_c, layers, loads=None, want_basis=False, device="cuda"):
+    """NLMC spaces split by continuum and their Galerkin blocks on the GPU
+    (pe_nlmc_spaces). kappa: (n, n) cell values; counts: regions per coarse
+    element (matrix region + fracture pieces); rdata: (n_c^2, (m+1)^2, J)
+    region integrals of the local Q1 functions; loads: (R, (n-1)^2) or None.
+    Returns a dict of device tensors M11, M12, M22, A11, A12, A22 (V_H1 = the
+    fracture functions, V_H2 = the matrix functions), G (if loads) and Psi
+    (if want_basis)."""
+    lib = L.load()
+    dev = torch.device(device)
+    kappa = _dev(np.ascontiguousarray(kappa, dtype=np.float64), dev)
+    rdata = _dev(np.ascontiguousarray(rdata, dtype=np.float64), dev)
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    n = kappa.shape[0]
+    n_el, _, J = rdata.shape
+    d1, d2 = int(counts.sum()) - n_el, n_el
+    D = d1 + d2
+    z = lambda r, c: torch.zeros((r, c), dtype=torch.float64, device=dev)
+    out = {"M11": z(d1, d1), "M12": z(d1, d2), "M22": z(d2, d2), "A11": z(d1, d1), "A12": z(d1, d2),
+           "A22": z(d2, d2)}
+    R = 0
+    ld = None
+    if loads is not None:
+        ld = _dev(np.ascontiguousarray(np.atleast_2d(loads), dtype=np.float64), dev)
+        R = ld.shape[0]
+        out["G"] = z(D, R)
+    if want_basis:
+        out["Psi"] = z(D, (n - 1) ** 2)
+    p = lambda k: _ptr(out[k]) if k in out else None
+    with torch.cuda.device(dev):
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        L.check(lib.pe_nlmc_spaces(n, n_c, layers, J, counts.ctypes.data_as(ctypes.c_void_p), _ptr(kappa),
+                                   _ptr(rdata), R, _ptr(ld) if ld is not None else None, p("M11"), p("M12"),
+                                   p("M22"), p("A11"), p("A12"), p("A22"), p("G"), p("Psi"), st))
+    return out
+
+
 def problem_from(prob, precision="fp64", device="cuda"):
     """Problem + source from a workload dict (blocks, G, H, time_mode)."""
     blocks = {k: prob[k] for k in ("M11", "M12", "M22", "A11", "A12", "A22")}

@@ -49,7 +49,11 @@ constexpr int CEM_NAUX = 128;  // largest number of constraints per patch
 constexpr int CEM_LDS_S = CEM_NAUX * CEM_NAUX;  // doubles of the step-4 LDS area
 
 struct CemGeom {
-    int n, n_c, m, layers, J;
+    int n, n_c, m, layers, J;  // J: constraint slots per element in the constraint data
+    // per-element function counts (nullable: J for every element) and the
+    // first function of every element in the element-major order (n_c^2 + 1)
+    const int* cnt = nullptr;
+    const int* foff = nullptr;
     long lb_stride;  // doubles of band storage per patch
     long y_stride;   // doubles of Y per patch (rows x CEM_NAUX)
     long ldp;        // row length of Psi^T (fine interior nodes, padded)
@@ -61,9 +65,12 @@ struct Patch {
     int gx0, gy0;            // global node of patch node 0
     int nx, ny, nf;          // interior nodes per row, rows, total
     int bw, wn;              // half-bandwidth nx + 1, window bw + 1
-    int naux;                // constraints nex * ney * J
+    int naux;                // constraints: sum of the patch elements' counts
     int ai;                  // position of the patch's own element
+    int aoff, jown;          // its first constraint and its count
 };
+
+__device__ inline int elem_count(const CemGeom& g, int k) { return g.cnt ? g.cnt[k] : g.J; }
 
 __device__ inline Patch patch_of(const CemGeom& g, int i) {
     Patch p;
@@ -81,9 +88,27 @@ __device__ inline Patch patch_of(const CemGeom& g, int i) {
     p.nf = p.nx * p.ny;
     p.bw = p.nx + 1;
     p.wn = p.bw + 1;
-    p.naux = p.nex * p.ney * g.J;
     p.ai = (ey - ey0) * p.nex + (ex - ex0);
+    p.naux = 0;
+    p.aoff = 0;
+    for (int a = 0; a < p.nex * p.ney; ++a) {
+        if (a == p.ai) p.aoff = p.naux;
+        p.naux += elem_count(g, (ey0 + a / p.nex) * g.n_c + ex0 + a % p.nex);
+    }
+    p.jown = elem_count(g, i);
     return p;
+}
+
+// constraint q of a patch -> (patch element a, slot l)
+__device__ inline void constraint_slot(const CemGeom& g, const Patch& p, int q, int* a, int* l) {
+    int rem = q, k = 0;
+    for (; k < p.nex * p.ney - 1; ++k) {
+        const int c = elem_count(g, (p.ey0 + k / p.nex) * g.n_c + p.ex0 + k % p.nex);
+        if (rem < c) break;
+        rem -= c;
+    }
+    *a = k;
+    *l = rem;
 }
 
 // Q1 stiffness between interior fine nodes (gy, gx) and (hy, hx): the
@@ -113,11 +138,11 @@ __device__ inline double patch_stiff(const double* __restrict__ kappa, const Cem
     return q1_stiff(kappa, g.n, p.gy0 + ry, p.gx0 + rx, p.gy0 + cy, p.gx0 + cx);
 }
 
-// constraint q = (patch element a, eigen-index l) at patch node r:
-// (S_k psi_l^(k)) at the node if it belongs to element k, else 0
-__device__ inline double constraint(const double* __restrict__ spsi, const CemGeom& g, const Patch& p, int q,
-                                    int r) {
-    const int a = q / g.J, l = q - a * g.J;
+// constraint (patch element a, slot l) at patch node r: the constraint
+// data of element k (S_k psi_l^(k) for CEM, the region integrals for NLMC)
+// at the node if it belongs to element k, else 0
+__device__ inline double constraint(const double* __restrict__ spsi, const CemGeom& g, const Patch& p, int a,
+                                    int l, int r) {
     const int ky = p.ey0 + a / p.nex, kx = p.ex0 + a % p.nex;
     const int ry = r / p.nx, rx = r - ry * p.nx;
     const int ly = p.gy0 + ry - ky * g.m, lx = p.gx0 + rx - kx * g.m;
@@ -187,16 +212,18 @@ __global__ __launch_bounds__(CEM_NAUX) void k_cem_forward(const CemGeom g, const
     const double* L = Lb + (long)i * g.lb_stride;
     double* Y = Yg + (long)i * g.y_stride;
     const bool act = q < p.naux;
+    int qa = 0, ql = 0;
+    if (act) constraint_slot(g, p, q, &qa, &ql);
     // row 0 operands
     if (q < wn) lrow[0][q] = q == 0 ? L[0] : 0.0;
-    double c = act ? constraint(spsi, g, p, q, 0) : 0.0;
+    double c = act ? constraint(spsi, g, p, qa, ql, 0) : 0.0;
     __syncthreads();
     for (int r = 0; r < nf; ++r) {
         const int cur = r & 1;
         // next row's operands, loaded before this row's arithmetic
         const int rn = r + 1;
         const double ln = (q < wn && rn < nf && q <= rn) ? L[(long)rn * wn + q] : 0.0;
-        const double cn = (act && rn < nf) ? constraint(spsi, g, p, q, rn) : 0.0;
+        const double cn = (act && rn < nf) ? constraint(spsi, g, p, qa, ql, rn) : 0.0;
         if (act) {
             double s = c;
             const int dmax = min(p.bw, r);
@@ -264,7 +291,8 @@ __global__ __launch_bounds__(256) void k_cem_finish(const CemGeom g, const doubl
     __shared__ int bad;
     const int i = blockIdx.x, tid = threadIdx.x;
     const Patch p = patch_of(g, i);
-    const int na = p.naux, J = g.J, nf = p.nf, wn = p.wn;
+    const int na = p.naux, J = p.jown, nf = p.nf, wn = p.wn;
+    const long row0 = g.foff ? (long)g.foff[i] : (long)i * g.J;  // the element's first row of Psi^T
     const double* Sgl = Sg + (long)i * CEM_NAUX * CEM_NAUX;
     for (int idx = tid; idx < na * na; idx += 256) sh[idx] = Sgl[(long)(idx / na) * CEM_NAUX + idx % na];
     if (tid == 0) bad = 0;
@@ -293,9 +321,9 @@ __global__ __launch_bounds__(256) void k_cem_finish(const CemGeom g, const doubl
         if (tid == 0) info[i] = -bad;
         return;  // uniform
     }
-    // z = S^-1 e_(ai*J + l): forward and backward substitution, thread l
+    // z = S^-1 e_(aoff + l): forward and backward substitution, thread l
     if (tid < J) {
-        const int l = tid, e = p.ai * J + l;
+        const int l = tid, e = p.aoff + l;
         for (int r = 0; r < na; ++r) {
             double v = r == e ? 1.0 : 0.0;
             for (int c = 0; c < r; ++c) v -= sh[r * na + c] * z[c][l];
@@ -355,7 +383,7 @@ __global__ __launch_bounds__(256) void k_cem_finish(const CemGeom g, const doubl
             phw[r % wn][lane] = ph;
             const int ry = r / p.nx, rx = r - ry * p.nx;
             const long dof = (long)(p.gy0 + ry - 1) * n1 + (p.gx0 + rx - 1);
-            PsiT[(long)(i * J + lane) * g.ldp + dof] = ph;
+            PsiT[(row0 + lane) * g.ldp + dof] = ph;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -410,8 +438,9 @@ __global__ void k_cem_pad(const double* __restrict__ src, long nd, long ldp, lon
 }
 
 // space index -> full index (element-major, J per element) of the V_H1 /
-// V_H2 split
-__device__ inline int cem_full(int s, int d1, int J, int J1) {
+// V_H2 split; fmap (nullable) gives it as a table
+__device__ inline int cem_full(int s, int d1, int J, int J1, const int* __restrict__ fmap) {
+    if (fmap) return fmap[s];
     if (s < d1) return (s / J1) * J + s % J1;
     const int J2 = J - J1, t = s - d1;
     return (t / J2) * J + J1 + t % J2;
@@ -419,14 +448,14 @@ __device__ inline int cem_full(int s, int d1, int J, int J1) {
 
 // blocks of eq. (3.8) from the Gram matrices of the unnormalised functions
 __global__ void k_cem_blocks(const double* __restrict__ Gm, const double* __restrict__ Gk, int Dall, int d1,
-                             int d2, int J, int J1, double* __restrict__ M11, double* __restrict__ M12,
+                             int d2, int J, int J1, const int* __restrict__ fmap, double* __restrict__ M11, double* __restrict__ M12,
                              double* __restrict__ M22, double* __restrict__ A11, double* __restrict__ A12,
                              double* __restrict__ A22) {
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
     const int D = d1 + d2;
     if (t >= (long)D * D) return;
     const int a = (int)(t / D), b = (int)(t % D);
-    const int fa = cem_full(a, d1, J, J1), fb = cem_full(b, d1, J, J1);
+    const int fa = cem_full(a, d1, J, J1, fmap), fb = cem_full(b, d1, J, J1, fmap);
     const double s = 1.0 / (sqrt(Gm[(long)fa * Dall + fa]) * sqrt(Gm[(long)fb * Dall + fb]));
     const double mab = Gm[(long)fa * Dall + fb] * s, mba = Gm[(long)fb * Dall + fa] * s;
     const double kab = Gk[(long)fa * Dall + fb] * s, kba = Gk[(long)fb * Dall + fa] * s;
@@ -444,21 +473,22 @@ __global__ void k_cem_blocks(const double* __restrict__ Gm, const double* __rest
 
 // source factors G (D x R) and, optionally, the normalised basis (D x n_dof)
 __global__ void k_cem_sources(const double* __restrict__ Gm, const double* __restrict__ GL, int Dall, int d1, int D,
-                              int J, int J1, int R, double* __restrict__ G) {
+                              int J, int J1, const int* __restrict__ fmap, int R, double* __restrict__ G) {
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long)D * R) return;
     const int a = (int)(t / R), c = (int)(t % R);
-    const int fa = cem_full(a, d1, J, J1);
+    const int fa = cem_full(a, d1, J, J1, fmap);
     G[t] = GL[(long)fa * R + c] / sqrt(Gm[(long)fa * Dall + fa]);
 }
 
 __global__ void k_cem_basis_out(const double* __restrict__ Gm, const double* __restrict__ PsiT, int Dall, int d1,
-                                int D, int J, int J1, long nd, long ldp, double* __restrict__ out) {
+                                int D, int J, int J1, const int* __restrict__ fmap, long nd, long ldp,
+                                double* __restrict__ out) {
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long)D * nd) return;
     const int a = (int)(t / nd);
     const long c = t % nd;
-    const int fa = cem_full(a, d1, J, J1);
+    const int fa = cem_full(a, d1, J, J1, fmap);
     out[t] = PsiT[(long)fa * ldp + c] / sqrt(Gm[(long)fa * Dall + fa]);
 }
 
@@ -798,30 +828,57 @@ __global__ __launch_bounds__(256) void k_spec_element(int n, int n_c, int J, con
 
 using namespace pe;
 
-extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, const double* kappa,
-                                   const double* spsi, int R, const double* loads, double* M11, double* M12,
-                                   double* M22, double* A11, double* A12, double* A22, double* G, double* Psi,
-                                   void* hip_stream) {
-    hipStream_t st = (hipStream_t)hip_stream;
-    if (n <= 0 || n_c <= 0 || n % n_c != 0 || layers < 0 || J <= 0 || J > 8 || J1 <= 0 || J1 > J || !kappa ||
-        !spsi || R < 0 || (R > 0 && (!loads || !G)) || !M11 || !M22 || !A11 || !A22 ||
-        (J1 < J && (!M12 || !A12)))
-        return set_error(PE_ERR_ARG, "pe_cem_spaces: bad arguments");
+namespace pe {
+namespace {
+
+// The set-up pipeline for constraint data with J slots per element: every
+// element has J functions (cnt_h null; the J1 lowest span V_H1), or cnt_h[k]
+// functions (host counts) placed in the blocks by fmap_h (host, D entries:
+// space index -> element-major function index; the first d1 span V_H1).
+pe_status spaces_impl(const char* who, int n, int n_c, int layers, int J, int J1, const double* kappa,
+                      const double* spsi, const int* cnt_h, const int* fmap_h, int d1, int d2, int R,
+                      const double* loads, double* M11, double* M12, double* M22, double* A11, double* A12,
+                      double* A22, double* G, double* Psi, hipStream_t st) {
+    const std::string tag = std::string(who) + ": ";
     const int m = n / n_c;
-    if (m < 2) return set_error(PE_ERR_ARG, "pe_cem_spaces: a coarse element needs at least 2 fine cells per side");
+    if (m < 2) return set_error(PE_ERR_ARG, tag + "a coarse element needs at least 2 fine cells per side");
     const int span = std::min(2 * layers + 1, n_c);  // coarse elements per patch side, at most
     const int nx_max = span * m - 1, nf_max = nx_max * nx_max;
     if (nx_max + 2 > CEM_WN)
-        return set_error(PE_ERR_ARG, "pe_cem_spaces: patch rows of " + std::to_string(nx_max) +
+        return set_error(PE_ERR_ARG, tag + "patch rows of " + std::to_string(nx_max) +
                                          " nodes exceed the band window (at most " + std::to_string(CEM_WN - 2) +
                                          ")");
-    if (span * span * J > CEM_NAUX)
-        return set_error(PE_ERR_ARG, "pe_cem_spaces: more than " + std::to_string(CEM_NAUX) +
-                                         " constraints per patch");
-    if ((long)nf_max * J > CEM_LDS_S)
-        return set_error(PE_ERR_ARG, "pe_cem_spaces: patch too large for the final sweep");
-    const int n_elem = n_c * n_c, Dall = n_elem * J;
-    const int d1 = n_elem * J1, d2 = n_elem * (J - J1), D = d1 + d2;
+    const int n_elem = n_c * n_c;
+    // constraints per patch (at most CEM_NAUX) and functions per element
+    int naux_max = span * span * J, own_max = J, Dall = n_elem * J;
+    std::vector<int> foff_h;
+    if (cnt_h) {
+        foff_h.assign(n_elem + 1, 0);
+        own_max = 0;
+        for (int k = 0; k < n_elem; ++k) {
+            if (cnt_h[k] < 1 || cnt_h[k] > J)
+                return set_error(PE_ERR_ARG, tag + "element " + std::to_string(k) + " has " +
+                                                 std::to_string(cnt_h[k]) + " functions (1.." + std::to_string(J) +
+                                                 ")");
+            foff_h[k + 1] = foff_h[k] + cnt_h[k];
+            own_max = std::max(own_max, cnt_h[k]);
+        }
+        Dall = foff_h[n_elem];
+        naux_max = 0;
+        for (int i = 0; i < n_elem; ++i) {
+            const int ey = i / n_c, ex = i % n_c;
+            int tot = 0;
+            for (int ky = std::max(ey - layers, 0); ky <= std::min(ey + layers, n_c - 1); ++ky)
+                for (int kx = std::max(ex - layers, 0); kx <= std::min(ex + layers, n_c - 1); ++kx)
+                    tot += cnt_h[ky * n_c + kx];
+            naux_max = std::max(naux_max, tot);
+        }
+    }
+    if (naux_max > CEM_NAUX)
+        return set_error(PE_ERR_ARG, tag + "more than " + std::to_string(CEM_NAUX) + " constraints per patch");
+    if ((long)nf_max * own_max > CEM_LDS_S) return set_error(PE_ERR_ARG, tag + "patch too large for the final sweep");
+    const int D = d1 + d2;
+    if (D != Dall || d1 < 1) return set_error(PE_ERR_ARG, tag + "split sizes do not match the functions");
     const long nd = (long)(n - 1) * (n - 1);
     const long ldp = (nd + 7) / 8 * 8;
 
@@ -853,6 +910,19 @@ extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, co
     };
     double *Lb, *Yb, *Sb, *PsiT, *MX, *KX, *Gm, *Gk, *Ld = nullptr, *GL = nullptr;
     int* info;
+    int *cnt_d = nullptr, *foff_d = nullptr, *fmap_d = nullptr;
+    if (cnt_h) {
+        if (!alloc((void**)&cnt_d, sizeof(int) * n_elem) || !alloc((void**)&foff_d, sizeof(int) * (n_elem + 1)) ||
+            !alloc((void**)&fmap_d, sizeof(int) * D))
+            return done(set_error(PE_ERR_NOMEM, tag + "device memory"));
+        if (hipMemcpyAsync(cnt_d, cnt_h, sizeof(int) * n_elem, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(foff_d, foff_h.data(), sizeof(int) * (n_elem + 1), hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(fmap_d, fmap_h, sizeof(int) * D, hipMemcpyHostToDevice, st) != hipSuccess)
+            return done(set_error(PE_ERR_HIP, tag + "table upload"));
+        g.cnt = cnt_d;
+        g.foff = foff_d;
+    }
     if (!alloc((void**)&Lb, sizeof(double) * g.lb_stride * n_elem) ||
         !alloc((void**)&Yb, sizeof(double) * g.y_stride * n_elem) ||
         !alloc((void**)&Sb, sizeof(double) * CEM_NAUX * CEM_NAUX * n_elem) ||
@@ -860,10 +930,10 @@ extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, co
         !alloc((void**)&KX, sizeof(double) * ldp * Dall) || !alloc((void**)&Gm, sizeof(double) * Dall * Dall) ||
         !alloc((void**)&Gk, sizeof(double) * Dall * Dall) || !alloc((void**)&info, sizeof(int) * n_elem) ||
         (R > 0 && (!alloc((void**)&Ld, sizeof(double) * ldp * R) || !alloc((void**)&GL, sizeof(double) * Dall * R))))
-        return done(set_error(PE_ERR_NOMEM, "pe_cem_spaces: device memory"));
+        return done(set_error(PE_ERR_NOMEM, tag + "device memory"));
     auto hip_ok = [&](hipError_t e, const char* what) -> pe_status {
         if (e == hipSuccess) return PE_OK;
-        return set_error(PE_ERR_HIP, std::string("pe_cem_spaces: ") + what + ": " + hipGetErrorString(e));
+        return set_error(PE_ERR_HIP, tag + what + ": " + hipGetErrorString(e));
     };
     pe_status s;
     if ((s = hip_ok(hipMemsetAsync(PsiT, 0, sizeof(double) * ldp * Dall, st), "clear")) != PE_OK) return done(s);
@@ -881,7 +951,7 @@ extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, co
     if ((s = hip_ok(hipStreamSynchronize(st), "patch factorisations")) != PE_OK) return done(s);
     for (int i = 0; i < n_elem; ++i)
         if (hinfo[i] != 0)
-            return done(set_error(PE_ERR_NOT_SPD, "pe_cem_spaces: patch " + std::to_string(i) +
+            return done(set_error(PE_ERR_NOT_SPD, tag + "patch " + std::to_string(i) +
                                                       " stiffness not positive definite at row " +
                                                       std::to_string(hinfo[i])));
     hipLaunchKernelGGL(k_cem_finish, dim3(n_elem), dim3(256), 0, st, g, Lb, Yb, Sb, PsiT, info);
@@ -892,7 +962,7 @@ extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, co
     if ((s = hip_ok(hipStreamSynchronize(st), "basis functions")) != PE_OK) return done(s);
     for (int i = 0; i < n_elem; ++i)
         if (hinfo[i] != 0)
-            return done(set_error(PE_ERR_NOT_SPD, "pe_cem_spaces: constraint Gram matrix of patch " +
+            return done(set_error(PE_ERR_NOT_SPD, tag + "constraint Gram matrix of patch " +
                                                       std::to_string(i) + " not positive definite at row " +
                                                       std::to_string(-hinfo[i])));
     // projections
@@ -930,7 +1000,7 @@ extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, co
             ws.part_bytes = 0;
             if (hipMalloc(&ws.part, need) != hipSuccess) {
                 (void)hipGetLastError();
-                return set_error(PE_ERR_NOMEM, "pe_cem_spaces: product workspace");
+                return set_error(PE_ERR_NOMEM, tag + "product workspace");
             }
             ws.part_bytes = need;
         }
@@ -947,22 +1017,66 @@ extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, co
     {
         const long tot = (long)D * D;
         hipLaunchKernelGGL(k_cem_blocks, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Gm, Gk, Dall, d1,
-                           d2, J, J1, M11, M12, M22, A11, A12, A22);
+                           d2, J, J1, fmap_d, M11, M12, M22, A11, A12, A22);
     }
     if (R > 0) {
         const long tot = (long)D * R;
         hipLaunchKernelGGL(k_cem_sources, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Gm, GL, Dall, d1,
-                           D, J, J1, R, G);
+                           D, J, J1, fmap_d, R, G);
     }
     if (Psi) {
         const long tot = (long)D * nd;
         hipLaunchKernelGGL(k_cem_basis_out, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Gm, PsiT, Dall,
-                           d1, D, J, J1, nd, ldp, Psi);
+                           d1, D, J, J1, fmap_d, nd, ldp, Psi);
     }
     s = hip_ok(hipGetLastError(), "block kernels");
     pe_status r = done(s);
     if (ws.part) (void)hipFree(ws.part);
     return r;
+}
+
+}  // namespace
+}  // namespace pe
+
+extern "C" pe_status pe_cem_spaces(int n, int n_c, int layers, int J, int J1, const double* kappa,
+                                   const double* spsi, int R, const double* loads, double* M11, double* M12,
+                                   double* M22, double* A11, double* A12, double* A22, double* G, double* Psi,
+                                   void* hip_stream) {
+    if (n <= 0 || n_c <= 0 || n % n_c != 0 || layers < 0 || J <= 0 || J > 8 || J1 <= 0 || J1 > J || !kappa ||
+        !spsi || R < 0 || (R > 0 && (!loads || !G)) || !M11 || !M22 || !A11 || !A22 ||
+        (J1 < J && (!M12 || !A12)))
+        return set_error(PE_ERR_ARG, "pe_cem_spaces: bad arguments");
+    const int n_elem = n_c * n_c;
+    return spaces_impl("pe_cem_spaces", n, n_c, layers, J, J1, kappa, spsi, nullptr, nullptr, n_elem * J1,
+                       n_elem * (J - J1), R, loads, M11, M12, M22, A11, A12, A22, G, Psi, (hipStream_t)hip_stream);
+}
+
+extern "C" pe_status pe_nlmc_spaces(int n, int n_c, int layers, int J, const int* counts, const double* kappa,
+                                    const double* rdata, int R, const double* loads, double* M11, double* M12,
+                                    double* M22, double* A11, double* A12, double* A22, double* G, double* Psi,
+                                    void* hip_stream) {
+    if (n <= 0 || n_c <= 0 || n % n_c != 0 || layers < 0 || J <= 1 || J > 8 || !counts || !rdata || !kappa ||
+        R < 0 || (R > 0 && (!loads || !G)) || !M11 || !M12 || !M22 || !A11 || !A12 || !A22)
+        return set_error(PE_ERR_ARG, "pe_nlmc_spaces: bad arguments");
+    const int n_elem = n_c * n_c;
+    // V_H1: the fracture functions (slots 1.. of every element), V_H2: the
+    // matrix functions (slot 0), both element-major
+    std::vector<int> fmap;
+    int off = 0, d1 = 0;
+    std::vector<int> first(n_elem);
+    for (int k = 0; k < n_elem; ++k) {
+        if (counts[k] < 1 || counts[k] > J)
+            return set_error(PE_ERR_ARG, "pe_nlmc_spaces: element " + std::to_string(k) + " has " +
+                                             std::to_string(counts[k]) + " regions (1.." + std::to_string(J) + ")");
+        first[k] = off;
+        for (int l = 1; l < counts[k]; ++l) fmap.push_back(off + l);
+        d1 += counts[k] - 1;
+        off += counts[k];
+    }
+    if (d1 < 1) return set_error(PE_ERR_ARG, "pe_nlmc_spaces: no fracture function");
+    for (int k = 0; k < n_elem; ++k) fmap.push_back(first[k]);
+    return spaces_impl("pe_nlmc_spaces", n, n_c, layers, J, 0, kappa, rdata, counts, fmap.data(), d1, n_elem, R,
+                       loads, M11, M12, M22, A11, A12, A22, G, Psi, (hipStream_t)hip_stream);
 }
 
 extern "C" pe_status pe_local_spectral(int n, int n_c, int J, const double* kappa, double* lam, double* psi,

@@ -226,8 +226,13 @@ def _cache_dir():
     return d
 
 
+# version of the generators' arithmetic: part of every cache key, so cached
+# workloads from an earlier version are not reused
+GENERATOR_VERSION = 2
+
+
 def cfg_key(cfg):
-    return hashlib.sha256(json.dumps(cfg, sort_keys=True).encode()).hexdigest()[:16]
+    return hashlib.sha256(json.dumps({"cfg": cfg, "v": GENERATOR_VERSION}, sort_keys=True).encode()).hexdigest()[:16]
 
 
 # fields that fix the medium and the multiscale spaces (workloads that differ
@@ -296,30 +301,3 @@ def build_problem(name_or_cfg, use_cache=True, keep_spaces=False, verbose=False)
         np.savez(path, meta=json.dumps(meta), **{k: prob[k] for k in
                  ("M11", "M12", "M22", "A11", "A12", "A22", "G", "H", "x0")})
     return prob
-
-
-def c2_workload(n_solves=256, n_pool=8, seed=2):
-    """Stand-in for the ragged batched configuration: `n_solves` independent
-    solves over `n_pool` generated media/space pairs. Pool entry i has
-    n_c at the (i + 1/2)/n_pool quantile of U{8..32}, n = 10 n_c,
-    kappa = 1 with floor(n_c/4) horizontal and floor(n_c/4) vertical
-    channels of contrast 10^U(4,6), and its own 8 Fourier modes. Solve b
-    takes a pool entry uniformly, N_b ~ U{16..128} intervals of P = 32 fine
-    steps, amplitudes N(0,1) constant in time, u0 = 0; the step is the pool
-    entry's (half the stable coarse step: independent of N_b).
-    Returns (pool problems, list of per-solve dicts: pool, N, H (1, 8, N))."""
-    rng = np.random.default_rng(seed)
-    pool = []
-    for i in range(n_pool):
-        n_c = int(round(8 + 24 * (i + 0.5) / n_pool))
-        cfg = dict(n=10 * n_c, n_c=n_c, layers=2, J1=2, J2=3, medium="channels", n_h=n_c // 4,
-                   n_v=n_c // 4, contrast=float(10 ** rng.uniform(4, 6)), seed=1000 + i,
-                   source="fourier8_const", u0="zero", N=16, P=32, T=None, B=1, src_seed=2000 + i)
-        pool.append(build_problem(cfg))
-    solves = []
-    for b in range(n_solves):
-        i = int(rng.integers(n_pool))
-        N = int(rng.integers(16, 129))
-        a = rng.standard_normal((1, 8, 1))
-        solves.append(dict(pool=i, N=N, H=np.repeat(a, N, axis=2)))
-    return pool, solves

@@ -29,6 +29,8 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+REFINE_STEPS = 5  # iterative refinement of every patch's saddle-point solve
+
 
 def fracture_regions(cg, threshold):
     """Per coarse element: (matrix cells, [cells of each fracture]) as
@@ -111,12 +113,19 @@ def nlmc_basis(cg, regions, layers, return_checks=False):
                 vals.append(v)
                 r += 1
         C = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(r, nf))
-        lu = spla.splu(sp.bmat([[Ap, C.T], [C, None]], format="csc"), permc_spec="MMD_AT_PLUS_A",
-                       diag_pivot_thresh=0.01, options=dict(SymmetricMode=True))
+        K = sp.bmat([[Ap, C.T], [C, None]], format="csc")
+        lu = spla.splu(K, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.01, options=dict(SymmetricMode=True))
         nb = 1 + len(regions[i][1])
         rhs = np.zeros((nf + r, nb))
         rhs[nf + own + np.arange(nb), np.arange(nb)] = 1.0
-        psi = lu.solve(rhs)[:nf]
+        # the fracture rows of the stiffness carry the contrast, and the LU
+        # with threshold pivoting leaves the constraints of eq. (3.6) violated
+        # by up to ~1e-5 at contrast 1e6: iterative refinement with the same
+        # factors brings them to rounding level
+        x = lu.solve(rhs)
+        for _ in range(REFINE_STEPS):
+            x += lu.solve(rhs - K @ x)
+        psi = x[:nf]
         out.append((free_ids.copy(), psi))
         if return_checks:
             E = np.zeros((r, nb))
@@ -124,6 +133,31 @@ def nlmc_basis(cg, regions, layers, return_checks=False):
             checks.append(np.abs(C @ psi - E).max())
         lookup[free_ids] = -1
     return (out, checks) if return_checks else out
+
+
+def region_data(cg, regions, J=None):
+    """Constraint data of eq. (3.6) per coarse element for the GPU set-up
+    pipeline: counts[k] = 1 + number of fractures of element k, and
+    rdata (n_el x (m+1)^2 x J): slot l of element k (0: matrix region,
+    1..: fractures) on the element's local node (row-major) holds the region's
+    integral of that node's Q1 function, h^2/4 per region cell the node is a
+    corner of."""
+    fine = cg.fine
+    n, m, n_c = fine.n, cg.m, cg.n_c
+    counts = np.array([1 + len(fr) for _, fr in regions], dtype=np.int32)
+    J = int(counts.max()) if J is None else int(J)
+    ml = m + 1
+    rdata = np.zeros((cg.n_elem, ml * ml, J))
+    q = fine.h * fine.h / 4.0
+    for k, (mat, fr) in enumerate(regions):
+        ey, ex = divmod(k, n_c)
+        for l, cells in enumerate([mat] + list(fr)):
+            cy, cx = np.divmod(np.asarray(cells), n)
+            ly, lx = cy - ey * m, cx - ex * m
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    np.add.at(rdata[k, :, l], (ly + dy) * ml + (lx + dx), q)
+    return counts, rdata
 
 
 def nlmc_split(cg, psis, variant="paper"):

@@ -66,6 +66,7 @@ def test_batch_solve_spaces_match_cpu_generator(b):
 def batch64():
     pe = _pe()
     probs = [gpu_problem(solve_spec(b)) for b in range(64)]
+    print(f"batch of {len(probs)} solves built on the GPU", flush=True)
     out = {}
     for prec in ("fp64", "mixed", "mixed_refine"):
         prs = []
@@ -78,6 +79,7 @@ def batch64():
         Xs, its, st = bt.solve(x0s, tol=1e-7, norm="rel")
         assert st == 0
         out[prec] = ([X[0].cpu().numpy() for X in Xs], np.array([int(i[0]) for i in its]))
+        print(f"{prec}: batch solved, iterations mean {out[prec][1].mean():.2f}", flush=True)
         bt.close()
         for pr in prs:
             pr.close()
@@ -88,9 +90,11 @@ def batch64():
 
 def test_batch64_sample_against_oracle(batch64):
     probs, out = batch64
+    # a seeded sample the oracle finishes in seconds each (D <= 720, N <= 64)
     rng = np.random.default_rng(5)
-    sample = [int(b) for b in rng.permutation(len(probs)) if probs[b]["d1"] + probs[b]["d2"] <= 1280][:6]
-    assert len(sample) == 6
+    sample = [int(b) for b in rng.permutation(len(probs))
+              if probs[b]["d1"] + probs[b]["d2"] <= 720 and probs[b]["N"] <= 64][:4]
+    assert len(sample) == 4
     for b in sample:
         p = _host(probs[b])
         bl, src = S.Blocks.from_problem(p), S.Source.from_problem(p)

@@ -171,6 +171,24 @@ pe_status pe_fine_propagate(pe_problem p, int B, const double* Xin, double* Y);
 pe_status pe_coarse_propagate(pe_problem p, int B, const double* Xin, double* Y);
 
 /*
+ * pe_coarse_propagate_noalloc - pe_coarse_propagate for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same G with the same kernels and
+ * results, but its workspace (packed input, residual, increment, split-K
+ * planes) is a 64 MiB array in the library's device memory, one per GPU,
+ * held until the process ends. No hipMalloc, hipFree or allocating library
+ * routine is called.
+ *   Xin, Y      device, B x N x D (may not alias), as pe_coarse_propagate.
+ * Limit: 3 * B * N * D_pad * 8 bytes <= 64 MiB (D_pad = D rounded up to
+ * whole multiples of 8 per block), else PE_ERR_ARG naming the size.
+ * The handle's device must be current (PE_ERR_ARG otherwise); restarting
+ * history only (PE_ERR_STATE otherwise). Every call on a GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.
+ */
+pe_status pe_coarse_propagate_noalloc(pe_problem p, int B, const double* Xin, double* Y);
+
+/*
  * pe_mass_norms - |x|_M for `count` states (the norm of eq. (2.8)).
  *   X           device, count x D;  out  host, count doubles.
  */

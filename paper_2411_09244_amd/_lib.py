@@ -27,7 +27,7 @@ PE_NORM_M_REL = 1
 
 # every entry point declared in include/pe.h
 EXPORTS = ("pe_problem_create", "pe_source_set", "pe_solve", "pe_fine_propagate",
-           "pe_coarse_propagate", "pe_mass_norms", "pe_adjoint", "pe_tracking", "pe_fine_wr", "pe_set_fine_solver", "pe_set_history", "pe_probe_peaks", "pe_cem_spaces", "pe_nlmc_spaces", "pe_local_spectral", "pe_batch_create", "pe_batch_solve",
+           "pe_coarse_propagate", "pe_coarse_propagate_noalloc", "pe_mass_norms", "pe_adjoint", "pe_tracking", "pe_fine_wr", "pe_set_fine_solver", "pe_set_history", "pe_probe_peaks", "pe_cem_spaces", "pe_nlmc_spaces", "pe_local_spectral", "pe_batch_create", "pe_batch_solve",
            "pe_batch_destroy", "pe_batch_profile", "pe_batch_profile_read", "pe_profile", "pe_profile_read",
            "pe_autotune", "pe_last_tiles", "pe_problem_info", "pe_problem_destroy", "pe_last_error", "pe_version")
 
@@ -61,6 +61,7 @@ def load():
     lib.pe_solve.argtypes = [vp, ci, vp, cd, ci, ci, vp, vp, vp]
     lib.pe_fine_propagate.argtypes = [vp, ci, vp, vp]
     lib.pe_coarse_propagate.argtypes = [vp, ci, vp, vp]
+    lib.pe_coarse_propagate_noalloc.argtypes = [vp, ci, vp, vp]
     lib.pe_mass_norms.argtypes = [vp, ci, vp, vp]
     lib.pe_adjoint.argtypes = [vp, ci, vp, cd, vp, vp, cd, ci, vp, vp, vp, vp, vp]
     lib.pe_tracking.argtypes = [vp, ci, vp, vp, cd, vp]

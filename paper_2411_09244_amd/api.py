@@ -171,6 +171,13 @@ class Problem:
         L.check(self.lib.pe_coarse_propagate(self.handle, B, _ptr(Xin), _ptr(Y)))
         return Y
 
+    def coarse_noalloc(self, Xin, Y):
+        """G applied to Xin (B, N, D) into the caller's Y, with the library's
+        static workspace (pe_coarse_propagate_noalloc: no device allocation)."""
+        self._order()
+        L.check(self.lib.pe_coarse_propagate_noalloc(self.handle, int(Xin.shape[0]), _ptr(Xin), _ptr(Y)))
+        return Y
+
     def mass_norms(self, X):
         X = _dev(X, self.device).reshape(-1, self.D)
         out = np.zeros(X.shape[0])

@@ -27,6 +27,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <tuple>
@@ -112,6 +113,7 @@ struct pe_problem_s {
     hipStream_t st = nullptr;
     int own_stream = 0;  // st created by the handle (the caller passed NULL)
     int n_cu = 256;
+    int device = 0;  // the device current at creation (the handle's operators live there)
 
     // operators (padded, row-major)
     double* A64 = nullptr;   // Dp x Dp   full stiffness
@@ -2892,6 +2894,7 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
     }
     int dev = 0;
     (void)hipGetDevice(&dev);
+    p->device = dev;
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
         p->n_cu = ncu;
@@ -3230,6 +3233,93 @@ pe_status pe_coarse_propagate(pe_problem p, int B, const double* Xin, double* Y)
     g2.k1b = Dp;
     PE_TRY(gemm<double>(p, g2, store_epi(p->Ya, Dp, 1.0, p->Xa, Dp, 1.0)));
     PE_HIP(unpack_states(p->Ya, Y, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    PE_HIP(hipStreamSynchronize(p->st));
+    return PE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The coarse propagator without allocations (pe_coarse_propagate_noalloc):
+// its workspace - the packed input, the residual, the increment and the
+// split-K partial planes - lives in a static device array. Host code never
+// uses the array's name as a device address: the address is taken once per
+// device with hipGetSymbolAddress and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t PE_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[PE_SCRATCH_BYTES];
+
+namespace {
+constexpr int PE_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[PE_MAX_DEVICES] = {};
+
+// the scratch array's device address on the current device
+pe_status scratch_address(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= PE_MAX_DEVICES) return fail(PE_ERR_ARG, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(PE_ERR_HIP, std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                                        hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (unsigned char*)g_scratch_ptr[dev];
+    return PE_OK;
+}
+}  // namespace
+
+pe_status pe_coarse_propagate_noalloc(pe_problem p, int B, const double* Xin, double* Y) {
+    g_err.clear();
+    PE_TRY(check_handle(p));
+    if (B < 1 || !Xin || !Y) return fail(PE_ERR_ARG, "bad arguments");
+    if (p->src_set && p->src_kind != 0 && B != p->B_src) return fail(PE_ERR_ARG, "B differs from the source's B");
+    if (p->hist == PE_HIST_CARRY)
+        return fail(PE_ERR_STATE, "pe_coarse_propagate_noalloc needs the restarting history (pe_set_history 0)");
+    int dev = -1;
+    PE_HIP(hipGetDevice(&dev));
+    if (dev != p->device) return fail(PE_ERR_ARG, "the handle's device is not the current device");
+    const int Dp = p->Dp;
+    const long rows = (long)B * p->N;
+    const size_t plane = sizeof(double) * (size_t)rows * Dp;
+    const size_t fixed = 3 * ((plane + 255) / 256 * 256);
+    if (fixed > PE_SCRATCH_BYTES)
+        return fail(PE_ERR_ARG, "B*N*D too large for the 64 MiB scratch of pe_coarse_propagate_noalloc (needs " +
+                                    std::to_string(fixed) + " bytes)");
+    unsigned char* base = nullptr;
+    PE_TRY(scratch_address(dev, &base));
+    const size_t step = fixed / 3;
+    double* xa = (double*)base;
+    double* res = (double*)(base + step);
+    double* ya = (double*)(base + 2 * step);
+    GemmWork ws;
+    ws.part = base + fixed;
+    ws.part_bytes = PE_SCRATCH_BYTES - fixed;
+    // tile choice as pe_coarse_propagate's, split-K only while its planes fit
+    auto tiles = [&](const GemmShape& sh) {
+        TileCfg c = choose_tiles(sh, false, p->n_cu);
+        while (c.splitk > 1 && gemm_part_bytes(sh, c, sizeof(double)) > ws.part_bytes) c.splitk /= 2;
+        return c;
+    };
+    // G(x) = x + Z_dt (F(t_{n+1}) - A x): residual product, then the increment
+    PE_HIP(pack_states(Xin, xa, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
+    Epi e1;
+    e1.mode = EPI_RESID;
+    e1.R64 = res;
+    e1.ldr = Dp;
+    source_fields(p, e1);
+    e1.cols_per_b = p->N;
+    e1.p_step = p->P - 1;
+    const GemmShape g1 = shape((int)rows, Dp, xa, Dp, p->A64, Dp, 0, Dp);
+    PE_HIP(gemm_launch<double>(g1, e1, tiles(g1), ws, p->st));
+    GemmShape g2 = shape((int)rows, Dp, res, Dp, p->Zc64, Dp, 0, p->d1p);
+    g2.s_split = p->d1p;
+    g2.k0b = 0;
+    g2.k1b = Dp;
+    PE_HIP(gemm_launch<double>(g2, store_epi(ya, Dp, 1.0, xa, Dp, 1.0), tiles(g2), ws, p->st));
+    PE_HIP(unpack_states(ya, Y, rows, p->d1, p->d2, p->d1p, p->d2p, p->st));
     PE_HIP(hipStreamSynchronize(p->st));
     return PE_OK;
 }

@@ -1857,6 +1857,8 @@ struct pe_batch_s {
     std::vector<int> pact, fin_buf;
     std::vector<long> t_fine, t_nk, t_u;  // tiles per problem of the fine, jump and V_H1-row product families
     int *fi_d = nullptr, *ft_d = nullptr, *ki_d = nullptr, *kt_d = nullptr, *ui_d = nullptr, *ut_d = nullptr;
+    // XCD-aware work-group order of the grouped products (PE_BATCH_XCD=1)
+    int xcd = 0;
     int tables_all = 1;
     long act_hash = 0;
 };
@@ -1878,9 +1880,77 @@ pe_status upload(pe_batch bt, const std::vector<T>& v, T** out) {
     return PE_OK;
 }
 
-// work-group tables of a grouped product family (one product per problem)
+// XCD-aware order of a grouped launch's work-group table. The dispatcher
+// sends work-group w to XCD w % 8, and each XCD has its own L2: with this
+// order all tiles of one product run on one XCD (its state operand is read
+// into one L2, its row tiles of one operator tile share it), the products
+// are spread over the XCDs by weight (greedy, heaviest first), and the eight
+// lists are interleaved, the shorter ones padded with item -1 (work-groups
+// that return at once). weight(item) is the cost of one tile of the item.
+template <typename W>
+void xcd_order(std::vector<int>& wi, std::vector<int>& wt, W weight) {
+    constexpr int X = 8;
+    std::vector<std::pair<size_t, size_t>> runs;
+    for (size_t a = 0; a < wi.size();) {
+        size_t b = a;
+        while (b < wi.size() && wi[b] == wi[a]) ++b;
+        runs.push_back({a, b});
+        a = b;
+    }
+    std::vector<double> w(runs.size());
+    for (size_t r = 0; r < runs.size(); ++r) w[r] = weight(wi[runs[r].first]) * (double)(runs[r].second - runs[r].first);
+    std::vector<size_t> idx(runs.size());
+    for (size_t r = 0; r < idx.size(); ++r) idx[r] = r;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t p, size_t q) { return w[p] > w[q]; });
+    std::vector<std::vector<int>> bi(X), bt(X);
+    std::vector<double> load(X, 0.0);
+    for (size_t r : idx) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (size_t e = runs[r].first; e < runs[r].second; ++e) {
+            bi[x].push_back(wi[e]);
+            bt[x].push_back(wt[e]);
+        }
+        load[x] += w[r];
+    }
+    size_t L = 0;
+    for (int x = 0; x < X; ++x) L = std::max(L, bi[x].size());
+    std::vector<int> oi, ot;
+    oi.reserve(L * X);
+    ot.reserve(L * X);
+    for (size_t j = 0; j < L; ++j)
+        for (int x = 0; x < X; ++x) {
+            oi.push_back(j < bi[x].size() ? bi[x][j] : -1);
+            ot.push_back(j < bt[x].size() ? bt[x][j] : 0);
+        }
+    while (!oi.empty() && oi.back() < 0) {
+        oi.pop_back();
+        ot.pop_back();
+    }
+    wi.swap(oi);
+    wt.swap(ot);
+}
+
+// device copy of a table with room for any later (padded) version of it
+pe_status upload_cap(pe_batch bt, const std::vector<int>& v, size_t cap, int** out) {
+    *out = nullptr;
+    cap = std::max(cap, v.size());
+    if (cap == 0) return PE_OK;
+    void* d = nullptr;
+    if (hipMalloc(&d, sizeof(int) * cap) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PE_ERR_NOMEM, "device allocation for a batch plan failed");
+    }
+    bt->allocs.push_back(d);
+    if (!v.empty()) PE_HIP(hipMemcpy(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
+    *out = (int*)d;
+    return PE_OK;
+}
+
+// work-group tables of a grouped product family (one product per item);
+// dp(item) weighs an item's tiles for the XCD-aware order
+template <typename DP>
 pe_status group_tables(pe_batch bt, const std::vector<GemmShape>& shapes, const int** wg_item, const int** wg_tile,
-                       int* n_wg) {
+                       int* n_wg, DP dp) {
     std::vector<int> wi, wt;
     for (size_t g = 0; g < shapes.size(); ++g) {
         const long tiles = (long)((shapes[g].Mr + bt->cfg.br - 1) / bt->cfg.br) *
@@ -1890,9 +1960,11 @@ pe_status group_tables(pe_batch bt, const std::vector<GemmShape>& shapes, const 
             wt.push_back((int)t);
         }
     }
+    const size_t cap = bt->xcd ? 8 * wi.size() + 8 : wi.size();
+    if (bt->xcd) xcd_order(wi, wt, dp);
     int *a = nullptr, *b = nullptr;
-    PE_TRY(upload(bt, wi, &a));
-    PE_TRY(upload(bt, wt, &b));
+    PE_TRY(upload_cap(bt, wi, cap, &a));
+    PE_TRY(upload_cap(bt, wt, cap, &b));
     *wg_item = a;
     *wg_tile = b;
     *n_wg = (int)wi.size();
@@ -2043,9 +2115,10 @@ pe_status batch_plan(pe_batch bt) {
     }
     const int *fi, *ft, *ri, *rt, *ki, *kt;
     int fn, rn, kn;
-    PE_TRY(group_tables(bt, fine_sh, &fi, &ft, &fn));
-    PE_TRY(group_tables(bt, nrel_sh, &ri, &rt, &rn));
-    PE_TRY(group_tables(bt, nk_sh, &ki, &kt, &kn));
+    auto dp_of = [&](int g) { return (double)bt->pr[g]->Dp; };
+    PE_TRY(group_tables(bt, fine_sh, &fi, &ft, &fn, dp_of));
+    PE_TRY(group_tables(bt, nrel_sh, &ri, &rt, &rn, dp_of));
+    PE_TRY(group_tables(bt, nk_sh, &ki, &kt, &kn, dp_of));
     if (mixed) {
         PE_TRY(group_plan(bt, a1, e_a1, sizeof(double), fi, ft, fn, &bt->anc1));
         PE_TRY(group_plan(bt, fsh, e_fin[0], sizeof(double), fi, ft, fn, &bt->fin[0]));
@@ -2066,7 +2139,7 @@ pe_status batch_plan(pe_batch bt) {
     if (bt->refine) {
         const int *ui, *ut;
         int un;
-        PE_TRY(group_tables(bt, a3, &ui, &ut, &un));
+        PE_TRY(group_tables(bt, a3, &ui, &ut, &un, dp_of));
         PE_TRY(group_plan(bt, a3, e_a3, sizeof(double), ui, ut, un, &bt->anc3));
         for (int w = 0; w < 2; ++w) {
             bt->rres[w].assign(bt->P, GroupPlan());
@@ -2141,7 +2214,8 @@ pe_status batch_plan(pe_batch bt) {
             }
             const int *wi, *wt;
             int wn;
-            PE_TRY(group_tables(bt, sh, &wi, &wt, &wn));
+            const std::vector<int>& ig = bt->scan_item_g[l];
+            PE_TRY(group_tables(bt, sh, &wi, &wt, &wn, [&](int i) { return (double)bt->pr[ig[i]]->Dp; }));
             PE_TRY(group_plan(bt, sh, ep, sizeof(float), wi, wt, wn, &bt->scanp[l]));
             bt->scan_wi_d[l] = (int*)wi;
             bt->scan_wt_d[l] = (int*)wt;
@@ -2274,6 +2348,12 @@ pe_status batch_tables(pe_batch bt) {
         if (!v.empty()) PE_HIP(hipMemcpy(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
         return PE_OK;
     };
+    if (bt->xcd) {
+        auto dp_of = [&](int g) { return (double)bt->pr[g]->Dp; };
+        xcd_order(fi, ft, dp_of);
+        xcd_order(ki, kt, dp_of);
+        if (bt->refine) xcd_order(ui, ut, dp_of);
+    }
     PE_TRY(put(bt->fi_d, fi));
     PE_TRY(put(bt->ft_d, ft));
     PE_TRY(put(bt->ki_d, ki));
@@ -2300,6 +2380,10 @@ pe_status batch_tables(pe_batch bt) {
                 si.push_back((int)i);
                 st.push_back((int)t);
             }
+        }
+        if (bt->xcd) {
+            const std::vector<int>& ig = bt->scan_item_g[l];
+            xcd_order(si, st, [&](int i) { return (double)bt->pr[ig[i]]->Dp; });
         }
         PE_TRY(put(bt->scan_wi_d[l], si));
         PE_TRY(put(bt->scan_wt_d[l], st));
@@ -3102,7 +3186,12 @@ pe_status pe_source_set(pe_problem p, int B, int R, const double* G, const doubl
         return PE_OK;
     }
     const int D = p->D, d1 = p->d1, d1p = p->d1p, Dp = p->Dp;
-    const bool dense = (time_mode == PE_T_INTERVAL && R > 16);
+    // per-interval amplitudes with more than a few terms: one dense table
+    // Z F per (sample, interval), so the fused step's epilogue reads one value
+    // per output instead of 2R (PE_DENSE_SOURCE_R overrides the term count)
+    int dense_r = 16;
+    if (const char* dr = getenv("PE_DENSE_SOURCE_R")) dense_r = std::max(0, atoi(dr));
+    const bool dense = (time_mode == PE_T_INTERVAL && R > dense_r);
     p->Rp = dense ? roundup(R, 2) : R;
     PE_TRY(dalloc_t(p, p->op_allocs, &p->Gs, (size_t)Dp * p->Rp));
     PE_HIP(hipMemsetAsync(p->Gs, 0, sizeof(double) * Dp * p->Rp, p->st));
@@ -3721,14 +3810,21 @@ pe_status pe_batch_create(pe_batch* out, int count, const pe_problem* problems, 
     for (pe_problem p : bt->pr) bt->N_max = std::max(bt->N_max, p->N);
     const char* gr = getenv("PE_GRAPHS");
     bt->gc.use_graphs = (gr && gr[0] == '0') ? 0 : 1;
+    const char* xo = getenv("PE_BATCH_XCD");
+    bt->xcd = (xo && xo[0] == '1') ? 1 : 0;
     bt->cfg.br = 64;
     bt->cfg.bs = 64;
     bt->cfg.splitk = 1;
-    bt->cfg.bk2 = prec == PE_MIXED ? 1 : 0;
+    // 64 x 64 tiles, K depth 32 (FP32) / 16 (FP64): the LDS stages of a
+    // work-group take 35 KiB (FP32), four work-groups per CU (measured on the
+    // ragged 256-solve batch: 3 % faster than K depth 64, which fits two)
+    bt->cfg.bk2 = 0;
     if (const char* t = getenv("PE_BATCH_TILE")) {
         int br = 0, bs = 0, bk2 = 0;
-        if (sscanf(t, "%d %d %d", &br, &bs, &bk2) == 3 && (br == 32 || br == 64) && bs == 64) {
+        if (sscanf(t, "%d %d %d", &br, &bs, &bk2) == 3 &&
+            ((br == 32 && bs == 64) || (br == 64 && (bs == 64 || bs == 128)))) {
             bt->cfg.br = br;
+            bt->cfg.bs = bs;
             bt->cfg.bk2 = bk2 ? 1 : 0;
         }
     }

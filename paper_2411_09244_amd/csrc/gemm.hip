@@ -698,7 +698,9 @@ template <typename T, int BR, int BS, int BK>
 __global__ __launch_bounds__(256) void gemm_grouped_kernel(const GemmItem* __restrict__ items,
                                                            const int* __restrict__ wg_item,
                                                            const int* __restrict__ wg_tile) {
-    const GemmItem& it = items[wg_item[blockIdx.x]];
+    const int item = wg_item[blockIdx.x];
+    if (item < 0) return;  // padding of an XCD-aware table
+    const GemmItem& it = items[item];
     gemm_tile<T, BR, BS, BK>(it.sh, it.epi, it.tiles_r, wg_tile[blockIdx.x], 0, 1, nullptr);
 }
 
@@ -989,6 +991,7 @@ hipError_t gemm_grouped_launch(const GemmItem* items, const int* wg_item, const 
     }
     PE_GCFG(64, 64)
     PE_GCFG(32, 64)
+    PE_GCFG(64, 128)
 #undef PE_GCFG
     return hipErrorInvalidValue;
 }

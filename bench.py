@@ -328,22 +328,25 @@ def batch_main(args, torch, pe):
                       "iterations_mean": round(float(head["iters"].mean()), 3),
                       "iterations_max": int(head["iters"].max()),
                       "gpu_setup_pipeline_s": round(t_build, 2), "handles_setup_s": round(head["setup"], 2)},
-           # the fused fine-step product of a ragged batch streams every
-           # solve's operator once per step at N/2 flop per byte (N = 16..128
-           # interval columns): at or below the FP32 ridge (157.3 / 8 = 19.7
-           # flop/B) once the operator is read, so HBM bounds it
+           # the fused fine-step product of a ragged batch: N_b / 2 flops per
+           # byte of each solve's FP32 operator (N_b = 16..128 interval
+           # columns), 33 flop/B averaged over a batch solve's launches, above
+           # the FP32 ridge (157.3 / 8 = 19.7 flop/B): matrix-core bound
            "roofline": dict(kernel="gemm_grouped_kernel<float,64,64,32> fused fine-step products of all solves",
-                            bound="hbm", achieved=round(bytes_res / avg / 1e9, 1), peak=PEAK_HBM_TBPS * 1e3,
-                            unit="GB/s", frac=round(bytes_res / avg / 1e12 / PEAK_HBM_TBPS, 5),
+                            bound="mfma", achieved=round(flops_res / avg / 1e12, 3), peak=PEAK_FP32_MFMA,
+                            unit="TFLOP/s", frac=round(flops_res / avg / 1e12 / PEAK_FP32_MFMA, 5),
                             traffic=MEASURED_TRAFFIC.get(("c2", n_solves)),
-                            avg_launch_us=round(avg * 1e6, 3), launches=n, bytes_per_launch=round(bytes_res),
-                            flops_per_launch=round(flops_res),
-                            mfma_achieved_tflops=round(flops_res / avg / 1e12, 3),
-                            mfma_frac=round(flops_res / avg / 1e12 / PEAK_FP32_MFMA, 5),
-                            work_note="algorithmic bytes and flops (2(d1^2 + 4 d1 d2 + 2 d2^2) per column) of the "
-                                      "solves each launch covered, averaged over the launches of one profiled "
-                                      "batch solve; traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE and "
-                                      "WRITE_SIZE, calibrated by a device copy of known size")}
+                            avg_launch_us=round(avg * 1e6, 3), launches=n, flops_per_launch=round(flops_res),
+                            bytes_per_launch=round(bytes_res),
+                            hbm_achieved_GBps=round(bytes_res / avg / 1e9, 1),
+                            hbm_frac=round(bytes_res / avg / 1e12 / PEAK_HBM_TBPS, 5),
+                            work_note="algorithmic flops (2(d1^2 + 4 d1 d2 + 2 d2^2) per interval column) and bytes "
+                                      "(FP32 operator blocks once, FP32 state read, FP64 state and anchor read, FP64 "
+                                      "and FP32 state written, refinement operands) of the solves each launch "
+                                      "covered, averaged over the launches of one profiled batch solve (launches "
+                                      "late in the solve cover only the solves still iterating); traffic: HBM bytes "
+                                      "per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, calibrated by a device "
+                                      "copy of known size")}
     ms_r, n_r = head["prof"]["refine"]
     out["roofline"]["refine_launches"] = n_r
     out["roofline"]["refine_ms_per_batch_solve"] = round(ms_r, 3)

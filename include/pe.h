@@ -97,7 +97,7 @@ enum {
  *               (relative tolerance 1e-12), else PE_ERR_ARG.
  *   dt_coarse   coarse step Delta t = T/N (> 0).
  *   dt_fine     fine step delta t; P = dt_coarse/dt_fine must be an integer
- *               within 1e-9 relative, else PE_ERR_ARG.
+ *               within 1e-12 relative, else PE_ERR_ARG.
  *   N           number of coarse intervals (>= 1).
  *   precision   PE_FP64, PE_MIXED or PE_MIXED_REFINE.
  *   hip_stream  hipStream_t for all work of this handle. NULL: the handle
@@ -515,7 +515,10 @@ pe_status pe_profile_read(pe_problem p, int kind, double* total_ms, long long* l
  * configurations measured on MI355X) are not re-tuned. PE_FORCE_WSK=
  * "bs,waves,splitk" at problem creation runs every product of at most 64
  * state columns on the wave-split-K kernel with that configuration (for
- * tests; operator tiles of 16 or 32 rows, 4 or 8 waves).
+ * tests; operator tiles of 16 or 32 rows, 4 or 8 waves). PE_FORCE_TILES=
+ * "br,bs,bk2,splitk" at problem creation runs every product of more than 4
+ * state columns with that tile configuration (for tests: tile shapes 32x64,
+ * 64x32, 64x64, 64x128, 128x64, 128x128, K depth flag 0/1, 1..64 splits).
  * Results are bitwise reproducible for fixed configurations.
  */
 pe_status pe_autotune(pe_problem p, int B);

@@ -144,12 +144,13 @@ struct pe_problem_s {
     double* scan64[2] = {nullptr, nullptr};
     float* scan32[2] = {nullptr, nullptr};
     std::vector<void*> scan_allocs;
-    // the coarse correction of a batch (PE_MIXED) as the same scan, for B
-    // samples: FP32 powers Phi_G^(2^l), l = 1..bscan_L-1 (l = 0 is PhiG32),
-    // formed by FP64 squaring, and two B x (Z + N) x Dp ping-pong buffers
-    // (FP64 sums, FP32 copies) whose first Z = 2^(bscan_L - 1) rows per
-    // sample stay zero
-    int bscan_L = -1, bscan_Z = 0, bscan_B = 0;
+    // the coarse sweeps of a batch (PE_MIXED) as the same scan, for B
+    // samples: the correction over N terms in bscan_L levels, the initial
+    // sweep over N + 1 terms in bscan_L0 levels; FP32 powers Phi_G^(2^l),
+    // l = 1..bscan_L0-1 (l = 0 is PhiG32), formed by FP64 squaring, and two
+    // B x (Z + N + 1) x Dp ping-pong buffers (FP64 sums, FP32 copies) whose
+    // first Z = 2^(bscan_L0 - 1) rows per sample stay zero
+    int bscan_L = -1, bscan_L0 = -1, bscan_Z = 0, bscan_B = 0;
     std::vector<float*> bpow32;
     double* bscan64[2] = {nullptr, nullptr};
     float* bscan32[2] = {nullptr, nullptr};
@@ -237,6 +238,8 @@ struct pe_problem_s {
     // PE_FORCE_WSK="bs,waves,splitk": every product whose state columns fit
     // one 64-row tile runs the wave-split-K kernel with this configuration
     pe::TileCfg force_wsk;
+    pe::TileCfg force_tiles;  // every product of more than 4 state columns, if force_tiles_on (PE_FORCE_TILES)
+    int force_tiles_on = 0;
 
     // captured HIP graphs of the sweeps, keyed by (kind, B, buffer parity)
     GraphCache gc;
@@ -618,6 +621,8 @@ pe_status gemm(pe_problem p, const GemmShape& sh, const Epi& epi, int force_spli
     TileCfg cfg = choose_tiles(sh, sizeof(T) == 4, p->n_cu);
     if (force_splitk > 0) {
         cfg.splitk = force_splitk;
+    } else if (p->force_tiles_on && sh.Mr > 4) {
+        cfg = p->force_tiles;
     } else if (p->force_wsk.wsk > 0 && sh.Mr > 4 && sh.Mr <= 64) {
         cfg = p->force_wsk;
     } else if (site != SITE_NONE && p->autotune && sh.Mr > 4) {
@@ -1379,17 +1384,18 @@ pe_status scan_prepare(pe_problem p) {
 // scan operators and buffers of a batch's coarse correction (B samples)
 pe_status batch_scan_prepare(pe_problem p, int B) {
     const int N = p->N, Dp = p->Dp;
-    int L = 0;
-    while ((1 << L) < N) ++L;
-    const int Z = L > 0 ? 1 << (L - 1) : 1;
-    if (p->bscan_L == L && p->bscan_B == B) return PE_OK;
+    int L = 0, L0 = 0;
+    while ((1 << L) < N) ++L;       // correction: N terms
+    while ((1 << L0) < N + 1) ++L0;  // initial sweep: N + 1 terms (L0 >= 1)
+    const int Z = 1 << (L0 - 1);
+    if (p->bscan_L == L && p->bscan_L0 == L0 && p->bscan_B == B) return PE_OK;
     PE_HIP(hipStreamSynchronize(p->st));
     free_list(p->bscan_allocs);
-    p->bscan_L = -1;
+    p->bscan_L = p->bscan_L0 = -1;
     std::vector<void*>& OL = p->bscan_allocs;
-    p->bpow32.assign(std::max(L, 1), nullptr);
+    p->bpow32.assign(L0, nullptr);
     p->bpow32[0] = p->PhiG32;
-    if (L > 1) {
+    if (L0 > 1) {
         TmpList tmpl(p->st);
         std::vector<void*>& tmp = tmpl.v;
         double *P, *PT, *Q, *QT;
@@ -1399,10 +1405,10 @@ pe_status batch_scan_prepare(pe_problem p, int B) {
         PE_TRY(dalloc_t(p, tmp, &QT, (size_t)Dp * Dp));
         PE_HIP(hipMemcpyAsync(P, p->PhiG64, sizeof(double) * Dp * Dp, hipMemcpyDeviceToDevice, p->st));
         PE_HIP(place(PT, Dp, 0, 0, p->PhiG64, Dp, Dp, Dp, 1.0, 1, p->st));
-        for (int l = 1; l < L; ++l) {
+        for (int l = 1; l < L0; ++l) {
             // P^2 as the NT product of P with P^T (and its transpose, for the next level)
             PE_TRY(gemm<double>(p, shape(Dp, Dp, P, Dp, PT, Dp, 0, Dp), store_epi(Q, Dp)));
-            if (l + 1 < L) PE_TRY(gemm<double>(p, shape(Dp, Dp, PT, Dp, P, Dp, 0, Dp), store_epi(QT, Dp)));
+            if (l + 1 < L0) PE_TRY(gemm<double>(p, shape(Dp, Dp, PT, Dp, P, Dp, 0, Dp), store_epi(QT, Dp)));
             PE_TRY(dalloc_t(p, OL, &p->bpow32[l], (size_t)Dp * Dp));
             PE_HIP(to_f32(Q, p->bpow32[l], (long)Dp * Dp, p->st));
             std::swap(P, Q);
@@ -1410,7 +1416,7 @@ pe_status batch_scan_prepare(pe_problem p, int B) {
         }
         PE_HIP(hipStreamSynchronize(p->st));
     }
-    const long rows = (long)B * (Z + N);
+    const long rows = (long)B * (Z + N + 1);
     for (int c = 0; c < 2; ++c) {
         PE_TRY(dalloc_t(p, OL, &p->bscan64[c], (size_t)rows * Dp));
         PE_TRY(dalloc_t(p, OL, &p->bscan32[c], (size_t)rows * Dp));
@@ -1418,6 +1424,7 @@ pe_status batch_scan_prepare(pe_problem p, int B) {
     }
     PE_HIP(hipStreamSynchronize(p->st));
     p->bscan_L = L;
+    p->bscan_L0 = L0;
     p->bscan_Z = Z;
     p->bscan_B = B;
     return PE_OK;
@@ -1453,7 +1460,7 @@ pe_status coarse_sweep_scan(pe_problem p, double* Xk, const double* Xprev, const
 pe_status coarse_sweep_initial_scan(pe_problem p, double* Xk) {
     const int N = p->N, Dp = p->Dp, L0 = p->scan_L0;
     const long zoff = (long)(1 << (L0 - 1)) * Dp;
-    PE_HIP(scan_init0(Xk, p->CS, p->scan64[0] + zoff, N, Dp, p->st));
+    PE_HIP(scan_init0(Xk, p->CS, p->scan64[0] + zoff, nullptr, N, Dp, p->st));
     for (int l = 0; l < L0; ++l) {
         const int c = l & 1;
         const long shift = zoff - (long)(1 << l) * Dp;
@@ -1842,6 +1849,8 @@ struct pe_batch_s {
     // more than 2^l intervals
     int scan = 0, scan_L = 0;
     std::vector<GroupPlan> scanp;                    // [level]
+    int iscan_L = 0;                                 // the initial sweep as a scan (all problems)
+    std::vector<GroupPlan> iscanp;                   // [level]
     std::vector<std::vector<int>> scan_item_g;       // [level][item] -> problem
     std::vector<std::vector<long>> scan_item_tiles;  // [level][item] -> tiles
     std::vector<int*> scan_wi_d, scan_wt_d;          // [level] work-group tables
@@ -1856,8 +1865,11 @@ struct pe_batch_s {
     // problems still iterating: finished ones leave the launch tables
     std::vector<int> pact, fin_buf;
     std::vector<long> t_fine, t_nk, t_u;  // tiles per problem of the fine, jump and V_H1-row product families
+    std::vector<int> tr_fine, tr_nk, tr_u;  // row tiles per problem of the same families
     int *fi_d = nullptr, *ft_d = nullptr, *ki_d = nullptr, *kt_d = nullptr, *ui_d = nullptr, *ut_d = nullptr;
-    // XCD-aware work-group order of the grouped products (PE_BATCH_XCD=1)
+    // XCD-aware work-group order of the grouped products (PE_BATCH_XCD=1:
+    // each product on one XCD; 2, the default: the row tiles of each
+    // operator column tile on one XCD; 0: plain order)
     int xcd = 0;
     int tables_all = 1;
     long act_hash = 0;
@@ -1930,6 +1942,116 @@ void xcd_order(std::vector<int>& wi, std::vector<int>& wt, W weight) {
     wt.swap(ot);
 }
 
+// Row-tile grouping of a grouped launch's work-group table: the row tiles
+// of one product that share an operator column tile (tiles ts * g ..
+// ts * g + g - 1, g = tiles_r(item)) are placed 8 entries apart, so the
+// dispatcher (work-group w to XCD w % 8) sends them to one XCD at about
+// the same time and that XCD's L2 serves the operator panel to all of
+// them. Runs of 8 groups of one size g fill 8 g consecutive entries (every
+// run starts at a multiple of 8); the last run of each size is padded with
+// item -1 (at most 7 g entries per size).
+template <typename TR>
+void rowtile_order(std::vector<int>& wi, std::vector<int>& wt, TR tiles_r) {
+    constexpr int X = 8;
+    std::map<int, std::vector<std::pair<int, int>>> pend;  // group size -> (item, first tile)
+    std::vector<int> oi, ot;
+    oi.reserve(wi.size() + 64);
+    ot.reserve(wi.size() + 64);
+    auto flush = [&](int g, std::vector<std::pair<int, int>>& v) {
+        for (int rr = 0; rr < g; ++rr)
+            for (int x = 0; x < X; ++x) {
+                const bool live = x < (int)v.size();
+                oi.push_back(live ? v[x].first : -1);
+                ot.push_back(live ? v[x].second + rr : 0);
+            }
+        v.clear();
+    };
+    for (size_t e = 0; e < wi.size(); ++e) {
+        const int g = std::max(1, tiles_r(wi[e]));
+        if (wt[e] % g) continue;  // not the first row tile of its group
+        std::vector<std::pair<int, int>>& v = pend[g];
+        v.push_back({wi[e], wt[e]});
+        if ((int)v.size() == X) flush(g, v);
+    }
+    for (auto& kv : pend)
+        if (!kv.second.empty()) flush(kv.first, kv.second);
+    while (!oi.empty() && oi.back() < 0) {
+        oi.pop_back();
+        ot.pop_back();
+    }
+    wi.swap(oi);
+    wt.swap(ot);
+}
+
+// Product-per-XCD order in lockstep: the products are sorted by tile cost
+// and tile count and taken in groups of 8 of about the same size; within a
+// group product x goes to XCD x, and the group's tile lists are
+// interleaved (entry 8 j + x is tile j of product x; a shorter list is
+// padded with item -1). Every tile of a product then runs on one XCD, so
+// its state operand is fetched into one L2 and shared by all of that
+// product's tiles there, while the eight XCDs work on tiles of equal cost
+// at every point of the launch (work-groups are handed to the XCDs in
+// turn, so a list of heavier tiles on one XCD would hold the others back).
+template <typename W>
+void lockstep_order(std::vector<int>& wi, std::vector<int>& wt, W weight) {
+    constexpr int X = 8;
+    struct Run {
+        size_t a, b;
+        double w;
+    };
+    std::vector<Run> runs;
+    for (size_t a = 0; a < wi.size();) {
+        size_t b = a;
+        while (b < wi.size() && wi[b] == wi[a]) ++b;
+        runs.push_back({a, b, weight(wi[a])});
+        a = b;
+    }
+    std::stable_sort(runs.begin(), runs.end(), [](const Run& p, const Run& q) {
+        return p.w != q.w ? p.w > q.w : (p.b - p.a) > (q.b - q.a);
+    });
+    std::vector<int> oi, ot;
+    oi.reserve(wi.size() + 64);
+    ot.reserve(wi.size() + 64);
+    for (size_t g0 = 0; g0 < runs.size(); g0 += X) {
+        const size_t g1 = std::min(runs.size(), g0 + X);
+        size_t L = 0;
+        for (size_t r = g0; r < g1; ++r) L = std::max(L, runs[r].b - runs[r].a);
+        for (size_t j = 0; j < L; ++j)
+            for (size_t x = 0; x < (size_t)X; ++x) {
+                const size_t r = g0 + x;
+                const bool live = r < g1 && j < runs[r].b - runs[r].a;
+                oi.push_back(live ? wi[runs[r].a + j] : -1);
+                ot.push_back(live ? wt[runs[r].a + j] : 0);
+            }
+    }
+    while (!oi.empty() && oi.back() < 0) {
+        oi.pop_back();
+        ot.pop_back();
+    }
+    wi.swap(oi);
+    wt.swap(ot);
+}
+
+// entries a table can need after rowtile_order: the plain count plus the
+// padding of one partial run per distinct group size
+size_t rowtile_cap(size_t n, const std::vector<int>& sizes) {
+    std::set<int> d(sizes.begin(), sizes.end());
+    size_t pad = 0;
+    for (int g : d) pad += 8 * (size_t)std::max(1, g);
+    return n + pad;
+}
+
+// work-group order of a grouped launch's table (PE_BATCH_XCD: 1 every tile
+// of a product on one XCD, balanced by weight; 2 the row tiles of an
+// operator column tile on one XCD; 3 every tile of a product on one XCD,
+// eight products of equal size in lockstep; 0 the plain order)
+template <typename W, typename TR>
+void wg_order(int mode, std::vector<int>& wi, std::vector<int>& wt, W weight, TR tiles_r) {
+    if (mode == 1) xcd_order(wi, wt, weight);
+    if (mode == 2) rowtile_order(wi, wt, tiles_r);
+    if (mode == 3) lockstep_order(wi, wt, weight);
+}
+
 // device copy of a table with room for any later (padded) version of it
 pe_status upload_cap(pe_batch bt, const std::vector<int>& v, size_t cap, int** out) {
     *out = nullptr;
@@ -1960,8 +2082,12 @@ pe_status group_tables(pe_batch bt, const std::vector<GemmShape>& shapes, const 
             wt.push_back((int)t);
         }
     }
-    const size_t cap = bt->xcd ? 8 * wi.size() + 8 : wi.size();
-    if (bt->xcd) xcd_order(wi, wt, dp);
+    std::vector<int> trs(shapes.size());
+    for (size_t g = 0; g < shapes.size(); ++g) trs[g] = (shapes[g].Mr + bt->cfg.br - 1) / bt->cfg.br;
+    const size_t cap = (bt->xcd == 1 || bt->xcd == 3) ? 8 * wi.size() + 8
+                       : bt->xcd == 2                   ? rowtile_cap(wi.size(), trs)
+                                                        : wi.size();
+    wg_order(bt->xcd, wi, wt, dp, [&](int g) { return trs[g]; });
     int *a = nullptr, *b = nullptr;
     PE_TRY(upload_cap(bt, wi, cap, &a));
     PE_TRY(upload_cap(bt, wt, cap, &b));
@@ -2153,9 +2279,11 @@ pe_status batch_plan(pe_batch bt) {
         bt->ui_d = (int*)ui;
         bt->ut_d = (int*)ut;
     }
-    // coarse correction as a scan (PE_MIXED; PE_BATCH_SCAN=0 keeps the sequential sweep)
+    // coarse sweeps as scans (PE_MIXED; PE_BATCH_SCAN=0 keeps the sequential sweeps)
     bt->scan = 0;
     bt->scan_L = 0;
+    bt->iscan_L = 0;
+    bt->iscanp.clear();
     bt->scanp.clear();
     bt->scan_item_g.clear();
     bt->scan_item_tiles.clear();
@@ -2201,7 +2329,7 @@ pe_status batch_plan(pe_batch bt) {
                 if (p->bscan_L <= l) continue;
                 const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
                 for (int b = 0; b < bt->Bs[g]; ++b) {
-                    const long o = ((long)b * (Z + N) + Z) * Dp;
+                    const long o = ((long)b * (Z + N + 1) + Z) * Dp;
                     const long oa = o - (long)(1 << l) * Dp;
                     sh.push_back(shape(N, Dp, p->bscan32[c] + oa, Dp, p->bpow32[l], Dp, 0, Dp));
                     Epi e = store_epi(p->bscan64[1 - c] + o, Dp, 1.0, p->bscan64[c] + o, Dp, 1.0);
@@ -2220,6 +2348,35 @@ pe_status batch_plan(pe_batch bt) {
             bt->scan_wi_d[l] = (int*)wi;
             bt->scan_wt_d[l] = (int*)wt;
         }
+        // the initial sweep over the N + 1 terms t_0 = x0, t_n = c_{n-1}
+        // (tables over every problem: the initial sweep runs before any
+        // problem finishes)
+        for (int g = 0; g < G; ++g) bt->iscan_L = std::max(bt->iscan_L, bt->pr[g]->bscan_L0);
+        bt->iscanp.assign(bt->iscan_L, GroupPlan());
+        for (int l = 0; l < bt->iscan_L; ++l) {
+            const int c = l & 1;
+            std::vector<GemmShape> sh;
+            std::vector<Epi> ep;
+            std::vector<int> ig;
+            for (int g = 0; g < G; ++g) {
+                pe_problem p = bt->pr[g];
+                if (p->bscan_L0 <= l) continue;
+                const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
+                for (int b = 0; b < bt->Bs[g]; ++b) {
+                    const long o = ((long)b * (Z + N + 1) + Z) * Dp;
+                    const long oa = o - (long)(1 << l) * Dp;
+                    sh.push_back(shape(N + 1, Dp, p->bscan32[c] + oa, Dp, p->bpow32[l], Dp, 0, Dp));
+                    Epi e = store_epi(p->bscan64[1 - c] + o, Dp, 1.0, p->bscan64[c] + o, Dp, 1.0);
+                    e.C32 = p->bscan32[1 - c] + o;
+                    ep.push_back(e);
+                    ig.push_back(g);
+                }
+            }
+            const int *wi, *wt;
+            int wn;
+            PE_TRY(group_tables(bt, sh, &wi, &wt, &wn, [&](int i) { return (double)bt->pr[ig[i]]->Dp; }));
+            PE_TRY(group_plan(bt, sh, ep, sizeof(float), wi, wt, wn, &bt->iscanp[l]));
+        }
     }
     bt->fi_d = (int*)fi;
     bt->ft_d = (int*)ft;
@@ -2228,11 +2385,18 @@ pe_status batch_plan(pe_batch bt) {
     bt->t_fine.assign(G, 0);
     bt->t_nk.assign(G, 0);
     bt->t_u.assign(G, 0);
+    bt->tr_fine.assign(G, 1);
+    bt->tr_nk.assign(G, 1);
+    bt->tr_u.assign(G, 1);
     for (int g = 0; g < G; ++g) {
-        bt->t_fine[g] = (long)((fine_sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br) * ((fine_sh[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
-        bt->t_nk[g] = (long)((nk_sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br) * ((nk_sh[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
-        if (bt->refine)
-            bt->t_u[g] = (long)((a3[g].Mr + bt->cfg.br - 1) / bt->cfg.br) * ((a3[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
+        bt->tr_fine[g] = (fine_sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br;
+        bt->tr_nk[g] = (nk_sh[g].Mr + bt->cfg.br - 1) / bt->cfg.br;
+        bt->t_fine[g] = (long)bt->tr_fine[g] * ((fine_sh[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
+        bt->t_nk[g] = (long)bt->tr_nk[g] * ((nk_sh[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
+        if (bt->refine) {
+            bt->tr_u[g] = (a3[g].Mr + bt->cfg.br - 1) / bt->cfg.br;
+            bt->t_u[g] = (long)bt->tr_u[g] * ((a3[g].Ns + bt->cfg.bs - 1) / bt->cfg.bs);
+        }
     }
 
     // coarse steps: problems by decreasing N, so the problems still running
@@ -2350,9 +2514,9 @@ pe_status batch_tables(pe_batch bt) {
     };
     if (bt->xcd) {
         auto dp_of = [&](int g) { return (double)bt->pr[g]->Dp; };
-        xcd_order(fi, ft, dp_of);
-        xcd_order(ki, kt, dp_of);
-        if (bt->refine) xcd_order(ui, ut, dp_of);
+        wg_order(bt->xcd, fi, ft, dp_of, [&](int g) { return bt->tr_fine[g]; });
+        wg_order(bt->xcd, ki, kt, dp_of, [&](int g) { return bt->tr_nk[g]; });
+        if (bt->refine) wg_order(bt->xcd, ui, ut, dp_of, [&](int g) { return bt->tr_u[g]; });
     }
     PE_TRY(put(bt->fi_d, fi));
     PE_TRY(put(bt->ft_d, ft));
@@ -2383,7 +2547,9 @@ pe_status batch_tables(pe_batch bt) {
         }
         if (bt->xcd) {
             const std::vector<int>& ig = bt->scan_item_g[l];
-            xcd_order(si, st, [&](int i) { return (double)bt->pr[ig[i]]->Dp; });
+            wg_order(
+                bt->xcd, si, st, [&](int i) { return (double)bt->pr[ig[i]]->Dp; },
+                [&](int i) { return (bt->pr[ig[i]]->N + bt->cfg.br - 1) / bt->cfg.br; });
         }
         PE_TRY(put(bt->scan_wi_d[l], si));
         PE_TRY(put(bt->scan_wt_d[l], st));
@@ -2918,7 +3084,7 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
         return fail(PE_ERR_ARG, "step sizes must be positive and finite");
     const double ratio = dt_coarse / dt_fine;
     const double Pr = std::round(ratio);
-    if (Pr < 1 || std::fabs(ratio - Pr) > 1e-9 * Pr || Pr > 1e7)
+    if (Pr < 1 || std::fabs(ratio - Pr) > 1e-12 * Pr || Pr > 1e7)
         return fail(PE_ERR_ARG, "dt_coarse / dt_fine must be a positive integer");
     if (precision != PE_FP64 && precision != PE_MIXED && precision != PE_MIXED_REFINE)
         return fail(PE_ERR_ARG, "unknown precision");
@@ -2972,6 +3138,19 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
                 p->force_wsk.bs = bs;
                 p->force_wsk.wsk = w;
                 p->force_wsk.splitk = sk;
+            }
+        }
+        if (const char* ft = getenv("PE_FORCE_TILES")) {
+            int br = 0, bs = 0, bk2 = 0, sk = 0;
+            const bool shape_ok = sscanf(ft, "%d,%d,%d,%d", &br, &bs, &bk2, &sk) == 4 &&
+                                  ((br == 32 && bs == 64) || (br == 64 && bs == 32) || (br == 64 && bs == 64) ||
+                                   (br == 64 && bs == 128) || (br == 128 && bs == 64) || (br == 128 && bs == 128));
+            if (shape_ok && (bk2 == 0 || bk2 == 1) && sk >= 1 && sk <= 64) {
+                p->force_tiles.br = br;
+                p->force_tiles.bs = bs;
+                p->force_tiles.bk2 = bk2;
+                p->force_tiles.splitk = sk;
+                p->force_tiles_on = 1;
             }
         }
         tune_cache_load(p);
@@ -3811,7 +3990,7 @@ pe_status pe_batch_create(pe_batch* out, int count, const pe_problem* problems, 
     const char* gr = getenv("PE_GRAPHS");
     bt->gc.use_graphs = (gr && gr[0] == '0') ? 0 : 1;
     const char* xo = getenv("PE_BATCH_XCD");
-    bt->xcd = (xo && xo[0] == '1') ? 1 : 0;
+    bt->xcd = (xo && xo[0] >= '0' && xo[0] <= '3') ? xo[0] - '0' : 2;
     bt->cfg.br = 64;
     bt->cfg.bs = 64;
     bt->cfg.splitk = 1;
@@ -3822,7 +4001,7 @@ pe_status pe_batch_create(pe_batch* out, int count, const pe_problem* problems, 
     if (const char* t = getenv("PE_BATCH_TILE")) {
         int br = 0, bs = 0, bk2 = 0;
         if (sscanf(t, "%d %d %d", &br, &bs, &bk2) == 3 &&
-            ((br == 32 && bs == 64) || (br == 64 && (bs == 64 || bs == 128)))) {
+            ((br == 32 && bs == 64) || (br == 64 && (bs == 64 || bs == 128)) || (br == 128 && bs == 64))) {
             bt->cfg.br = br;
             bt->cfg.bs = bs;
             bt->cfg.bk2 = bk2 ? 1 : 0;
@@ -3914,7 +4093,31 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
             pe_problem p = bt->pr[g];
             PE_HIP(set_x0(p->x0p, p->Xk[0], (long)(p->N + 1) * p->Dp, bt->Bs[g], p->Dp, bt->st));
         }
-        for (int n = 0; n < bt->N_max; ++n) PE_TRY(coarse_grouped<double>(bt, bt->c_init, n, 0, 0));
+        if (bt->scan) {
+            // x_{n+1} = Phi_G x_n + c_n summed by the doubling scan over
+            // t_0 = x0, t_n = c_{n-1} (FP32 products, FP64 sums)
+            for (int g = 0; g < G; ++g) {
+                pe_problem p = bt->pr[g];
+                const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
+                for (int b = 0; b < bt->Bs[g]; ++b) {
+                    const long o = ((long)b * (Z + N + 1) + Z) * Dp, ox = (long)b * (N + 1) * Dp;
+                    PE_HIP(scan_init0(p->Xk[0] + ox, p->CS ? p->CS + (long)b * N * Dp : nullptr, p->bscan64[0] + o,
+                                      p->bscan32[0] + o, N, Dp, bt->st));
+                }
+            }
+            for (int l = 0; l < bt->iscan_L; ++l) PE_TRY(grouped<float>(bt, bt->iscanp[l], PE_PROF_COARSE));
+            for (int g = 0; g < G; ++g) {
+                pe_problem p = bt->pr[g];
+                const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
+                for (int b = 0; b < bt->Bs[g]; ++b) {
+                    const long o = ((long)b * (Z + N + 1) + Z) * Dp, ox = (long)b * (N + 1) * Dp;
+                    PE_HIP(scan_final(nullptr, p->bscan64[p->bscan_L0 & 1] + o + Dp, p->Xk[0] + ox, 1, N, Dp,
+                                      nullptr, bt->st));
+                }
+            }
+        } else {
+            for (int n = 0; n < bt->N_max; ++n) PE_TRY(coarse_grouped<double>(bt, bt->c_init, n, 0, 0));
+        }
         if (rel) PE_TRY(batch_jumps(bt, 0, true));
         return PE_OK;
     }));
@@ -3977,7 +4180,7 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
                     pe_problem p = bt->pr[g];
                     const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
                     for (int b = 0; b < bt->Bs[g]; ++b) {
-                        const long o = ((long)b * (Z + N) + Z) * Dp;
+                        const long o = ((long)b * (Z + N + 1) + Z) * Dp;
                         PE_HIP(scan_init(p->Fbuf + (long)b * N * Dp, p->Xk[cur] + (long)b * (N + 1) * Dp, 1,
                                          p->bscan64[0] + o, p->bscan32[0] + o, N, Dp, bt->st));
                     }
@@ -3988,7 +4191,7 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
                     pe_problem p = bt->pr[g];
                     const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
                     for (int b = 0; b < bt->Bs[g]; ++b) {
-                        const long o = ((long)b * (Z + N) + Z) * Dp, ox = (long)b * (N + 1) * Dp;
+                        const long o = ((long)b * (Z + N + 1) + Z) * Dp, ox = (long)b * (N + 1) * Dp;
                         PE_HIP(scan_final(p->Xk[cur] + ox, p->bscan64[p->bscan_L & 1] + o, p->Xk[nxt] + ox, 1, N,
                                           Dp, p->active_d + b, bt->st));
                     }

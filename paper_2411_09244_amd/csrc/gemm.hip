@@ -320,11 +320,17 @@ __device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, c
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave & 1, wsi = wave >> 1;
     const int tr = tile % tiles_r, ts = tile / tiles_r;
     const int r0 = tr * BR, s0 = ts * BS;
     const int s1 = min(s0 + BS, sh.Ns);
+    // 16 x 16 blocks of this wave's quarter that hold rows and columns of
+    // the product: i < ni, j < nj. Blocks wholly in the padding past Mr or
+    // Ns (a ragged last tile) are not sent to the matrix cores.
+    const int ni = min(MI, max(0, (sh.Mr - (r0 + wr * (BR / 2)) + 15) / 16));
+    const int nj = min(MJ, max(0, (sh.Ns - (s0 + wsi * (BS / 2)) + 15) / 16));
+    const bool full = ni == MI && nj == MJ;
 
     int k0, k1;
     if (s1 <= sh.s_split) {
@@ -395,23 +401,24 @@ __device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, c
         sstore(0);
         __syncthreads();
     }
-    for (int kt = kt0; kt < kt1; ++kt) {
-        const bool more = kt + 1 < kt1;
-        if (more) gload(k0 + (kt + 1) * BK);
-        const T* Asc = As[stage];
-        const T* Bsc = Bs[stage];
+    // the products of one staged K tile; FULL: every block of the quarter
+    // is live (no per-block conditions in the unrolled loop)
+    auto kstep = [&](auto full_c, const T* Asc, const T* Bsc) {
+        constexpr bool FULL = decltype(full_c)::value;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             T a[MI][4], b[MJ][4];
             const int koff = kk + 4 * (lane >> 4);
 #pragma unroll
             for (int i = 0; i < MI; ++i) {
+                if (!FULL && i >= ni) continue;
                 const T* pa = Asc + (wr * (BR / 2) + i * 16 + (lane & 15)) * LDT + koff;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) a[i][q] = pa[q];
             }
 #pragma unroll
             for (int j = 0; j < MJ; ++j) {
+                if (!FULL && j >= nj) continue;
                 const T* pb = Bsc + (wsi * (BS / 2) + j * 16 + (lane & 15)) * LDT + koff;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) b[j][q] = pb[q];
@@ -421,8 +428,18 @@ __device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, c
 #pragma unroll
                 for (int i = 0; i < MI; ++i)
 #pragma unroll
-                    for (int j = 0; j < MJ; ++j) acc[i][j] = Op::mma(a[i][q], b[j][q], acc[i][j]);
+                    for (int j = 0; j < MJ; ++j)
+                        if (FULL || (i < ni && j < nj)) acc[i][j] = Op::mma(a[i][q], b[j][q], acc[i][j]);
         }
+    };
+
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const bool more = kt + 1 < kt1;
+        if (more) gload(k0 + (kt + 1) * BK);
+        if (full)
+            kstep(std::true_type{}, As[stage], Bs[stage]);
+        else if (ni > 0 && nj > 0)
+            kstep(std::false_type{}, As[stage], Bs[stage]);
         if (more) sstore(stage ^ 1);
         __syncthreads();
         stage ^= 1;
@@ -992,6 +1009,7 @@ hipError_t gemm_grouped_launch(const GemmItem* items, const int* wg_item, const 
     PE_GCFG(64, 64)
     PE_GCFG(32, 64)
     PE_GCFG(64, 128)
+    PE_GCFG(128, 64)
 #undef PE_GCFG
     return hipErrorInvalidValue;
 }

@@ -208,15 +208,18 @@ __global__ void k_scan_final(const double* __restrict__ Xp, const double* __rest
 }
 
 __global__ void k_scan_init0(const double* __restrict__ x0, const double* __restrict__ cs, double* __restrict__ t,
-                             long n_el, int Dp) {
+                             float* __restrict__ t32, long n_el, int Dp) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n_el) return;
-    t[i] = i < Dp ? x0[i] : (cs ? cs[i - Dp] : 0.0);
+    const double v = i < Dp ? x0[i] : (cs ? cs[i - Dp] : 0.0);
+    t[i] = v;
+    if (t32) t32[i] = (float)v;
 }
 
-hipError_t scan_init0(const double* x0, const double* cs, double* t, int N, int Dp, hipStream_t st) {
+hipError_t scan_init0(const double* x0, const double* cs, double* t, float* t32, int N, int Dp, hipStream_t st) {
     const long n_el = (long)(N + 1) * Dp;
-    hipLaunchKernelGGL(k_scan_init0, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, x0, cs, t, n_el, Dp);
+    hipLaunchKernelGGL(k_scan_init0, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, st, x0, cs, t, t32, n_el,
+                       Dp);
     return hipGetLastError();
 }
 

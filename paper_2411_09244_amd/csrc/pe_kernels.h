@@ -37,7 +37,7 @@ hipError_t scan_final(const double* Xp, const double* t, double* X, int xrow, in
                       hipStream_t st);
 // initial sweep as a scan: t[0] = x0, t[n] = cs[n-1] (n = 1..N; cs nullable:
 // zero source). scan_final with Xp = nullptr then copies t[1..N] to X[1..N].
-hipError_t scan_init0(const double* x0, const double* cs, double* t, int N, int Dp, hipStream_t st);
+hipError_t scan_init0(const double* x0, const double* cs, double* t, float* t32, int N, int Dp, hipStream_t st);
 hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStream_t st, int sx = 0);
 // carried history
 hipError_t gather_rows(const double* X, long ldXb, int sx, int off, int row_off, int nvalid, double* out, int B,

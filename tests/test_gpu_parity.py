@@ -332,3 +332,45 @@ def test_coarse_scan_matches_sequential(name, prec, tol, monkeypatch):
         e_ab = S.rel_l2_M(bl, out["1"][b], out["0"][b])
         print(f"{name} {prec}: scan {e_scan:.3e}, sequential {e_seq:.3e}, scan vs sequential {e_ab:.3e}")
         assert e_scan < tol and e_seq < tol and e_ab < tol
+
+
+TILE_CFGS = ["64,32,1,8", "32,64,0,4", "64,64,0,2", "128,64,0,3", "128,128,0,1"]
+
+
+@pytest.mark.parametrize("cfg", TILE_CFGS)
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX)])
+def test_forced_tile_configurations(cfg, prec, tol, monkeypatch):
+    """Every product of more than 4 state columns forced onto one tile
+    configuration (cfg = state rows, operator rows per tile, K-depth flag,
+    K splits), so that ragged last tiles, tiles mostly past the state rows
+    (128-row tiles over 64 or 65 state rows: matrix-core blocks wholly in the
+    padding are skipped) and split-K planes are all exercised: the fine
+    propagator against the oracle on ragged and tiled sizes up to the 200x200
+    workload, and parareal at equal k on two of them (fine steps, anchors,
+    stopping-test norms and coarse scans run through the same products)."""
+    pe = _pe()
+    monkeypatch.setenv("PE_FORCE_TILES", cfg)
+    for name in ("t1", "ragged", "c0", "c1"):
+        p = _prob(name)
+        bl, src = S.Blocks.from_problem(p), S.Source.from_problem(p)
+        B, N = p["B"], p["N"]
+        print(f"[tiles] {cfg} {prec} {name}", flush=True)
+        Xin = _random_states(p, 5, B, N)
+        pr = pe.problem_from(p, prec)
+        Y = pr.fine(Xin).cpu().numpy()
+        tiles = pr.last_tiles("fine_step")
+        want = [int(v) for v in cfg.split(",")]
+        assert tiles[0] == want[0] and tiles[1] == want[1] and tiles[3] == want[3], tiles
+        for b in range(B):
+            ref = S.fine_propagator_cols(bl, src, Xin[b].T.copy(), list(range(N)), [b] * N).T
+            err = _colwise_rel(bl, Y[b], ref)
+            print(f"  F vs oracle b={b}: {err:.3e}")
+            assert err < tol, (name, cfg, prec, b, err)
+        if name in ("t1", "ragged"):
+            X, iters, hist, st = pr.solve(p["x0"], tol=0.0, k_max=3)
+            _, refs = _oracle_parareal(p, 3)
+            for b in range(B):
+                err = S.rel_l2_M(bl, X[b].cpu().numpy(), refs[b]["X"][3])
+                print(f"  parareal k=3 vs oracle b={b}: {err:.3e}")
+                assert err < tol, (name, cfg, prec, b, err)
+        pr.close()

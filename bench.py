@@ -43,7 +43,10 @@ PEAK_HBM_TBPS = 8.0      # MI355X HBM3E
 # copy reads for the same counters), keyed by workload and the kernel's tile
 # configuration (state-tile rows, operator-tile rows, K depth, split-K).
 # Reported only when the timed run used that kernel class and configuration.
-MEASURED_TRAFFIC = {("c1", "fine_step", (64, 32, 64, 8)): 2.0 * 18546.6 * 1024 + 1.0 * 4000.0 * 1024}
+MEASURED_TRAFFIC = {("c1", "fine_step", (64, 32, 64, 8)): 2.0 * 18546.6 * 1024 + 1.0 * 4000.0 * 1024,
+                    # the 256-solve batch: FETCH_SIZE x 2 + WRITE_SIZE x 1 of the grouped FP32
+                    # product over one batch solve, divided by its 558 fine-step launches
+                    ("c2", 256): (2.0 * 6383410687.4 + 1.0 * 435397878.5) * 1024 / 2 / 558}
 
 
 def time_solves(pr, x0, tol, steps, warmup, torch):
@@ -335,7 +338,10 @@ def batch_main(args, torch, pe):
            "roofline": dict(kernel="gemm_grouped_kernel<float,64,64,32> fused fine-step products of all solves",
                             bound="mfma", achieved=round(flops_res / avg / 1e12, 3), peak=PEAK_FP32_MFMA,
                             unit="TFLOP/s", frac=round(flops_res / avg / 1e12 / PEAK_FP32_MFMA, 5),
-                            traffic=MEASURED_TRAFFIC.get(("c2", n_solves)),
+                            traffic=(round(MEASURED_TRAFFIC[("c2", n_solves)])
+                                     if ("c2", n_solves) in MEASURED_TRAFFIC else None),
+                            traffic_ratio=(round(MEASURED_TRAFFIC[("c2", n_solves)] / bytes_res, 3)
+                                           if ("c2", n_solves) in MEASURED_TRAFFIC else None),
                             avg_launch_us=round(avg * 1e6, 3), launches=n, flops_per_launch=round(flops_res),
                             bytes_per_launch=round(bytes_res),
                             hbm_achieved_GBps=round(bytes_res / avg / 1e9, 1),

@@ -231,7 +231,8 @@ def batch_main(args, torch, pe):
     P = probs[0]["P"]
     rng = np.random.default_rng(7)
     # the oracle's sample: seeded solves it finishes in seconds each
-    sample = [int(b) for b in rng.permutation(n_solves) if d1[b] + d2[b] <= 1280 and Ns[b] <= 64][:3]
+    # (12 solves with D <= 2000, N <= 96: about 10-20 s of the oracle on 16 cores)
+    sample = [int(b) for b in rng.permutation(n_solves) if d1[b] + d2[b] <= 2000 and Ns[b] <= 96][:12]
     # the headline leg is the refined mixed path (FP32 MFMA products, FP64
     # residual and FP32 correction of every fine step's implicit solve in the
     # sweeps at the state's scale); the unrefined mixed path and the plain
@@ -388,7 +389,7 @@ def batch_main(args, torch, pe):
         scale = sum(work) / sum(work[b] for b in sample)
         out["cpu_baseline"] = {"value": round(n_solves / (dt_cpu * scale), 6), "unit": "solves/s",
                                "cores": threads, "kind": "oracle",
-                               "sample": f"{len(sample)} seeded solves of the batch with D <= 1280, N <= 64 (b = {sample}), "
+                               "sample": f"{len(sample)} seeded solves of the batch with D <= 2000, N <= 96 (b = {sample}), "
                                          f"FP64 NumPy/SciPy parareal ({blas}), {dt_cpu:.1f}s, scaled to the whole "
                                          f"batch by the fine-sweep work iterations x N x D^2 (x{scale:.1f})"}
         out["rel_l2_vs_oracle_sampled"] = {k: [float(f"{e:.3e}") for e in v] for k, v in errs.items()}

@@ -10,11 +10,14 @@ SOURCES = ["api.hip", "gemm.hip", "kernels.hip", "cem.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          # no packed FP32 instructions in generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core accumulators in ordinary vector registers: the
+         # grouped FP32 product then needs 96 of them and, with 32 KB of LDS
+         # per work-group, runs five work-groups per CU
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-function"]
-# the peak probes are compiled as a separate object with matrix-core
-# accumulators in ordinary vector registers
+# the peak probes are compiled as a separate object
 PROBE_SOURCE = "probe.hip"
-PROBE_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+PROBE_FLAGS = []
 
 
 def _run(cmd, verbose):

@@ -306,8 +306,9 @@ __device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, c
     using acc_t = typename Op::acc_t;
     using vec_t = typename Op::vec_t;
     constexpr int VW = 16 / sizeof(T);      // elements per 16-byte vector
-    constexpr int LDT = BK + VW;            // padded LDS row (elements)
+    constexpr int LDT = BK;                 // LDS row (elements), 16-byte chunks XOR-swizzled
     constexpr int KV = BK / VW;             // vectors per tile row
+    constexpr int R2 = (256 / (KV * 16)) > 0 ? (256 / (KV * 16)) : 1;  // rows per 256-byte bank line
     constexpr int AV = BR * KV / 256;       // A vectors per thread
     constexpr int BV = BS * KV / 256;       // B vectors per thread
     constexpr int MI = BR / 32, MJ = BS / 32;
@@ -380,18 +381,20 @@ __device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, c
                 rb[v] = vec_t{};
         }
     };
+    // physical chunk of logical chunk c in row r: c ^ ((r / R2) % KV), so
+    // the 16 rows one MFMA operand read spans fall in distinct banks
     auto sstore = [&](int stage) {
 #pragma unroll
         for (int v = 0; v < AV; ++v) {
             const int idx = tid + v * 256;
-            const int row = idx / KV, kk = (idx % KV) * VW;
-            *(vec_t*)(&As[stage][row * LDT + kk]) = ra[v];
+            const int row = idx / KV, c = idx % KV;
+            *(vec_t*)(&As[stage][row * LDT + ((c ^ ((row / R2) % KV)) * VW)]) = ra[v];
         }
 #pragma unroll
         for (int v = 0; v < BV; ++v) {
             const int idx = tid + v * 256;
-            const int row = idx / KV, kk = (idx % KV) * VW;
-            *(vec_t*)(&Bs[stage][row * LDT + kk]) = rb[v];
+            const int row = idx / KV, c = idx % KV;
+            *(vec_t*)(&Bs[stage][row * LDT + ((c ^ ((row / R2) % KV)) * VW)]) = rb[v];
         }
     };
 
@@ -408,20 +411,31 @@ __device__ __forceinline__ void gemm_tile(const GemmShape& sh, const Epi& epi, c
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             T a[MI][4], b[MJ][4];
+            // four consecutive k of this lane: element offset koff in the
+            // row, inside one 16-byte chunk (VW = 4: the whole chunk; VW =
+            // 2: chunks koff / 2 and koff / 2 + 1)
             const int koff = kk + 4 * (lane >> 4);
 #pragma unroll
             for (int i = 0; i < MI; ++i) {
                 if (!FULL && i >= ni) continue;
-                const T* pa = Asc + (wr * (BR / 2) + i * 16 + (lane & 15)) * LDT + koff;
+                const int row = wr * (BR / 2) + i * 16 + (lane & 15);
+                const T* pr = Asc + row * LDT;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) a[i][q] = pa[q];
+                for (int q = 0; q < 4; ++q) {
+                    const int e = koff + q, c = e / VW;
+                    a[i][q] = pr[((c ^ ((row / R2) % KV)) * VW) + e % VW];
+                }
             }
 #pragma unroll
             for (int j = 0; j < MJ; ++j) {
                 if (!FULL && j >= nj) continue;
-                const T* pb = Bsc + (wsi * (BS / 2) + j * 16 + (lane & 15)) * LDT + koff;
+                const int row = wsi * (BS / 2) + j * 16 + (lane & 15);
+                const T* pr = Bsc + row * LDT;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) b[j][q] = pb[q];
+                for (int q = 0; q < 4; ++q) {
+                    const int e = koff + q, c = e / VW;
+                    b[j][q] = pr[((c ^ ((row / R2) % KV)) * VW) + e % VW];
+                }
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)

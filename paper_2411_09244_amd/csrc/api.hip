@@ -1856,6 +1856,11 @@ struct pe_batch_s {
     std::vector<int*> scan_wi_d, scan_wt_d;          // [level] work-group tables
     CoarseItem* c_init = nullptr;
     CoarseItem* c_corr[2] = {nullptr, nullptr};
+    // grouped element-wise steps: one BatchElem per problem, the active
+    // problems' indices (act_d[0..n_act-1]) and the largest sample count
+    BatchElem* elems_d = nullptr;
+    int* act_d = nullptr;
+    int n_act = 0, B_max = 0;
     int *c_wg_item = nullptr, *c_wg_row = nullptr;
     std::vector<int> c_nwg;  // coarse step n: work-groups of the problems with N > n
     std::vector<int> order;  // problems by decreasing N
@@ -2466,6 +2471,49 @@ pe_status batch_plan(pe_batch bt) {
     }
     bt->allocs.push_back(jd);
     bt->J_all = (double*)jd;
+    {
+        std::vector<BatchElem> el(G);
+        bt->B_max = 0;
+        for (int g = 0; g < G; ++g) {
+            pe_problem p = bt->pr[g];
+            BatchElem& e = el[g];
+            e.Xk[0] = p->Xk[0];
+            e.Xk[1] = p->Xk[1];
+            e.E = p->E;
+            e.Yn = p->Yn;
+            e.nrm = p->nrm;
+            e.J = bt->J_all + bt->J_off[g];
+            e.x0p = p->x0p;
+            e.Dl64 = p->Dl64[0];
+            e.Dl32 = p->Dl32[0];
+            e.Xa = p->Xa;
+            e.R64 = p->R64;
+            e.dev64[0] = p->dev64[0];
+            e.dev64[1] = p->dev64[1];
+            e.dev32 = p->dev32[0];
+            e.Fbuf = p->Fbuf;
+            e.CS = p->CS;
+            e.active = p->active_d;
+            e.B = bt->Bs[g];
+            e.N = p->N;
+            e.Dp = p->Dp;
+            e.d1p = p->d1p;
+            if (bt->scan) {
+                e.t64[0] = p->bscan64[0];
+                e.t64[1] = p->bscan64[1];
+                e.t32 = p->bscan32[0];
+                e.Z = p->bscan_Z;
+                e.L = p->bscan_L;
+                e.L0 = p->bscan_L0;
+            }
+            bt->B_max = std::max(bt->B_max, bt->Bs[g]);
+        }
+        PE_TRY(upload(bt, el, &bt->elems_d));
+        std::vector<int> all(G);
+        for (int g = 0; g < G; ++g) all[g] = g;
+        PE_TRY(upload(bt, all, &bt->act_d));
+        bt->n_act = G;
+    }
     bt->plan_keys = batch_plan_keys(bt);
     bt->planned = 1;
     bt->pact.assign(G, 1);
@@ -2528,6 +2576,13 @@ pe_status batch_tables(pe_batch bt) {
         PE_TRY(put(bt->ui_d, ui));
         PE_TRY(put(bt->ut_d, ut));
     }
+    {
+        std::vector<int> act;
+        for (int g = 0; g < G; ++g)
+            if (bt->pact[g]) act.push_back(g);
+        PE_TRY(put(bt->act_d, act));
+        bt->n_act = (int)act.size();
+    }
     const int fn = (int)fi.size(), kn = (int)ki.size(), un = (int)ui.size();
     for (GroupPlan* g : {&bt->anc1, &bt->anc2, &bt->fin[0], &bt->fin[1]}) g->n_wg = fn;
     for (int w = 0; w < 2; ++w)
@@ -2589,15 +2644,7 @@ pe_status coarse_grouped(pe_batch bt, const CoarseItem* items, int n, int delta,
 // F on every interval of every problem (as fine_sweep, one grouped launch per product)
 pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
     const bool mixed = bt->prec == PE_MIXED;
-    for (int g = 0; g < bt->count; ++g) {
-        if (!bt->pact[g]) continue;
-        pe_problem p = bt->pr[g];
-        const int B = bt->Bs[g], N = p->N, Dp = p->Dp;
-        const double* Xs = incremental ? p->E : p->Xk[cur];
-        const long ld = incremental ? (long)N * Dp : (long)(N + 1) * Dp;
-        PE_HIP(fine_init(Xs, ld, incremental ? -1 : 0, N, mixed ? p->R64 : p->Xa, p->dev64[0],
-                         mixed ? p->dev32[0] : nullptr, B, N, Dp, bt->st));
-    }
+    PE_HIP(grp_fine_init(bt->elems_d, bt->act_d, bt->n_act, cur, incremental ? 1 : 0, mixed ? 1 : 0, bt->st));
     if (mixed) PE_TRY(grouped<double>(bt, bt->anc1, PE_PROF_ANCHOR));
     PE_TRY(grouped<double>(bt, bt->anc2, PE_PROF_ANCHOR));
     const int w = incremental ? 0 : 1;
@@ -2615,12 +2662,7 @@ pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
             PE_TRY(grouped<float>(bt, bt->rcorr[step], PE_PROF_REFINE));
         }
     }
-    for (int g = 0; g < bt->count; ++g) {
-        if (!bt->pact[g]) continue;
-        pe_problem p = bt->pr[g];
-        const long rows = (long)bt->Bs[g] * p->N;
-        PE_HIP(fine_final(p->Xa, p->dev64[bt->P & 1], mixed ? p->R64 : p->Fbuf, rows, p->Dp, p->d1p, 0, bt->st));
-    }
+    PE_HIP(grp_fine_final(bt->elems_d, bt->act_d, bt->n_act, bt->P, mixed ? 1 : 0, bt->st));
     if (mixed) PE_TRY(grouped<double>(bt, bt->fin[incremental ? 1 : 0], PE_PROF_ANCHOR));
     return PE_OK;
 }
@@ -2628,20 +2670,9 @@ pe_status batch_fine_sweep(pe_batch bt, int cur, bool incremental) {
 // jumps of every problem into J_all: rel (X^0 norms over n = 0..N) or the
 // change of iterate xk against 1 - xk over n = 1..N
 pe_status batch_jumps(pe_batch bt, int xk, bool rel) {
-    for (int g = 0; g < bt->count; ++g) {
-        if (!bt->pact[g]) continue;
-        pe_problem p = bt->pr[g];
-        const int N = p->N;
-        PE_HIP(jump_diff(p->Xk[xk], rel ? nullptr : p->Xk[1 - xk], (long)(N + 1) * p->Dp, rel ? 0 : 1,
-                         rel ? N + 1 : N, bt->Bs[g], p->Dp, p->E, bt->st));
-    }
+    PE_HIP(grp_jump_diff(bt->elems_d, bt->act_d, bt->n_act, xk, rel ? 1 : 0, bt->st));
     PE_TRY(grouped<double>(bt, rel ? bt->nrm_rel : bt->nrm_k, PE_PROF_NORM));
-    for (int g = 0; g < bt->count; ++g) {
-        if (!bt->pact[g]) continue;
-        pe_problem p = bt->pr[g];
-        PE_HIP(jump_reduce(p->E, p->Yn, bt->Bs[g], rel ? p->N + 1 : p->N, p->Dp, bt->J_all + bt->J_off[g], p->nrm,
-                           bt->st));
-    }
+    PE_HIP(grp_jump_reduce(bt->elems_d, bt->act_d, bt->n_act, bt->B_max, rel ? 1 : 0, bt->st));
     return PE_OK;
 }
 pe_status check_handle(pe_problem p) {
@@ -4089,32 +4120,13 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
     }
     int cur = 0;
     PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {0, rel}, [&]() -> pe_status {
-        for (int g = 0; g < G; ++g) {
-            pe_problem p = bt->pr[g];
-            PE_HIP(set_x0(p->x0p, p->Xk[0], (long)(p->N + 1) * p->Dp, bt->Bs[g], p->Dp, bt->st));
-        }
+        PE_HIP(grp_set_x0(bt->elems_d, bt->act_d, bt->n_act, 0, 0, bt->st));
         if (bt->scan) {
             // x_{n+1} = Phi_G x_n + c_n summed by the doubling scan over
             // t_0 = x0, t_n = c_{n-1} (FP32 products, FP64 sums)
-            for (int g = 0; g < G; ++g) {
-                pe_problem p = bt->pr[g];
-                const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
-                for (int b = 0; b < bt->Bs[g]; ++b) {
-                    const long o = ((long)b * (Z + N + 1) + Z) * Dp, ox = (long)b * (N + 1) * Dp;
-                    PE_HIP(scan_init0(p->Xk[0] + ox, p->CS ? p->CS + (long)b * N * Dp : nullptr, p->bscan64[0] + o,
-                                      p->bscan32[0] + o, N, Dp, bt->st));
-                }
-            }
+            PE_HIP(grp_scan_init0(bt->elems_d, bt->act_d, bt->n_act, bt->st));
             for (int l = 0; l < bt->iscan_L; ++l) PE_TRY(grouped<float>(bt, bt->iscanp[l], PE_PROF_COARSE));
-            for (int g = 0; g < G; ++g) {
-                pe_problem p = bt->pr[g];
-                const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
-                for (int b = 0; b < bt->Bs[g]; ++b) {
-                    const long o = ((long)b * (Z + N + 1) + Z) * Dp, ox = (long)b * (N + 1) * Dp;
-                    PE_HIP(scan_final(nullptr, p->bscan64[p->bscan_L0 & 1] + o + Dp, p->Xk[0] + ox, 1, N, Dp,
-                                      nullptr, bt->st));
-                }
-            }
+            PE_HIP(grp_scan_final0(bt->elems_d, bt->act_d, bt->n_act, bt->st));
         } else {
             for (int n = 0; n < bt->N_max; ++n) PE_TRY(coarse_grouped<double>(bt, bt->c_init, n, 0, 0));
         }
@@ -4165,37 +4177,13 @@ pe_status pe_batch_solve(pe_batch bt, const double* const* x0, double tol, int n
                                        bt->st));
         }
         PE_TRY(graph_run_on(bt->gc, bt->st, bt->prof.on != 0, {2, cur, ah}, [&]() -> pe_status {
-            for (int g = 0; g < G; ++g) {
-                if (!bt->pact[g]) continue;
-                pe_problem p = bt->pr[g];
-                PE_HIP(set_x0(p->x0p, p->Xk[nxt], (long)(p->N + 1) * p->Dp, bt->Bs[g], p->Dp, bt->st));
-                PE_HIP(zero_fill(mixed ? nullptr : p->Dl64[0], mixed ? p->Dl32[0] : nullptr, (long)bt->Bs[g] * p->Dp,
-                                 bt->st));
-            }
+            PE_HIP(grp_set_x0(bt->elems_d, bt->act_d, bt->n_act, nxt, mixed ? 2 : 1, bt->st));
             if (bt->scan) {
                 // change form d_{n+1} = Phi_G d_n + e_n, e_n = F(x_n^{k-1}) - x_{n+1}^{k-1},
                 // summed by the doubling scan; then x_n^k = x_n^{k-1} + d_n
-                for (int g = 0; g < G; ++g) {
-                    if (!bt->pact[g]) continue;
-                    pe_problem p = bt->pr[g];
-                    const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
-                    for (int b = 0; b < bt->Bs[g]; ++b) {
-                        const long o = ((long)b * (Z + N + 1) + Z) * Dp;
-                        PE_HIP(scan_init(p->Fbuf + (long)b * N * Dp, p->Xk[cur] + (long)b * (N + 1) * Dp, 1,
-                                         p->bscan64[0] + o, p->bscan32[0] + o, N, Dp, bt->st));
-                    }
-                }
+                PE_HIP(grp_scan_init(bt->elems_d, bt->act_d, bt->n_act, cur, bt->st));
                 for (int l = 0; l < bt->scan_L; ++l) PE_TRY(grouped<float>(bt, bt->scanp[l], PE_PROF_COARSE));
-                for (int g = 0; g < G; ++g) {
-                    if (!bt->pact[g]) continue;
-                    pe_problem p = bt->pr[g];
-                    const int N = p->N, Dp = p->Dp, Z = p->bscan_Z;
-                    for (int b = 0; b < bt->Bs[g]; ++b) {
-                        const long o = ((long)b * (Z + N + 1) + Z) * Dp, ox = (long)b * (N + 1) * Dp;
-                        PE_HIP(scan_final(p->Xk[cur] + ox, p->bscan64[p->bscan_L & 1] + o, p->Xk[nxt] + ox, 1, N,
-                                          Dp, p->active_d + b, bt->st));
-                    }
-                }
+                PE_HIP(grp_scan_final(bt->elems_d, bt->act_d, bt->n_act, cur, nxt, bt->st));
             } else {
                 for (int n = 0; n < bt->N_max; ++n) {
                     if (mixed)

@@ -410,6 +410,198 @@ hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStr
 }
 
 // ---------------------------------------------------------------------------
+// grouped element-wise steps of a batch: GRP_CH work-groups per active
+// problem, each striding over that problem's elements
+// ---------------------------------------------------------------------------
+constexpr int GRP_CH = 64;
+
+#define GRP_LOOP(n_el) \
+    for (long i = (long)(blockIdx.x % GRP_CH) * 256 + threadIdx.x; i < (n_el); i += (long)GRP_CH * 256)
+
+__global__ void k_grp_set_x0(const BatchElem* __restrict__ it, const int* __restrict__ act, int xk, int zero_mode) {
+    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    GRP_LOOP((long)e.B * e.Dp) {
+        const long b = i / e.Dp;
+        const int s = (int)(i - b * e.Dp);
+        e.Xk[xk][b * (long)(e.N + 1) * e.Dp + s] = e.x0p[i];
+        if (zero_mode == 1) e.Dl64[i] = 0.0;
+        if (zero_mode == 2) e.Dl32[i] = 0.0f;
+    }
+}
+
+__global__ void k_grp_fine_init(const BatchElem* __restrict__ it, const int* __restrict__ act, int cur, int inc,
+                                int mixed) {
+    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    GRP_LOOP((long)e.B * e.N * e.Dp) {
+        const int Dp = e.Dp, N = e.N;
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const long b = r / N, n = r - b * N;
+        const long j = n + (inc ? -1 : 0);
+        const double* X = inc ? e.E : e.Xk[cur];
+        const long ldXb = inc ? (long)N * Dp : (long)(N + 1) * Dp;
+        double* Xa = mixed ? e.R64 : e.Xa;
+        Xa[i] = (j >= 0 && j < N) ? X[b * ldXb + j * Dp + s] : 0.0;
+        e.dev64[0][r * 2 * Dp + s] = 0.0;
+        e.dev64[0][r * 2 * Dp + Dp + s] = 0.0;
+        if (mixed) {
+            e.dev32[r * 2 * Dp + s] = 0.0f;
+            e.dev32[r * 2 * Dp + Dp + s] = 0.0f;
+        }
+    }
+}
+
+__global__ void k_grp_fine_final(const BatchElem* __restrict__ it, const int* __restrict__ act, int P, int mixed) {
+    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    GRP_LOOP((long)e.B * e.N * e.Dp) {
+        const int Dp = e.Dp;
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const double v = e.Xa[i] + e.dev64[P & 1][r * 2 * Dp + e.d1p + s];
+        (mixed ? e.R64 : e.Fbuf)[r * Dp + s] = v;
+    }
+}
+
+__global__ void k_grp_jump_diff(const BatchElem* __restrict__ it, const int* __restrict__ act, int xk, int rel) {
+    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    const int nr0 = rel ? e.N + 1 : e.N;
+    GRP_LOOP((long)e.B * nr0 * e.Dp) {
+        const int Dp = e.Dp, nr = rel ? e.N + 1 : e.N, n0 = rel ? 0 : 1;
+        const long r = i / Dp;
+        const int s = (int)(i - r * Dp);
+        const long b = r / nr, j = r - b * nr;
+        const long o = b * (long)(e.N + 1) * Dp + (n0 + j) * Dp + s;
+        e.E[i] = rel ? e.Xk[xk][o] : (e.Xk[xk][o] - e.Xk[1 - xk][o]);
+    }
+}
+
+// one work-group per (problem, sample): the sample's row norms (each row
+// reduced exactly as k_row_norms does) and their maximum (as k_sample_max)
+__global__ __launch_bounds__(256) void k_grp_jump_reduce(const BatchElem* __restrict__ it, const int* __restrict__ act,
+                                                         int Bmax, int rel) {
+    const BatchElem& e = it[act[blockIdx.x / Bmax]];
+    const int b = blockIdx.x % Bmax;
+    if (b >= e.B) return;
+    __shared__ double red[4];
+    const int Dp = e.Dp, nr = rel ? e.N + 1 : e.N;
+    double m = 0.0;
+    bool bad = false;
+    for (int j = 0; j < nr; ++j) {
+        const long r = (long)b * nr + j;
+        double acc = 0.0;
+        for (int s = threadIdx.x; s < Dp; s += 256) acc += e.E[r * Dp + s] * e.Yn[r * Dp + s];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double q = (red[0] + red[1]) + (red[2] + red[3]);
+            const double v = (q == q && q < 1.7e308 && q > -1.7e308) ? sqrt(q > 0.0 ? q : 0.0) : __builtin_nan("");
+            e.nrm[r] = v;
+            if (!(v == v)) bad = true;
+            if (v > m) m = v;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e.J[b] = bad ? __builtin_nan("") : m;
+}
+
+__global__ void k_grp_scan_init(const BatchElem* __restrict__ it, const int* __restrict__ act, int cur) {
+    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    GRP_LOOP((long)e.B * e.N * e.Dp) {
+        const long per = (long)e.N * e.Dp;
+        const long b = i / per, j = i - b * per;
+        const long o = (b * (long)(e.Z + e.N + 1) + e.Z) * e.Dp + j;
+        const double v = e.Fbuf[i] - e.Xk[cur][b * (long)(e.N + 1) * e.Dp + e.Dp + j];
+        e.t64[0][o] = v;
+        e.t32[o] = (float)v;
+    }
+}
+
+__global__ void k_grp_scan_final(const BatchElem* __restrict__ it, const int* __restrict__ act, int cur, int nxt) {
+    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    GRP_LOOP((long)e.B * e.N * e.Dp) {
+        const long per = (long)e.N * e.Dp;
+        const long b = i / per, j = i - b * per;
+        if (!e.active[b]) continue;
+        const long o = (b * (long)(e.Z + e.N + 1) + e.Z) * e.Dp + j;
+        const long x = b * (long)(e.N + 1) * e.Dp + e.Dp + j;
+        e.Xk[nxt][x] = e.Xk[cur][x] + e.t64[e.L & 1][o];
+    }
+}
+
+__global__ void k_grp_scan_init0(const BatchElem* __restrict__ it, const int* __restrict__ act) {
+    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    GRP_LOOP((long)e.B * (e.N + 1) * e.Dp) {
+        const long per = (long)(e.N + 1) * e.Dp;
+        const long b = i / per, j = i - b * per;
+        const long o = (b * (long)(e.Z + e.N + 1) + e.Z) * e.Dp + j;
+        const double v = j < e.Dp ? e.Xk[0][b * per + j] : (e.CS ? e.CS[b * (long)e.N * e.Dp + j - e.Dp] : 0.0);
+        e.t64[0][o] = v;
+        e.t32[o] = (float)v;
+    }
+}
+
+__global__ void k_grp_scan_final0(const BatchElem* __restrict__ it, const int* __restrict__ act) {
+    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    GRP_LOOP((long)e.B * e.N * e.Dp) {
+        const long per = (long)e.N * e.Dp;
+        const long b = i / per, j = i - b * per;
+        const long o = (b * (long)(e.Z + e.N + 1) + e.Z) * e.Dp + e.Dp + j;
+        e.Xk[0][b * (long)(e.N + 1) * e.Dp + e.Dp + j] = 0.0 + e.t64[e.L0 & 1][o];
+    }
+}
+#undef GRP_LOOP
+
+static inline dim3 grp_grid(int n_act) { return dim3((unsigned)(n_act * GRP_CH)); }
+
+hipError_t grp_set_x0(const BatchElem* it, const int* act, int n_act, int xk, int zero_mode, hipStream_t st) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_set_x0, grp_grid(n_act), dim3(256), 0, st, it, act, xk, zero_mode);
+    return hipGetLastError();
+}
+hipError_t grp_fine_init(const BatchElem* it, const int* act, int n_act, int cur, int incremental, int mixed,
+                         hipStream_t st) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_fine_init, grp_grid(n_act), dim3(256), 0, st, it, act, cur, incremental, mixed);
+    return hipGetLastError();
+}
+hipError_t grp_fine_final(const BatchElem* it, const int* act, int n_act, int P, int mixed, hipStream_t st) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_fine_final, grp_grid(n_act), dim3(256), 0, st, it, act, P, mixed);
+    return hipGetLastError();
+}
+hipError_t grp_jump_diff(const BatchElem* it, const int* act, int n_act, int xk, int rel, hipStream_t st) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_jump_diff, grp_grid(n_act), dim3(256), 0, st, it, act, xk, rel);
+    return hipGetLastError();
+}
+hipError_t grp_jump_reduce(const BatchElem* it, const int* act, int n_act, int Bmax, int rel, hipStream_t st) {
+    if (n_act <= 0 || Bmax <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_jump_reduce, dim3((unsigned)(n_act * Bmax)), dim3(256), 0, st, it, act, Bmax, rel);
+    return hipGetLastError();
+}
+hipError_t grp_scan_init(const BatchElem* it, const int* act, int n_act, int cur, hipStream_t st) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_scan_init, grp_grid(n_act), dim3(256), 0, st, it, act, cur);
+    return hipGetLastError();
+}
+hipError_t grp_scan_final(const BatchElem* it, const int* act, int n_act, int cur, int nxt, hipStream_t st) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_scan_final, grp_grid(n_act), dim3(256), 0, st, it, act, cur, nxt);
+    return hipGetLastError();
+}
+hipError_t grp_scan_init0(const BatchElem* it, const int* act, int n_act, hipStream_t st) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_scan_init0, grp_grid(n_act), dim3(256), 0, st, it, act);
+    return hipGetLastError();
+}
+hipError_t grp_scan_final0(const BatchElem* it, const int* act, int n_act, hipStream_t st) {
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grp_scan_final0, grp_grid(n_act), dim3(256), 0, st, it, act);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // operator assembly
 // ---------------------------------------------------------------------------
 // generic placement: dst[(ro + i) * ldd + co + j] = scale * (trans ? src[j*lds + i] : src[i*lds + j])

@@ -65,6 +65,48 @@ hipError_t wr_cat(const double* L, double* out, int P, long NB, int d, int mode,
 hipError_t wr_axmy(double* y, const double* a, const double* b, double alpha, long n, hipStream_t st);
 hipError_t wr_io(int dir, const double* X, long ldXb, double* Fout, int N, int d1, int d2, int d1p, int d2p,
                  int c0, int NBc, int P, double* Ul, double* Wl, hipStream_t st);
+// Grouped element-wise steps of a batch of different problems: one launch
+// covers every active problem (act[0..n_act-1] index the BatchElem array),
+// each with the arithmetic and order of the one-problem kernels above.
+struct BatchElem {
+    double* Xk[2] = {nullptr, nullptr};  // B x (N + 1) x Dp iterates
+    double* E = nullptr;                 // jump differences (B x (N + 1) x Dp)
+    const double* Yn = nullptr;          // M E
+    double* nrm = nullptr;               // B x (N + 1) row norms
+    double* J = nullptr;                 // B jumps
+    const double* x0p = nullptr;         // B x Dp
+    double* Dl64 = nullptr;              // B x Dp change buffer to clear (nullable)
+    float* Dl32 = nullptr;
+    double* Xa = nullptr;                // fine sweep: anchors (B x N x Dp)
+    double* R64 = nullptr;               // mixed: whitened anchors / results
+    double* dev64[2] = {nullptr, nullptr};
+    float* dev32 = nullptr;
+    double* Fbuf = nullptr;              // B x N x Dp fine values
+    const double* CS = nullptr;          // B x N x Dp coarse source (nullable)
+    double* t64[2] = {nullptr, nullptr}; // scan buffers (B x (Z + N + 1) x Dp)
+    float* t32 = nullptr;                // FP32 copy of t64[0]
+    const int* active = nullptr;         // B flags
+    int B = 0, N = 0, Dp = 0, d1p = 0, Z = 0, L = 0, L0 = 0;
+};
+// x0 into row 0 of X^xk; zero_mode 1/2 also clears the B x Dp change buffer
+// (FP64 / FP32)
+hipError_t grp_set_x0(const BatchElem* it, const int* act, int n_act, int xk, int zero_mode, hipStream_t st);
+// fine sweep start (incremental: anchors from E with rows shifted by one,
+// else from X^cur) and end (mixed: R64, else Fbuf, gets anchors + deviation)
+hipError_t grp_fine_init(const BatchElem* it, const int* act, int n_act, int cur, int incremental, int mixed,
+                         hipStream_t st);
+hipError_t grp_fine_final(const BatchElem* it, const int* act, int n_act, int P, int mixed, hipStream_t st);
+// jump differences (rel: the rows n = 0..N of X^xk) and the row norms with the
+// per-sample maximum
+hipError_t grp_jump_diff(const BatchElem* it, const int* act, int n_act, int xk, int rel, hipStream_t st);
+hipError_t grp_jump_reduce(const BatchElem* it, const int* act, int n_act, int Bmax, int rel, hipStream_t st);
+// scans of the coarse sweeps: correction (t = F - X^cur rows 1..N, then
+// X^nxt = X^cur + t) and initial sweep (t_0 = x0, t_n = c_{n-1}, then X^0
+// rows 1..N = t)
+hipError_t grp_scan_init(const BatchElem* it, const int* act, int n_act, int cur, hipStream_t st);
+hipError_t grp_scan_final(const BatchElem* it, const int* act, int n_act, int cur, int nxt, hipStream_t st);
+hipError_t grp_scan_init0(const BatchElem* it, const int* act, int n_act, hipStream_t st);
+hipError_t grp_scan_final0(const BatchElem* it, const int* act, int n_act, hipStream_t st);
 // peak probes: kind 0 FP32 MFMA, 1 FP64 MFMA (blocks x 256 threads, iters
 // rounds of 16 independent 16x16x4 products per wave), 2 copy of n float4
 hipError_t probe_launch(int kind, int blocks, int iters, void* out, const void* src, long n, hipStream_t st);

@@ -43,8 +43,9 @@ PEAK_HBM_TBPS = 8.0      # MI355X HBM3E
 # copy reads for the same counters), keyed by workload and the kernel's tile
 # configuration (state-tile rows, operator-tile rows, K depth, split-K).
 # Reported only when the timed run used that kernel class and configuration.
-MEASURED_TRAFFIC = {("c1", "fine_step", (64, 32, 64, 8)): 2.0 * 18546.6 * 1024 + 1.0 * 4000.0 * 1024,
-                    # the 256-solve batch: FETCH_SIZE x 2 + WRITE_SIZE x 1 of the grouped FP32
+# (the 200x200 single-problem product's counters predate the current product
+# kernel, so its line reports no traffic)
+MEASURED_TRAFFIC = {# the 256-solve batch: FETCH_SIZE x 2 + WRITE_SIZE x 1 of the grouped FP32
                     # product over one batch solve, divided by its 558 fine-step launches
                     ("c2", 256): (2.0 * 6432177144.2 + 1.0 * 433136376.4) * 1024 / 2 / 558}
 

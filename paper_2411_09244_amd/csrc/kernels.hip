@@ -3,6 +3,8 @@
 // assembly and the per-block part of the FP64 Cholesky factorisation.
 #include "pe_kernels.h"
 
+#include <algorithm>
+
 namespace pe {
 
 static inline dim3 grid1(long n, int bs = 256) {
@@ -410,16 +412,18 @@ hipError_t set_x0(const double* x0p, double* X, long ldXb, int B, int Dp, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// grouped element-wise steps of a batch: GRP_CH work-groups per active
-// problem, each striding over that problem's elements
+// grouped element-wise steps of a batch: ch work-groups per active problem
+// (64 for 256 or more problems, up to 4096 for one), each striding over
+// that problem's elements
 // ---------------------------------------------------------------------------
-constexpr int GRP_CH = 64;
+static inline int grp_ch(int n_act) { return std::max(64, std::min(4096, 16384 / std::max(1, n_act))); }
 
 #define GRP_LOOP(n_el) \
-    for (long i = (long)(blockIdx.x % GRP_CH) * 256 + threadIdx.x; i < (n_el); i += (long)GRP_CH * 256)
+    for (long i = (long)(blockIdx.x % ch) * 256 + threadIdx.x; i < (n_el); i += (long)ch * 256)
 
-__global__ void k_grp_set_x0(const BatchElem* __restrict__ it, const int* __restrict__ act, int xk, int zero_mode) {
-    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+__global__ void k_grp_set_x0(const BatchElem* __restrict__ it, const int* __restrict__ act, int ch, int xk,
+                             int zero_mode) {
+    const BatchElem& e = it[act[blockIdx.x / ch]];
     GRP_LOOP((long)e.B * e.Dp) {
         const long b = i / e.Dp;
         const int s = (int)(i - b * e.Dp);
@@ -429,9 +433,9 @@ __global__ void k_grp_set_x0(const BatchElem* __restrict__ it, const int* __rest
     }
 }
 
-__global__ void k_grp_fine_init(const BatchElem* __restrict__ it, const int* __restrict__ act, int cur, int inc,
+__global__ void k_grp_fine_init(const BatchElem* __restrict__ it, const int* __restrict__ act, int ch, int cur, int inc,
                                 int mixed) {
-    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+    const BatchElem& e = it[act[blockIdx.x / ch]];
     GRP_LOOP((long)e.B * e.N * e.Dp) {
         const int Dp = e.Dp, N = e.N;
         const long r = i / Dp;
@@ -451,8 +455,9 @@ __global__ void k_grp_fine_init(const BatchElem* __restrict__ it, const int* __r
     }
 }
 
-__global__ void k_grp_fine_final(const BatchElem* __restrict__ it, const int* __restrict__ act, int P, int mixed) {
-    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+__global__ void k_grp_fine_final(const BatchElem* __restrict__ it, const int* __restrict__ act, int ch, int P,
+                                 int mixed) {
+    const BatchElem& e = it[act[blockIdx.x / ch]];
     GRP_LOOP((long)e.B * e.N * e.Dp) {
         const int Dp = e.Dp;
         const long r = i / Dp;
@@ -462,8 +467,9 @@ __global__ void k_grp_fine_final(const BatchElem* __restrict__ it, const int* __
     }
 }
 
-__global__ void k_grp_jump_diff(const BatchElem* __restrict__ it, const int* __restrict__ act, int xk, int rel) {
-    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+__global__ void k_grp_jump_diff(const BatchElem* __restrict__ it, const int* __restrict__ act, int ch, int xk,
+                                int rel) {
+    const BatchElem& e = it[act[blockIdx.x / ch]];
     const int nr0 = rel ? e.N + 1 : e.N;
     GRP_LOOP((long)e.B * nr0 * e.Dp) {
         const int Dp = e.Dp, nr = rel ? e.N + 1 : e.N, n0 = rel ? 0 : 1;
@@ -505,8 +511,8 @@ __global__ __launch_bounds__(256) void k_grp_jump_reduce(const BatchElem* __rest
     if (threadIdx.x == 0) e.J[b] = bad ? __builtin_nan("") : m;
 }
 
-__global__ void k_grp_scan_init(const BatchElem* __restrict__ it, const int* __restrict__ act, int cur) {
-    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+__global__ void k_grp_scan_init(const BatchElem* __restrict__ it, const int* __restrict__ act, int ch, int cur) {
+    const BatchElem& e = it[act[blockIdx.x / ch]];
     GRP_LOOP((long)e.B * e.N * e.Dp) {
         const long per = (long)e.N * e.Dp;
         const long b = i / per, j = i - b * per;
@@ -517,8 +523,9 @@ __global__ void k_grp_scan_init(const BatchElem* __restrict__ it, const int* __r
     }
 }
 
-__global__ void k_grp_scan_final(const BatchElem* __restrict__ it, const int* __restrict__ act, int cur, int nxt) {
-    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+__global__ void k_grp_scan_final(const BatchElem* __restrict__ it, const int* __restrict__ act, int ch, int cur,
+                                 int nxt) {
+    const BatchElem& e = it[act[blockIdx.x / ch]];
     GRP_LOOP((long)e.B * e.N * e.Dp) {
         const long per = (long)e.N * e.Dp;
         const long b = i / per, j = i - b * per;
@@ -529,8 +536,8 @@ __global__ void k_grp_scan_final(const BatchElem* __restrict__ it, const int* __
     }
 }
 
-__global__ void k_grp_scan_init0(const BatchElem* __restrict__ it, const int* __restrict__ act) {
-    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+__global__ void k_grp_scan_init0(const BatchElem* __restrict__ it, const int* __restrict__ act, int ch) {
+    const BatchElem& e = it[act[blockIdx.x / ch]];
     GRP_LOOP((long)e.B * (e.N + 1) * e.Dp) {
         const long per = (long)(e.N + 1) * e.Dp;
         const long b = i / per, j = i - b * per;
@@ -541,8 +548,8 @@ __global__ void k_grp_scan_init0(const BatchElem* __restrict__ it, const int* __
     }
 }
 
-__global__ void k_grp_scan_final0(const BatchElem* __restrict__ it, const int* __restrict__ act) {
-    const BatchElem& e = it[act[blockIdx.x / GRP_CH]];
+__global__ void k_grp_scan_final0(const BatchElem* __restrict__ it, const int* __restrict__ act, int ch) {
+    const BatchElem& e = it[act[blockIdx.x / ch]];
     GRP_LOOP((long)e.B * e.N * e.Dp) {
         const long per = (long)e.N * e.Dp;
         const long b = i / per, j = i - b * per;
@@ -552,27 +559,28 @@ __global__ void k_grp_scan_final0(const BatchElem* __restrict__ it, const int* _
 }
 #undef GRP_LOOP
 
-static inline dim3 grp_grid(int n_act) { return dim3((unsigned)(n_act * GRP_CH)); }
+static inline dim3 grp_grid(int n_act) { return dim3((unsigned)(n_act * grp_ch(n_act))); }
 
 hipError_t grp_set_x0(const BatchElem* it, const int* act, int n_act, int xk, int zero_mode, hipStream_t st) {
     if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grp_set_x0, grp_grid(n_act), dim3(256), 0, st, it, act, xk, zero_mode);
+    hipLaunchKernelGGL(k_grp_set_x0, grp_grid(n_act), dim3(256), 0, st, it, act, grp_ch(n_act), xk, zero_mode);
     return hipGetLastError();
 }
 hipError_t grp_fine_init(const BatchElem* it, const int* act, int n_act, int cur, int incremental, int mixed,
                          hipStream_t st) {
     if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grp_fine_init, grp_grid(n_act), dim3(256), 0, st, it, act, cur, incremental, mixed);
+    hipLaunchKernelGGL(k_grp_fine_init, grp_grid(n_act), dim3(256), 0, st, it, act, grp_ch(n_act), cur, incremental,
+                       mixed);
     return hipGetLastError();
 }
 hipError_t grp_fine_final(const BatchElem* it, const int* act, int n_act, int P, int mixed, hipStream_t st) {
     if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grp_fine_final, grp_grid(n_act), dim3(256), 0, st, it, act, P, mixed);
+    hipLaunchKernelGGL(k_grp_fine_final, grp_grid(n_act), dim3(256), 0, st, it, act, grp_ch(n_act), P, mixed);
     return hipGetLastError();
 }
 hipError_t grp_jump_diff(const BatchElem* it, const int* act, int n_act, int xk, int rel, hipStream_t st) {
     if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grp_jump_diff, grp_grid(n_act), dim3(256), 0, st, it, act, xk, rel);
+    hipLaunchKernelGGL(k_grp_jump_diff, grp_grid(n_act), dim3(256), 0, st, it, act, grp_ch(n_act), xk, rel);
     return hipGetLastError();
 }
 hipError_t grp_jump_reduce(const BatchElem* it, const int* act, int n_act, int Bmax, int rel, hipStream_t st) {
@@ -582,22 +590,22 @@ hipError_t grp_jump_reduce(const BatchElem* it, const int* act, int n_act, int B
 }
 hipError_t grp_scan_init(const BatchElem* it, const int* act, int n_act, int cur, hipStream_t st) {
     if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grp_scan_init, grp_grid(n_act), dim3(256), 0, st, it, act, cur);
+    hipLaunchKernelGGL(k_grp_scan_init, grp_grid(n_act), dim3(256), 0, st, it, act, grp_ch(n_act), cur);
     return hipGetLastError();
 }
 hipError_t grp_scan_final(const BatchElem* it, const int* act, int n_act, int cur, int nxt, hipStream_t st) {
     if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grp_scan_final, grp_grid(n_act), dim3(256), 0, st, it, act, cur, nxt);
+    hipLaunchKernelGGL(k_grp_scan_final, grp_grid(n_act), dim3(256), 0, st, it, act, grp_ch(n_act), cur, nxt);
     return hipGetLastError();
 }
 hipError_t grp_scan_init0(const BatchElem* it, const int* act, int n_act, hipStream_t st) {
     if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grp_scan_init0, grp_grid(n_act), dim3(256), 0, st, it, act);
+    hipLaunchKernelGGL(k_grp_scan_init0, grp_grid(n_act), dim3(256), 0, st, it, act, grp_ch(n_act));
     return hipGetLastError();
 }
 hipError_t grp_scan_final0(const BatchElem* it, const int* act, int n_act, hipStream_t st) {
     if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grp_scan_final0, grp_grid(n_act), dim3(256), 0, st, it, act);
+    hipLaunchKernelGGL(k_grp_scan_final0, grp_grid(n_act), dim3(256), 0, st, it, act, grp_ch(n_act));
     return hipGetLastError();
 }
 

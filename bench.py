@@ -688,8 +688,8 @@ def main():
                          "HBM traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "the multi-GPU design is described, not built.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (--gpus {args.gpus} requested); "
+              "the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

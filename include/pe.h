@@ -436,6 +436,15 @@ pe_status pe_nlmc_spaces(int n, int n_c, int layers, int J, const int* counts, c
  *   batch and keep their sources; a later pe_source_set or a pe_solve with
  *   more samples is picked up at the next pe_batch_solve). hip_stream: the
  *   stream for all batch work (NULL: the batch creates its own).
+ *   Launch options read from the environment at creation: PE_BATCH_TILE=
+ *   "br bs bk2" the grouped products' tile (32 64, 64 64 (default), 64 128
+ *   or 128 64; bk2 = 1 twice the K depth); PE_BATCH_XCD the work-group order
+ *   (2, the default: the row tiles of each operator column tile on one XCD;
+ *   1 or 3: every tile of a product on one XCD; 0: plain); PE_BATCH_SCAN=0
+ *   keeps the sequential coarse sweeps of the mixed path (the default runs
+ *   the initial sweep and the corrections as doubling scans). Results are
+ *   bitwise reproducible for a fixed tile; the work-group order does not
+ *   change them.
  * pe_batch_solve - Algorithm 1 for every problem of the batch.
  *   x0          host array of `count` device pointers, x0[i]: B_i x D_i
  *               (B_i the sample count of problem i's source, 1 without one).

@@ -1191,13 +1191,18 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
             PE_TRY(gemm<double>(p, g, e, 0, kind, SITE_FINE_STEP));
         if (ref_step) {
             // FP64 residual of the implicit V_H1 equation (eq. (2.4)) at the
-            // FP32 step's u': r = F~1(t) - (A~ x_a)_u - Wr [du | u - u_a | w - w_a | dw_prev]
+            // FP32 step's u': r = F~1(t) - (A~ x_a)_u - K~ du - A~11 (u - u_a)
+            // - A~12 (w - w_a) - M~12 dw_prev / h, as Wr [du + u - u_a | w - w_a
+            // | dw_prev] and the diagonal term du / h
             Epi er;
             er.mode = EPI_RESID;
             er.R32 = p->res32;
             er.ldr = d1p;
             er.base = p->AxU;
             er.ldb = d1p;
+            er.dres = p->Vr + d1p + 2 * d2p;
+            er.lddres = ldS;
+            er.cres = 1.0 / p->dtf;
             source_fields(p, er, true);
             if (sv) {
                 er.src_kind = sv->kind;
@@ -1208,8 +1213,8 @@ pe_status fine_sweep(pe_problem p, int B, const double* Xsrc, long ldXb, double*
             er.cols_per_b = p->N;
             er.n_fixed = -1;
             er.p_step = step;
-            PE_TRY(gemm<double>(p, shape(rows, d1p, p->Vr, ldS, p->Wr64, ldS, 0, (int)ldS), er, 0, PE_PROF_REFINE,
-                                SITE_REFINE_RES));
+            PE_TRY(gemm<double>(p, shape(rows, d1p, p->Vr, ldS, p->Wr64, ldS, 0, d1p + 2 * d2p), er, 0,
+                                PE_PROF_REFINE, SITE_REFINE_RES));
             // FP32 correction of both increments: Z_h[:, u] r
             Epi ec;
             ec.mode = EPI_FCORR;
@@ -2032,6 +2037,9 @@ pe_status batch_plan(pe_batch bt) {
                     er.ldr = d1p;
                     er.base = p->AxU;
                     er.ldb = d1p;
+                    er.dres = p->Vr + d1p + 2 * d2p;
+                    er.lddres = ldS;
+                    er.cres = 1.0 / p->dtf;
                     source_fields(p, er, true);
                     if (!w) er.src_kind = 0;
                     er.cols_per_b = N;
@@ -2069,7 +2077,7 @@ pe_status batch_plan(pe_batch bt) {
         if (bt->refine) {
             a3[g] = shape(rows, d1p, p->Xa, Dp, p->Aw64, Dp, 0, Dp);
             e_a3[g] = store_epi(p->AxU, d1p);
-            rr_sh[g] = shape(rows, d1p, p->Vr, ldS, p->Wr64, ldS, 0, (int)ldS);
+            rr_sh[g] = shape(rows, d1p, p->Vr, ldS, p->Wr64, ldS, 0, d1p + 2 * d2p);
             rc_sh[g] = shape(rows, Dp, p->res32, d1p, p->Zc32, d1p, 0, d1p);
         }
         // back to the caller's coordinates (mixed)
@@ -3176,12 +3184,14 @@ pe_status pe_problem_create(pe_problem* out, int d1, int d2, const double* M11, 
             CK(dalloc_t(p, tmp, &ZW, (size_t)Dp * 2 * Dp));
             Aop = p->Aw64;
             if (refine) {
-                // Wr = the u rows of W_h [0 | A~11 | A~12 | M~12/h] with the
-                // implicit operator K~ = I/h + A~11 in the first block
+                // Wr = [A~11 | A~12 | M~12/h]: the u rows of W_h = [0 | A~11 |
+                // A~12 | M~12/h] past their zero first block. With the
+                // operands [du + u - u_a | w - w_a | dw_prev] the product is
+                // K~ du + A~11 (u - u_a) + A~12 (w - w_a) + M~12 dw_prev / h
+                // (K~ = I/h + A~11) less du / h, which the residual's
+                // epilogue subtracts as a diagonal term
                 CK(dalloc_t(p, OL, &p->Wr64, (size_t)d1p * 2 * Dp));
-                CKH(hipMemcpyAsync(p->Wr64, W64, sizeof(double) * d1p * 2 * Dp, hipMemcpyDeviceToDevice, p->st));
-                CKH(place(p->Wr64, 2L * Dp, 0, 0, wA11, d1p, d1, d1, 1.0, 0, p->st, 1));
-                CKH(place(p->Wr64, 2L * Dp, 0, 0, I11, d1p, d1, d1, 1.0 / dt_fine, 0, p->st, 1));
+                CKH(place(p->Wr64, 2L * Dp, 0, 0, W64 + d1p, 2L * Dp, d1p, d1p + 2 * d2p, 1.0, 0, p->st));
                 // Zc = Z_h[:, u]: the solve of a V_H1 residual and its effect
                 // on the explicit V_H2 increment
                 double* Zc = nullptr;

@@ -143,6 +143,7 @@ __device__ inline EpiIn epi_load(const Epi& e, int r, int s) {
         if (e.beta != 0.0) in.a = e.C0[(long)r * e.ldc0 + s];
     } else if constexpr (MODE == EPI_RESID) {
         if (e.base) in.b = e.base[(long)r * e.ldb + s];
+        if (e.dres) in.c = e.dres[(long)r * e.lddres + s];
         in.a = source_value(e, r, s);
     } else if constexpr (MODE == EPI_FSTEP) {
         // branch-free load first, the source term (branches, waits) last
@@ -184,6 +185,7 @@ __device__ inline void epi_finish(const Epi& e, int r, int s, double acc, const 
     } else if constexpr (MODE == EPI_RESID) {
         double v = in.a - acc;
         if (e.base) v -= in.b;
+        if (e.dres) v -= e.cres * in.c;
         if (e.R64) e.R64[(long)r * e.ldr + s] = v;
         if (e.R32) e.R32[(long)r * e.ldr + s] = (float)v;
     } else if constexpr (MODE == EPI_FSTEP) {
@@ -205,8 +207,8 @@ __device__ inline void epi_finish(const Epi& e, int r, int s, double acc, const 
             full_dev = u;
             if (e.vr) {
                 double* q = e.vr + (long)r * e.ldd;
-                q[s] = v;
-                q[e.d1p + s] = in.c;
+                q[s] = u;
+                q[e.d1p + 2L * e.d2p + s] = v;
             }
         } else {
             const int j = s - e.d1p;
@@ -221,8 +223,8 @@ __device__ inline void epi_finish(const Epi& e, int r, int s, double acc, const 
             full_dev = w;
             if (e.vr) {
                 double* q = e.vr + (long)r * e.ldd;
-                q[ow] = in.c;
-                q[oh] = in.d;
+                q[e.d1p + j] = in.c;
+                q[e.d1p + e.d2p + j] = in.d;
             }
         }
         if (e.traj) e.traj[(long)r * e.ldtraj + s] = e.xa[(long)r * (e.d1p + e.d2p) + s] + full_dev;

@@ -45,12 +45,15 @@ struct Epi {
     float* C32 = nullptr;  // EPI_STORE: nullable FP32 copy of C (same ldc)
     const double* C0 = nullptr;
     long ldc = 0, ldc0 = 0;
-    // EPI_RESID (R64 and R32 nullable)
+    // EPI_RESID (R64 and R32 nullable): R = f - base - acc (- cres * dres)
     double* R64 = nullptr;
     float* R32 = nullptr;
     long ldr = 0;
     const double* base = nullptr;
     long ldb = 0;
+    const double* dres = nullptr;  // nullable: a diagonal term cres * dres[r][s] (ld lddres)
+    long lddres = 0;
+    double cres = 0.0;
     int src_kind = 0;            // 0: f = 0, 1: low-rank G*H, 2: dense per-interval table
     const double* Gs = nullptr;  // Dp x R
     const double* Hs = nullptr;  // B x R x Tlen
@@ -78,8 +81,8 @@ struct Epi {
     const double* xa = nullptr;     // anchors, ld d1p + d2p
     long ldtraj = 0;
     // EPI_FSTEP with refinement (nullable): the implicit equation's operands
-    // [du_new | u - u_a | w - w_a | dw_prev] (the step's input state with its
-    // first block replaced by the new V_H1 increment), ld ldd
+    // [du_new + u - u_a | w - w_a | dw_prev | du_new] (u - u_a of the step's
+    // input state; the last block feeds the residual's diagonal term), ld ldd
     double* vr = nullptr;
     // EPI_FCORR uses dev64 / dev32 (state updated in place), ldd, d1p, d2p, traj, ldtraj
     // EPI_COARSE_*  (column r is sample r)
